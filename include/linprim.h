@@ -1,0 +1,214 @@
+/*
+ * linprim.h -- C ABI of the MI355X (gfx950) differentiable tile rasterizer
+ * for transparent linear primitives: octahedra and tetrahedra, following
+ * LinPrim (von Luetzow & Niessner, arXiv 2501.16312).
+ *
+ * Pipeline (Sec. 3.2 "Rendering Process", Sec. 3.4 "Optimization"):
+ *   linprim_preprocess  -> per primitive and view: build the primitive from
+ *                          its features, transform it to the camera, colour
+ *                          it from its SH along the viewing direction,
+ *                          project it into the EWA affine ray space and bound
+ *                          it on screen; count the tiles it touches and
+ *                          prefix-sum the counts.
+ *   linprim_bin_sort    -> one (tile | depth, primitive) pair per touched
+ *                          tile, sorted by key ("Global Sorting and Tiling"),
+ *                          and the [start, end) range of every tile.
+ *   linprim_render_fwd  -> per pixel, front-to-back compositing of the tile's
+ *                          list with the chord-based opacity of Eq. 1 and
+ *                          App. E, stopping once cumulative opacity reaches
+ *                          0.999 ("Rasterization", "Compositing").
+ *   linprim_render_bwd  -> gradients of a loss given dL/dC, through blending,
+ *                          chords, ray space and the view transform down to
+ *                          the primitive features ("Rasterization/
+ *                          Preprocessing Backpropagation", App. E).
+ *
+ * Conventions shared by every entry point:
+ *   - Every array argument is a DEVICE pointer owned by the caller, except
+ *     the linprim_camera array, the background colour and the outputs of
+ *     linprim_pair_count / linprim_read_status, which are HOST pointers.
+ *   - Calls only enqueue work on `stream` (a hipStream_t; NULL = the null
+ *     stream) and return at once; none allocates device memory.  The single
+ *     call that waits for the stream is linprim_pair_count (it must return a
+ *     number to the host).
+ *   - Return value: LINPRIM_OK (0) or a negative LINPRIM_ERR_* code; the
+ *     outputs are then untouched.  linprim_strerror names the code.
+ *   - Degenerate primitives (zero quaternion, a distance <= 0, non-finite
+ *     values, opacity outside [0, 1], centre not beyond the near plane, or a
+ *     box that covers no pixel centre) are culled, not reported.
+ */
+#ifndef LINPRIM_H
+#define LINPRIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { LINPRIM_OCTAHEDRON = 0, LINPRIM_TETRAHEDRON = 1 };
+
+enum {
+    LINPRIM_OK = 0,
+    LINPRIM_ERR_INVALID_ARG = -1,     /* null pointer, bad size, unknown type or tile */
+    LINPRIM_ERR_WORKSPACE = -2,       /* a workspace is smaller than its *_size() */
+    LINPRIM_ERR_PAIR_OVERFLOW = -3,   /* more (tile, primitive) pairs than max_pairs */
+    LINPRIM_ERR_HIP = -4,             /* a HIP launch or query failed */
+    LINPRIM_ERR_DEVICE = -5           /* current device is not gfx950 */
+};
+
+/* Primitives (Sec. 3.1).  Octahedron: centre mu, rotation q, one distance per
+ * pair of opposite vertices (corners mu +/- R(q) d_k e_k).  Tetrahedron:
+ * centre mu, rotation q, one distance per corner along four equally spaced
+ * directions (corners mu + R(q) d_i b_i, b_i = (1,1,1), (1,-1,-1), (-1,1,-1),
+ * (-1,-1,1) over sqrt(3)).  All float32, row-major, device memory. */
+typedef struct linprim_prims {
+    int32_t type;          /* LINPRIM_OCTAHEDRON or LINPRIM_TETRAHEDRON */
+    int32_t sh_degree;     /* 0..3: (sh_degree+1)^2 coefficients per channel */
+    int64_t n;             /* number of primitives, 0 <= n < 2^31 */
+    const float *means;    /* [n,3] */
+    const float *quats;    /* [n,4] (w,x,y,z); need not be unit, normalised inside */
+    const float *dists;    /* [n,3] octahedron, [n,4] tetrahedron; > 0 */
+    const float *opacity;  /* [n] activated opacity alpha in [0,1] (Eq. 1) */
+    const float *sh;       /* [n,(sh_degree+1)^2,3] SH coefficients, RGB last */
+} linprim_prims;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  HOST struct. */
+typedef struct linprim_camera {
+    float world_to_cam[12];   /* row-major 3x4 [R | t]: x_cam = R x_world + t */
+    float fx, fy, cx, cy;     /* pixels; pixel (i,j) has its centre at (i+1/2, j+1/2) */
+    int32_t width, height;    /* 1..32768 */
+    float near_z;             /* primitives with centre depth <= near_z are culled */
+    int32_t reserved;
+} linprim_camera;
+
+/* Launch configuration. */
+typedef struct linprim_tuning {
+    int32_t tile;             /* screen tile edge in pixels: 8, 16 or 32 */
+    int32_t sort_digit_bits;  /* radix-sort digit width, 4..8 (0 = 8) */
+    int32_t flags;            /* LINPRIM_FLAG_* */
+    int32_t reserved;
+} linprim_tuning;
+
+/* Count iterated / evaluated / intersected (pixel, primitive) pairs in
+ * render_fwd (slower; for measurements). */
+#define LINPRIM_FLAG_COUNTERS 1
+
+/* Bytes of the per-view workspace (payloads, counts, offsets, tile ranges,
+ * status) for n primitives of `type` over n_views cameras. */
+size_t linprim_view_workspace_size(int32_t type, int64_t n, const linprim_camera *cams,
+                                   int32_t n_views, const linprim_tuning *tuning);
+
+/* Bytes of the pair workspace (sort keys and values, double-buffered, sort
+ * histograms and the per-pair gradient records of render_bwd) for up to
+ * max_pairs (tile, primitive) pairs. */
+size_t linprim_pair_workspace_size(int64_t max_pairs, const linprim_camera *cams, int32_t n_views,
+                                   const linprim_tuning *tuning);
+
+/* Sec. 3.2 "Preprocessing".  Writes, into view_ws, the ray-space render
+ * payload of every (view, primitive), its pixel and tile rectangles, depth
+ * key and tile count, and the exclusive prefix sum of the tile counts (the
+ * total is the pair count).  The binning quantities are computed in IEEE
+ * double precision with a fixed evaluation order, so they are reproducible
+ * bit for bit by any implementation that follows the same expressions.
+ * cams: HOST array [n_views].  The same prims, cams, n_views and tuning
+ * must be passed to every later call that uses this view_ws. */
+int linprim_preprocess(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                       const linprim_tuning *tuning, void *view_ws, size_t view_ws_bytes, void *stream);
+
+/* Waits for `stream` and returns the pair count of the last preprocess. */
+int linprim_pair_count(const void *view_ws, int64_t *n_pairs, void *stream);
+
+/* Sec. 3.2 "Global Sorting and Tiling".  Emits key = (global tile << 32) |
+ * float32 bits of the centre's camera depth and value = primitive index for
+ * every touched tile, sorts the pairs by key with a stable on-device LSD
+ * radix sort (ties keep primitive order), and writes every tile's [start,
+ * end) range into view_ws.  If the pair count exceeds max_pairs nothing is
+ * sorted, the overflow flag in view_ws is set and the render calls leave
+ * their outputs untouched; linprim_read_status reports it.  The
+ * sorted keys/values stay in pair_ws. */
+int linprim_bin_sort(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                     const linprim_tuning *tuning, void *view_ws, size_t view_ws_bytes, void *pair_ws,
+                     size_t pair_ws_bytes, int64_t max_pairs, void *stream);
+
+/* Sec. 3.2 "Rasterization" and "Compositing".  For every pixel, walks its
+ * tile's sorted list; a primitive whose pixel rectangle contains the pixel
+ * contributes opacity o = min(1 - exp(-sigma * chord), 0.99), with the chord
+ * the length of the pixel ray inside the ray-space primitive and sigma from
+ * Eq. 1; C += T o rgb, T *= 1 - o, and the walk stops after T <= 1e-3.
+ * Finally C += T bg.
+ *   bg       HOST float[3] background colour
+ *   out_rgb  [sum_v 3 H_v W_v] view-major, each view [3,H,W]
+ *   out_T    [sum_v H_v W_v] final transmittance
+ *   out_last [sum_v H_v W_v] one past the list position of the last blended
+ *            primitive (the tile's list start if none) */
+int linprim_render_fwd(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                       const linprim_tuning *tuning, const float *bg, const void *view_ws,
+                       size_t view_ws_bytes, const void *pair_ws, size_t pair_ws_bytes, int64_t max_pairs,
+                       float *out_rgb, float *out_T, int32_t *out_last, void *stream);
+
+/* Sec. 3.4 and App. E.  Given grad_rgb = dL/dC (layout of out_rgb) and the
+ * forward's out_T and out_last, walks every pixel's list backwards,
+ * recomputing transmittance (no per-sample state is stored), and writes the
+ * gradients with respect to the primitive features, summed over views.  The
+ * density normaliser min(d) of Eq. 1 is held constant (App. G).  Gradients
+ * are OVERWRITTEN; grad_sh has the layout of prims->sh.  Deterministic: no
+ * floating-point atomics. */
+int linprim_render_bwd(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                       const linprim_tuning *tuning, const float *bg, const void *view_ws,
+                       size_t view_ws_bytes, void *pair_ws, size_t pair_ws_bytes, int64_t max_pairs,
+                       const float *out_T, const int32_t *out_last, const float *grad_rgb,
+                       float *grad_means, float *grad_quats, float *grad_dists, float *grad_opacity,
+                       float *grad_sh, void *stream);
+
+/* The two stages of linprim_render_bwd, callable on their own (Sec. 3.4
+ * "Rasterization Backpropagation" and "Preprocessing Backpropagation").
+ * linprim_raster_bwd writes one gradient record per (tile, primitive) pair
+ * into pair_ws: dL/d(ray-space plane coefficients), dL/d rgb and dL/d sigma
+ * summed over the tile's pixels.  linprim_preprocess_bwd sums each
+ * primitive's records in a fixed order and carries them to the features;
+ * outputs as in linprim_render_bwd. */
+int linprim_raster_bwd(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                       const linprim_tuning *tuning, const float *bg, const void *view_ws,
+                       size_t view_ws_bytes, void *pair_ws, size_t pair_ws_bytes, int64_t max_pairs,
+                       const float *out_T, const int32_t *out_last, const float *grad_rgb, void *stream);
+int linprim_preprocess_bwd(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                           const linprim_tuning *tuning, const void *view_ws, size_t view_ws_bytes,
+                           const void *pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float *grad_means,
+                           float *grad_quats, float *grad_dists, float *grad_opacity, float *grad_sh,
+                           void *stream);
+
+/* Waits for `stream`; reports the pair count and whether the last bin_sort
+ * overflowed its capacity (HOST outputs). */
+int linprim_read_status(const void *view_ws, int64_t *pairs_needed, int32_t *overflow, void *stream);
+
+/* Same as linprim_render_fwd, and adds the iterated / evaluated /
+ * intersected (pixel, primitive) pair counts of this call to counters[0..2]
+ * (DEVICE uint64[3], accumulated with atomics).  Iterated: list entries a
+ * pixel walks up to its stop; evaluated: those whose pixel rectangle holds
+ * the pixel; intersected: those with a positive chord. */
+int linprim_render_fwd_counted(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                               const linprim_tuning *tuning, const float *bg, const void *view_ws,
+                               size_t view_ws_bytes, const void *pair_ws, size_t pair_ws_bytes,
+                               int64_t max_pairs, float *out_rgb, float *out_T, int32_t *out_last,
+                               uint64_t *counters, void *stream);
+
+/* Static description of an error code. */
+const char *linprim_strerror(int code);
+
+/* Device pointers into the workspaces, for tests and diagnostics:
+ * payload [n_views*n][32] (float; words 0..3 are the int pixel rectangle
+ * i0, j0, i1, j1 with i0 = -1 when culled), depth_keys [n_views*n] u32,
+ * tiles_touched [n_views*n] u32, offsets [n_views*n] u32, sorted keys
+ * [max_pairs] u64 and values [max_pairs] u32 (first n_pairs valid),
+ * ranges [total tiles] (u32 start, u32 end). */
+int linprim_debug_pointers(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                           const linprim_tuning *tuning, const void *view_ws, const void *pair_ws,
+                           int64_t max_pairs, void **payload, void **depth_keys, void **tiles_touched,
+                           void **offsets, void **keys, void **values, void **ranges);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LINPRIM_H */

@@ -60,6 +60,7 @@ def _load():
     lib.orc_num_tiles.argtypes = [P]
     lib.orc_get_sort.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_render.argtypes = [P, ctypes.c_int] + [ctypes.c_void_p] * 7
+    lib.orc_render_band.argtypes = [P, ctypes.c_int] + [ctypes.c_void_p] * 7 + [ctypes.c_int, ctypes.c_int]
     lib.orc_render_pixels.argtypes = [P, ctypes.c_int, I64] + [ctypes.c_void_p] * 6
     lib.orc_chord.restype = ctypes.c_double
     lib.orc_chord.argtypes = [P, ctypes.c_int, I64, ctypes.c_double, ctypes.c_double, ctypes.c_int]
@@ -197,6 +198,23 @@ class OracleScene:
         b = self._bg(bg)
         rc = _load().orc_render(self.h, m, _ptr(b), _ptr(rgb), _ptr(T), _ptr(last), _ptr(ill),
                                 _ptr(cond), _ptr(counts))
+        if rc != 0:
+            raise RuntimeError("oracle render failed")
+        return {"rgb": rgb, "T": T, "last": last, "ill": ill, "cond": cond, "counts": counts}
+
+    def render_band(self, j0: int, j1: int, bg=None) -> dict:
+        """Tiled render of the rows [j0, j1) of every view only (others zero)."""
+        self._ensure_sorted()
+        npx = sum(c.width * c.height for c in self.cams)
+        rgb = np.zeros(3 * npx)
+        T = np.zeros(npx)
+        last = np.zeros(npx, np.int64)
+        ill = np.zeros(npx, np.uint8)
+        cond = np.zeros(npx)
+        counts = np.zeros((len(self.cams), 4), np.int64)
+        b = self._bg(bg)
+        rc = _load().orc_render_band(self.h, 0, _ptr(b), _ptr(rgb), _ptr(T), _ptr(last), _ptr(ill),
+                                     _ptr(cond), _ptr(counts), int(j0), int(j1))
         if rc != 0:
             raise RuntimeError("oracle render failed")
         return {"rgb": rgb, "T": T, "last": last, "ill": ill, "cond": cond, "counts": counts}

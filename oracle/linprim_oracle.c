@@ -924,10 +924,27 @@ static int64_t pixel_list(const orc_scene *S, int v, int i, int j, int brute, in
  * rgb [3,H,W], T [H,W], last [H,W] (one past the tile-list position of the
  * last blended primitive, or the tile's list start), ill [H,W], cond [H,W].
  * counts[4*v + 0..3] = iterated, evaluated, intersected, frustum. */
+static int render_rows(orc_scene *S, int mode, const double *bg, double *rgb, double *T, int64_t *last,
+                       uint8_t *ill, double *cond, int64_t *counts, int band_j0, int band_j1);
+
 int orc_render(void *h, int mode, const double *bg, double *rgb, double *T, int64_t *last,
                uint8_t *ill, double *cond, int64_t *counts)
 {
-    orc_scene *S = (orc_scene *)h;
+    return render_rows((orc_scene *)h, mode, bg, rgb, T, last, ill, cond, counts, 0, 1 << 30);
+}
+
+/* orc_render restricted to the rows [j0, j1) of every view (the other
+ * pixels of the outputs are left untouched); used to time a bounded
+ * sample of a large workload. */
+int orc_render_band(void *h, int mode, const double *bg, double *rgb, double *T, int64_t *last,
+                    uint8_t *ill, double *cond, int64_t *counts, int j0, int j1)
+{
+    return render_rows((orc_scene *)h, mode, bg, rgb, T, last, ill, cond, counts, j0, j1);
+}
+
+static int render_rows(orc_scene *S, int mode, const double *bg, double *rgb, double *T, int64_t *last,
+                       uint8_t *ill, double *cond, int64_t *counts, int band_j0, int band_j1)
+{
     if (!S || !S->prep || (mode != 1 && !S->rlo)) return -1;
     const int brute = (mode == 1), clip = (mode == 2);
     int64_t rgb_base = 0;
@@ -939,8 +956,10 @@ int orc_render(void *h, int mode, const double *bg, double *rgb, double *T, int6
 #pragma omp parallel reduction(+ : it, ev, hit)
         {
             int64_t *list = NULL, *pos = NULL, cap = 0, start = 0;
+            const int jlo = band_j0 > 0 ? band_j0 : 0;
+            const int jhi = band_j1 < V->H ? band_j1 : V->H;
 #pragma omp for schedule(dynamic, 1)
-            for (int j = 0; j < V->H; ++j) {
+            for (int j = jlo; j < jhi; ++j) {
                 for (int i = 0; i < V->W; ++i) {
                     const int64_t len = pixel_list(S, v, i, j, brute, &list, &pos, &cap, &start);
                     orc_pix px;

@@ -1,0 +1,324 @@
+// abi.hip -- the extern "C" entry points of liblinprim.so: argument
+// validation, workspace layouts and launch order.  Every call enqueues on
+// the caller's stream; only linprim_pair_count / linprim_read_status wait.
+#include <string.h>
+
+#include "linprim_common.h"
+
+namespace linprim {
+
+int key_tile_bits(int64_t n_tiles_total) {
+    int b = 1;
+    while ((int64_t(1) << b) < n_tiles_total) ++b;
+    return b;
+}
+
+static int64_t total_tiles(const linprim_camera* cams, int32_t n_views, int tile) {
+    int64_t t = 0;
+    for (int v = 0; v < n_views; ++v)
+        t += (int64_t)((cams[v].width + tile - 1) / tile) * ((cams[v].height + tile - 1) / tile);
+    return t;
+}
+
+ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, int tile) {
+    ViewLayout L;
+    L.n = n;
+    L.n_views = n_views;
+    L.n_tiles_total = total_tiles(cams, n_views, tile);
+    const int64_t vn = n * n_views;
+    L.scan_blocks = (vn + kScanItems - 1) / kScanItems;
+    size_t off = 0;
+    L.status = off; off = align256(off + sizeof(Status));
+    L.views = off; off = align256(off + sizeof(ViewInfo) * (size_t)n_views);
+    L.payload = off; off = align256(off + (size_t)vn * kRecordWords * 4);
+    L.depth_keys = off; off = align256(off + (size_t)vn * 4);
+    L.tiles = off; off = align256(off + (size_t)vn * 4);
+    L.offsets = off; off = align256(off + (size_t)vn * 4);
+    L.block_sums = off; off = align256(off + (size_t)(L.scan_blocks + 1) * 8);
+    L.ranges = off; off = align256(off + (size_t)L.n_tiles_total * 8);
+    L.total = off;
+    return L;
+}
+
+PairLayout pair_layout(int64_t max_pairs, int digit_bits) {
+    (void)digit_bits;
+    PairLayout P;
+    P.capacity = max_pairs;
+    P.sort_blocks = (max_pairs + kSortTile - 1) / kSortTile;
+    size_t off = 0;
+    P.keys_a = off; off = align256(off + (size_t)max_pairs * 8);
+    P.keys_b = off; off = align256(off + (size_t)max_pairs * 8);
+    P.vals_a = off; off = align256(off + (size_t)max_pairs * 4);
+    P.vals_b = off; off = align256(off + (size_t)max_pairs * 4);
+    P.hist = off; off = align256(off + ((size_t)256 * P.sort_blocks + 256) * 4);
+    P.grads = off; off = align256(off + (size_t)max_pairs * kGradWords * 4);
+    P.total = off;
+    return P;
+}
+
+hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
+                                int result_in_b, int type, int tile, int32_t n_views, const float bg[3],
+                                float* out_rgb, float* out_T, int32_t* out_last, unsigned long long* counters,
+                                hipStream_t stream);
+
+}  // namespace linprim
+
+using namespace linprim;
+
+namespace {
+
+bool valid_tile(int t) { return t == 8 || t == 16 || t == 32; }
+
+int tile_of(const linprim_tuning* tu) { return tu ? tu->tile : 16; }
+
+int digit_of(const linprim_tuning* tu) {
+    const int d = tu ? tu->sort_digit_bits : 0;
+    return d == 0 ? 8 : d;
+}
+
+bool valid_tuning(const linprim_tuning* tu) {
+    if (!valid_tile(tile_of(tu))) return false;
+    const int d = digit_of(tu);
+    return d >= 4 && d <= 8;
+}
+
+bool valid_cams(const linprim_camera* cams, int32_t n_views) {
+    if (!cams || n_views < 1 || n_views > kMaxViews) return false;
+    for (int v = 0; v < n_views; ++v)
+        if (cams[v].width < 1 || cams[v].height < 1 || cams[v].width > 32768 || cams[v].height > 32768) return false;
+    return true;
+}
+
+bool valid_prims(const linprim_prims* p) {
+    if (!p) return false;
+    if (p->type != LINPRIM_OCTAHEDRON && p->type != LINPRIM_TETRAHEDRON) return false;
+    if (p->sh_degree < 0 || p->sh_degree > 3) return false;
+    if (p->n < 0 || p->n >= (int64_t(1) << 31)) return false;
+    if (p->n > 0 && (!p->means || !p->quats || !p->dists || !p->opacity || !p->sh)) return false;
+    return true;
+}
+
+// Architecture check, answered once per device (the answer is cached so
+// that calls made under stream capture issue no device queries).
+int check_device() {
+    static int verdict[64];   // 0 unknown, 1 gfx950, 2 other
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return LINPRIM_ERR_HIP;
+    if (dev < 0 || dev >= 64) return LINPRIM_ERR_DEVICE;
+    if (verdict[dev] == 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return LINPRIM_ERR_HIP;
+        verdict[dev] = (strncmp(prop.gcnArchName, "gfx950", 6) == 0) ? 1 : 2;
+    }
+    return verdict[dev] == 1 ? LINPRIM_OK : LINPRIM_ERR_DEVICE;
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? LINPRIM_OK : LINPRIM_ERR_HIP; }
+
+// The bin_sort call decides in which buffer the sorted pairs end (the
+// parity of the number of digit passes); the render calls recompute it.
+int result_buffer(const ViewLayout& L, int digit_bits) {
+    const int key_bits = 32 + key_tile_bits(L.n_tiles_total);
+    const int passes = (key_bits + digit_bits - 1) / digit_bits;
+    return passes & 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t linprim_view_workspace_size(int32_t type, int64_t n, const linprim_camera* cams, int32_t n_views,
+                                   const linprim_tuning* tuning) {
+    if ((type != LINPRIM_OCTAHEDRON && type != LINPRIM_TETRAHEDRON) || n < 0 || !valid_cams(cams, n_views) ||
+        !valid_tuning(tuning))
+        return 0;
+    return view_layout(n, cams, n_views, tile_of(tuning)).total;
+}
+
+size_t linprim_pair_workspace_size(int64_t max_pairs, const linprim_camera* cams, int32_t n_views,
+                                   const linprim_tuning* tuning) {
+    if (max_pairs < 0 || max_pairs >= (int64_t(1) << 31) || !valid_cams(cams, n_views) || !valid_tuning(tuning))
+        return 0;
+    return pair_layout(max_pairs, digit_of(tuning)).total;
+}
+
+int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                       const linprim_tuning* tuning, void* view_ws, size_t view_ws_bytes, void* stream) {
+    if (!valid_prims(prims) || !valid_cams(cams, n_views) || !valid_tuning(tuning) || !view_ws)
+        return LINPRIM_ERR_INVALID_ARG;
+    const int tile = tile_of(tuning);
+    const ViewLayout L = view_layout(prims->n, cams, n_views, tile);
+    if (view_ws_bytes < L.total) return LINPRIM_ERR_WORKSPACE;
+    if (int rc = check_device()) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)view_ws;
+    hipError_t e = launch_store_views(cams, n_views, tile, reinterpret_cast<ViewInfo*>(ws + L.views), s);
+    if (e == hipSuccess) e = launch_preprocess(*prims, n_views, tile, L, ws, s);
+    if (e == hipSuccess) e = launch_scan(L, ws, s);
+    return hip_status(e);
+}
+
+int linprim_pair_count(const void* view_ws, int64_t* n_pairs, void* stream) {
+    if (!view_ws || !n_pairs) return LINPRIM_ERR_INVALID_ARG;
+    Status st;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&st, view_ws, sizeof(Status), hipMemcpyDeviceToHost, s) != hipSuccess) return LINPRIM_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return LINPRIM_ERR_HIP;
+    *n_pairs = (int64_t)st.n_pairs;
+    return LINPRIM_OK;
+}
+
+// Common validation of the calls that follow preprocess: rebuilds both
+// layouts and checks the workspace sizes.
+static int prepare(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                   const linprim_tuning* tuning, size_t view_ws_bytes, size_t pair_ws_bytes, int64_t max_pairs,
+                   ViewLayout& L, PairLayout& P) {
+    if (!valid_prims(prims) || !valid_cams(cams, n_views) || !valid_tuning(tuning) || max_pairs < 0 ||
+        max_pairs >= (int64_t(1) << 31))
+        return LINPRIM_ERR_INVALID_ARG;
+    L = view_layout(prims->n, cams, n_views, tile_of(tuning));
+    P = pair_layout(max_pairs, digit_of(tuning));
+    if (view_ws_bytes < L.total || pair_ws_bytes < P.total) return LINPRIM_ERR_WORKSPACE;
+    return LINPRIM_OK;
+}
+
+int linprim_bin_sort(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                     const linprim_tuning* tuning, void* view_ws, size_t view_ws_bytes, void* pair_ws,
+                     size_t pair_ws_bytes, int64_t max_pairs, void* stream) {
+    if (!view_ws || !pair_ws) return LINPRIM_ERR_INVALID_ARG;
+    ViewLayout L;
+    PairLayout P;
+    if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
+    int in_b = 0;
+    hipError_t e = launch_bin_sort(L, (char*)view_ws, P, (char*)pair_ws, tile_of(tuning), digit_of(tuning), n_views,
+                                   cams, (hipStream_t)stream, &in_b);
+    return hip_status(e);
+}
+
+static int render_fwd_common(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                             const linprim_tuning* tuning, const float* bg, const void* view_ws, size_t view_ws_bytes,
+                             const void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float* out_rgb,
+                             float* out_T, int32_t* out_last, uint64_t* counters, void* stream) {
+    if (!bg || !view_ws || !pair_ws || !out_rgb || !out_T || !out_last) return LINPRIM_ERR_INVALID_ARG;
+    ViewLayout L;
+    PairLayout P;
+    if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
+    const int in_b = result_buffer(L, digit_of(tuning));
+    hipError_t e = launch_render_fwd_ex(L, (const char*)view_ws, P, (const char*)pair_ws, in_b, prims->type,
+                                        tile_of(tuning), n_views, bg, out_rgb, out_T, out_last,
+                                        reinterpret_cast<unsigned long long*>(counters), (hipStream_t)stream);
+    return hip_status(e);
+}
+
+int linprim_render_fwd(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                       const linprim_tuning* tuning, const float* bg, const void* view_ws, size_t view_ws_bytes,
+                       const void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float* out_rgb, float* out_T,
+                       int32_t* out_last, void* stream) {
+    return render_fwd_common(prims, cams, n_views, tuning, bg, view_ws, view_ws_bytes, pair_ws, pair_ws_bytes,
+                             max_pairs, out_rgb, out_T, out_last, nullptr, stream);
+}
+
+int linprim_render_fwd_counted(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                               const linprim_tuning* tuning, const float* bg, const void* view_ws,
+                               size_t view_ws_bytes, const void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs,
+                               float* out_rgb, float* out_T, int32_t* out_last, uint64_t* counters, void* stream) {
+    if (!counters) return LINPRIM_ERR_INVALID_ARG;
+    return render_fwd_common(prims, cams, n_views, tuning, bg, view_ws, view_ws_bytes, pair_ws, pair_ws_bytes,
+                             max_pairs, out_rgb, out_T, out_last, counters, stream);
+}
+
+int linprim_render_bwd(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                       const linprim_tuning* tuning, const float* bg, const void* view_ws, size_t view_ws_bytes,
+                       void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, const float* out_T,
+                       const int32_t* out_last, const float* grad_rgb, float* grad_means, float* grad_quats,
+                       float* grad_dists, float* grad_opacity, float* grad_sh, void* stream) {
+    if (!bg || !view_ws || !pair_ws || !out_T || !out_last || !grad_rgb) return LINPRIM_ERR_INVALID_ARG;
+    if (prims && prims->n > 0 && (!grad_means || !grad_quats || !grad_dists || !grad_opacity || !grad_sh))
+        return LINPRIM_ERR_INVALID_ARG;
+    ViewLayout L;
+    PairLayout P;
+    if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
+    const int in_b = result_buffer(L, digit_of(tuning));
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_render_bwd(L, (const char*)view_ws, P, (char*)pair_ws, in_b, prims->type, tile_of(tuning),
+                                     n_views, bg, out_T, out_last, grad_rgb, s);
+    if (e == hipSuccess)
+        e = launch_preprocess_bwd(*prims, n_views, tile_of(tuning), L, (const char*)view_ws, P, (const char*)pair_ws,
+                                  grad_means, grad_quats, grad_dists, grad_opacity, grad_sh, s);
+    return hip_status(e);
+}
+
+int linprim_raster_bwd(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                       const linprim_tuning* tuning, const float* bg, const void* view_ws, size_t view_ws_bytes,
+                       void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, const float* out_T,
+                       const int32_t* out_last, const float* grad_rgb, void* stream) {
+    if (!bg || !view_ws || !pair_ws || !out_T || !out_last || !grad_rgb) return LINPRIM_ERR_INVALID_ARG;
+    ViewLayout L;
+    PairLayout P;
+    if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
+    const int in_b = result_buffer(L, digit_of(tuning));
+    return hip_status(launch_render_bwd(L, (const char*)view_ws, P, (char*)pair_ws, in_b, prims->type,
+                                        tile_of(tuning), n_views, bg, out_T, out_last, grad_rgb,
+                                        (hipStream_t)stream));
+}
+
+int linprim_preprocess_bwd(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                           const linprim_tuning* tuning, const void* view_ws, size_t view_ws_bytes,
+                           const void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float* grad_means,
+                           float* grad_quats, float* grad_dists, float* grad_opacity, float* grad_sh, void* stream) {
+    if (!view_ws || !pair_ws) return LINPRIM_ERR_INVALID_ARG;
+    if (prims && prims->n > 0 && (!grad_means || !grad_quats || !grad_dists || !grad_opacity || !grad_sh))
+        return LINPRIM_ERR_INVALID_ARG;
+    ViewLayout L;
+    PairLayout P;
+    if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
+    return hip_status(launch_preprocess_bwd(*prims, n_views, tile_of(tuning), L, (const char*)view_ws, P,
+                                            (const char*)pair_ws, grad_means, grad_quats, grad_dists, grad_opacity,
+                                            grad_sh, (hipStream_t)stream));
+}
+
+int linprim_read_status(const void* view_ws, int64_t* pairs_needed, int32_t* overflow, void* stream) {
+    if (!view_ws || !pairs_needed || !overflow) return LINPRIM_ERR_INVALID_ARG;
+    Status st;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(&st, view_ws, sizeof(Status), hipMemcpyDeviceToHost, s) != hipSuccess) return LINPRIM_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return LINPRIM_ERR_HIP;
+    *pairs_needed = (int64_t)st.n_pairs;
+    *overflow = (int32_t)st.overflow;
+    return LINPRIM_OK;
+}
+
+const char* linprim_strerror(int code) {
+    switch (code) {
+        case LINPRIM_OK: return "ok";
+        case LINPRIM_ERR_INVALID_ARG: return "invalid argument";
+        case LINPRIM_ERR_WORKSPACE: return "workspace too small";
+        case LINPRIM_ERR_PAIR_OVERFLOW: return "more (tile, primitive) pairs than the pair workspace holds";
+        case LINPRIM_ERR_HIP: return "HIP runtime error";
+        case LINPRIM_ERR_DEVICE: return "unsupported device (gfx950 required)";
+        default: return "unknown error";
+    }
+}
+
+int linprim_debug_pointers(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                           const linprim_tuning* tuning, const void* view_ws, const void* pair_ws, int64_t max_pairs,
+                           void** payload, void** depth_keys, void** tiles_touched, void** offsets, void** keys,
+                           void** values, void** ranges) {
+    if (!view_ws || !pair_ws) return LINPRIM_ERR_INVALID_ARG;
+    ViewLayout L;
+    PairLayout P;
+    if (int rc = prepare(prims, cams, n_views, tuning, (size_t)-1, (size_t)-1, max_pairs, L, P)) return rc;
+    const char* v = (const char*)view_ws;
+    const char* p = (const char*)pair_ws;
+    const int in_b = result_buffer(L, digit_of(tuning));
+    if (payload) *payload = (void*)(v + L.payload);
+    if (depth_keys) *depth_keys = (void*)(v + L.depth_keys);
+    if (tiles_touched) *tiles_touched = (void*)(v + L.tiles);
+    if (offsets) *offsets = (void*)(v + L.offsets);
+    if (keys) *keys = (void*)(p + (in_b ? P.keys_b : P.keys_a));
+    if (values) *values = (void*)(p + (in_b ? P.vals_b : P.vals_a));
+    if (ranges) *ranges = (void*)(v + L.ranges);
+    return LINPRIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,294 @@
+// k_preprocess.hip -- per-primitive preprocessing (Sec. 3.2 "Preprocessing")
+// and the prefix sum of the per-primitive tile counts.
+//
+// Compiled with -ffp-contract=off: the pixel rectangles and depth keys are
+// integer decisions taken in IEEE double precision with the fixed
+// expression order of build_geometry().
+#include "linprim_common.h"
+
+namespace linprim {
+
+struct ViewChunk {
+    ViewInfo v[8];
+};
+
+__global__ void k_store_views(ViewChunk chunk, int count, ViewInfo* __restrict__ dst) {
+    const int i = threadIdx.x;
+    if (i < count) dst[i] = chunk.v[i];
+}
+
+hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int tile, ViewInfo* views,
+                              hipStream_t stream) {
+    int64_t tile_base = 0, pix_base = 0;
+    for (int v0 = 0; v0 < n_views; v0 += 8) {
+        ViewChunk ch;
+        const int cnt = (n_views - v0) < 8 ? (n_views - v0) : 8;
+        for (int k = 0; k < cnt; ++k) {
+            const linprim_camera& c = cams[v0 + k];
+            ViewInfo& V = ch.v[k];
+            for (int r = 0; r < 3; ++r) {
+                for (int q = 0; q < 3; ++q) V.Rw[3 * r + q] = (double)c.world_to_cam[4 * r + q];
+                V.tw[r] = (double)c.world_to_cam[4 * r + 3];
+            }
+            // camera position -R^T t
+            for (int q = 0; q < 3; ++q)
+                V.cam_pos[q] = -(V.Rw[q] * V.tw[0] + V.Rw[3 + q] * V.tw[1] + V.Rw[6 + q] * V.tw[2]);
+            V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
+            V.near_z = c.near_z;
+            V.width = c.width; V.height = c.height;
+            V.tiles_x = (c.width + tile - 1) / tile;
+            V.tiles_y = (c.height + tile - 1) / tile;
+            V.tile_base = tile_base;
+            V.pix_base = pix_base;
+            tile_base += (int64_t)V.tiles_x * V.tiles_y;
+            pix_base += (int64_t)c.width * c.height;
+        }
+        hipLaunchKernelGGL(k_store_views, dim3(1), dim3(64), 0, stream, ch, cnt, views + v0);
+    }
+    return hipGetLastError();
+}
+
+// One thread per (primitive, view).  Writes the 32-dword payload record,
+// the depth key and the tile count.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ means, const float* __restrict__ quats,
+                                                    const float* __restrict__ dists, const float* __restrict__ opacity,
+                                                    const float* __restrict__ sh, int sh_degree, int64_t n,
+                                                    const ViewInfo* __restrict__ views, int tile_shift,
+                                                    float* __restrict__ payload, uint32_t* __restrict__ depth_keys,
+                                                    uint32_t* __restrict__ tiles) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = blockIdx.y;
+    if (i >= n) return;
+    const int nd = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
+    const ViewInfo& V = views[v];
+    const int64_t slot = (int64_t)v * n + i;
+    float* rec = payload + slot * kRecordWords;
+    Geom G;
+    const float alpha = opacity[i];
+    if (!build_geometry(KIND, means + 3 * i, quats + 4 * i, dists + nd * i, alpha, V, G)) {
+        reinterpret_cast<int4*>(rec)[0] = make_int4(-1, -1, -1, -1);
+        depth_keys[slot] = 0u;
+        tiles[slot] = 0u;
+        return;
+    }
+    const int i0 = G.rect[0], j0 = G.rect[1], i1 = G.rect[2], j1 = G.rect[3];
+    const uint32_t ntile = (uint32_t)((i1 >> tile_shift) - (i0 >> tile_shift) + 1) *
+                           (uint32_t)((j1 >> tile_shift) - (j0 >> tile_shift) + 1);
+    depth_keys[slot] = G.key;
+    tiles[slot] = ntile;
+
+    // Eq. 1 density; colour from the SH along the viewing direction.
+    double dmin = (double)dists[nd * i];
+    for (int k = 1; k < nd; ++k) dmin = fmin(dmin, (double)dists[nd * i + k]);
+    const double sigma = -log(1.0 - kAlphaScaleD * (double)alpha) / (2.0 * dmin);
+    double dx = (double)means[3 * i + 0] - V.cam_pos[0];
+    double dy = (double)means[3 * i + 1] - V.cam_pos[1];
+    double dz = (double)means[3 * i + 2] - V.cam_pos[2];
+    const double dn = sqrt(dx * dx + dy * dy + dz * dz);
+    dx /= dn; dy /= dn; dz /= dn;
+    double Y[16];
+    sh_eval(sh_degree, dx, dy, dz, Y);
+    const int K = (sh_degree + 1) * (sh_degree + 1);
+    const float* shp = sh + (int64_t)i * K * 3;
+    float rgb[3];
+    for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) acc += (double)shp[3 * k + c] * Y[k];
+        rgb[c] = (float)fmax(acc + 0.5, 0.0);
+    }
+
+    float out[kRecordWords];
+    for (int k = 0; k < kRecordWords; ++k) out[k] = 0.0f;
+    out[R_I0] = __int_as_float(i0);
+    out[R_J0] = __int_as_float(j0);
+    out[R_I1] = __int_as_float(i1);
+    out[R_J1] = __int_as_float(j1);
+    out[R_S2] = (float)(sigma * kLog2e);
+    out[R_RGB + 0] = rgb[0];
+    out[R_RGB + 1] = rgb[1];
+    out[R_RGB + 2] = rgb[2];
+    out[R_FI0] = (float)i0;
+    out[R_FJ0] = (float)j0;
+    out[R_FWI] = (float)(i1 - i0);
+    out[R_FWJ] = (float)(j1 - j0);
+    out[R_SIGMA] = (float)sigma;
+
+    // Offsets of the rectangle origin's pixel centre from the ray-space centre:
+    // the render kernels evaluate planes at integer ki = i - i0, kj = j - j0.
+    const double ox = (double)i0 + 0.5 - G.c[0];
+    const double oy = (double)j0 + 0.5 - G.c[1];
+    if (KIND == LINPRIM_OCTAHEDRON) {
+        // primitive = c + M s, |s|_1 <= 1, M = [a0 a1 a2]; the pair of faces
+        // with sign pattern sg is the slab |sg . M^-1 (X - c)| <= 1.
+        double M[9], N[9];
+        for (int r = 0; r < 3; ++r)
+            for (int k = 0; k < 3; ++k) M[3 * r + k] = G.a[k][r];
+        inverse3(M, N);
+        for (int s = 0; s < 4; ++s) {
+            double nu[3];
+            for (int c = 0; c < 3; ++c)
+                nu[c] = kSlab[s][0] * N[c] + kSlab[s][1] * N[3 + c] + kSlab[s][2] * N[6 + c];
+            const double nl = sqrt(nu[0] * nu[0] + nu[1] * nu[1] + nu[2] * nu[2]);
+            const double nz = clamp_nz(nu[2], nl);
+            const double A = -nu[0] / nz, B = -nu[1] / nz, W = 1.0 / fabs(nz);
+            const double ctr = A * ox + B * oy;
+            out[R_PLANES + 4 * s + 0] = (float)A;
+            out[R_PLANES + 4 * s + 1] = (float)B;
+            out[R_PLANES + 4 * s + 2] = (float)(ctr + W);
+            out[R_PLANES + 4 * s + 3] = (float)(ctr - W);
+        }
+    } else {
+        // face f holds the three corners other than f; its outward normal
+        // decides whether it bounds the ray from above (n_z > 0) or below.
+        double pA[4], pB[4], pD[4];
+        int up[4], lo[4], nu = 0, nl = 0;
+        for (int f = 0; f < 4; ++f) {
+            int m[3], q = 0;
+            for (int k = 0; k < 4; ++k)
+                if (k != f) m[q++] = k;
+            const double* P0 = G.a[m[0]];
+            const double e1[3] = {G.a[m[1]][0] - P0[0], G.a[m[1]][1] - P0[1], G.a[m[1]][2] - P0[2]};
+            const double e2[3] = {G.a[m[2]][0] - P0[0], G.a[m[2]][1] - P0[1], G.a[m[2]][2] - P0[2]};
+            double nv[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+            const double to_f = nv[0] * (G.a[f][0] - P0[0]) + nv[1] * (G.a[f][1] - P0[1]) + nv[2] * (G.a[f][2] - P0[2]);
+            if (to_f > 0.0) { nv[0] = -nv[0]; nv[1] = -nv[1]; nv[2] = -nv[2]; }
+            const double nlen = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            const double nz = clamp_nz(nv[2], nlen);
+            const double A = -nv[0] / nz, B = -nv[1] / nz;
+            pA[f] = A;
+            pB[f] = B;
+            pD[f] = P0[2] - A * P0[0] - B * P0[1] + A * ox + B * oy;
+            if (nz > 0.0) up[nu++] = f; else lo[nl++] = f;
+        }
+        // an empty side cannot occur for a bounded primitive; guard anyway
+        if (nu == 0) { up[nu++] = lo[--nl]; }
+        if (nl == 0) { lo[nl++] = up[--nu]; }
+        int fmap = 0;
+        for (int s = 0; s < 3; ++s) {
+            const int fu = up[s < nu ? s : nu - 1];
+            const int fl = lo[s < nl ? s : nl - 1];
+            out[R_PLANES + 3 * s + 0] = (float)pA[fu];
+            out[R_PLANES + 3 * s + 1] = (float)pB[fu];
+            out[R_PLANES + 3 * s + 2] = (float)pD[fu];
+            out[R_PLANES + 9 + 3 * s + 0] = (float)pA[fl];
+            out[R_PLANES + 9 + 3 * s + 1] = (float)pB[fl];
+            out[R_PLANES + 9 + 3 * s + 2] = (float)pD[fl];
+            fmap |= fu << (2 * s);
+            fmap |= fl << (2 * (s + 3));
+        }
+        out[R_FACEMAP] = __int_as_float(fmap);
+    }
+    float4* dst = reinterpret_cast<float4*>(rec);
+    for (int k = 0; k < kRecordWords / 4; ++k)
+        dst[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
+}
+
+hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L, char* ws,
+                             hipStream_t stream) {
+    if (p.n == 0) return hipSuccess;
+    const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
+    dim3 grid((unsigned)((p.n + 255) / 256), (unsigned)n_views);
+    const ViewInfo* views = reinterpret_cast<const ViewInfo*>(ws + L.views);
+    float* payload = reinterpret_cast<float*>(ws + L.payload);
+    uint32_t* keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
+    uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
+    if (p.type == LINPRIM_OCTAHEDRON)
+        hipLaunchKernelGGL(k_preprocess<LINPRIM_OCTAHEDRON>, grid, dim3(256), 0, stream, p.means, p.quats, p.dists,
+                           p.opacity, p.sh, p.sh_degree, p.n, views, shift, payload, keys, tiles);
+    else
+        hipLaunchKernelGGL(k_preprocess<LINPRIM_TETRAHEDRON>, grid, dim3(256), 0, stream, p.means, p.quats, p.dists,
+                           p.opacity, p.sh, p.sh_degree, p.n, views, shift, payload, keys, tiles);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix sum of the tile counts (three passes: block totals, a
+// single-block scan of the totals, block-local scans).
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t block_exclusive_scan_u64(uint64_t x, uint64_t* lds, uint64_t* total) {
+    // 256 threads: Hillis-Steele in shared memory
+    const int t = threadIdx.x;
+    lds[t] = x;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint64_t y = (t >= off) ? lds[t - off] : 0;
+        __syncthreads();
+        lds[t] += y;
+        __syncthreads();
+    }
+    const uint64_t incl = lds[t];
+    *total = lds[255];
+    __syncthreads();
+    return incl - x;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t count,
+                                                     uint64_t* __restrict__ block_sums) {
+    __shared__ uint64_t lds[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanItems;
+    uint64_t s = 0;
+    for (int k = 0; k < kScanItems / 256; ++k) {
+        const int64_t idx = base + k * 256 + threadIdx.x;
+        if (idx < count) s += in[idx];
+    }
+    uint64_t total;
+    block_exclusive_scan_u64(s, lds, &total);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(256) void k_scan_totals(uint64_t* __restrict__ block_sums, int64_t nblocks,
+                                                     Status* __restrict__ status) {
+    __shared__ uint64_t lds[256];
+    uint64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
+        const int64_t idx = b0 + threadIdx.x;
+        const uint64_t x = (idx < nblocks) ? block_sums[idx] : 0;
+        uint64_t total;
+        const uint64_t ex = block_exclusive_scan_u64(x, lds, &total);
+        if (idx < nblocks) block_sums[idx] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) {
+        status->n_pairs = carry;
+        status->overflow = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t count,
+                                                    const uint64_t* __restrict__ block_sums,
+                                                    uint32_t* __restrict__ out) {
+    __shared__ uint64_t lds[256];
+    // thread t handles the 16 consecutive elements base + 16 t .. 16 t + 15
+    const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * 16;
+    uint32_t v[16];
+    uint64_t s = 0;
+    for (int k = 0; k < 16; ++k) {
+        const int64_t idx = base + k;
+        v[k] = (idx < count) ? in[idx] : 0u;
+        s += v[k];
+    }
+    uint64_t total;
+    uint64_t run = block_sums[blockIdx.x] + block_exclusive_scan_u64(s, lds, &total);
+    for (int k = 0; k < 16; ++k) {
+        const int64_t idx = base + k;
+        if (idx < count) out[idx] = (uint32_t)run;
+        run += v[k];
+    }
+}
+
+hipError_t launch_scan(const ViewLayout& L, char* ws, hipStream_t stream) {
+    const int64_t count = L.n * L.n_views;
+    const uint32_t* tiles = reinterpret_cast<const uint32_t*>(ws + L.tiles);
+    uint32_t* offsets = reinterpret_cast<uint32_t*>(ws + L.offsets);
+    uint64_t* bsums = reinterpret_cast<uint64_t*>(ws + L.block_sums);
+    Status* status = reinterpret_cast<Status*>(ws + L.status);
+    const int64_t nb = L.scan_blocks;
+    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(256), 0, stream, bsums, nb, status);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, offsets);
+    return hipGetLastError();
+}
+
+}  // namespace linprim

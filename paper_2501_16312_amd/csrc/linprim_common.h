@@ -1,0 +1,354 @@
+// linprim_common.h -- internal layout and device helpers of the gfx950
+// rasterizer for transparent octahedra and tetrahedra (LinPrim, arXiv
+// 2501.16312).  Included by every kernel file of liblinprim.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/linprim.h"
+
+namespace linprim {
+
+// ----------------------------------------------------------------------------
+// Constants.
+// ----------------------------------------------------------------------------
+constexpr float kAlphaScale = 0.99f;      // Eq. 1
+constexpr double kAlphaScaleD = 0.99;
+constexpr float kTStop = 1e-3f;           // cumulative opacity 0.999 (Sec. 3.2)
+constexpr float kOMax = 0.99f;            // opacity clamp: 1 - o >= 0.01
+constexpr float kOneMinusOMax = 0.01f;
+constexpr double kInvSqrt3 = 0.57735026918962576451;
+constexpr double kLog2e = 1.44269504088896340736;
+constexpr int kMaxViews = 4096;
+constexpr int kRecordWords = 32;          // payload record: 32 x 4 bytes
+constexpr int kGradWords = 20;            // backward record per (tile, primitive) pair
+
+// ----------------------------------------------------------------------------
+// Payload record of one (view, primitive), 32 dwords, written by the
+// preprocess kernel and read with scalar loads by the render kernels.
+//   [0..3]  int   pixel rectangle i0, j0, i1, j1 (inclusive); i0 = -1 if culled
+//   [4]     float sigma * log2(e)            (so exp(-sigma d) = exp2(-s2 d))
+//   [5..7]  float rgb
+//   [8..11] float i0, j0, i1 - i0, j1 - j0
+//   octahedron:
+//   [12..27] float 4 slabs x (A, B, Dup, Dlo): with ki = i - i0, kj = j - j0
+//            the slab is A ki + B kj + Dlo <= z' <= A ki + B kj + Dup
+//   tetrahedron:
+//   [12..20] float 3 upper planes (A, B, D): z' <= A ki + B kj + D
+//   [21..29] float 3 lower planes (A, B, D): z' >= A ki + B kj + D
+//   [31]     int   face of each of the 6 plane slots, 2 bits each
+//   [30]    float sigma
+// The chord through the primitive at a pixel is
+//   max(0, min over upper planes - max over lower planes).
+// ----------------------------------------------------------------------------
+enum : int {
+    R_I0 = 0, R_J0 = 1, R_I1 = 2, R_J1 = 3, R_S2 = 4, R_RGB = 5, R_FI0 = 8, R_FJ0 = 9, R_FWI = 10,
+    R_FWJ = 11, R_PLANES = 12, R_SIGMA = 30, R_FACEMAP = 31
+};
+
+// Per-view constants, in the view table at the front of the view workspace.
+struct ViewInfo {
+    double Rw[9];
+    double tw[3];
+    double cam_pos[3];
+    double fx, fy, cx, cy, near_z;
+    int32_t width, height, tiles_x, tiles_y;
+    int64_t tile_base;   // first global tile id of this view
+    int64_t pix_base;    // first pixel of this view in the packed outputs
+    int32_t pad[4];
+};
+
+// Header of the view workspace.
+struct Status {
+    uint64_t n_pairs;      // written by the scan
+    uint32_t overflow;     // set by bin_sort when n_pairs > capacity
+    uint32_t pad0;
+    uint64_t capacity;
+    uint64_t pad[5];
+};
+
+// Offsets into the view workspace (all 256-byte aligned).
+struct ViewLayout {
+    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, total;
+    int64_t n, n_views, n_tiles_total, scan_blocks;
+};
+
+// Offsets into the pair workspace.
+struct PairLayout {
+    size_t keys_a, keys_b, vals_a, vals_b, hist, grads, total;
+    int64_t capacity, sort_blocks;
+};
+
+constexpr int kScanItems = 4096;     // elements per scan block (256 threads x 16)
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;       // keys per thread per sort block
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, int tile);
+PairLayout pair_layout(int64_t max_pairs, int digit_bits);
+int key_tile_bits(int64_t n_tiles_total);
+
+// ----------------------------------------------------------------------------
+// Host-side launchers (one per kernel file).
+// ----------------------------------------------------------------------------
+hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int tile, ViewInfo* views,
+                              hipStream_t stream);
+hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L,
+                             char* ws, hipStream_t stream);
+hipError_t launch_scan(const ViewLayout& L, char* ws, hipStream_t stream);
+hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, char* pws,
+                           int tile, int digit_bits, int32_t n_views, const linprim_camera* cams,
+                           hipStream_t stream, int* result_in_b);
+hipError_t launch_render_fwd(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
+                             int result_in_b, int type, int tile, int32_t n_views, const float bg[3],
+                             float* out_rgb, float* out_T, int32_t* out_last, hipStream_t stream);
+hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLayout& P, char* pws,
+                             int result_in_b, int type, int tile, int32_t n_views, const float bg[3],
+                             const float* out_T, const int32_t* out_last, const float* grad_rgb,
+                             hipStream_t stream);
+hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L,
+                                 const char* vws, const PairLayout& P, const char* pws, float* g_means,
+                                 float* g_quats, float* g_dists, float* g_opacity, float* g_sh,
+                                 hipStream_t stream);
+
+// ----------------------------------------------------------------------------
+// Device helpers.
+// ----------------------------------------------------------------------------
+
+// Rotation of q / |q| written with s = 2 / |q|^2 (no square root).  The
+// expressions and their left-to-right order are part of the binning
+// contract: compiled without contraction into fused multiply-adds.
+#pragma clang fp contract(off)
+__device__ inline bool quat_rotation_d(double w, double x, double y, double z, double R[9]) {
+    const double n2 = w * w + x * x + y * y + z * z;
+    if (!(n2 > 0.0) || !isfinite(n2)) return false;
+    const double s = 2.0 / n2;
+    R[0] = 1.0 - s * (y * y + z * z);
+    R[1] = s * (x * y - w * z);
+    R[2] = s * (x * z + w * y);
+    R[3] = s * (x * y + w * z);
+    R[4] = 1.0 - s * (x * x + z * z);
+    R[5] = s * (y * z - w * x);
+    R[6] = s * (x * z - w * y);
+    R[7] = s * (y * z + w * x);
+    R[8] = 1.0 - s * (x * x + y * y);
+    return true;
+}
+
+// Tetrahedron corner directions, before the 1/sqrt(3) scale.
+__device__ constexpr double kTetDir[4][3] = {{1, 1, 1}, {1, -1, -1}, {-1, 1, -1}, {-1, -1, 1}};
+
+// Geometry of one primitive in one view, in double precision.
+struct Geom {
+    double R[9];        // primitive rotation
+    double o[4][3];     // world-space offsets of the axes / corners
+    double oc[4][3];    // camera-space offsets
+    double tc[3];       // camera-space centre
+    double c[3];        // ray-space centre
+    double a[4][3];     // ray-space offsets
+    double J[9];        // ray-space Jacobian at tc (row-major)
+    int rect[4];
+    uint32_t key;
+};
+
+// Builds the primitive, transforms it and bounds it.  Returns false if the
+// primitive is culled.  The rectangle and key computations follow the
+// binning contract exactly (double precision, fixed order, no contraction).
+__device__ inline bool build_geometry(int type, const float* mu_f, const float* q_f, const float* d_f,
+                                      float alpha, const ViewInfo& V, Geom& G) {
+    const int na = (type == LINPRIM_OCTAHEDRON) ? 3 : 4;
+    if (!quat_rotation_d((double)q_f[0], (double)q_f[1], (double)q_f[2], (double)q_f[3], G.R)) return false;
+    double d[4];
+    for (int k = 0; k < na; ++k) {
+        d[k] = (double)d_f[k];
+        if (!(d[k] > 0.0) || !isfinite(d[k])) return false;
+    }
+    const double mu[3] = {(double)mu_f[0], (double)mu_f[1], (double)mu_f[2]};
+    if (!isfinite(mu[0]) || !isfinite(mu[1]) || !isfinite(mu[2])) return false;
+    const double al = (double)alpha;
+    if (!(al >= 0.0 && al <= 1.0)) return false;
+
+    for (int r = 0; r < 3; ++r)
+        G.tc[r] = V.Rw[3 * r + 0] * mu[0] + V.Rw[3 * r + 1] * mu[1] + V.Rw[3 * r + 2] * mu[2] + V.tw[r];
+    if (!(G.tc[2] > V.near_z)) return false;
+
+    if (type == LINPRIM_OCTAHEDRON) {
+        for (int k = 0; k < 3; ++k)
+            for (int r = 0; r < 3; ++r) G.o[k][r] = G.R[3 * r + k] * d[k];
+    } else {
+        for (int i = 0; i < 4; ++i) {
+            const double g = d[i] * kInvSqrt3;
+            for (int r = 0; r < 3; ++r)
+                G.o[i][r] = (kTetDir[i][0] * G.R[3 * r + 0] + kTetDir[i][1] * G.R[3 * r + 1] +
+                             kTetDir[i][2] * G.R[3 * r + 2]) * g;
+        }
+    }
+    for (int k = 0; k < na; ++k)
+        for (int r = 0; r < 3; ++r)
+            G.oc[k][r] = V.Rw[3 * r + 0] * G.o[k][0] + V.Rw[3 * r + 1] * G.o[k][1] + V.Rw[3 * r + 2] * G.o[k][2];
+
+    const double iz = 1.0 / G.tc[2];
+    const double px = V.fx * G.tc[0] * iz, py = V.fy * G.tc[1] * iz;
+    const double cxp = px + V.cx, cyp = py + V.cy;
+    const double J00 = V.fx * iz, J02 = -(px * iz), J11 = V.fy * iz, J12 = -(py * iz);
+    const double l = sqrt(G.tc[0] * G.tc[0] + G.tc[1] * G.tc[1] + G.tc[2] * G.tc[2]);
+    G.J[0] = J00; G.J[1] = 0.0; G.J[2] = J02;
+    G.J[3] = 0.0; G.J[4] = J11; G.J[5] = J12;
+    G.J[6] = G.tc[0] / l; G.J[7] = G.tc[1] / l; G.J[8] = G.tc[2] / l;
+    G.c[0] = cxp; G.c[1] = cyp; G.c[2] = l;
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    for (int k = 0; k < na; ++k) {
+        const double ax = J00 * G.oc[k][0] + J02 * G.oc[k][2];
+        const double ay = J11 * G.oc[k][1] + J12 * G.oc[k][2];
+        G.a[k][0] = ax;
+        G.a[k][1] = ay;
+        G.a[k][2] = G.J[6] * G.oc[k][0] + G.J[7] * G.oc[k][1] + G.J[8] * G.oc[k][2];
+        const double xp = cxp + ax, yp = cyp + ay;
+        if (xp < xmin) xmin = xp;
+        if (xp > xmax) xmax = xp;
+        if (yp < ymin) ymin = yp;
+        if (yp > ymax) ymax = yp;
+        if (type == LINPRIM_OCTAHEDRON) {
+            const double xm = cxp - ax, ym = cyp - ay;
+            if (xm < xmin) xmin = xm;
+            if (xm > xmax) xmax = xm;
+            if (ym < ymin) ymin = ym;
+            if (ym > ymax) ymax = ym;
+        }
+    }
+    if (!isfinite(xmin) || !isfinite(xmax) || !isfinite(ymin) || !isfinite(ymax)) return false;
+    double fi0 = ceil(xmin - 0.5), fi1 = floor(xmax - 0.5);
+    double fj0 = ceil(ymin - 0.5), fj1 = floor(ymax - 0.5);
+    if (fi0 < 0.0) fi0 = 0.0;
+    if (fj0 < 0.0) fj0 = 0.0;
+    if (fi1 > (double)(V.width - 1)) fi1 = (double)(V.width - 1);
+    if (fj1 > (double)(V.height - 1)) fj1 = (double)(V.height - 1);
+    if (fi0 > fi1 || fj0 > fj1) return false;
+    G.rect[0] = (int)fi0; G.rect[1] = (int)fj0; G.rect[2] = (int)fi1; G.rect[3] = (int)fj1;
+    const float zf = (float)G.tc[2];
+    G.key = __float_as_uint(zf);
+    return true;
+}
+#pragma clang fp contract(on)
+
+// Real SH basis, degree <= 3, Condon-Shortley phase for odd m, ordered
+// l = 0..3, m = -l..l; constants from their closed forms.
+struct ShConst {
+    double c0, c1, c2a, c2b, c2c, c3a, c3b, c3c, c3d, c3e;
+};
+
+__device__ inline ShConst sh_constants() {
+    const double pi = 3.14159265358979323846;
+    ShConst K;
+    K.c0 = 0.5 * sqrt(1.0 / pi);
+    K.c1 = sqrt(3.0 / (4.0 * pi));
+    K.c2a = 0.5 * sqrt(15.0 / pi);
+    K.c2b = 0.25 * sqrt(5.0 / pi);
+    K.c2c = 0.25 * sqrt(15.0 / pi);
+    K.c3a = 0.25 * sqrt(35.0 / (2.0 * pi));
+    K.c3b = 0.5 * sqrt(105.0 / pi);
+    K.c3c = 0.25 * sqrt(21.0 / (2.0 * pi));
+    K.c3d = 0.25 * sqrt(7.0 / pi);
+    K.c3e = 0.25 * sqrt(105.0 / pi);
+    return K;
+}
+
+__device__ inline void sh_eval(int deg, double x, double y, double z, double Y[16]) {
+    const ShConst K = sh_constants();
+    for (int k = 0; k < 16; ++k) Y[k] = 0.0;
+    Y[0] = K.c0;
+    if (deg >= 1) {
+        Y[1] = -K.c1 * y;
+        Y[2] = K.c1 * z;
+        Y[3] = -K.c1 * x;
+    }
+    if (deg >= 2) {
+        Y[4] = K.c2a * x * y;
+        Y[5] = -K.c2a * y * z;
+        Y[6] = K.c2b * (2.0 * z * z - x * x - y * y);
+        Y[7] = -K.c2a * x * z;
+        Y[8] = K.c2c * (x * x - y * y);
+    }
+    if (deg >= 3) {
+        Y[9] = -K.c3a * y * (3.0 * x * x - y * y);
+        Y[10] = K.c3b * x * y * z;
+        Y[11] = -K.c3c * y * (4.0 * z * z - x * x - y * y);
+        Y[12] = K.c3d * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y);
+        Y[13] = -K.c3c * x * (4.0 * z * z - x * x - y * y);
+        Y[14] = K.c3e * z * (x * x - y * y);
+        Y[15] = -K.c3a * x * (x * x - 3.0 * y * y);
+    }
+}
+
+// Gradient of every basis function with respect to the (unnormalised)
+// direction components, used by the backward pass.
+__device__ inline void sh_eval_grad(int deg, double x, double y, double z, double G[16][3]) {
+    const ShConst K = sh_constants();
+    for (int k = 0; k < 16; ++k) G[k][0] = G[k][1] = G[k][2] = 0.0;
+    if (deg >= 1) {
+        G[1][1] = -K.c1;
+        G[2][2] = K.c1;
+        G[3][0] = -K.c1;
+    }
+    if (deg >= 2) {
+        G[4][0] = K.c2a * y; G[4][1] = K.c2a * x;
+        G[5][1] = -K.c2a * z; G[5][2] = -K.c2a * y;
+        G[6][0] = -2.0 * K.c2b * x; G[6][1] = -2.0 * K.c2b * y; G[6][2] = 4.0 * K.c2b * z;
+        G[7][0] = -K.c2a * z; G[7][2] = -K.c2a * x;
+        G[8][0] = 2.0 * K.c2c * x; G[8][1] = -2.0 * K.c2c * y;
+    }
+    if (deg >= 3) {
+        G[9][0] = -6.0 * K.c3a * x * y;
+        G[9][1] = -K.c3a * (3.0 * x * x - 3.0 * y * y);
+        G[10][0] = K.c3b * y * z; G[10][1] = K.c3b * x * z; G[10][2] = K.c3b * x * y;
+        G[11][0] = 2.0 * K.c3c * x * y;
+        G[11][1] = -K.c3c * (4.0 * z * z - x * x - 3.0 * y * y);
+        G[11][2] = -8.0 * K.c3c * y * z;
+        G[12][0] = -6.0 * K.c3d * x * z;
+        G[12][1] = -6.0 * K.c3d * y * z;
+        G[12][2] = K.c3d * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y);
+        G[13][0] = -K.c3c * (4.0 * z * z - 3.0 * x * x - y * y);
+        G[13][1] = 2.0 * K.c3c * x * y;
+        G[13][2] = -8.0 * K.c3c * x * z;
+        G[14][0] = 2.0 * K.c3e * x * z; G[14][1] = -2.0 * K.c3e * y * z; G[14][2] = K.c3e * (x * x - y * y);
+        G[15][0] = -K.c3a * (3.0 * x * x - 3.0 * y * y);
+        G[15][1] = 6.0 * K.c3a * x * y;
+    }
+}
+
+// The four slab directions of an octahedron (pairs of opposite faces).
+__device__ constexpr double kSlab[4][3] = {{1, 1, 1}, {1, 1, -1}, {1, -1, 1}, {-1, 1, 1}};
+
+// 3x3 inverse (row-major) by the adjugate; returns the determinant.
+__device__ inline double inverse3(const double M[9], double N[9]) {
+    const double c00 = M[4] * M[8] - M[5] * M[7];
+    const double c01 = M[5] * M[6] - M[3] * M[8];
+    const double c02 = M[3] * M[7] - M[4] * M[6];
+    const double det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+    const double id = 1.0 / det;
+    N[0] = c00 * id;
+    N[1] = (M[2] * M[7] - M[1] * M[8]) * id;
+    N[2] = (M[1] * M[5] - M[2] * M[4]) * id;
+    N[3] = c01 * id;
+    N[4] = (M[0] * M[8] - M[2] * M[6]) * id;
+    N[5] = (M[2] * M[3] - M[0] * M[5]) * id;
+    N[6] = c02 * id;
+    N[7] = (M[1] * M[6] - M[0] * M[7]) * id;
+    N[8] = (M[0] * M[4] - M[1] * M[3]) * id;
+    return det;
+}
+
+// Smallest |z| component allowed for a face normal relative to its length;
+// a face closer to parallel with the viewing rays is treated as this steep.
+constexpr double kMinNormalZ = 1e-9;
+
+__device__ inline double clamp_nz(double nz, double nlen) {
+    const double lim = kMinNormalZ * nlen;
+    if (fabs(nz) >= lim) return nz;
+    return nz < 0.0 ? -lim : lim;
+}
+
+}  // namespace linprim

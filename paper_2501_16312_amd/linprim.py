@@ -1,0 +1,263 @@
+"""ctypes binding of liblinprim.so, the gfx950 rasterizer for transparent
+octahedra and tetrahedra (LinPrim, arXiv 2501.16312).
+
+Argument marshalling only: every function here has the name of the C entry
+point it calls and passes torch device pointers and the current HIP stream
+through.  Nothing is computed on the host; if the library is missing the
+import fails loudly (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblinprim.so")
+
+OCTAHEDRON = 0
+TETRAHEDRON = 1
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_WORKSPACE = -2
+ERR_PAIR_OVERFLOW = -3
+ERR_HIP = -4
+ERR_DEVICE = -5
+
+FLAG_COUNTERS = 1
+
+
+class linprim_prims(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int32), ("sh_degree", ctypes.c_int32), ("n", ctypes.c_int64),
+                ("means", ctypes.c_void_p), ("quats", ctypes.c_void_p), ("dists", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p)]
+
+
+class linprim_camera(ctypes.Structure):
+    _fields_ = [("world_to_cam", ctypes.c_float * 12), ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("near_z", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class linprim_tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("sort_digit_bits", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linprim_preprocess",
+           "linprim_pair_count", "linprim_bin_sort", "linprim_render_fwd", "linprim_render_fwd_counted",
+           "linprim_render_bwd", "linprim_raster_bwd", "linprim_preprocess_bwd", "linprim_read_status",
+           "linprim_strerror", "linprim_debug_pointers")
+
+_lib = None
+
+
+class LinPrimError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH):
+    """Loads liblinprim.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise LinPrimError(f"{path} is missing: build it with paper_2501_16312_amd/build.py "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    pr, cm, tu = ctypes.POINTER(linprim_prims), ctypes.POINTER(linprim_camera), ctypes.POINTER(linprim_tuning)
+    lib.linprim_view_workspace_size.restype = SZ
+    lib.linprim_view_workspace_size.argtypes = [I32, I64, cm, I32, tu]
+    lib.linprim_pair_workspace_size.restype = SZ
+    lib.linprim_pair_workspace_size.argtypes = [I64, cm, I32, tu]
+    lib.linprim_preprocess.argtypes = [pr, cm, I32, tu, P, SZ, P]
+    lib.linprim_pair_count.argtypes = [P, ctypes.POINTER(I64), P]
+    lib.linprim_bin_sort.argtypes = [pr, cm, I32, tu, P, SZ, P, SZ, I64, P]
+    lib.linprim_render_fwd.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ, I64,
+                                       P, P, P, P]
+    lib.linprim_render_fwd_counted.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ,
+                                               I64, P, P, P, P, P]
+    lib.linprim_render_bwd.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ, I64,
+                                       P, P, P, P, P, P, P, P, P]
+    lib.linprim_raster_bwd.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ, I64,
+                                       P, P, P, P]
+    lib.linprim_preprocess_bwd.argtypes = [pr, cm, I32, tu, P, SZ, P, SZ, I64, P, P, P, P, P, P]
+    lib.linprim_read_status.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32), P]
+    lib.linprim_strerror.restype = ctypes.c_char_p
+    lib.linprim_strerror.argtypes = [ctypes.c_int]
+    lib.linprim_debug_pointers.argtypes = [pr, cm, I32, tu, P, P, I64] + [ctypes.POINTER(P)] * 7
+    for f in (lib.linprim_preprocess, lib.linprim_pair_count, lib.linprim_bin_sort, lib.linprim_render_fwd,
+              lib.linprim_render_fwd_counted, lib.linprim_render_bwd, lib.linprim_raster_bwd,
+              lib.linprim_preprocess_bwd, lib.linprim_read_status,
+              lib.linprim_debug_pointers):
+        f.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        msg = load().linprim_strerror(rc).decode()
+        raise LinPrimError(f"{what} failed: {msg} ({rc})")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ structs
+class Prims:
+    """Primitive features as float32 CUDA tensors (the C struct keeps raw
+    pointers, so this object keeps the tensors alive)."""
+
+    def __init__(self, kind: int, means, quats, dists, opacity, sh, sh_degree: int = 3):
+        self.kind = int(kind)
+        self.sh_degree = int(sh_degree)
+        self.means = means.contiguous()
+        self.quats = quats.contiguous()
+        self.dists = dists.contiguous()
+        self.opacity = opacity.contiguous()
+        self.sh = sh.contiguous()
+        for t in (self.means, self.quats, self.dists, self.opacity, self.sh):
+            if t.dtype != torch.float32 or not t.is_cuda:
+                raise LinPrimError("primitive tensors must be float32 on the GPU")
+
+    @classmethod
+    def from_scene(cls, scene, device="cuda"):
+        K = (scene.sh_degree + 1) ** 2
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32, device=device).contiguous()
+        return cls(scene.kind, f(scene.means), f(scene.quats), f(scene.dists), f(scene.opacity),
+                   f(scene.sh[:, :K]), scene.sh_degree)
+
+    @property
+    def n(self) -> int:
+        return int(self.means.shape[0])
+
+    def c(self) -> linprim_prims:
+        return linprim_prims(self.kind, self.sh_degree, self.n, self.means.data_ptr(), self.quats.data_ptr(),
+                             self.dists.data_ptr(), self.opacity.data_ptr(), self.sh.data_ptr())
+
+
+def cameras(cams: Sequence) -> ctypes.Array:
+    """ctypes array of linprim_camera from scene cameras (world_to_cam, fx,
+    fy, cx, cy, width, height, near)."""
+    arr = (linprim_camera * len(cams))()
+    for k, c in enumerate(cams):
+        w = c.world_to_cam.astype("float32").reshape(-1)
+        for i in range(12):
+            arr[k].world_to_cam[i] = float(w[i])
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = float(c.fx), float(c.fy), float(c.cx), float(c.cy)
+        arr[k].width, arr[k].height = int(c.width), int(c.height)
+        arr[k].near_z = float(c.near)
+        arr[k].reserved = 0
+    return arr
+
+
+def tuning(tile: int = 16, sort_digit_bits: int = 8, flags: int = 0) -> linprim_tuning:
+    return linprim_tuning(int(tile), int(sort_digit_bits), int(flags), 0)
+
+
+# --------------------------------------------------------------- entry points
+def linprim_view_workspace_size(kind: int, n: int, cams, tune) -> int:
+    return int(load().linprim_view_workspace_size(kind, n, cams, len(cams), ctypes.byref(tune)))
+
+
+def linprim_pair_workspace_size(max_pairs: int, cams, tune) -> int:
+    return int(load().linprim_pair_workspace_size(max_pairs, cams, len(cams), ctypes.byref(tune)))
+
+
+def linprim_preprocess(prims: Prims, cams, tune, view_ws: torch.Tensor, stream=None):
+    p = prims.c()
+    _check(load().linprim_preprocess(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _ptr(view_ws),
+                                     view_ws.numel(), _stream(stream)), "linprim_preprocess")
+
+
+def linprim_pair_count(view_ws: torch.Tensor, stream=None) -> int:
+    out = ctypes.c_int64(0)
+    _check(load().linprim_pair_count(_ptr(view_ws), ctypes.byref(out), _stream(stream)), "linprim_pair_count")
+    return int(out.value)
+
+
+def linprim_bin_sort(prims: Prims, cams, tune, view_ws, pair_ws, max_pairs: int, stream=None):
+    p = prims.c()
+    _check(load().linprim_bin_sort(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _ptr(view_ws),
+                                   view_ws.numel(), _ptr(pair_ws), pair_ws.numel(), max_pairs, _stream(stream)),
+           "linprim_bin_sort")
+
+
+def _bg(bg):
+    b = [0.0, 0.0, 0.0] if bg is None else [float(x) for x in bg]
+    return (ctypes.c_float * 3)(*b)
+
+
+def linprim_render_fwd(prims: Prims, cams, tune, bg, view_ws, pair_ws, max_pairs, out_rgb, out_T, out_last,
+                       stream=None, counters: Optional[torch.Tensor] = None):
+    p = prims.c()
+    lib = load()
+    if counters is None:
+        rc = lib.linprim_render_fwd(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _bg(bg), _ptr(view_ws),
+                                    view_ws.numel(), _ptr(pair_ws), pair_ws.numel(), max_pairs, _ptr(out_rgb),
+                                    _ptr(out_T), _ptr(out_last), _stream(stream))
+    else:
+        rc = lib.linprim_render_fwd_counted(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _bg(bg),
+                                            _ptr(view_ws), view_ws.numel(), _ptr(pair_ws), pair_ws.numel(),
+                                            max_pairs, _ptr(out_rgb), _ptr(out_T), _ptr(out_last), _ptr(counters),
+                                            _stream(stream))
+    _check(rc, "linprim_render_fwd")
+
+
+def linprim_render_bwd(prims: Prims, cams, tune, bg, view_ws, pair_ws, max_pairs, out_T, out_last, grad_rgb,
+                       grads: dict, stream=None):
+    p = prims.c()
+    _check(load().linprim_render_bwd(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _bg(bg), _ptr(view_ws),
+                                     view_ws.numel(), _ptr(pair_ws), pair_ws.numel(), max_pairs, _ptr(out_T),
+                                     _ptr(out_last), _ptr(grad_rgb), _ptr(grads["means"]), _ptr(grads["quats"]),
+                                     _ptr(grads["dists"]), _ptr(grads["opacity"]), _ptr(grads["sh"]),
+                                     _stream(stream)), "linprim_render_bwd")
+
+
+def linprim_raster_bwd(prims: Prims, cams, tune, bg, view_ws, pair_ws, max_pairs, out_T, out_last, grad_rgb,
+                       stream=None):
+    p = prims.c()
+    _check(load().linprim_raster_bwd(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _bg(bg), _ptr(view_ws),
+                                     view_ws.numel(), _ptr(pair_ws), pair_ws.numel(), max_pairs, _ptr(out_T),
+                                     _ptr(out_last), _ptr(grad_rgb), _stream(stream)), "linprim_raster_bwd")
+
+
+def linprim_preprocess_bwd(prims: Prims, cams, tune, view_ws, pair_ws, max_pairs, grads: dict, stream=None):
+    p = prims.c()
+    _check(load().linprim_preprocess_bwd(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _ptr(view_ws),
+                                         view_ws.numel(), _ptr(pair_ws), pair_ws.numel(), max_pairs,
+                                         _ptr(grads["means"]), _ptr(grads["quats"]), _ptr(grads["dists"]),
+                                         _ptr(grads["opacity"]), _ptr(grads["sh"]), _stream(stream)),
+           "linprim_preprocess_bwd")
+
+
+def linprim_read_status(view_ws, stream=None):
+    n = ctypes.c_int64(0)
+    ov = ctypes.c_int32(0)
+    _check(load().linprim_read_status(_ptr(view_ws), ctypes.byref(n), ctypes.byref(ov), _stream(stream)),
+           "linprim_read_status")
+    return int(n.value), bool(ov.value)
+
+
+def linprim_debug_pointers(prims: Prims, cams, tune, view_ws, pair_ws, max_pairs) -> dict:
+    p = prims.c()
+    outs = [ctypes.c_void_p() for _ in range(7)]
+    _check(load().linprim_debug_pointers(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _ptr(view_ws),
+                                         _ptr(pair_ws), max_pairs, *[ctypes.byref(o) for o in outs]),
+           "linprim_debug_pointers")
+    names = ("payload", "depth_keys", "tiles", "offsets", "keys", "values", "ranges")
+    return {k: int(o.value or 0) for k, o in zip(names, outs)}

@@ -1,0 +1,337 @@
+"""HIP path vs the FP64 oracle through the C ABI (MI355X only).
+
+Bit-exact: pixel rectangles, depth keys, tile counts, offsets, sorted keys
+and values, tile ranges.  Images within 1e-5 absolute and gradients within
+1e-3 relative on well-conditioned pixels / primitives, as flagged by the
+oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2501_16312_amd import scenes
+from tests import gpu_common as GC
+
+pytestmark = pytest.mark.gpu
+
+OCTA, TETRA = scenes.OCTAHEDRON, scenes.TETRAHEDRON
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    oracle._load()
+    return oracle
+
+
+def _scene_small(kind, n=600, seed=3):
+    gen = scenes.uniform_octahedra if kind == OCTA else scenes.uniform_tetrahedra
+    return gen(n, seed=seed, dmin=0.03, dmax=0.2)
+
+
+def _oracle_render(oracle_mod, sc, cams, tile, bg):
+    O = oracle_mod.OracleScene(sc, cams, tile=tile)
+    r = O.render(bg=np.asarray(bg))
+    r["cams"] = cams
+    return O, r
+
+
+# ------------------------------------------------------------ binning
+@pytest.mark.parametrize("kind", [OCTA, TETRA])
+@pytest.mark.parametrize("tile", [8, 16])
+def test_preprocess_and_sort_bit_exact(oracle_mod, kind, tile):
+    _say(f"binning kind={kind} tile={tile}")
+    sc = _scene_small(kind, 800, seed=5)
+    cams = [scenes.look_at((0.3, -0.2, -3.2), (0, 0, 0), 96, 72),
+            scenes.look_at((3.0, 0.4, 0.2), (0, 0, 0), 50, 37)]
+    g = GC.gpu_forward(sc, cams, tile=tile)
+    dbg = g["rast"].debug_arrays(g["prims"])
+    O = oracle_mod.OracleScene(sc, cams, tile=tile)
+    for v in range(len(cams)):
+        p = O.prep(v)
+        pay = dbg["payload"][v * sc.n:(v + 1) * sc.n].numpy()
+        rect = pay[:, :4].view(np.int32)
+        ref = p["rect"].copy()
+        assert np.array_equal(rect[p["valid"]], ref[p["valid"]])
+        assert np.all(rect[~p["valid"], 0] == -1)
+        keys = dbg["depth_keys"][v * sc.n:(v + 1) * sc.n].numpy().view(np.uint32)
+        assert np.array_equal(keys[p["valid"]], p["key"][p["valid"]])
+        tiles = dbg["tiles"][v * sc.n:(v + 1) * sc.n].numpy()
+        assert np.array_equal(tiles, p["tiles"])
+    tiles_all = dbg["tiles"].numpy().astype(np.int64)
+    offs = dbg["offsets"].numpy().view(np.uint32).astype(np.int64)
+    assert np.array_equal(offs, np.concatenate([[0], np.cumsum(tiles_all)[:-1]]))
+    s = O.sort()
+    assert g["n_pairs"] == len(s["keys"])
+    assert np.array_equal(dbg["keys"].numpy().view(np.uint64), s["keys"])
+    assert np.array_equal(dbg["values"].numpy().view(np.uint32), s["values"])
+    rg = dbg["ranges"].numpy().view(np.uint32).astype(np.int64)
+    nonempty = s["ranges"][:, 1] > s["ranges"][:, 0]
+    assert np.array_equal(rg[nonempty], s["ranges"][nonempty])
+    assert np.all(rg[~nonempty, 0] == rg[~nonempty, 1])
+
+
+@pytest.mark.parametrize("digit", [4, 5, 7, 8])
+def test_sort_digit_widths(oracle_mod, digit):
+    _say(f"sort digit={digit}")
+    sc = _scene_small(OCTA, 500, seed=9)
+    cams = [scenes.look_at((0, 0, -3.0), (0, 0, 0), 64, 64)]
+    g = GC.gpu_forward(sc, cams, tile=8, digit=digit)
+    dbg = g["rast"].debug_arrays(g["prims"])
+    s = oracle_mod.OracleScene(sc, cams, tile=8).sort()
+    assert np.array_equal(dbg["keys"].numpy().view(np.uint64), s["keys"])
+    assert np.array_equal(dbg["values"].numpy().view(np.uint32), s["values"])
+
+
+# ------------------------------------------------------------ forward
+@pytest.mark.parametrize("kind", [OCTA, TETRA])
+def test_forward_parity_small(oracle_mod, kind):
+    _say(f"forward small kind={kind}")
+    sc = _scene_small(kind, 900, seed=11)
+    cams = [scenes.look_at((0.2, 0.1, -3.0), (0, 0, 0), 88, 61)]   # ragged: not a multiple of the tile
+    bg = (0.1, 0.2, 0.3)
+    g = GC.gpu_forward(sc, cams, tile=16, bg=bg)
+    O, r = _oracle_render(oracle_mod, sc, cams, 16, bg)
+    good, _, ill = GC.compare_images(g, r, f"small kind={kind}")
+    assert good <= GC.IMG_TOL
+    assert ill < 0.01
+    ok = (r["ill"] & 1) == 0
+    assert np.mean(g["last"][ok] == r["last"][ok]) > 0.999
+    assert (r["T"] < 1).mean() > 0.2
+
+
+def test_forward_parity_config0(oracle_mod):
+    _say("forward config0")
+    sc, cams = scenes.config0()
+    g = GC.gpu_forward(sc, cams, tile=16, counters=True)
+    O, r = _oracle_render(oracle_mod, sc, cams, 16, (0, 0, 0))
+    good, _, ill = GC.compare_images(g, r, "config0")
+    assert good <= GC.IMG_TOL
+    assert ill < 0.01
+    it, ev, hit, fr = r["counts"][0]
+    _say(f"counts gpu {g['counts'].tolist()} oracle {[it, ev, hit]}")
+    assert abs(int(g["counts"][1]) - ev) <= max(2, 1e-3 * ev)
+    assert abs(int(g["counts"][2]) - hit) <= max(2, 1e-3 * hit)
+
+
+def test_tile_size_invariance(oracle_mod):
+    _say("tile invariance")
+    sc = _scene_small(OCTA, 700, seed=13)
+    cams = [scenes.look_at((0.1, -0.3, -3.0), (0, 0, 0), 100, 70)]
+    imgs = [GC.gpu_forward(sc, cams, tile=t)["rgb"] for t in (8, 16, 32)]
+    assert np.array_equal(imgs[0], imgs[1])
+    assert np.array_equal(imgs[0], imgs[2])
+
+
+def test_multiview_equals_single_views(oracle_mod):
+    _say("multiview")
+    sc = _scene_small(OCTA, 500, seed=17)
+    cams = [scenes.look_at((0, 0, -3), (0, 0, 0), 64, 48), scenes.look_at((3, 0.5, 0), (0, 0, 0), 40, 56),
+            scenes.look_at((-2, 1, -2), (0, 0, 0), 33, 17)]
+    multi = GC.gpu_forward(sc, cams, tile=16)
+    off = 0
+    for c in cams:
+        single = GC.gpu_forward(sc, [c], tile=16)
+        n = 3 * c.width * c.height
+        assert np.array_equal(multi["rgb"][off:off + n], single["rgb"])
+        off += n
+    O, r = _oracle_render(oracle_mod, sc, cams, 16, (0, 0, 0))
+    good, _, _ = GC.compare_images(multi, r, "multiview")
+    assert good <= GC.IMG_TOL
+
+
+# ------------------------------------------------------------ backward
+@pytest.mark.parametrize("kind", [OCTA, TETRA])
+def test_backward_parity_small(oracle_mod, kind):
+    _say(f"backward small kind={kind}")
+    sc = _scene_small(kind, 500, seed=23)
+    cams = [scenes.look_at((0.2, 0.1, -3.0), (0, 0, 0), 72, 56)]
+    bg = (0.3, 0.1, 0.2)
+    grad = scenes.image_gradient(cams, seed=4)
+    g = GC.gpu_forward(sc, cams, tile=16, bg=bg)
+    gg = GC.gpu_backward(g, grad, bg)
+    O = oracle_mod.OracleScene(sc, cams, tile=16)
+    rb = O.backward(grad.astype(np.float64), bg=np.asarray(bg))
+    ok = ~rb["ill"]
+    _say(f"prims ill {rb['ill'].mean() * 100:.2f}%")
+    w = GC.grad_errors(gg, rb, ok, f"small kind={kind}")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k
+
+
+def test_backward_parity_config0(oracle_mod):
+    _say("backward config0")
+    sc, cams = scenes.config0()
+    grad = scenes.image_gradient(cams, seed=1)
+    g = GC.gpu_forward(sc, cams, tile=16)
+    gg = GC.gpu_backward(g, grad)
+    rb = oracle_mod.OracleScene(sc, cams, tile=16).backward(grad.astype(np.float64))
+    ok = ~rb["ill"]
+    _say(f"prims ill {rb['ill'].mean() * 100:.2f}%")
+    w = GC.grad_errors(gg, rb, ok, "config0")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k
+
+
+def test_backward_tile_sizes_agree(oracle_mod):
+    _say("backward tile sizes")
+    sc = _scene_small(OCTA, 400, seed=29)
+    cams = [scenes.look_at((0, 0.2, -3.0), (0, 0, 0), 64, 40)]
+    grad = scenes.image_gradient(cams, seed=6)
+    res = []
+    for t in (8, 16, 32):
+        g = GC.gpu_forward(sc, cams, tile=t)
+        res.append(GC.gpu_backward(g, grad))
+    for k in ("means", "opacity", "sh"):
+        scale = np.abs(res[0][k]).max() + 1e-12
+        assert np.abs(res[0][k] - res[1][k]).max() <= 1e-4 * scale
+        assert np.abs(res[0][k] - res[2][k]).max() <= 1e-4 * scale
+
+
+# ------------------------------------------------------------ edge cases
+def test_edge_cases(oracle_mod):
+    _say("edge cases")
+    import torch
+    # empty scene
+    sc = _scene_small(OCTA, 0, seed=1)
+    cams = [scenes.look_at((0, 0, -3.0), (0, 0, 0), 20, 10)]
+    g = GC.gpu_forward(sc, cams, tile=8, bg=(0.25, 0.5, 0.75))
+    assert np.allclose(g["rgb"].reshape(3, -1), np.array([[0.25], [0.5], [0.75]]))
+    assert np.all(g["T"] == 1.0)
+    # everything culled (behind the camera) and a 1x1 image
+    sc = _scene_small(OCTA, 50, seed=2)
+    cams = [scenes.look_at((0, 0, -3.0), (0, 0, -6.0), 1, 1)]
+    g = GC.gpu_forward(sc, cams, tile=8)
+    assert g["n_pairs"] == 0 and np.all(g["T"] == 1.0)
+    # pair overflow: outputs untouched, status reports it
+    from paper_2501_16312_amd import linprim as L
+    from paper_2501_16312_amd.render import Rasterizer
+    sc = _scene_small(OCTA, 300, seed=3)
+    cams = [scenes.look_at((0, 0, -3.0), (0, 0, 0), 64, 64)]
+    prims = L.Prims.from_scene(sc)
+    rast = Rasterizer(sc.kind, sc.n, cams, tile=16)
+    need = rast.preprocess(prims, sync_count=True)
+    assert need > 10
+    small = need // 2
+    rast.pair_ws = torch.empty(L.linprim_pair_workspace_size(small, rast.cams_c, rast.tune), dtype=torch.uint8,
+                               device="cuda")
+    rast.max_pairs = small
+    rast.bin_sort(prims)
+    rgb, T, last = rast.alloc_outputs()
+    rgb.fill_(-7.0)
+    rast.render(prims, None, out=(rgb, T, last))
+    n, ov = rast.status()
+    assert n == need and ov
+    assert torch.all(rgb == -7.0).item()
+
+
+# ------------------------------------------------------------ full-size workloads
+def _sample_pixels(rng, cam, k):
+    idx = rng.choice(cam.width * cam.height, size=k, replace=False)
+    return np.stack([idx % cam.width, idx // cam.width], 1).astype(np.int32), idx
+
+
+@pytest.mark.parametrize("config", [1, 2])
+def test_full_size_sampled_forward(oracle_mod, config):
+    _say(f"full-size forward config{config}")
+    sc, cams = scenes.CONFIGS[config]()
+    cam = cams[0]
+    g = GC.gpu_forward(sc, cams, tile=16)
+    _say(f"pairs {g['n_pairs']}")
+    O = oracle_mod.OracleScene(sc, cams, tile=16)
+    rng = np.random.default_rng(100 + config)
+    pix, idx = _sample_pixels(rng, cam, 1500)
+    r = O.render_pixels(0, pix)
+    hw = cam.width * cam.height
+    rgb = np.stack([g["rgb"][c * hw + idx] for c in range(3)], 1)
+    ok = (r["ill"] & 1) == 0
+    err = np.maximum(np.abs(rgb - r["rgb"]).max(1), np.abs(g["T"][idx] - r["T"]))
+    _say(f"sampled max err (ok) {err[ok].max():.3e}, overall {err.max():.3e}, ill {(~ok).mean() * 100:.2f}%, "
+         f"covered {(r['T'] < 1).mean() * 100:.1f}%")
+    assert err[ok].max() <= GC.IMG_TOL
+    assert (r["T"] < 1).mean() > 0.05
+
+
+@pytest.mark.parametrize("config", [1, 2])
+def test_full_size_sparse_backward(oracle_mod, config):
+    """Gradient of a loss on a sparse set of pixels: an exact sub-problem the
+    oracle can finish at full scene size."""
+    _say(f"full-size backward config{config}")
+    sc, cams = scenes.CONFIGS[config]()
+    grad = scenes.sparse_image_gradient(cams, 0.002, seed=7)
+    g = GC.gpu_forward(sc, cams, tile=16)
+    gg = GC.gpu_backward(g, grad)
+    O = oracle_mod.OracleScene(sc, cams, tile=16)
+    rb = O.backward(grad.astype(np.float64))
+    touched = np.abs(rb["opacity"]) + np.abs(rb["means"]).sum(1) > 0
+    ok = touched & ~rb["ill"]
+    _say(f"touched prims {touched.sum()}, ill {rb['ill'][touched].mean() * 100:.2f}%")
+    w = GC.grad_errors(gg, rb, ok, f"config{config} sparse")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k
+    # primitives no gradient pixel reaches get exactly zero
+    untouched = ~touched & (np.abs(rb["sh"]).sum((1, 2)) == 0)
+    assert np.abs(gg["means"][untouched]).max(initial=0.0) == 0.0
+
+
+def test_config1_finite_differences(oracle_mod):
+    """64 sampled parameters of the 100k-tetrahedron workload: the GPU's
+    analytic gradient vs central differences of the FP64 oracle, evaluated
+    on the pixels the perturbed primitive covers."""
+    _say("config1 finite differences")
+    sc, cams = scenes.config1()
+    cam = cams[0]
+    grad = scenes.image_gradient(cams, seed=2).astype(np.float64)
+    g = GC.gpu_forward(sc, cams, tile=16)
+    gg = GC.gpu_backward(g, grad.astype(np.float32))
+    O = oracle_mod.OracleScene(sc, cams, tile=16)
+    p = O.prep()
+    vis = np.nonzero(p["valid"] & ((p["rect"][:, 2] - p["rect"][:, 0]) >= 2))[0]
+    rng = np.random.default_rng(2)
+    hw = cam.width * cam.height
+    base64 = {k: getattr(sc, k).astype(np.float64) for k in ("means", "quats", "dists", "opacity", "sh")}
+    plan = [("means", 16), ("quats", 8), ("dists", 16), ("opacity", 8), ("sh", 16)]
+    results = []
+    for field, count in plan:
+        for _ in range(count):
+            n = int(rng.choice(vis))
+            comp = tuple(int(rng.integers(0, s)) for s in base64[field].shape[1:])
+            i0, j0, i1, j1 = p["rect"][n]
+            i0, j0 = max(i0 - 2, 0), max(j0 - 2, 0)
+            i1, j1 = min(i1 + 2, cam.width - 1), min(j1 + 2, cam.height - 1)
+            jj, ii = np.mgrid[j0:j1 + 1, i0:i1 + 1]
+            pix = np.stack([ii.ravel(), jj.ravel()], 1).astype(np.int32)
+            pidx = jj.ravel() * cam.width + ii.ravel()
+            gsel = np.stack([grad[c * hw + pidx] for c in range(3)], 1)
+            if field in ("means", "dists"):
+                h = 1e-3 * float(base64["dists"][n].min())
+            else:
+                h = 1e-3
+            vals = []
+            for sgn in (1, -1):
+                pp = {k: v.copy() for k, v in base64.items()}
+                pp[field][(n,) + comp] += sgn * h
+                Op = oracle_mod.OracleScene(sc, cams, tile=16, inputs64=pp)
+                vals.append(float((Op.render_pixels(0, pix)["rgb"] * gsel).sum()))
+            fd = (vals[0] - vals[1]) / (2 * h)
+            an = float(gg[field][(n,) + comp])
+            if field == "dists" and comp[0] == int(np.argmin(base64["dists"][n])):
+                # the GPU holds min(d) of Eq. 1 constant (App. G); central
+                # differences move it: add dL/dsigma dsigma/dmin
+                al = base64["opacity"][n]
+                dmin = base64["dists"][n].min()
+                sig = -math.log(1 - 0.99 * al) / (2 * dmin)
+                an += float(gg["opacity"][n]) / (0.99 / ((1 - 0.99 * al) * 2 * dmin)) * (-sig / dmin)
+            results.append((field, n, comp, an, fd))
+    scale = {f: max(abs(fd) for ff, _, _, _, fd in results if ff == f) for f, _ in plan}
+    bad = [(f, n, c, a, d) for f, n, c, a, d in results if abs(a - d) > 2e-2 * max(abs(d), 0.05 * scale[f])]
+    for r in results[:8]:
+        _say(f"fd sample {r}")
+    _say(f"fd mismatches {len(bad)} of {len(results)}: {bad[:5]}")
+    assert len(bad) <= 2
