@@ -178,6 +178,37 @@ int linprim_preprocess_bwd(const linprim_prims *prims, const linprim_camera *cam
                            float *grad_quats, float *grad_dists, float *grad_opacity, float *grad_sh,
                            void *stream);
 
+/* The optimisation step around the rasterizer (Sec. 3.4 "Optimization";
+ * learning rates of App. G, Table "learning rates").
+ *
+ * linprim_l1_grad: for L = scale * sum_i |rgb_i - target_i| over `count`
+ * floats, writes grad = dL/drgb = scale * sign(rgb - target) and, for each
+ * block of 1024 elements, the block's share of L into
+ * partial[ceil(count / 1024)] (summing the partials gives L; they are for
+ * logging, the gradient does not need them).  All DEVICE pointers. */
+int linprim_l1_grad(const float *rgb, const float *target, int64_t count, float scale, float *grad,
+                    float *partial, void *stream);
+
+/* One Adam step (Kingma & Ba; Sec. 3.4) over up to 8 parameter groups in
+ * a single launch: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), then p is clamped to
+ * [lo, hi] (use -inf/+inf for none; e.g. distances stay positive and
+ * opacities inside [0, 1]).  groups: HOST array; the tensors are DEVICE
+ * float32 arrays of `numel` elements; step t >= 1. */
+typedef struct linprim_adam_group {
+    float *param;
+    const float *grad;
+    float *exp_avg;
+    float *exp_avg_sq;
+    int64_t numel;
+    float lr;
+    float lo, hi;
+    int32_t reserved;
+} linprim_adam_group;
+
+int linprim_adam_step(const linprim_adam_group *groups, int32_t n_groups, float beta1, float beta2,
+                      float eps, int32_t step, void *stream);
+
 /* Waits for `stream`; reports the pair count and whether the last bin_sort
  * overflowed its capacity (HOST outputs). */
 int linprim_read_status(const void *view_ws, int64_t *pairs_needed, int32_t *overflow, void *stream);

@@ -40,8 +40,9 @@ ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, i
     return L;
 }
 
-PairLayout pair_layout(int64_t max_pairs, int digit_bits) {
+PairLayout pair_layout(int64_t max_pairs, int digit_bits, int tile) {
     (void)digit_bits;
+    const int nq = (tile / 8) * (tile / 8);
     PairLayout P;
     P.capacity = max_pairs;
     P.sort_blocks = (max_pairs + kSortTile - 1) / kSortTile;
@@ -51,7 +52,7 @@ PairLayout pair_layout(int64_t max_pairs, int digit_bits) {
     P.vals_a = off; off = align256(off + (size_t)max_pairs * 4);
     P.vals_b = off; off = align256(off + (size_t)max_pairs * 4);
     P.hist = off; off = align256(off + ((size_t)256 * P.sort_blocks + 256) * 4);
-    P.grads = off; off = align256(off + (size_t)max_pairs * kGradWords * 4);
+    P.grads = off; off = align256(off + (size_t)max_pairs * nq * kGradWords * 4);
     P.total = off;
     return P;
 }
@@ -139,7 +140,7 @@ size_t linprim_pair_workspace_size(int64_t max_pairs, const linprim_camera* cams
                                    const linprim_tuning* tuning) {
     if (max_pairs < 0 || max_pairs >= (int64_t(1) << 31) || !valid_cams(cams, n_views) || !valid_tuning(tuning))
         return 0;
-    return pair_layout(max_pairs, digit_of(tuning)).total;
+    return pair_layout(max_pairs, digit_of(tuning), tile_of(tuning)).total;
 }
 
 int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
@@ -177,7 +178,7 @@ static int prepare(const linprim_prims* prims, const linprim_camera* cams, int32
         max_pairs >= (int64_t(1) << 31))
         return LINPRIM_ERR_INVALID_ARG;
     L = view_layout(prims->n, cams, n_views, tile_of(tuning));
-    P = pair_layout(max_pairs, digit_of(tuning));
+    P = pair_layout(max_pairs, digit_of(tuning), tile_of(tuning));
     if (view_ws_bytes < L.total || pair_ws_bytes < P.total) return LINPRIM_ERR_WORKSPACE;
     return LINPRIM_OK;
 }
@@ -275,6 +276,37 @@ int linprim_preprocess_bwd(const linprim_prims* prims, const linprim_camera* cam
     return hip_status(launch_preprocess_bwd(*prims, n_views, tile_of(tuning), L, (const char*)view_ws, P,
                                             (const char*)pair_ws, grad_means, grad_quats, grad_dists, grad_opacity,
                                             grad_sh, (hipStream_t)stream));
+}
+
+int linprim_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad, float* partial,
+                    void* stream) {
+    if (count < 0 || (count > 0 && (!rgb || !target || !grad || !partial))) return LINPRIM_ERR_INVALID_ARG;
+    return hip_status(launch_l1_grad(rgb, target, count, scale, grad, partial, (hipStream_t)stream));
+}
+
+int linprim_adam_step(const linprim_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps,
+                      int32_t step, void* stream) {
+    if (!groups || n_groups < 1 || n_groups > 8 || step < 1) return LINPRIM_ERR_INVALID_ARG;
+    AdamGroups G;
+    memset(&G, 0, sizeof(G));
+    G.count = n_groups;
+    G.start[0] = 0;
+    for (int k = 0; k < n_groups; ++k) {
+        const linprim_adam_group& g = groups[k];
+        if (g.numel < 0 || (g.numel > 0 && (!g.param || !g.grad || !g.exp_avg || !g.exp_avg_sq)))
+            return LINPRIM_ERR_INVALID_ARG;
+        G.param[k] = g.param;
+        G.grad[k] = g.grad;
+        G.m[k] = g.exp_avg;
+        G.v[k] = g.exp_avg_sq;
+        G.lr[k] = g.lr;
+        G.lo[k] = g.lo;
+        G.hi[k] = g.hi;
+        G.start[k + 1] = G.start[k] + g.numel;
+    }
+    const double bc1 = 1.0 - pow((double)beta1, (double)step);
+    const double bc2 = 1.0 - pow((double)beta2, (double)step);
+    return hip_status(launch_adam(G, beta1, beta2, eps, (float)bc1, (float)bc2, (hipStream_t)stream));
 }
 
 int linprim_read_status(const void* view_ws, int64_t* pairs_needed, int32_t* overflow, void* stream) {

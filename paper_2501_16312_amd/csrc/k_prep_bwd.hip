@@ -3,14 +3,10 @@
 // undo the plane construction, the ray-space projection and the view
 // transform, and split the corner gradients onto rotation and distances.
 // One thread per primitive loops over the views, so gradients summed over
-// views are deterministic.  Double precision throughout (memory-bound).
+// views are deterministic.  Geometry in double precision (memory-bound).
 #include "linprim_common.h"
 
 namespace linprim {
-
-struct V3 {
-    double x, y, z;
-};
 
 __device__ inline void cross3(const double a[3], const double b[3], double o[3]) {
     o[0] = a[1] * b[2] - a[2] * b[1];
@@ -18,184 +14,385 @@ __device__ inline void cross3(const double a[3], const double b[3], double o[3])
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
+// Record r of a primitive (tile r / NQ of its tile rectangle in row-major
+// order, group r % NQ of that tile) exists only if the group meets the
+// primitive's pixel rectangle.
+__device__ inline bool record_exists(int r, int NQ, int QX, int tile, int4 rect, int tx0, int ty0, int ntx) {
+    const int t = r / NQ, q = r % NQ;
+    const int tx = tx0 + t % ntx, ty = ty0 + t / ntx;
+    const int gx0 = tx * tile + (q % QX) * 8, gy0 = ty * tile + (q / QX) * 8;
+    return !(rect.x > gx0 + 7 || rect.z < gx0 || rect.y > gy0 + 7 || rect.w < gy0);
+}
+
+// Sums the gradient records of every (view, primitive) into its first
+// record, in record order.  Short runs are summed by one lane; runs longer
+// than a wavefront by the whole wave (lane-strided, then a fixed-order
+// cross-lane sum), so primitives that span thousands of tiles do not hold
+// up a lane.
+__global__ __launch_bounds__(256) void k_sum_records(const float* __restrict__ payload,
+                                                     const uint32_t* __restrict__ tiles,
+                                                     const uint32_t* __restrict__ offsets, int64_t count, int tile,
+                                                     const Status* __restrict__ status, uint64_t capacity,
+                                                     float* __restrict__ grads) {
+    if (status->n_pairs > capacity) return;
+    const int QX = tile / 8, NQ = QX * QX;
+    const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    uint32_t cnt = 0;
+    int4 rect = make_int4(0, 0, -1, -1);
+    uint32_t off = 0;
+    if (slot < count) {
+        cnt = tiles[slot];
+        if (cnt) {
+            rect = *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
+            off = offsets[slot];
+        }
+    }
+    const int nrec = (int)cnt * NQ;
+    const bool small = nrec > 0 && nrec <= 64;
+    if (small) {
+        const int tx0 = rect.x >> shift, ty0 = rect.y >> shift, ntx = (rect.z >> shift) - tx0 + 1;
+        float acc[kGradWords];
+        for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
+        const float4* g = reinterpret_cast<const float4*>(grads + (int64_t)off * NQ * kGradWords);
+        for (int r = 0; r < nrec; ++r) {
+            if (NQ > 1 && !record_exists(r, NQ, QX, tile, rect, tx0, ty0, ntx)) continue;
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k) {
+                const float4 x = g[(int64_t)r * (kGradWords / 4) + k];
+                acc[4 * k] += x.x;
+                acc[4 * k + 1] += x.y;
+                acc[4 * k + 2] += x.z;
+                acc[4 * k + 3] += x.w;
+            }
+        }
+        float4* d = reinterpret_cast<float4*>(grads + (int64_t)off * NQ * kGradWords);
+#pragma unroll
+        for (int k = 0; k < kGradWords / 4; ++k)
+            d[k] = make_float4(acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]);
+    }
+    uint64_t big = __ballot(nrec > 64);
+    while (big) {
+        const int b = __builtin_ctzll(big);
+        big &= big - 1;
+        const int nr = __builtin_amdgcn_readlane(nrec, b);
+        const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, b);
+        const int4 rc = make_int4(__builtin_amdgcn_readlane(rect.x, b), __builtin_amdgcn_readlane(rect.y, b),
+                                  __builtin_amdgcn_readlane(rect.z, b), __builtin_amdgcn_readlane(rect.w, b));
+        const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
+        float acc[kGradWords];
+        for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
+        const float* g = grads + (int64_t)o * NQ * kGradWords;
+        for (int r = lane; r < nr; r += 64) {
+            if (NQ > 1 && !record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx)) continue;
+#pragma unroll
+            for (int k = 0; k < kGradWords; ++k) acc[k] += g[(int64_t)r * kGradWords + k];
+        }
+        const float outv = wave_reduce20(acc, lane);
+        const int ridx = reduce20_index(lane);
+        if (ridx >= 0) grads[(int64_t)o * NQ * kGradWords + ridx] = outv;
+    }
+}
+
+// Colour backward along the viewing direction, one basis function at a
+// time (single precision): gsh_k += grgb Y_k, gdir += sum_ch grgb sh_k
+// dY_k/ddir.  The basis polynomials are those of sh_eval.
+struct ShBack {
+    int K;
+    const float* sh;
+    float* gsh;          // [48] accumulators
+    float gr[3];
+    float gdir[3];
+    __device__ inline void term(int k, float Y, float gx, float gy, float gz) {
+        if (k >= K) return;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            gsh[3 * k + ch] += gr[ch] * Y;
+            const float w = gr[ch] * sh[3 * k + ch];
+            gdir[0] += w * gx;
+            gdir[1] += w * gy;
+            gdir[2] += w * gz;
+        }
+    }
+};
+
+struct ShConstF {
+    float c0, c1, c2a, c2b, c2c, c3a, c3b, c3c, c3d, c3e;
+};
+
+__device__ inline ShConstF sh_constants_f() {
+    const ShConst K = sh_constants();
+    return {(float)K.c0, (float)K.c1, (float)K.c2a, (float)K.c2b, (float)K.c2c,
+            (float)K.c3a, (float)K.c3b, (float)K.c3c, (float)K.c3d, (float)K.c3e};
+}
+
+// raw colour (before the clamp) along dir, single precision
+__device__ inline void sh_raw_f(int K, const float* sh, float x, float y, float z, float raw[3]) {
+    const ShConstF C = sh_constants_f();
+    float Y[16];
+    Y[0] = C.c0;
+    Y[1] = -C.c1 * y; Y[2] = C.c1 * z; Y[3] = -C.c1 * x;
+    Y[4] = C.c2a * x * y; Y[5] = -C.c2a * y * z; Y[6] = C.c2b * (2 * z * z - x * x - y * y);
+    Y[7] = -C.c2a * x * z; Y[8] = C.c2c * (x * x - y * y);
+    Y[9] = -C.c3a * y * (3 * x * x - y * y); Y[10] = C.c3b * x * y * z;
+    Y[11] = -C.c3c * y * (4 * z * z - x * x - y * y); Y[12] = C.c3d * z * (2 * z * z - 3 * x * x - 3 * y * y);
+    Y[13] = -C.c3c * x * (4 * z * z - x * x - y * y); Y[14] = C.c3e * z * (x * x - y * y);
+    Y[15] = -C.c3a * x * (x * x - 3 * y * y);
+    raw[0] = raw[1] = raw[2] = 0.5f;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (k < K)
+            for (int ch = 0; ch < 3; ++ch) raw[ch] += sh[3 * k + ch] * Y[k];
+}
+
+__device__ inline void sh_backward(ShBack& S, float x, float y, float z) {
+    const ShConstF K = sh_constants_f();
+    S.term(0, K.c0, 0, 0, 0);
+    S.term(1, -K.c1 * y, 0, -K.c1, 0);
+    S.term(2, K.c1 * z, 0, 0, K.c1);
+    S.term(3, -K.c1 * x, -K.c1, 0, 0);
+    S.term(4, K.c2a * x * y, K.c2a * y, K.c2a * x, 0);
+    S.term(5, -K.c2a * y * z, 0, -K.c2a * z, -K.c2a * y);
+    S.term(6, K.c2b * (2 * z * z - x * x - y * y), -2 * K.c2b * x, -2 * K.c2b * y, 4 * K.c2b * z);
+    S.term(7, -K.c2a * x * z, -K.c2a * z, 0, -K.c2a * x);
+    S.term(8, K.c2c * (x * x - y * y), 2 * K.c2c * x, -2 * K.c2c * y, 0);
+    S.term(9, -K.c3a * y * (3 * x * x - y * y), -6 * K.c3a * x * y, -K.c3a * (3 * x * x - 3 * y * y), 0);
+    S.term(10, K.c3b * x * y * z, K.c3b * y * z, K.c3b * x * z, K.c3b * x * y);
+    S.term(11, -K.c3c * y * (4 * z * z - x * x - y * y), 2 * K.c3c * x * y, -K.c3c * (4 * z * z - x * x - 3 * y * y),
+           -8 * K.c3c * y * z);
+    S.term(12, K.c3d * z * (2 * z * z - 3 * x * x - 3 * y * y), -6 * K.c3d * x * z, -6 * K.c3d * y * z,
+           K.c3d * (6 * z * z - 3 * x * x - 3 * y * y));
+    S.term(13, -K.c3c * x * (4 * z * z - x * x - y * y), -K.c3c * (4 * z * z - 3 * x * x - y * y), 2 * K.c3c * x * y,
+           -8 * K.c3c * x * z);
+    S.term(14, K.c3e * z * (x * x - y * y), 2 * K.c3e * x * z, -2 * K.c3e * y * z, K.c3e * (x * x - y * y));
+    S.term(15, -K.c3a * x * (x * x - 3 * y * y), -K.c3a * (3 * x * x - 3 * y * y), 6 * K.c3a * x * y, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 1, one thread per (view, primitive): the summed record (dL/d plane
+// coefficients, dL/d rgb, dL/d sigma) -> dL/d(ray-space centre, offsets) ->
+// camera -> world.  Writes back in place, into the same record:
+//   [0..2] dL/d mu (geometric part), [3..11] dL/dR (row-major),
+//   [12..15] dL/d distances, [16..19] unchanged (rgb, sigma).
+// ---------------------------------------------------------------------------
 template <int KIND>
-__global__ __launch_bounds__(128) void k_prep_bwd(const float* __restrict__ means, const float* __restrict__ quats,
+__global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ means, const float* __restrict__ quats,
+                                                  const float* __restrict__ dists, const float* __restrict__ opacity,
+                                                  int64_t n, const ViewInfo* __restrict__ views,
+                                                  const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
+                                                  const uint32_t* __restrict__ offsets, float* __restrict__ grads,
+                                                  int nq, const Status* __restrict__ status, uint64_t capacity) {
+    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (status->n_pairs > capacity) return;
+    const int v = blockIdx.y;
+    if (slot >= n) return;
+    const int64_t vs = (int64_t)v * n + slot;
+    if (tiles[vs] == 0) return;
+    const int64_t i = slot;
+    constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
+    float4* rp = reinterpret_cast<float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
+    float r[16];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float4 x = rp[k];
+        r[4 * k] = x.x;
+        r[4 * k + 1] = x.y;
+        r[4 * k + 2] = x.z;
+        r[4 * k + 3] = x.w;
+    }
+    const ViewInfo& V = views[v];
+    Geom G;
+    if (!build_geometry(KIND, means + 3 * i, quats + 4 * i, dists + ND * i, opacity[i], V, G)) return;
+    const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
+    const double ox = (double)rc.x + 0.5 - G.c[0];
+    const double oy = (double)rc.y + 0.5 - G.c[1];
+
+    // ---- planes -> ray-space centre (xy) and offsets a_k
+    double gox = 0.0, goy = 0.0;
+    double ga[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (KIND == LINPRIM_OCTAHEDRON) {
+        double M[9], N[9], gN[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int rr = 0; rr < 3; ++rr)
+            for (int k = 0; k < 3; ++k) M[3 * rr + k] = G.a[k][rr];
+        inverse3(M, N);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            double nu[3];
+            for (int c = 0; c < 3; ++c) nu[c] = kSlab[s][0] * N[c] + kSlab[s][1] * N[3 + c] + kSlab[s][2] * N[6 + c];
+            const double nl = sqrt(nu[0] * nu[0] + nu[1] * nu[1] + nu[2] * nu[2]);
+            const double nz = clamp_nz(nu[2], nl);
+            const double inz = 1.0 / nz;
+            const double A = -nu[0] * inz, B = -nu[1] * inz, Wd = fabs(inz);
+            const double gA = r[4 * s], gB = r[4 * s + 1], gUp = r[4 * s + 2], gLo = r[4 * s + 3];
+            const double gsum = gUp + gLo;         // both offsets carry A ox + B oy
+            const double gW = gUp - gLo;
+            const double gAt = gA + gsum * ox, gBt = gB + gsum * oy;
+            gox += gsum * A;
+            goy += gsum * B;
+            const double gn0 = -gAt * inz, gn1 = -gBt * inz, gn2 = -(gAt * A + gBt * B + gW * Wd) * inz;
+            for (int q = 0; q < 3; ++q) {
+                gN[3 * q + 0] += kSlab[s][q] * gn0;
+                gN[3 * q + 1] += kSlab[s][q] * gn1;
+                gN[3 * q + 2] += kSlab[s][q] * gn2;
+            }
+        }
+        // N = M^-1:  dL/dM = -N^T dL/dN N^T; column b of M is a_b
+        double T1[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                T1[3 * a + b] = N[a] * gN[b] + N[3 + a] * gN[3 + b] + N[6 + a] * gN[6 + b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                ga[b][a] = -(T1[3 * a] * N[3 * b] + T1[3 * a + 1] * N[3 * b + 1] + T1[3 * a + 2] * N[3 * b + 2]);
+    } else {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const double gA = r[3 * f], gB = r[3 * f + 1], gDp = r[3 * f + 2];
+            const int m0 = (f == 0) ? 1 : 0, m1 = (f <= 1) ? 2 : 1, m2 = (f <= 2) ? 3 : 2;
+            const double* P0 = G.a[m0];
+            const double e1[3] = {G.a[m1][0] - P0[0], G.a[m1][1] - P0[1], G.a[m1][2] - P0[2]};
+            const double e2[3] = {G.a[m2][0] - P0[0], G.a[m2][1] - P0[1], G.a[m2][2] - P0[2]};
+            double nv[3];
+            cross3(e1, e2, nv);
+            const double to_f = nv[0] * (G.a[f][0] - P0[0]) + nv[1] * (G.a[f][1] - P0[1]) + nv[2] * (G.a[f][2] - P0[2]);
+            const double sgn = (to_f > 0.0) ? -1.0 : 1.0;
+            for (int c = 0; c < 3; ++c) nv[c] *= sgn;
+            const double nlen = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            const double nz = clamp_nz(nv[2], nlen);
+            const double A = -nv[0] / nz, B = -nv[1] / nz;
+            // D' = P0z - A P0x - B P0y + A ox + B oy
+            const double gAt = gA + gDp * (ox - P0[0]);
+            const double gBt = gB + gDp * (oy - P0[1]);
+            gox += gDp * A;
+            goy += gDp * B;
+            double gn[3] = {-gAt / nz * sgn, -gBt / nz * sgn, -(gAt * A + gBt * B) / nz * sgn};  // d(e1 x e2)
+            double ge1[3], ge2[3];
+            cross3(e2, gn, ge1);
+            cross3(gn, e1, ge2);
+            const double gP0[3] = {-gDp * A, -gDp * B, gDp};
+            for (int c = 0; c < 3; ++c) {
+                ga[m0][c] += gP0[c] - ge1[c] - ge2[c];
+                ga[m1][c] += ge1[c];
+                ga[m2][c] += ge2[c];
+            }
+        }
+    }
+    // ox = i0 + 1/2 - c_x, oy = j0 + 1/2 - c_y; c_z does not enter a chord
+    const double gc0 = -gox, gc1 = -goy;
+
+    // ---- ray space -> camera: c = phi(t) with d phi/dt = J; a_k = J(t) oc_k
+    const double* J = G.J;
+    const double x = G.tc[0], y = G.tc[1], z = G.tc[2];
+    const double l = G.c[2];
+    double gt[3];
+    for (int c = 0; c < 3; ++c) gt[c] = J[c] * gc0 + J[3 + c] * gc1;
+    double gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double gd[4] = {0, 0, 0, 0};
+    const double iz2 = 1.0 / (z * z), il = 1.0 / l, il3 = il * il * il;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        double goc[3];
+        for (int c = 0; c < 3; ++c) goc[c] = J[c] * ga[k][0] + J[3 + c] * ga[k][1] + J[6 + c] * ga[k][2];
+        const double* w = G.oc[k];
+        const double tw = x * w[0] + y * w[1] + z * w[2];
+        // derivatives of J w with respect to t
+        const double d00 = -V.fx * w[2] * iz2, d02 = -V.fx * w[0] * iz2 + 2.0 * V.fx * x * w[2] * iz2 / z;
+        const double d11 = -V.fy * w[2] * iz2, d12 = -V.fy * w[1] * iz2 + 2.0 * V.fy * y * w[2] * iz2 / z;
+        const double d20 = w[0] * il - tw * x * il3, d21 = w[1] * il - tw * y * il3, d22 = w[2] * il - tw * z * il3;
+        gt[0] += d00 * ga[k][0] + d20 * ga[k][2];
+        gt[1] += d11 * ga[k][1] + d21 * ga[k][2];
+        gt[2] += d02 * ga[k][0] + d12 * ga[k][1] + d22 * ga[k][2];
+        // camera -> world offset, then onto R and the distance
+        double go[3];
+        for (int c = 0; c < 3; ++c) go[c] = V.Rw[c] * goc[0] + V.Rw[3 + c] * goc[1] + V.Rw[6 + c] * goc[2];
+        if (KIND == LINPRIM_OCTAHEDRON) {
+            const double dk = (double)dists[ND * i + k];
+            for (int rr = 0; rr < 3; ++rr) {
+                gR[3 * rr + k] += go[rr] * dk;
+                gd[k] += go[rr] * G.R[3 * rr + k];
+            }
+        } else {
+            const double gk = (double)dists[ND * i + k] * kInvSqrt3;
+            for (int rr = 0; rr < 3; ++rr) {
+                const double rb = kTetDir[k][0] * G.R[3 * rr] + kTetDir[k][1] * G.R[3 * rr + 1] +
+                                  kTetDir[k][2] * G.R[3 * rr + 2];
+                for (int c = 0; c < 3; ++c) gR[3 * rr + c] += go[rr] * kTetDir[k][c] * gk;
+                gd[k] += go[rr] * rb * kInvSqrt3;
+            }
+        }
+    }
+    double gm[3];
+    for (int c = 0; c < 3; ++c) gm[c] = V.Rw[c] * gt[0] + V.Rw[3 + c] * gt[1] + V.Rw[6 + c] * gt[2];
+    rp[0] = make_float4((float)gm[0], (float)gm[1], (float)gm[2], (float)gR[0]);
+    rp[1] = make_float4((float)gR[1], (float)gR[2], (float)gR[3], (float)gR[4]);
+    rp[2] = make_float4((float)gR[5], (float)gR[6], (float)gR[7], (float)gR[8]);
+    rp[3] = make_float4((float)gd[0], (float)gd[1], (float)gd[2], (float)gd[3]);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2, one thread per primitive: sums the views, then rotation ->
+// quaternion, Eq. 1 -> opacity (min d held constant), colour -> SH and the
+// viewing direction.  Outputs are overwritten.
+// ---------------------------------------------------------------------------
+template <int KIND>
+__global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ means, const float* __restrict__ quats,
                                                   const float* __restrict__ dists, const float* __restrict__ opacity,
                                                   const float* __restrict__ sh, int sh_degree, int64_t n, int n_views,
-                                                  const ViewInfo* __restrict__ views, const float* __restrict__ payload,
+                                                  const ViewInfo* __restrict__ views,
                                                   const uint32_t* __restrict__ tiles,
-                                                  const uint32_t* __restrict__ offsets,
-                                                  const float* __restrict__ grads, const Status* __restrict__ status,
-                                                  uint64_t capacity, float* __restrict__ g_means,
-                                                  float* __restrict__ g_quats, float* __restrict__ g_dists,
-                                                  float* __restrict__ g_opacity, float* __restrict__ g_sh) {
+                                                  const uint32_t* __restrict__ offsets, const float* __restrict__ grads,
+                                                  int nq, const Status* __restrict__ status, uint64_t capacity,
+                                                  float* __restrict__ g_means, float* __restrict__ g_quats,
+                                                  float* __restrict__ g_dists, float* __restrict__ g_opacity,
+                                                  float* __restrict__ g_sh) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
     const int K = (sh_degree + 1) * (sh_degree + 1);
     const bool ok = status->n_pairs <= capacity;
-    double gm[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gd[4] = {0, 0, 0, 0}, ga_total = 0.0;
-    float* gsh = g_sh + i * (int64_t)K * 3;
-    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.0f;
-    for (int v = 0; ok && v < n_views; ++v) {
-        const int64_t slot = (int64_t)v * n + i;
-        const uint32_t cnt = tiles[slot];
-        if (cnt == 0) continue;
-        // sum of the per-tile records, in tile order
-        double r[kGradWords];
-        for (int k = 0; k < kGradWords; ++k) r[k] = 0.0;
-        const float4* gp = reinterpret_cast<const float4*>(grads + (int64_t)offsets[slot] * kGradWords);
-        for (uint32_t t = 0; t < cnt; ++t) {
+    double gm[3] = {0, 0, 0}, gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gd[4] = {0, 0, 0, 0}, gsig = 0.0;
+    float gsh[48];
 #pragma unroll
-            for (int k = 0; k < kGradWords / 4; ++k) {
-                const float4 x = gp[(int64_t)t * (kGradWords / 4) + k];
-                r[4 * k + 0] += x.x;
-                r[4 * k + 1] += x.y;
-                r[4 * k + 2] += x.z;
-                r[4 * k + 3] += x.w;
-            }
-        }
+    for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
+    const float* shp = sh + i * (int64_t)K * 3;
+    for (int v = 0; ok && v < n_views; ++v) {
+        const int64_t vs = (int64_t)v * n + i;
+        if (tiles[vs] == 0) continue;
+        const float4* rp = reinterpret_cast<const float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
+        const float4 a = rp[0], b = rp[1], c = rp[2], d = rp[3], e = rp[4];
+        gm[0] += a.x; gm[1] += a.y; gm[2] += a.z;
+        gR[0] += a.w; gR[1] += b.x; gR[2] += b.y; gR[3] += b.z; gR[4] += b.w;
+        gR[5] += c.x; gR[6] += c.y; gR[7] += c.z; gR[8] += c.w;
+        gd[0] += d.x; gd[1] += d.y; gd[2] += d.z; gd[3] += d.w;
+        gsig += e.w;
+        // colour -> SH coefficients and viewing direction (single precision)
         const ViewInfo& V = views[v];
-        Geom G;
-        if (!build_geometry(KIND, means + 3 * i, quats + 4 * i, dists + ND * i, opacity[i], V, G)) continue;
-        const float* rec = payload + slot * kRecordWords;
-        const int i0 = __float_as_int(rec[R_I0]), j0 = __float_as_int(rec[R_J0]);
-        const double ox = (double)i0 + 0.5 - G.c[0];
-        const double oy = (double)j0 + 0.5 - G.c[1];
-
-        // ---- planes -> ray-space centre (xy) and offsets a_k
-        double gox = 0.0, goy = 0.0;
-        double ga[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-        if (KIND == LINPRIM_OCTAHEDRON) {
-            double M[9], N[9], gN[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-            for (int rr = 0; rr < 3; ++rr)
-                for (int k = 0; k < 3; ++k) M[3 * rr + k] = G.a[k][rr];
-            inverse3(M, N);
-            for (int s = 0; s < 4; ++s) {
-                double nu[3];
-                for (int c = 0; c < 3; ++c)
-                    nu[c] = kSlab[s][0] * N[c] + kSlab[s][1] * N[3 + c] + kSlab[s][2] * N[6 + c];
-                const double nl = sqrt(nu[0] * nu[0] + nu[1] * nu[1] + nu[2] * nu[2]);
-                const double nz = clamp_nz(nu[2], nl);
-                const double A = -nu[0] / nz, B = -nu[1] / nz, Wd = 1.0 / fabs(nz);
-                const double gA = r[4 * s], gB = r[4 * s + 1], gUp = r[4 * s + 2], gLo = r[4 * s + 3];
-                const double gsum = gUp + gLo;         // both offsets carry A ox + B oy
-                const double gW = gUp - gLo;
-                const double gAt = gA + gsum * ox, gBt = gB + gsum * oy;
-                gox += gsum * A;
-                goy += gsum * B;
-                const double gnu0 = -gAt / nz, gnu1 = -gBt / nz;
-                const double gnu2 = -(gAt * A + gBt * B + gW * Wd) / nz;
-                for (int c = 0; c < 3; ++c) {
-                    const double gn = (c == 0) ? gnu0 : (c == 1) ? gnu1 : gnu2;
-                    gN[0 + c] += kSlab[s][0] * gn;
-                    gN[3 + c] += kSlab[s][1] * gn;
-                    gN[6 + c] += kSlab[s][2] * gn;
-                }
-            }
-            // N = M^-1:  dL/dM = -N^T dL/dN N^T
-            double T1[9];
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) {
-                    double s = 0.0;
-                    for (int c = 0; c < 3; ++c) s += N[3 * c + a] * gN[3 * c + b];
-                    T1[3 * a + b] = s;     // N^T gN
-                }
-            for (int a = 0; a < 3; ++a)
-                for (int b = 0; b < 3; ++b) {
-                    double s = 0.0;
-                    for (int c = 0; c < 3; ++c) s += T1[3 * a + c] * N[3 * b + c];
-                    // column b of M is a_b: gM[a][b] = dL/d a_b[a]
-                    ga[b][a] = -s;
-                }
-        } else {
-            for (int f = 0; f < 4; ++f) {
-                const double gA = r[3 * f], gB = r[3 * f + 1], gDp = r[3 * f + 2];
-                int m[3], q = 0;
-                for (int k = 0; k < 4; ++k)
-                    if (k != f) m[q++] = k;
-                const double* P0 = G.a[m[0]];
-                const double e1[3] = {G.a[m[1]][0] - P0[0], G.a[m[1]][1] - P0[1], G.a[m[1]][2] - P0[2]};
-                const double e2[3] = {G.a[m[2]][0] - P0[0], G.a[m[2]][1] - P0[1], G.a[m[2]][2] - P0[2]};
-                double nv[3];
-                cross3(e1, e2, nv);
-                const double to_f = nv[0] * (G.a[f][0] - P0[0]) + nv[1] * (G.a[f][1] - P0[1]) + nv[2] * (G.a[f][2] - P0[2]);
-                const double sgn = (to_f > 0.0) ? -1.0 : 1.0;
-                for (int c = 0; c < 3; ++c) nv[c] *= sgn;
-                const double nlen = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
-                const double nz = clamp_nz(nv[2], nlen);
-                const double A = -nv[0] / nz, B = -nv[1] / nz;
-                // D' = P0z - A P0x - B P0y + A ox + B oy
-                const double gAt = gA + gDp * (ox - P0[0]);
-                const double gBt = gB + gDp * (oy - P0[1]);
-                double gP0[3] = {-gDp * A, -gDp * B, gDp};
-                gox += gDp * A;
-                goy += gDp * B;
-                double gn[3] = {-gAt / nz, -gBt / nz, -(gAt * A + gBt * B) / nz};
-                for (int c = 0; c < 3; ++c) gn[c] *= sgn;     // gradient of e1 x e2
-                double ge1[3], ge2[3];
-                cross3(e2, gn, ge1);
-                cross3(gn, e1, ge2);
-                for (int c = 0; c < 3; ++c) {
-                    ga[m[0]][c] += gP0[c] - ge1[c] - ge2[c];
-                    ga[m[1]][c] += ge1[c];
-                    ga[m[2]][c] += ge2[c];
-                }
-            }
-        }
-        // ox = i0 + 1/2 - c_x, oy = j0 + 1/2 - c_y
-        const double gc[3] = {-gox, -goy, 0.0};
-
-        // ---- ray space -> camera: c = phi(t) with d phi/dt = J; a_k = J(t) oc_k
-        const double* J = G.J;
-        const double x = G.tc[0], y = G.tc[1], z = G.tc[2];
-        const double l = G.c[2];
-        double gt[3];
-        for (int c = 0; c < 3; ++c) gt[c] = J[c] * gc[0] + J[3 + c] * gc[1] + J[6 + c] * gc[2];
-        double goc[4][3];
-        for (int k = 0; k < ND; ++k) {
-            for (int c = 0; c < 3; ++c) goc[k][c] = J[c] * ga[k][0] + J[3 + c] * ga[k][1] + J[6 + c] * ga[k][2];
-            const double* w = G.oc[k];
-            const double tw = x * w[0] + y * w[1] + z * w[2];
-            const double l3 = l * l * l, z2 = z * z, z3 = z2 * z;
-            // derivatives of J w with respect to t (rows: output, cols: t)
-            const double d00 = -V.fx * w[2] / z2, d02 = -V.fx * w[0] / z2 + 2.0 * V.fx * x * w[2] / z3;
-            const double d11 = -V.fy * w[2] / z2, d12 = -V.fy * w[1] / z2 + 2.0 * V.fy * y * w[2] / z3;
-            const double d20 = w[0] / l - tw * x / l3, d21 = w[1] / l - tw * y / l3, d22 = w[2] / l - tw * z / l3;
-            gt[0] += d00 * ga[k][0] + d20 * ga[k][2];
-            gt[1] += d11 * ga[k][1] + d21 * ga[k][2];
-            gt[2] += d02 * ga[k][0] + d12 * ga[k][1] + d22 * ga[k][2];
-        }
-        // ---- camera -> world
-        for (int c = 0; c < 3; ++c) gm[c] += V.Rw[c] * gt[0] + V.Rw[3 + c] * gt[1] + V.Rw[6 + c] * gt[2];
-        double gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-        for (int k = 0; k < ND; ++k) {
-            double go[3];
-            for (int c = 0; c < 3; ++c) go[c] = V.Rw[c] * goc[k][0] + V.Rw[3 + c] * goc[k][1] + V.Rw[6 + c] * goc[k][2];
-            if (KIND == LINPRIM_OCTAHEDRON) {
-                const double dk = (double)dists[ND * i + k];
-                double dd = 0.0;
-                for (int rr = 0; rr < 3; ++rr) {
-                    gR[3 * rr + k] += go[rr] * dk;
-                    dd += go[rr] * G.R[3 * rr + k];
-                }
-                gd[k] += dd;
-            } else {
-                const double gk = (double)dists[ND * i + k] * kInvSqrt3;
-                double dd = 0.0;
-                for (int rr = 0; rr < 3; ++rr) {
-                    const double rb = kTetDir[k][0] * G.R[3 * rr] + kTetDir[k][1] * G.R[3 * rr + 1] +
-                                      kTetDir[k][2] * G.R[3 * rr + 2];
-                    for (int c = 0; c < 3; ++c) gR[3 * rr + c] += go[rr] * kTetDir[k][c] * gk;
-                    dd += go[rr] * rb * kInvSqrt3;
-                }
-                gd[k] += dd;
-            }
-        }
-        // ---- rotation -> quaternion through R = I + s K(q), s = 2/|q|^2
-        {
-            const double w = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
-            const double n2 = w * w + qx * qx + qy * qy + qz * qz;
+        float dir[3] = {(float)((double)means[3 * i] - V.cam_pos[0]), (float)((double)means[3 * i + 1] - V.cam_pos[1]),
+                        (float)((double)means[3 * i + 2] - V.cam_pos[2])};
+        const float dn = sqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+        const float idn = 1.0f / dn;
+        for (int q = 0; q < 3; ++q) dir[q] *= idn;
+        float raw[3];
+        sh_raw_f(K, shp, dir[0], dir[1], dir[2], raw);
+        ShBack S;
+        S.K = K;
+        S.sh = shp;
+        S.gsh = gsh;
+        S.gr[0] = raw[0] > 0.0f ? e.x : 0.0f;
+        S.gr[1] = raw[1] > 0.0f ? e.y : 0.0f;
+        S.gr[2] = raw[2] > 0.0f ? e.z : 0.0f;
+        S.gdir[0] = S.gdir[1] = S.gdir[2] = 0.0f;
+        sh_backward(S, dir[0], dir[1], dir[2]);
+        const float dot = S.gdir[0] * dir[0] + S.gdir[1] * dir[1] + S.gdir[2] * dir[2];
+        for (int q = 0; q < 3; ++q) gm[q] += (double)((S.gdir[q] - dot * dir[q]) * idn);
+    }
+    // rotation -> quaternion through R = I + s K(q), s = 2/|q|^2
+    double gq[4] = {0, 0, 0, 0};
+    {
+        const double w = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+        const double n2 = w * w + qx * qx + qy * qy + qz * qz;
+        if (n2 > 0.0) {
             const double s = 2.0 / n2;
             const double Km[9] = {-(qy * qy + qz * qz), qx * qy - w * qz, qx * qz + w * qy,
                                   qx * qy + w * qz, -(qx * qx + qz * qz), qy * qz - w * qx,
@@ -203,75 +400,64 @@ __global__ __launch_bounds__(128) void k_prep_bwd(const float* __restrict__ mean
             double gK = 0.0;
             for (int k = 0; k < 9; ++k) gK += gR[k] * Km[k];
             const double qv[4] = {w, qx, qy, qz};
-            // dK/dw, dK/dx, dK/dy, dK/dz
             const double dK[4][9] = {{0, -qz, qy, qz, 0, -qx, -qy, qx, 0},
                                      {0, qy, qz, qy, -2 * qx, -w, qz, w, -2 * qx},
                                      {-2 * qy, qx, w, qx, 0, qz, -w, qz, -2 * qy},
                                      {-2 * qz, -w, qx, w, -2 * qz, qy, qx, qy, 0}};
+#pragma unroll
             for (int mm = 0; mm < 4; ++mm) {
                 double acc = -s * s * qv[mm] * gK;
                 for (int k = 0; k < 9; ++k) acc += s * gR[k] * dK[mm][k];
-                gq[mm] += acc;
+                gq[mm] = acc;
             }
-        }
-        // ---- Eq. 1 with min(d) held constant
-        {
-            double dmin = (double)dists[ND * i];
-            for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dists[ND * i + k]);
-            const double al = (double)opacity[i];
-            ga_total += r[19] * kAlphaScaleD / ((1.0 - kAlphaScaleD * al) * 2.0 * dmin);
-        }
-        // ---- colour -> SH coefficients and viewing direction
-        {
-            double dir[3] = {(double)means[3 * i] - V.cam_pos[0], (double)means[3 * i + 1] - V.cam_pos[1],
-                             (double)means[3 * i + 2] - V.cam_pos[2]};
-            const double dn = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-            for (int c = 0; c < 3; ++c) dir[c] /= dn;
-            double Y[16], GY[16][3];
-            sh_eval(sh_degree, dir[0], dir[1], dir[2], Y);
-            sh_eval_grad(sh_degree, dir[0], dir[1], dir[2], GY);
-            const float* shp = sh + i * (int64_t)K * 3;
-            double gdir[3] = {0, 0, 0};
-            for (int ch = 0; ch < 3; ++ch) {
-                double raw = 0.5;
-                for (int k = 0; k < K; ++k) raw += (double)shp[3 * k + ch] * Y[k];
-                if (!(raw > 0.0)) continue;
-                const double gr = r[16 + ch];
-                for (int k = 0; k < K; ++k) {
-                    gsh[3 * k + ch] += (float)(gr * Y[k]);
-                    for (int c = 0; c < 3; ++c) gdir[c] += gr * (double)shp[3 * k + ch] * GY[k][c];
-                }
-            }
-            const double dot = gdir[0] * dir[0] + gdir[1] * dir[1] + gdir[2] * dir[2];
-            for (int c = 0; c < 3; ++c) gm[c] += (gdir[c] - dot * dir[c]) / dn;
         }
     }
+    // Eq. 1 with min(d) held constant
+    double dmin = (double)dists[ND * i];
+    for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dists[ND * i + k]);
+    const double al = (double)opacity[i];
+    const double ga = gsig * kAlphaScaleD / ((1.0 - kAlphaScaleD * al) * 2.0 * dmin);
+
     for (int c = 0; c < 3; ++c) g_means[3 * i + c] = (float)gm[c];
     for (int c = 0; c < 4; ++c) g_quats[4 * i + c] = (float)gq[c];
     for (int c = 0; c < ND; ++c) g_dists[ND * i + c] = (float)gd[c];
-    g_opacity[i] = (float)ga_total;
+    g_opacity[i] = (float)ga;
+    float* gs = g_sh + i * (int64_t)K * 3;
+#pragma unroll
+    for (int k = 0; k < 48; ++k)
+        if (k < 3 * K) gs[k] = gsh[k];
 }
 
 hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L,
                                  const char* vws, const PairLayout& P, const char* pws, float* g_means,
                                  float* g_quats, float* g_dists, float* g_opacity, float* g_sh, hipStream_t stream) {
-    (void)tile;
     if (p.n == 0) return hipSuccess;
     const ViewInfo* views = reinterpret_cast<const ViewInfo*>(vws + L.views);
     const float* payload = reinterpret_cast<const float*>(vws + L.payload);
     const uint32_t* tiles = reinterpret_cast<const uint32_t*>(vws + L.tiles);
     const uint32_t* offsets = reinterpret_cast<const uint32_t*>(vws + L.offsets);
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
-    const float* grads = reinterpret_cast<const float*>(pws + P.grads);
-    dim3 grid((unsigned)((p.n + 127) / 128));
-    if (p.type == LINPRIM_OCTAHEDRON)
-        hipLaunchKernelGGL(k_prep_bwd<LINPRIM_OCTAHEDRON>, grid, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity,
-                           p.sh, p.sh_degree, p.n, n_views, views, payload, tiles, offsets, grads, st,
-                           (uint64_t)P.capacity, g_means, g_quats, g_dists, g_opacity, g_sh);
-    else
-        hipLaunchKernelGGL(k_prep_bwd<LINPRIM_TETRAHEDRON>, grid, dim3(128), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.sh, p.sh_degree, p.n, n_views, views, payload, tiles, offsets, grads, st,
-                           (uint64_t)P.capacity, g_means, g_quats, g_dists, g_opacity, g_sh);
+    float* grads = reinterpret_cast<float*>(const_cast<char*>(pws) + P.grads);
+    const int nq = (tile / 8) * (tile / 8);
+    const uint64_t cap = (uint64_t)P.capacity;
+    const int64_t vn = p.n * (int64_t)n_views;
+    hipLaunchKernelGGL(k_sum_records, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, stream, payload, tiles, offsets,
+                       vn, tile, st, cap, grads);
+    const dim3 g1((unsigned)((p.n + 127) / 128), (unsigned)n_views);
+    const dim3 g2((unsigned)((p.n + 127) / 128));
+    if (p.type == LINPRIM_OCTAHEDRON) {
+        hipLaunchKernelGGL(k_slot_bwd<LINPRIM_OCTAHEDRON>, g1, dim3(128), 0, stream, p.means, p.quats, p.dists,
+                           p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap);
+        hipLaunchKernelGGL(k_prim_bwd<LINPRIM_OCTAHEDRON>, g2, dim3(128), 0, stream, p.means, p.quats, p.dists,
+                           p.opacity, p.sh, p.sh_degree, p.n, n_views, views, tiles, offsets, grads, nq, st, cap,
+                           g_means, g_quats, g_dists, g_opacity, g_sh);
+    } else {
+        hipLaunchKernelGGL(k_slot_bwd<LINPRIM_TETRAHEDRON>, g1, dim3(128), 0, stream, p.means, p.quats, p.dists,
+                           p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap);
+        hipLaunchKernelGGL(k_prim_bwd<LINPRIM_TETRAHEDRON>, g2, dim3(128), 0, stream, p.means, p.quats, p.dists,
+                           p.opacity, p.sh, p.sh_degree, p.n, n_views, views, tiles, offsets, grads, nq, st, cap,
+                           g_means, g_quats, g_dists, g_opacity, g_sh);
+    }
     return hipGetLastError();
 }
 

@@ -2,15 +2,17 @@
 // "Compositing") and its backward pass (Sec. 3.4, App. E).
 //
 // Work decomposition (gfx950, wave64):
-//   * one 64-lane wavefront per screen tile; a TILE x TILE tile is split into
-//     (TILE/8)^2 groups of 8 x 8 pixels and lane l owns pixel (l & 7, l >> 3)
-//     of every group;
-//   * the tile's sorted list is walked in order; the primitive index and the
-//     32-dword payload record are wave-uniform and come in through scalar
-//     loads (no LDS staging, no barriers);
-//   * a group is skipped with scalar compares when the primitive's pixel
-//     rectangle misses it, and a pixel is evaluated only inside that
-//     rectangle, so images do not depend on the tile size.
+//   * one 64-lane wavefront per 8 x 8 pixel group; a TILE x TILE screen tile
+//     has (TILE/8)^2 groups, each an independent workgroup; lane l owns pixel
+//     (l & 7, l >> 3) of its group;
+//   * the tile's sorted list is walked in batches of 64 entries: one vector
+//     load brings 64 primitive indices (and, for tiles wider than a group,
+//     their pixel rectangles), a ballot keeps the entries whose rectangle
+//     meets the group, and only those entries' 32-dword payloads are read,
+//     wave-uniform, through scalar loads issued one entry ahead (no LDS, no
+//     barriers);
+//   * a pixel is evaluated only inside the primitive's pixel rectangle, so
+//     images do not depend on the tile size.
 //
 // Chord.  Pixel rays are parallel to the ray-space z axis, so the ray's
 // chord through a convex primitive is max(0, min_up - max_lo): the lowest
@@ -170,6 +172,67 @@ __device__ inline float chord_exp(float s2, float delta) {
 }
 
 // ---------------------------------------------------------------------------
+// Wave placement: wave w handles group q = w % NQ of global tile g = w / NQ.
+// ---------------------------------------------------------------------------
+struct Place {
+    int v, tx, ty, gx0, gy0, W, H, q;
+    int64_t g;
+};
+
+template <int TILE>
+__device__ inline Place place_wave(const ViewInfo* __restrict__ views, int n_views) {
+    constexpr int QX = TILE / 8, NQ = QX * QX;
+    const int64_t w = xcd_tile(blockIdx.x, gridDim.x);
+    Place P;
+    P.g = w / NQ;
+    P.q = (int)(w % NQ);
+    P.v = find_view(views, n_views, P.g);
+    P.W = views[P.v].width;
+    P.H = views[P.v].height;
+    const int tiles_x = views[P.v].tiles_x;
+    const int64_t lt = P.g - views[P.v].tile_base;
+    P.tx = (int)(lt % tiles_x);
+    P.ty = (int)(lt / tiles_x);
+    P.gx0 = P.tx * TILE + (P.q % QX) * 8;
+    P.gy0 = P.ty * TILE + (P.q / QX) * 8;
+    return P;
+}
+
+__device__ inline bool rect_meets_group(int4 r, int gx0, int gy0) {
+    return !(r.x > gx0 + 7 || r.z < gx0 || r.y > gy0 + 7 || r.w < gy0);
+}
+
+// One batch of up to 64 list entries starting at e0: lane l holds entry
+// e0 + l's primitive index (and, if needed, its rectangle / record offset).
+struct Batch {
+    uint32_t idx;
+    uint32_t off;
+    uint64_t mask;     // entries whose pixel rectangle meets the group
+};
+
+template <int NQ, bool WANT_OFF>
+__device__ inline Batch load_batch(const float* __restrict__ base, const uint32_t* __restrict__ vals,
+                                   const uint32_t* __restrict__ offs, uint32_t e0, uint32_t nb, int gx0, int gy0) {
+    const int lane = threadIdx.x;
+    Batch B;
+    B.idx = 0;
+    B.off = 0;
+    bool rel = false;
+    if ((uint32_t)lane < nb) {
+        B.idx = vals[e0 + lane];
+        if (NQ == 1) {
+            rel = true;   // every entry of a group-sized tile meets it
+        } else {
+            const int4 r = *reinterpret_cast<const int4*>(base + (size_t)B.idx * kRecordWords);
+            rel = rect_meets_group(r, gx0, gy0);
+        }
+        if (WANT_OFF) B.off = offs[B.idx];
+    }
+    B.mask = __ballot(rel);
+    return B;
+}
+
+// ---------------------------------------------------------------------------
 // Forward.
 // ---------------------------------------------------------------------------
 template <int TILE, int KIND, bool COUNT>
@@ -182,88 +245,80 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
                                                    unsigned long long* __restrict__ counters) {
     if (status->n_pairs > capacity) return;
     constexpr int QX = TILE / 8, NQ = QX * QX;
-    const int64_t g = xcd_tile(blockIdx.x, gridDim.x);
-    const int v = find_view(views, n_views, g);
-    const int W = views[v].width, H = views[v].height, tiles_x = views[v].tiles_x;
-    const int64_t lt = g - views[v].tile_base;
-    const int tx = (int)(lt % tiles_x), ty = (int)(lt / tiles_x);
+    const Place P = place_wave<TILE>(views, n_views);
+    if (P.gx0 >= P.W || P.gy0 >= P.H) return;
     const int lane = threadIdx.x;
-    const int lx = lane & 7, ly = lane >> 3;
-    const uint2 rg = ranges[g];
-
-    float pxf[NQ], pyf[NQ], T[NQ], C0[NQ], C1[NQ], C2[NQ];
-    int last[NQ];
-    bool done[NQ];
-    uint32_t ev[NQ], hit[NQ], term[NQ];
-    uint32_t alive = 0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int x = tx * TILE + (q % QX) * 8 + lx, y = ty * TILE + (q / QX) * 8 + ly;
-        const bool valid = x < W && y < H;
-        pxf[q] = (float)x;
-        pyf[q] = (float)y;
-        T[q] = 1.0f;
-        C0[q] = C1[q] = C2[q] = 0.0f;
-        last[q] = (int)rg.x;
-        done[q] = !valid;
-        ev[q] = hit[q] = 0;
-        term[q] = rg.y;
-        if (__ballot(valid)) alive |= 1u << q;
-    }
-    const float* base = payload + (size_t)v * (size_t)n * kRecordWords;
-    for (uint32_t e = rg.x; e < rg.y && alive; ++e) {
-        const uint32_t idx = vals[e];
-        Rec R;
-        load_rec<KIND>(base + (size_t)idx * kRecordWords, R);
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            if (!((alive >> q) & 1u)) continue;
-            const int gx0 = tx * TILE + (q % QX) * 8, gy0 = ty * TILE + (q / QX) * 8;
-            if (R.i0 > gx0 + 7 || R.i1 < gx0 || R.j0 > gy0 + 7 || R.j1 < gy0) continue;
-            if (!done[q]) {
-                const float ki = pxf[q] - R.fi0, kj = pyf[q] - R.fj0;
+    const int x = P.gx0 + (lane & 7), y = P.gy0 + (lane >> 3);
+    const bool valid = x < P.W && y < P.H;
+    const float pxf = (float)x, pyf = (float)y;
+    const uint2 rg = ranges[P.g];
+    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
+    int last = (int)rg.x;
+    bool done = !valid;
+    uint32_t ev = 0, hit = 0, term = rg.y;
+    const float* base = payload + (size_t)P.v * (size_t)n * kRecordWords;
+    bool alive = true;
+    Batch nxt = load_batch<NQ, false>(base, vals, nullptr, rg.x, min(64u, rg.y - rg.x), P.gx0, P.gy0);
+    for (uint32_t e0 = rg.x; e0 < rg.y && alive; e0 += 64) {
+        Batch cur = nxt;
+        const uint32_t e1 = e0 + 64;
+        if (e1 < rg.y) nxt = load_batch<NQ, false>(base, vals, nullptr, e1, min(64u, rg.y - e1), P.gx0, P.gy0);
+        uint64_t mask = cur.mask;
+        if (!mask) continue;
+        int b = __builtin_ctzll(mask);
+        Rec Rn;
+        load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)cur.idx, b) * kRecordWords, Rn);
+        while (mask) {
+            const Rec R = Rn;
+            const uint32_t e = e0 + (uint32_t)b;
+            mask &= mask - 1;
+            if (mask) {
+                b = __builtin_ctzll(mask);
+                load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)cur.idx, b) * kRecordWords, Rn);
+            }
+            if (!done) {
+                const float ki = pxf - R.fi0, kj = pyf - R.fj0;
                 if (ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj) {
-                    if (COUNT) ++ev[q];
+                    if (COUNT) ++ev;
                     const float delta = chord_fast<KIND>(R, ki, kj);
                     if (delta > 0.0f) {
-                        if (COUNT) ++hit[q];
+                        if (COUNT) ++hit;
                         const float ex = chord_exp(R.s2, delta);
                         const float onemo = fmaxf(ex, kOneMinusOMax);
-                        const float w = T[q] * (1.0f - onemo);
-                        C0[q] = __builtin_fmaf(w, R.r, C0[q]);
-                        C1[q] = __builtin_fmaf(w, R.g, C1[q]);
-                        C2[q] = __builtin_fmaf(w, R.b, C2[q]);
-                        T[q] = T[q] * onemo;
-                        last[q] = (int)e + 1;
-                        if (T[q] <= kTStop) {
-                            done[q] = true;
-                            term[q] = e + 1;
+                        const float w = T * (1.0f - onemo);
+                        C0 = __builtin_fmaf(w, R.r, C0);
+                        C1 = __builtin_fmaf(w, R.g, C1);
+                        C2 = __builtin_fmaf(w, R.b, C2);
+                        T = T * onemo;
+                        last = (int)e + 1;
+                        if (T <= kTStop) {
+                            done = true;
+                            term = e + 1;
                         }
                     }
                 }
             }
-            if (__ballot(!done[q]) == 0) alive &= ~(1u << q);
+            if (__ballot(!done) == 0) {
+                alive = false;
+                break;
+            }
         }
     }
     unsigned long long c_it = 0, c_ev = 0, c_hit = 0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int x = tx * TILE + (q % QX) * 8 + lx, y = ty * TILE + (q / QX) * 8 + ly;
-        if (x < W && y < H) {
-            const int64_t p = (int64_t)y * W + x;
-            const int64_t pix = views[v].pix_base + p;
-            const int64_t hw = (int64_t)W * H;
-            float* o = out_rgb + 3 * views[v].pix_base;
-            o[p] = C0[q] + T[q] * bg0;
-            o[hw + p] = C1[q] + T[q] * bg1;
-            o[2 * hw + p] = C2[q] + T[q] * bg2;
-            out_T[pix] = T[q];
-            out_last[pix] = last[q];
-            if (COUNT) {
-                c_it += term[q] - rg.x;
-                c_ev += ev[q];
-                c_hit += hit[q];
-            }
+    if (valid) {
+        const int64_t p = (int64_t)y * P.W + x;
+        const int64_t pix = views[P.v].pix_base + p;
+        const int64_t hw = (int64_t)P.W * P.H;
+        float* o = out_rgb + 3 * views[P.v].pix_base;
+        o[p] = C0 + T * bg0;
+        o[hw + p] = C1 + T * bg1;
+        o[2 * hw + p] = C2 + T * bg2;
+        out_T[pix] = T;
+        out_last[pix] = last;
+        if (COUNT) {
+            c_it = term - rg.x;
+            c_ev = ev;
+            c_hit = hit;
         }
     }
     if (COUNT) {
@@ -277,15 +332,18 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
 }
 
 // ---------------------------------------------------------------------------
-// Backward: reverse walk recomputing transmittance, one gradient record of
-// kGradWords floats per (tile, primitive) pair.
+// Backward: reverse walk recomputing transmittance.  One gradient record of
+// kGradWords floats per (tile, primitive) pair and group, at
+// (pair slot) * NQ + q, written for every entry whose rectangle meets the
+// group (zeros if no pixel of the group reached it):
 //   octahedron: [4 s + 0..3] dL/d(A_s, B_s, Dup_s, Dlo_s) for slab s
 //   tetrahedron: [3 f + 0..2] dL/d(A_f, B_f, D_f) for face f
 //   [16..18] dL/d rgb, [19] dL/d sigma
 // ---------------------------------------------------------------------------
-__device__ inline int64_t record_slot(const Rec& R, int tile_shift, int tx, int ty, uint32_t prim_offset) {
+__device__ inline int64_t record_slot(const Rec& R, int tile_shift, int tx, int ty, uint32_t prim_offset, int NQ,
+                                      int q) {
     const int tx0 = R.i0 >> tile_shift, ty0 = R.j0 >> tile_shift, tx1 = R.i1 >> tile_shift;
-    return (int64_t)prim_offset + (int64_t)(ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0);
+    return ((int64_t)prim_offset + (int64_t)(ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0)) * NQ + q;
 }
 
 template <int TILE, int KIND>
@@ -299,142 +357,150 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
     if (status->n_pairs > capacity) return;
     constexpr int QX = TILE / 8, NQ = QX * QX;
     constexpr int SHIFT = (TILE == 8) ? 3 : (TILE == 16) ? 4 : 5;
-    const int64_t g = xcd_tile(blockIdx.x, gridDim.x);
-    const int v = find_view(views, n_views, g);
-    const int W = views[v].width, H = views[v].height, tiles_x = views[v].tiles_x;
-    const int64_t lt = g - views[v].tile_base;
-    const int tx = (int)(lt % tiles_x), ty = (int)(lt / tiles_x);
+    const Place P = place_wave<TILE>(views, n_views);
+    if (P.gx0 >= P.W || P.gy0 >= P.H) return;
     const int lane = threadIdx.x;
-    const int lx = lane & 7, ly = lane >> 3;
-    const uint2 rg = ranges[g];
-    const int64_t hw = (int64_t)W * H;
+    const int x = P.gx0 + (lane & 7), y = P.gy0 + (lane >> 3);
+    const bool valid = x < P.W && y < P.H;
+    const float pxf = (float)x, pyf = (float)y;
+    const uint2 rg = ranges[P.g];
+    const int64_t hw = (int64_t)P.W * P.H;
+    const float* base = payload + (size_t)P.v * (size_t)n * kRecordWords;
+    const uint32_t* offs = offsets + (size_t)P.v * (size_t)n;
 
-    float pxf[NQ], pyf[NQ], T[NQ], B0[NQ], B1[NQ], B2[NQ], G0[NQ], G1[NQ], G2[NQ];
-    int last[NQ];
-    int walk_end = (int)rg.x;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int x = tx * TILE + (q % QX) * 8 + lx, y = ty * TILE + (q / QX) * 8 + ly;
-        const bool valid = x < W && y < H;
-        pxf[q] = (float)x;
-        pyf[q] = (float)y;
-        T[q] = 1.0f;
-        B0[q] = B1[q] = B2[q] = 0.0f;
-        G0[q] = G1[q] = G2[q] = 0.0f;
-        last[q] = (int)rg.x;
-        if (valid) {
-            const int64_t p = (int64_t)y * W + x;
-            const int64_t pix = views[v].pix_base + p;
-            const float* gi = grad_rgb + 3 * views[v].pix_base;
-            T[q] = out_T[pix];
-            // stay inside this tile's list whatever the caller passed
-            last[q] = min(max(out_last[pix], (int)rg.x), (int)rg.y);
-            G0[q] = gi[p];
-            G1[q] = gi[hw + p];
-            G2[q] = gi[2 * hw + p];
-            // colour behind the current step (absolute), starts with T_final bg
-            B0[q] = T[q] * bg0;
-            B1[q] = T[q] * bg1;
-            B2[q] = T[q] * bg2;
+    float T = 1.0f, B0 = 0.0f, B1 = 0.0f, B2 = 0.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
+    int last = (int)rg.x;
+    if (valid) {
+        const int64_t p = (int64_t)y * P.W + x;
+        const int64_t pix = views[P.v].pix_base + p;
+        const float* gi = grad_rgb + 3 * views[P.v].pix_base;
+        T = out_T[pix];
+        // stay inside this tile's list whatever the caller passed
+        last = min(max(out_last[pix], (int)rg.x), (int)rg.y);
+        G0 = gi[p];
+        G1 = gi[hw + p];
+        G2 = gi[2 * hw + p];
+        // colour behind the current step (absolute); starts with T_final bg
+        B0 = T * bg0;
+        B1 = T * bg1;
+        B2 = T * bg2;
+    }
+    const uint32_t walk_end = (uint32_t)wave_max_int(last);
+
+    // zero records of the entries that meet the group but no pixel reached
+    for (uint32_t e0 = walk_end; e0 < rg.y; e0 += 64) {
+        const Batch bt = load_batch<NQ, true>(base, vals, offs, e0, min(64u, rg.y - e0), P.gx0, P.gy0);
+        uint64_t mask = bt.mask;
+        while (mask) {
+            const int b = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const uint32_t idx = (uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b);
+            const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, b);
+            const int4 r = *reinterpret_cast<const int4*>(base + (size_t)idx * kRecordWords);
+            const int tx0 = r.x >> SHIFT, ty0 = r.y >> SHIFT, tx1 = r.z >> SHIFT;
+            const int64_t slot = ((int64_t)off + (int64_t)(P.ty - ty0) * (tx1 - tx0 + 1) + (P.tx - tx0)) * NQ + P.q;
+            if (lane < kGradWords) grads[slot * kGradWords + lane] = 0.0f;
         }
-        walk_end = max(walk_end, last[q]);
-    }
-    walk_end = wave_max_int(walk_end);
-    const float* base = payload + (size_t)v * (size_t)n * kRecordWords;
-    const uint32_t* offs = offsets + (size_t)v * (size_t)n;
-
-    // records of entries no pixel of this tile reached are zero
-    for (uint32_t e = (uint32_t)walk_end; e < rg.y; ++e) {
-        const uint32_t idx = vals[e];
-        Rec R;
-        load_rec<KIND>(base + (size_t)idx * kRecordWords, R);
-        const int64_t slot = record_slot(R, SHIFT, tx, ty, offs[idx]);
-        if (lane < kGradWords) grads[slot * kGradWords + lane] = 0.0f;
     }
 
-    for (int e = walk_end - 1; e >= (int)rg.x; --e) {
-        const uint32_t idx = vals[e];
-        Rec R;
-        load_rec<KIND>(base + (size_t)idx * kRecordWords, R);
-        float acc[kGradWords];
+    for (uint32_t e_hi = walk_end; e_hi > rg.x;) {
+        const uint32_t nb = min(64u, e_hi - rg.x);
+        const uint32_t e0 = e_hi - nb;
+        e_hi = e0;
+        const Batch bt = load_batch<NQ, true>(base, vals, offs, e0, nb, P.gx0, P.gy0);
+        uint64_t mask = bt.mask;
+        if (!mask) continue;
+        int b = 63 - __builtin_clzll(mask);
+        Rec Rn;
+        load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) * kRecordWords, Rn);
+        while (mask) {
+            const Rec R = Rn;
+            const int bcur = b;
+            const uint32_t e = e0 + (uint32_t)bcur;
+            mask &= ~(1ull << bcur);
+            if (mask) {
+                b = 63 - __builtin_clzll(mask);
+                load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) * kRecordWords, Rn);
+            }
+            float acc[kGradWords];
 #pragma unroll
-        for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
-        bool contributed = false;
+            for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
+            bool contributed = false;
+            const float ki = pxf - R.fi0, kj = pyf - R.fj0;
+            if ((int)e < last && ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj) {
+                int ih, il;
+                const float delta = chord<KIND>(R, ki, kj, ih, il);
+                if (delta > 0.0f) {
+                    const float ex = chord_exp(R.s2, delta);
+                    const float onemo = fmaxf(ex, kOneMinusOMax);
+                    const float o = 1.0f - onemo;
+                    const float ro = __builtin_amdgcn_rcpf(onemo);
+                    const float Tk = T * ro;                     // transmittance in front of this primitive
+                    // dC/do = T_k rgb - behind / (1 - o)
+                    const float dLdo = G0 * (Tk * R.r - B0 * ro) + G1 * (Tk * R.g - B1 * ro) +
+                                       G2 * (Tk * R.b - B2 * ro);
+                    const float wk = Tk * o;
+                    acc[16] = G0 * wk;
+                    acc[17] = G1 * wk;
+                    acc[18] = G2 * wk;
+                    B0 += wk * R.r;
+                    B1 += wk * R.g;
+                    B2 += wk * R.b;
+                    T = Tk;
+                    contributed = true;
+                    if (ex >= kOneMinusOMax) {                   // not clamped: o = 1 - exp(-sigma chord)
+                        const float gD = dLdo * R.sigma * ex;    // dL/dchord
+                        acc[19] = dLdo * delta * ex;             // dL/dsigma
+                        if (KIND == LINPRIM_OCTAHEDRON) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-            const int gx0 = tx * TILE + (q % QX) * 8, gy0 = ty * TILE + (q / QX) * 8;
-            if (R.i0 > gx0 + 7 || R.i1 < gx0 || R.j0 > gy0 + 7 || R.j1 < gy0) continue;
-            if (e >= last[q]) continue;
-            const float ki = pxf[q] - R.fi0, kj = pyf[q] - R.fj0;
-            if (!(ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj)) continue;
-            int ih, il;
-            const float delta = chord<KIND>(R, ki, kj, ih, il);
-            if (!(delta > 0.0f)) continue;
-            const float ex = chord_exp(R.s2, delta);
-            const float onemo = fmaxf(ex, kOneMinusOMax);
-            const float o = 1.0f - onemo;
-            const float ro = __builtin_amdgcn_rcpf(onemo);
-            const float Tk = T[q] * ro;                 // transmittance in front of this primitive
-            // dC/do = T_k rgb - behind / (1 - o)
-            const float dLdo = G0[q] * (Tk * R.r - B0[q] * ro) + G1[q] * (Tk * R.g - B1[q] * ro) +
-                               G2[q] * (Tk * R.b - B2[q] * ro);
-            const float wk = Tk * o;
-            acc[16] += G0[q] * wk;
-            acc[17] += G1[q] * wk;
-            acc[18] += G2[q] * wk;
-            B0[q] += wk * R.r;
-            B1[q] += wk * R.g;
-            B2[q] += wk * R.b;
-            T[q] = Tk;
-            contributed = true;
-            if (ex >= kOneMinusOMax) {                   // not clamped: o = 1 - exp(-sigma chord)
-                const float gD = dLdo * R.sigma * ex;    // dL/dchord
-                acc[19] += dLdo * delta * ex;            // dL/dsigma
-                if (KIND == LINPRIM_OCTAHEDRON) {
+                            for (int s = 0; s < 4; ++s) {
+                                const float gh = (ih == s) ? gD : 0.0f;
+                                const float gl = (il == s) ? gD : 0.0f;
+                                const float d = gh - gl;
+                                acc[4 * s + 0] = d * ki;
+                                acc[4 * s + 1] = d * kj;
+                                acc[4 * s + 2] = gh;
+                                acc[4 * s + 3] = -gl;
+                            }
+                        } else {
+                            const int fh = (R.fmap >> (2 * ih)) & 3;
+                            const int fl = (R.fmap >> (2 * (il + 3))) & 3;
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const float gh = (ih == s) ? gD : 0.0f;
-                        const float gl = (il == s) ? gD : 0.0f;
-                        const float d = gh - gl;
-                        acc[4 * s + 0] += d * ki;
-                        acc[4 * s + 1] += d * kj;
-                        acc[4 * s + 2] += gh;
-                        acc[4 * s + 3] -= gl;
-                    }
-                } else {
-                    const int fh = (R.fmap >> (2 * ih)) & 3;
-                    const int fl = (R.fmap >> (2 * (il + 3))) & 3;
-#pragma unroll
-                    for (int f = 0; f < 4; ++f) {
-                        const float d = ((fh == f) ? gD : 0.0f) - ((fl == f) ? gD : 0.0f);
-                        acc[3 * f + 0] += d * ki;
-                        acc[3 * f + 1] += d * kj;
-                        acc[3 * f + 2] += d;
+                            for (int f = 0; f < 4; ++f) {
+                                const float d = ((fh == f) ? gD : 0.0f) - ((fl == f) ? gD : 0.0f);
+                                acc[3 * f + 0] = d * ki;
+                                acc[3 * f + 1] = d * kj;
+                                acc[3 * f + 2] = d;
+                            }
+                        }
                     }
                 }
             }
+            const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, bcur);
+            const int64_t slot = record_slot(R, SHIFT, P.tx, P.ty, off, NQ, P.q);
+            float outv = 0.0f;
+            if (__ballot(contributed) != 0) outv = wave_reduce20(acc, lane);
+            const int ridx = reduce20_index(lane);
+            if (ridx >= 0) grads[slot * kGradWords + ridx] = outv;
         }
-        const int64_t slot = record_slot(R, SHIFT, tx, ty, offs[idx]);
-        float outv = 0.0f;
-        if (__ballot(contributed) != 0) {
-#pragma unroll
-            for (int k = 0; k < kGradWords; ++k) {
-                const float tot = wave_sum(acc[k]);
-                outv = (lane == k) ? tot : outv;
-            }
-        }
-        if (lane < kGradWords) grads[slot * kGradWords + lane] = outv;
     }
 }
 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+template <int TILE>
+static dim3 wave_grid(const ViewLayout& L) {
+    constexpr int NQ = (TILE / 8) * (TILE / 8);
+    return dim3((unsigned)(L.n_tiles_total * NQ));
+}
+
 template <int TILE, int KIND>
-static void fwd_dispatch(bool count, dim3 grid, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
+static void fwd_dispatch(bool count, const ViewLayout& Lv, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
                          const float* payload, const uint32_t* vals, const uint2* ranges, const Status* st,
                          uint64_t cap, const float bg[3], float* rgb, float* T, int32_t* last,
                          unsigned long long* counters) {
+    const dim3 grid = wave_grid<TILE>(Lv);
     if (count)
         hipLaunchKernelGGL((k_render_fwd<TILE, KIND, true>), grid, dim3(64), 0, s, views, nv, n, payload, vals, ranges,
                            st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters);
@@ -454,17 +520,15 @@ hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const Pair
     const uint2* ranges = reinterpret_cast<const uint2*>(vws + L.ranges);
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
     const uint64_t cap = (uint64_t)P.capacity;
-    dim3 grid((unsigned)L.n_tiles_total);
     const bool count = counters != nullptr;
+#define LP_FWD(T_, K_) fwd_dispatch<T_, K_>(count, L, stream, views, n_views, L.n, payload, vals, ranges, st, cap, bg, \
+                                            out_rgb, out_T, out_last, counters)
     if (type == LINPRIM_OCTAHEDRON) {
-        if (tile == 8) fwd_dispatch<8, 0>(count, grid, stream, views, n_views, L.n, payload, vals, ranges, st, cap, bg, out_rgb, out_T, out_last, counters);
-        else if (tile == 16) fwd_dispatch<16, 0>(count, grid, stream, views, n_views, L.n, payload, vals, ranges, st, cap, bg, out_rgb, out_T, out_last, counters);
-        else fwd_dispatch<32, 0>(count, grid, stream, views, n_views, L.n, payload, vals, ranges, st, cap, bg, out_rgb, out_T, out_last, counters);
+        if (tile == 8) LP_FWD(8, 0); else if (tile == 16) LP_FWD(16, 0); else LP_FWD(32, 0);
     } else {
-        if (tile == 8) fwd_dispatch<8, 1>(count, grid, stream, views, n_views, L.n, payload, vals, ranges, st, cap, bg, out_rgb, out_T, out_last, counters);
-        else if (tile == 16) fwd_dispatch<16, 1>(count, grid, stream, views, n_views, L.n, payload, vals, ranges, st, cap, bg, out_rgb, out_T, out_last, counters);
-        else fwd_dispatch<32, 1>(count, grid, stream, views, n_views, L.n, payload, vals, ranges, st, cap, bg, out_rgb, out_T, out_last, counters);
+        if (tile == 8) LP_FWD(8, 1); else if (tile == 16) LP_FWD(16, 1); else LP_FWD(32, 1);
     }
+#undef LP_FWD
     return hipGetLastError();
 }
 
@@ -476,12 +540,12 @@ hipError_t launch_render_fwd(const ViewLayout& L, const char* vws, const PairLay
 }
 
 template <int TILE, int KIND>
-static void bwd_dispatch(dim3 grid, hipStream_t s, const ViewInfo* views, int nv, int64_t n, const float* payload,
-                         const uint32_t* vals, const uint2* ranges, const uint32_t* offsets, const Status* st,
-                         uint64_t cap, const float bg[3], const float* T, const int32_t* last, const float* grad,
-                         float* grads) {
-    hipLaunchKernelGGL((k_render_bwd<TILE, KIND>), grid, dim3(64), 0, s, views, nv, n, payload, vals, ranges, offsets,
-                       st, cap, bg[0], bg[1], bg[2], T, last, grad, grads);
+static void bwd_dispatch(const ViewLayout& Lv, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
+                         const float* payload, const uint32_t* vals, const uint2* ranges, const uint32_t* offsets,
+                         const Status* st, uint64_t cap, const float bg[3], const float* T, const int32_t* last,
+                         const float* grad, float* grads) {
+    hipLaunchKernelGGL((k_render_bwd<TILE, KIND>), wave_grid<TILE>(Lv), dim3(64), 0, s, views, nv, n, payload, vals,
+                       ranges, offsets, st, cap, bg[0], bg[1], bg[2], T, last, grad, grads);
 }
 
 hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLayout& P, char* pws, int result_in_b,
@@ -496,16 +560,14 @@ hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLay
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
     float* grads = reinterpret_cast<float*>(pws + P.grads);
     const uint64_t cap = (uint64_t)P.capacity;
-    dim3 grid((unsigned)L.n_tiles_total);
+#define LP_BWD(T_, K_) bwd_dispatch<T_, K_>(L, stream, views, n_views, L.n, payload, vals, ranges, offsets, st, cap, \
+                                            bg, out_T, out_last, grad_rgb, grads)
     if (type == LINPRIM_OCTAHEDRON) {
-        if (tile == 8) bwd_dispatch<8, 0>(grid, stream, views, n_views, L.n, payload, vals, ranges, offsets, st, cap, bg, out_T, out_last, grad_rgb, grads);
-        else if (tile == 16) bwd_dispatch<16, 0>(grid, stream, views, n_views, L.n, payload, vals, ranges, offsets, st, cap, bg, out_T, out_last, grad_rgb, grads);
-        else bwd_dispatch<32, 0>(grid, stream, views, n_views, L.n, payload, vals, ranges, offsets, st, cap, bg, out_T, out_last, grad_rgb, grads);
+        if (tile == 8) LP_BWD(8, 0); else if (tile == 16) LP_BWD(16, 0); else LP_BWD(32, 0);
     } else {
-        if (tile == 8) bwd_dispatch<8, 1>(grid, stream, views, n_views, L.n, payload, vals, ranges, offsets, st, cap, bg, out_T, out_last, grad_rgb, grads);
-        else if (tile == 16) bwd_dispatch<16, 1>(grid, stream, views, n_views, L.n, payload, vals, ranges, offsets, st, cap, bg, out_T, out_last, grad_rgb, grads);
-        else bwd_dispatch<32, 1>(grid, stream, views, n_views, L.n, payload, vals, ranges, offsets, st, cap, bg, out_T, out_last, grad_rgb, grads);
+        if (tile == 8) LP_BWD(8, 1); else if (tile == 16) LP_BWD(16, 1); else LP_BWD(32, 1);
     }
+#undef LP_BWD
     return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ constexpr double kInvSqrt3 = 0.57735026918962576451;
 constexpr double kLog2e = 1.44269504088896340736;
 constexpr int kMaxViews = 4096;
 constexpr int kRecordWords = 32;          // payload record: 32 x 4 bytes
-constexpr int kGradWords = 20;            // backward record per (tile, primitive) pair
+constexpr int kGradWords = 20;            // backward record per (tile, primitive) pair and 8x8 group
 
 // ----------------------------------------------------------------------------
 // Payload record of one (view, primitive), 32 dwords, written by the
@@ -88,7 +88,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, int tile);
-PairLayout pair_layout(int64_t max_pairs, int digit_bits);
+PairLayout pair_layout(int64_t max_pairs, int digit_bits, int tile);
 int key_tile_bits(int64_t n_tiles_total);
 
 // ----------------------------------------------------------------------------
@@ -114,9 +114,65 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
                                  float* g_quats, float* g_dists, float* g_opacity, float* g_sh,
                                  hipStream_t stream);
 
+struct AdamGroups {
+    float* param[8];
+    const float* grad[8];
+    float* m[8];
+    float* v[8];
+    int64_t start[9];     // prefix of element counts
+    float lr[8];
+    float lo[8], hi[8];   // projection box after the update
+    int count;
+};
+hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,
+                       hipStream_t s);
+hipError_t launch_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad,
+                          float* partial, hipStream_t s);
+
 // ----------------------------------------------------------------------------
 // Device helpers.
 // ----------------------------------------------------------------------------
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline float dpp_mov(float src) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Sums 20 per-lane values over the 64 lanes of a wavefront (every lane must
+// be active).  Reduce-scatter: gfx950's permlane32 / permlane16 swaps pair
+// the two halves and then the two rows of each half, so that register j of
+// row r carries value j + 5 r summed over four lanes; four DPP steps finish
+// each row.  Lane L with k = L % 16 < 5 returns the total of value
+// k + 5 (L / 16) (see reduce20_index); other lanes return 0.
+__device__ inline float wave_reduce20(const float (&v)[20], int lane) {
+    float a[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 10]), false, false);
+        a[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+    float b[5];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[j]), __float_as_uint(a[j + 5]), false, false);
+        b[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        b[j] += dpp_mov<0xB1>(b[j]);     // quad_perm(1,0,3,2)
+        b[j] += dpp_mov<0x4E>(b[j]);     // quad_perm(2,3,0,1)
+        b[j] += dpp_mov<0x141>(b[j]);    // row_half_mirror
+        b[j] += dpp_mov<0x140>(b[j]);    // row_mirror
+    }
+    const int k = lane & 15;
+    return (k == 0) ? b[0] : (k == 1) ? b[1] : (k == 2) ? b[2] : (k == 3) ? b[3] : (k == 4) ? b[4] : 0.0f;
+}
+
+// Which of the 20 totals lane L returns from wave_reduce20 (-1: none).
+__device__ inline int reduce20_index(int lane) {
+    const int k = lane & 15;
+    return k < 5 ? k + 5 * (lane >> 4) : -1;
+}
 
 // Rotation of q / |q| written with s = 2 / |q|^2 (no square root).  The
 // expressions and their left-to-right order are part of the binning

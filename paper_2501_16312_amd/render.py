@@ -33,7 +33,7 @@ class Rasterizer:
         self.n_pairs = 0
 
     def reserve_pairs(self, n_pairs: int):
-        if n_pairs <= self.max_pairs:
+        if n_pairs <= self.max_pairs and self.pair_ws.numel() > 0:
             return
         cap = max(int(n_pairs * self.headroom), n_pairs, 1)
         size = L.linprim_pair_workspace_size(cap, self.cams_c, self.tune)

@@ -321,13 +321,17 @@ def test_config1_finite_differences(oracle_mod):
                 vals.append(float((Op.render_pixels(0, pix)["rgb"] * gsel).sum()))
             fd = (vals[0] - vals[1]) / (2 * h)
             an = float(gg[field][(n,) + comp])
-            if field == "dists" and comp[0] == int(np.argmin(base64["dists"][n])):
+            dn = base64["dists"][n]
+            if field == "dists" and dn[comp[0]] == dn.min():
                 # the GPU holds min(d) of Eq. 1 constant (App. G); central
-                # differences move it: add dL/dsigma dsigma/dmin
+                # differences move it: add dL/dsigma dsigma/dmin, in full when
+                # this distance is the only minimum, half when it ties (then
+                # only the downward step moves the minimum)
                 al = base64["opacity"][n]
-                dmin = base64["dists"][n].min()
+                dmin = dn.min()
                 sig = -math.log(1 - 0.99 * al) / (2 * dmin)
-                an += float(gg["opacity"][n]) / (0.99 / ((1 - 0.99 * al) * 2 * dmin)) * (-sig / dmin)
+                w = 1.0 if np.sum(dn == dmin) == 1 else 0.5
+                an += w * float(gg["opacity"][n]) / (0.99 / ((1 - 0.99 * al) * 2 * dmin)) * (-sig / dmin)
             results.append((field, n, comp, an, fd))
     scale = {f: max(abs(fd) for ff, _, _, _, fd in results if ff == f) for f, _ in plan}
     bad = [(f, n, c, a, d) for f, n, c, a, d in results if abs(a - d) > 2e-2 * max(abs(d), 0.05 * scale[f])]
