@@ -93,6 +93,11 @@ typedef struct linprim_tuning {
 /* Count iterated / evaluated / intersected (pixel, primitive) pairs in
  * render_fwd (slower; for measurements). */
 #define LINPRIM_FLAG_COUNTERS 1
+/* linprim_preprocess does not write the camera table into view_ws: the
+ * caller has done so with linprim_upload_views (e.g. before replaying a
+ * captured graph whose camera poses change between replays; image sizes
+ * must stay the same). */
+#define LINPRIM_FLAG_VIEWS_RESIDENT 2
 
 /* Bytes of the per-view workspace (payloads, counts, offsets, tile ranges,
  * status) for n primitives of `type` over n_views cameras. */
@@ -115,6 +120,13 @@ size_t linprim_pair_workspace_size(int64_t max_pairs, const linprim_camera *cams
  * must be passed to every later call that uses this view_ws. */
 int linprim_preprocess(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
                        const linprim_tuning *tuning, void *view_ws, size_t view_ws_bytes, void *stream);
+
+/* Writes the camera table of `cams` (HOST array) into view_ws, as
+ * linprim_preprocess does unless LINPRIM_FLAG_VIEWS_RESIDENT is set.  The
+ * camera values travel as kernel arguments, so the call is graph-capturable
+ * and the host array may be reused as soon as it returns. */
+int linprim_upload_views(const linprim_camera *cams, int32_t n_views, const linprim_tuning *tuning,
+                         void *view_ws, size_t view_ws_bytes, int64_t n, int32_t type, void *stream);
 
 /* Waits for `stream` and returns the pair count of the last preprocess. */
 int linprim_pair_count(const void *view_ws, int64_t *n_pairs, void *stream);
@@ -208,6 +220,15 @@ typedef struct linprim_adam_group {
 
 int linprim_adam_step(const linprim_adam_group *groups, int32_t n_groups, float beta1, float beta2,
                       float eps, int32_t step, void *stream);
+
+/* As linprim_adam_step, with the bias corrections 1 - beta1^t and
+ * 1 - beta2^t read from DEVICE memory bias_corr[2] when the kernel runs, so
+ * that one captured graph serves every step (the caller updates the two
+ * floats between replays).  linprim_adam_step forms them as
+ * (float)(1.0 - pow((double)beta, (double)t)); values formed the same way
+ * give bit-identical updates. */
+int linprim_adam_step_dev(const linprim_adam_group *groups, int32_t n_groups, float beta1, float beta2,
+                          float eps, const float *bias_corr, void *stream);
 
 /* Waits for `stream`; reports the pair count and whether the last bin_sort
  * overflowed its capacity (HOST outputs). */

@@ -153,10 +153,24 @@ int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, i
     if (int rc = check_device()) return rc;
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)view_ws;
-    hipError_t e = launch_store_views(cams, n_views, tile, reinterpret_cast<ViewInfo*>(ws + L.views), s);
+    hipError_t e = hipSuccess;
+    if (!(tuning && (tuning->flags & LINPRIM_FLAG_VIEWS_RESIDENT)))
+        e = launch_store_views(cams, n_views, tile, reinterpret_cast<ViewInfo*>(ws + L.views), s);
     if (e == hipSuccess) e = launch_preprocess(*prims, n_views, tile, L, ws, s);
     if (e == hipSuccess) e = launch_scan(L, ws, s);
     return hip_status(e);
+}
+
+int linprim_upload_views(const linprim_camera* cams, int32_t n_views, const linprim_tuning* tuning, void* view_ws,
+                         size_t view_ws_bytes, int64_t n, int32_t type, void* stream) {
+    if (!valid_cams(cams, n_views) || !valid_tuning(tuning) || !view_ws || n < 0 ||
+        (type != LINPRIM_OCTAHEDRON && type != LINPRIM_TETRAHEDRON))
+        return LINPRIM_ERR_INVALID_ARG;
+    const int tile = tile_of(tuning);
+    const ViewLayout L = view_layout(n, cams, n_views, tile);
+    if (view_ws_bytes < L.total) return LINPRIM_ERR_WORKSPACE;
+    return hip_status(launch_store_views(cams, n_views, tile,
+                                         reinterpret_cast<ViewInfo*>((char*)view_ws + L.views), (hipStream_t)stream));
 }
 
 int linprim_pair_count(const void* view_ws, int64_t* n_pairs, void* stream) {
@@ -284,9 +298,9 @@ int linprim_l1_grad(const float* rgb, const float* target, int64_t count, float 
     return hip_status(launch_l1_grad(rgb, target, count, scale, grad, partial, (hipStream_t)stream));
 }
 
-int linprim_adam_step(const linprim_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps,
-                      int32_t step, void* stream) {
-    if (!groups || n_groups < 1 || n_groups > 8 || step < 1) return LINPRIM_ERR_INVALID_ARG;
+static int adam_common(const linprim_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps,
+                       int32_t step, const float* bias_corr, void* stream) {
+    if (!groups || n_groups < 1 || n_groups > 8 || (step < 1 && !bias_corr)) return LINPRIM_ERR_INVALID_ARG;
     AdamGroups G;
     memset(&G, 0, sizeof(G));
     G.count = n_groups;
@@ -304,9 +318,20 @@ int linprim_adam_step(const linprim_adam_group* groups, int32_t n_groups, float 
         G.hi[k] = g.hi;
         G.start[k + 1] = G.start[k] + g.numel;
     }
-    const double bc1 = 1.0 - pow((double)beta1, (double)step);
-    const double bc2 = 1.0 - pow((double)beta2, (double)step);
-    return hip_status(launch_adam(G, beta1, beta2, eps, (float)bc1, (float)bc2, (hipStream_t)stream));
+    const double bc1 = bias_corr ? 1.0 : 1.0 - pow((double)beta1, (double)step);
+    const double bc2 = bias_corr ? 1.0 : 1.0 - pow((double)beta2, (double)step);
+    return hip_status(launch_adam(G, beta1, beta2, eps, (float)bc1, (float)bc2, bias_corr, (hipStream_t)stream));
+}
+
+int linprim_adam_step(const linprim_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps,
+                      int32_t step, void* stream) {
+    return adam_common(groups, n_groups, beta1, beta2, eps, step, nullptr, stream);
+}
+
+int linprim_adam_step_dev(const linprim_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps,
+                          const float* bias_corr, void* stream) {
+    if (!bias_corr) return LINPRIM_ERR_INVALID_ARG;
+    return adam_common(groups, n_groups, beta1, beta2, eps, 0, bias_corr, stream);
 }
 
 int linprim_read_status(const void* view_ws, int64_t* pairs_needed, int32_t* overflow, void* stream) {

@@ -35,8 +35,10 @@ __global__ __launch_bounds__(256) void k_l1_grad(const float* __restrict__ rgb, 
 }
 
 // One thread per 4 consecutive elements of the concatenated groups.
-__global__ __launch_bounds__(256) void k_adam(AdamGroups G, float beta1, float beta2, float eps, float bc1,
-                                              float bc2) {
+__global__ __launch_bounds__(256) void k_adam(AdamGroups G, float beta1, float beta2, float eps, float bc1_arg,
+                                              float bc2_arg, const float* __restrict__ bias_corr) {
+    const float bc1 = bias_corr ? bias_corr[0] : bc1_arg;
+    const float bc2 = bias_corr ? bias_corr[1] : bc2_arg;
     const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     if (e0 >= G.start[G.count]) return;
     int gi = 0;
@@ -67,11 +69,11 @@ hipError_t launch_l1_grad(const float* rgb, const float* target, int64_t count, 
 }
 
 hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,
-                       hipStream_t s) {
+                       const float* bias_corr, hipStream_t s) {
     const int64_t total = G.start[G.count];
     if (total <= 0) return hipSuccess;
     const int64_t blocks = (total + 1023) / 1024;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, G, beta1, beta2, eps, bc1, bc2);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, G, beta1, beta2, eps, bc1, bc2, bias_corr);
     return hipGetLastError();
 }
 

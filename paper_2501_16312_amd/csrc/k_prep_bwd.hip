@@ -24,11 +24,11 @@ __device__ inline bool record_exists(int r, int NQ, int QX, int tile, int4 rect,
     return !(rect.x > gx0 + 7 || rect.z < gx0 || rect.y > gy0 + 7 || rect.w < gy0);
 }
 
-// Sums the gradient records of every (view, primitive) into its first
-// record, in record order.  Short runs are summed by one lane; runs longer
-// than a wavefront by the whole wave (lane-strided, then a fixed-order
-// cross-lane sum), so primitives that span thousands of tiles do not hold
-// up a lane.
+// Sums the gradient records of every (view, primitive) with more than 64
+// records into its first record: the whole wavefront strides over the run
+// and then sums across lanes in a fixed order, so primitives that span
+// thousands of tiles do not hold up a lane.  Shorter runs are summed, in
+// record order, by k_slot_bwd.
 __global__ __launch_bounds__(256) void k_sum_records(const float* __restrict__ payload,
                                                      const uint32_t* __restrict__ tiles,
                                                      const uint32_t* __restrict__ offsets, int64_t count, int tile,
@@ -50,28 +50,7 @@ __global__ __launch_bounds__(256) void k_sum_records(const float* __restrict__ p
         }
     }
     const int nrec = (int)cnt * NQ;
-    const bool small = nrec > 0 && nrec <= 64;
-    if (small) {
-        const int tx0 = rect.x >> shift, ty0 = rect.y >> shift, ntx = (rect.z >> shift) - tx0 + 1;
-        float acc[kGradWords];
-        for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
-        const float4* g = reinterpret_cast<const float4*>(grads + (int64_t)off * NQ * kGradWords);
-        for (int r = 0; r < nrec; ++r) {
-            if (NQ > 1 && !record_exists(r, NQ, QX, tile, rect, tx0, ty0, ntx)) continue;
-#pragma unroll
-            for (int k = 0; k < kGradWords / 4; ++k) {
-                const float4 x = g[(int64_t)r * (kGradWords / 4) + k];
-                acc[4 * k] += x.x;
-                acc[4 * k + 1] += x.y;
-                acc[4 * k + 2] += x.z;
-                acc[4 * k + 3] += x.w;
-            }
-        }
-        float4* d = reinterpret_cast<float4*>(grads + (int64_t)off * NQ * kGradWords);
-#pragma unroll
-        for (int k = 0; k < kGradWords / 4; ++k)
-            d[k] = make_float4(acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]);
-    }
+    // runs of up to 64 records are summed by k_slot_bwd itself
     uint64_t big = __ballot(nrec > 64);
     while (big) {
         const int b = __builtin_ctzll(big);
@@ -83,11 +62,28 @@ __global__ __launch_bounds__(256) void k_sum_records(const float* __restrict__ p
         const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
         float acc[kGradWords];
         for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
-        const float* g = grads + (int64_t)o * NQ * kGradWords;
-        for (int r = lane; r < nr; r += 64) {
-            if (NQ > 1 && !record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx)) continue;
+        const float4* g = reinterpret_cast<const float4*>(grads + (int64_t)o * NQ * kGradWords);
+        for (int r0 = lane; r0 < nr; r0 += 128) {
+            // two records per lane per iteration, all ten loads in flight together
+            float4 x[2][kGradWords / 4];
+            bool use[2];
 #pragma unroll
-            for (int k = 0; k < kGradWords; ++k) acc[k] += g[(int64_t)r * kGradWords + k];
+            for (int h = 0; h < 2; ++h) {
+                const int r = r0 + 64 * h;
+                use[h] = r < nr && (NQ == 1 || record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx));
+#pragma unroll
+                for (int k = 0; k < kGradWords / 4; ++k)
+                    x[h][k] = use[h] ? g[(int64_t)r * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int k = 0; k < kGradWords / 4; ++k) {
+                    acc[4 * k] += x[h][k].x;
+                    acc[4 * k + 1] += x[h][k].y;
+                    acc[4 * k + 2] += x[h][k].z;
+                    acc[4 * k + 3] += x[h][k].w;
+                }
         }
         const float outv = wave_reduce20(acc, lane);
         const int ridx = reduce20_index(lane);
@@ -100,7 +96,7 @@ __global__ __launch_bounds__(256) void k_sum_records(const float* __restrict__ p
 // dY_k/ddir.  The basis polynomials are those of sh_eval.
 struct ShBack {
     int K;
-    const float* sh;
+    const float* sh;     // [48] coefficients (registers)
     float* gsh;          // [48] accumulators
     float gr[3];
     float gdir[3];
@@ -192,19 +188,40 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     const int64_t i = slot;
     constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
     float4* rp = reinterpret_cast<float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
-    float r[16];
+    const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
+    const int nrec = (int)tiles[vs] * nq;
+    float r[kGradWords];
+    if (nrec <= 64) {
+        // sum the run in record order (skipping groups the rectangle misses)
+        const int qx = (nq == 1) ? 1 : (nq == 4) ? 2 : 4, tile = 8 * qx;
+        const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
+        const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float4 x = rp[k];
-        r[4 * k] = x.x;
-        r[4 * k + 1] = x.y;
-        r[4 * k + 2] = x.z;
-        r[4 * k + 3] = x.w;
+        for (int k = 0; k < kGradWords; ++k) r[k] = 0.0f;
+        for (int q = 0; q < nrec; ++q) {
+            if (nq > 1 && !record_exists(q, nq, qx, tile, rc, tx0, ty0, ntx)) continue;
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k) {
+                const float4 x = rp[q * (kGradWords / 4) + k];
+                r[4 * k] += x.x;
+                r[4 * k + 1] += x.y;
+                r[4 * k + 2] += x.z;
+                r[4 * k + 3] += x.w;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kGradWords / 4; ++k) {
+            const float4 x = rp[k];
+            r[4 * k] = x.x;
+            r[4 * k + 1] = x.y;
+            r[4 * k + 2] = x.z;
+            r[4 * k + 3] = x.w;
+        }
     }
     const ViewInfo& V = views[v];
     Geom G;
     if (!build_geometry(KIND, means + 3 * i, quats + 4 * i, dists + ND * i, opacity[i], V, G)) return;
-    const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
     const double ox = (double)rc.x + 0.5 - G.c[0];
     const double oy = (double)rc.y + 0.5 - G.c[1];
 
@@ -328,6 +345,7 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     rp[1] = make_float4((float)gR[1], (float)gR[2], (float)gR[3], (float)gR[4]);
     rp[2] = make_float4((float)gR[5], (float)gR[6], (float)gR[7], (float)gR[8]);
     rp[3] = make_float4((float)gd[0], (float)gd[1], (float)gd[2], (float)gd[3]);
+    rp[4] = make_float4(r[16], r[17], r[18], r[19]);
 }
 
 // ---------------------------------------------------------------------------
@@ -335,10 +353,10 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
 // quaternion, Eq. 1 -> opacity (min d held constant), colour -> SH and the
 // viewing direction.  Outputs are overwritten.
 // ---------------------------------------------------------------------------
-template <int KIND>
+template <int KIND, int DEG>
 __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ means, const float* __restrict__ quats,
                                                   const float* __restrict__ dists, const float* __restrict__ opacity,
-                                                  const float* __restrict__ sh, int sh_degree, int64_t n, int n_views,
+                                                  const float* __restrict__ sh, int64_t n, int n_views,
                                                   const ViewInfo* __restrict__ views,
                                                   const uint32_t* __restrict__ tiles,
                                                   const uint32_t* __restrict__ offsets, const float* __restrict__ grads,
@@ -346,19 +364,27 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
                                                   float* __restrict__ g_means, float* __restrict__ g_quats,
                                                   float* __restrict__ g_dists, float* __restrict__ g_opacity,
                                                   float* __restrict__ g_sh) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    __shared__ float stage[128 * 48];
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t i = i0 + threadIdx.x;
     constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
-    const int K = (sh_degree + 1) * (sh_degree + 1);
-    const bool ok = status->n_pairs <= capacity;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const bool ok = status->n_pairs <= capacity && i < n;
     double gm[3] = {0, 0, 0}, gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gd[4] = {0, 0, 0, 0}, gsig = 0.0;
     float gsh[48];
 #pragma unroll
     for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
-    const float* shp = sh + i * (int64_t)K * 3;
+    float shp[48];
+    bool seen = false;
+    bool sh_loaded = false;
     for (int v = 0; ok && v < n_views; ++v) {
         const int64_t vs = (int64_t)v * n + i;
         if (tiles[vs] == 0) continue;
+        seen = true;
+        if (!sh_loaded) {
+            load_sh<DEG>(sh + i * (int64_t)K * 3, shp);
+            sh_loaded = true;
+        }
         const float4* rp = reinterpret_cast<const float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
         const float4 a = rp[0], b = rp[1], c = rp[2], d = rp[3], e = rp[4];
         gm[0] += a.x; gm[1] += a.y; gm[2] += a.z;
@@ -389,7 +415,7 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
     }
     // rotation -> quaternion through R = I + s K(q), s = 2/|q|^2
     double gq[4] = {0, 0, 0, 0};
-    {
+    if (seen) {
         const double w = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
         const double n2 = w * w + qx * qx + qy * qy + qz * qz;
         if (n2 > 0.0) {
@@ -413,19 +439,28 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
         }
     }
     // Eq. 1 with min(d) held constant
-    double dmin = (double)dists[ND * i];
-    for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dists[ND * i + k]);
-    const double al = (double)opacity[i];
-    const double ga = gsig * kAlphaScaleD / ((1.0 - kAlphaScaleD * al) * 2.0 * dmin);
-
-    for (int c = 0; c < 3; ++c) g_means[3 * i + c] = (float)gm[c];
-    for (int c = 0; c < 4; ++c) g_quats[4 * i + c] = (float)gq[c];
-    for (int c = 0; c < ND; ++c) g_dists[ND * i + c] = (float)gd[c];
-    g_opacity[i] = (float)ga;
-    float* gs = g_sh + i * (int64_t)K * 3;
+    double ga = 0.0;
+    if (seen) {
+        double dmin = (double)dists[ND * i];
+        for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dists[ND * i + k]);
+        const double al = (double)opacity[i];
+        ga = gsig * kAlphaScaleD / ((1.0 - kAlphaScaleD * al) * 2.0 * dmin);
+    }
+    if (i < n) {
+        for (int c = 0; c < 3; ++c) g_means[3 * i + c] = (float)gm[c];
+        for (int c = 0; c < 4; ++c) g_quats[4 * i + c] = (float)gq[c];
+        for (int c = 0; c < ND; ++c) g_dists[ND * i + c] = (float)gd[c];
+        g_opacity[i] = (float)ga;
+    }
+    // SH gradients: stage the block's [128][3K] slab in LDS, store coalesced
+    const int w3 = 3 * K;
 #pragma unroll
     for (int k = 0; k < 48; ++k)
-        if (k < 3 * K) gs[k] = gsh[k];
+        if (k < w3) stage[threadIdx.x * w3 + k] = gsh[k];
+    __syncthreads();
+    const int64_t rows = (n - i0) < 128 ? (n - i0) : 128;
+    float* gs = g_sh + i0 * (int64_t)w3;
+    for (int64_t j = threadIdx.x; j < rows * w3; j += 128) gs[j] = stage[j];
 }
 
 hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L,
@@ -445,19 +480,28 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
                        vn, tile, st, cap, grads);
     const dim3 g1((unsigned)((p.n + 127) / 128), (unsigned)n_views);
     const dim3 g2((unsigned)((p.n + 127) / 128));
+#define LP_PRIM(K_, D_)                                                                                        \
+    hipLaunchKernelGGL((k_prim_bwd<K_, D_>), g2, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, p.sh, \
+                       p.n, n_views, views, tiles, offsets, grads, nq, st, cap, g_means, g_quats, g_dists, g_opacity, \
+                       g_sh)
+#define LP_PRIM_DEG(K_)                      \
+    switch (p.sh_degree) {                   \
+        case 0: LP_PRIM(K_, 0); break;       \
+        case 1: LP_PRIM(K_, 1); break;       \
+        case 2: LP_PRIM(K_, 2); break;       \
+        default: LP_PRIM(K_, 3); break;      \
+    }
     if (p.type == LINPRIM_OCTAHEDRON) {
         hipLaunchKernelGGL(k_slot_bwd<LINPRIM_OCTAHEDRON>, g1, dim3(128), 0, stream, p.means, p.quats, p.dists,
                            p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap);
-        hipLaunchKernelGGL(k_prim_bwd<LINPRIM_OCTAHEDRON>, g2, dim3(128), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.sh, p.sh_degree, p.n, n_views, views, tiles, offsets, grads, nq, st, cap,
-                           g_means, g_quats, g_dists, g_opacity, g_sh);
+        LP_PRIM_DEG(LINPRIM_OCTAHEDRON)
     } else {
         hipLaunchKernelGGL(k_slot_bwd<LINPRIM_TETRAHEDRON>, g1, dim3(128), 0, stream, p.means, p.quats, p.dists,
                            p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap);
-        hipLaunchKernelGGL(k_prim_bwd<LINPRIM_TETRAHEDRON>, g2, dim3(128), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.sh, p.sh_degree, p.n, n_views, views, tiles, offsets, grads, nq, st, cap,
-                           g_means, g_quats, g_dists, g_opacity, g_sh);
+        LP_PRIM_DEG(LINPRIM_TETRAHEDRON)
     }
+#undef LP_PRIM_DEG
+#undef LP_PRIM
     return hipGetLastError();
 }
 

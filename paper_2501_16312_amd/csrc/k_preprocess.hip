@@ -50,10 +50,10 @@ hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int t
 
 // One thread per (primitive, view).  Writes the 32-dword payload record,
 // the depth key and the tile count.
-template <int KIND>
+template <int KIND, int DEG>
 __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ means, const float* __restrict__ quats,
                                                     const float* __restrict__ dists, const float* __restrict__ opacity,
-                                                    const float* __restrict__ sh, int sh_degree, int64_t n,
+                                                    const float* __restrict__ sh, int64_t n,
                                                     const ViewInfo* __restrict__ views, int tile_shift,
                                                     float* __restrict__ payload, uint32_t* __restrict__ depth_keys,
                                                     uint32_t* __restrict__ tiles) {
@@ -87,14 +87,17 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
     double dz = (double)means[3 * i + 2] - V.cam_pos[2];
     const double dn = sqrt(dx * dx + dy * dy + dz * dz);
     dx /= dn; dy /= dn; dz /= dn;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    float shv[48];
+    load_sh<DEG>(sh + (int64_t)i * K * 3, shv);
     double Y[16];
-    sh_eval(sh_degree, dx, dy, dz, Y);
-    const int K = (sh_degree + 1) * (sh_degree + 1);
-    const float* shp = sh + (int64_t)i * K * 3;
+    sh_eval(DEG, dx, dy, dz, Y);
     float rgb[3];
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
         double acc = 0.0;
-        for (int k = 0; k < K; ++k) acc += (double)shp[3 * k + c] * Y[k];
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc += (double)shv[3 * k + c] * Y[k];
         rgb[c] = (float)fmax(acc + 0.5, 0.0);
     }
 
@@ -193,12 +196,23 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
     float* payload = reinterpret_cast<float*>(ws + L.payload);
     uint32_t* keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
     uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
-    if (p.type == LINPRIM_OCTAHEDRON)
-        hipLaunchKernelGGL(k_preprocess<LINPRIM_OCTAHEDRON>, grid, dim3(256), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.sh, p.sh_degree, p.n, views, shift, payload, keys, tiles);
-    else
-        hipLaunchKernelGGL(k_preprocess<LINPRIM_TETRAHEDRON>, grid, dim3(256), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.sh, p.sh_degree, p.n, views, shift, payload, keys, tiles);
+#define LP_PRE(K_, D_)                                                                                        \
+    hipLaunchKernelGGL((k_preprocess<K_, D_>), grid, dim3(256), 0, stream, p.means, p.quats, p.dists, p.opacity, \
+                       p.sh, p.n, views, shift, payload, keys, tiles)
+#define LP_PRE_DEG(K_)                      \
+    switch (p.sh_degree) {                  \
+        case 0: LP_PRE(K_, 0); break;       \
+        case 1: LP_PRE(K_, 1); break;       \
+        case 2: LP_PRE(K_, 2); break;       \
+        default: LP_PRE(K_, 3); break;      \
+    }
+    if (p.type == LINPRIM_OCTAHEDRON) {
+        LP_PRE_DEG(LINPRIM_OCTAHEDRON)
+    } else {
+        LP_PRE_DEG(LINPRIM_TETRAHEDRON)
+    }
+#undef LP_PRE_DEG
+#undef LP_PRE
     return hipGetLastError();
 }
 

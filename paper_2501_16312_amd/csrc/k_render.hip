@@ -51,14 +51,17 @@ __device__ inline int wave_max_int(int v) {
     return v;
 }
 
-// Round-robin dispatch puts consecutive workgroups on different XCDs; map
-// them so that each XCD walks a contiguous run of tiles (neighbouring tiles
-// share primitives, and each XCD has its own L2).
+// Round-robin dispatch puts consecutive workgroups on different XCDs.  Deal
+// out chunks of kXcdChunk consecutive waves (neighbouring tiles, which share
+// primitives) round-robin instead, so each XCD's L2 sees whole chunks while
+// every XCD still gets a spread of the image (tiles differ a lot in work).
+constexpr int64_t kXcdChunk = 32;
 __device__ inline int64_t xcd_tile(int64_t b, int64_t nb) {
     constexpr int64_t X = 8;
-    const int64_t per = nb / X, rem = nb % X;
-    const int64_t x = b % X, loc = b / X;
-    return (x < rem) ? x * (per + 1) + loc : rem * (per + 1) + (x - rem) * per + loc;
+    const int64_t full = (nb / (X * kXcdChunk)) * (X * kXcdChunk);
+    if (b >= full) return b;
+    const int64_t x = b % X, k = b / X;
+    return ((k / kXcdChunk) * X + x) * kXcdChunk + (k % kXcdChunk);
 }
 
 __device__ inline int find_view(const ViewInfo* __restrict__ views, int n_views, int64_t g) {

@@ -21,27 +21,52 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
+    const int lane = threadIdx.x & 63;
     const uint64_t npairs = status->n_pairs;
     if (npairs > capacity) {
         if (i == 0 && v == 0) status->overflow = 1;
         return;
     }
-    if (i >= n) return;
-    const int64_t slot = (int64_t)v * n + i;
-    const uint32_t cnt = tiles[slot];
-    if (cnt == 0) return;
-    const int4 r = reinterpret_cast<const int4*>(payload + slot * kRecordWords)[0];
     const ViewInfo& V = views[v];
-    const uint32_t key = depth_keys[slot];
-    uint64_t out = offsets[slot];
+    const int64_t slot = (int64_t)v * n + i;
+    uint32_t cnt = 0;
+    int4 r = make_int4(0, 0, 0, 0);
+    uint32_t key = 0, off = 0;
+    if (i < n) {
+        cnt = tiles[slot];
+        if (cnt) {
+            r = reinterpret_cast<const int4*>(payload + slot * kRecordWords)[0];
+            key = depth_keys[slot];
+            off = offsets[slot];
+        }
+    }
     const int tx0 = r.x >> tile_shift, ty0 = r.y >> tile_shift;
-    const int tx1 = r.z >> tile_shift, ty1 = r.w >> tile_shift;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        for (int tx = tx0; tx <= tx1; ++tx) {
+    const int ntx = (r.z >> tile_shift) - tx0 + 1;
+    // short runs: one lane writes them in row-major tile order
+    if (cnt > 0 && cnt <= 32) {
+        for (uint32_t t = 0; t < cnt; ++t) {
+            const int tx = tx0 + (int)(t % ntx), ty = ty0 + (int)(t / ntx);
             const uint64_t g = (uint64_t)(V.tile_base + (int64_t)ty * V.tiles_x + tx);
-            keys[out] = (g << 32) | key;
-            vals[out] = (uint32_t)i;
-            ++out;
+            keys[off + t] = (g << 32) | key;
+            vals[off + t] = (uint32_t)i;
+        }
+    }
+    // long runs (near or large primitives): the whole wavefront writes them
+    uint64_t big = __ballot(cnt > 32);
+    while (big) {
+        const int b = __builtin_ctzll(big);
+        big &= big - 1;
+        const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cnt, b);
+        const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, b);
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, b);
+        const int bx0 = __builtin_amdgcn_readlane(tx0, b), by0 = __builtin_amdgcn_readlane(ty0, b);
+        const int bn = __builtin_amdgcn_readlane(ntx, b);
+        const uint32_t idx = (uint32_t)(i - (threadIdx.x & 63) + b);
+        for (uint32_t t = (uint32_t)lane; t < c; t += 64) {
+            const int tx = bx0 + (int)(t % bn), ty = by0 + (int)(t / bn);
+            const uint64_t g = (uint64_t)(V.tile_base + (int64_t)ty * V.tiles_x + tx);
+            keys[o + t] = (g << 32) | k;
+            vals[o + t] = idx;
         }
     }
 }

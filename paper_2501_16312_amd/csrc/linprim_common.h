@@ -82,7 +82,7 @@ struct PairLayout {
 
 constexpr int kScanItems = 4096;     // elements per scan block (256 threads x 16)
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;       // keys per thread per sort block
+constexpr int kSortItems = 4;        // keys per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -125,7 +125,7 @@ struct AdamGroups {
     int count;
 };
 hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,
-                       hipStream_t s);
+                       const float* bias_corr, hipStream_t s);
 hipError_t launch_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad,
                           float* partial, hipStream_t s);
 
@@ -372,6 +372,27 @@ __device__ inline void sh_eval_grad(int deg, double x, double y, double z, doubl
         G[14][0] = 2.0 * K.c3e * x * z; G[14][1] = -2.0 * K.c3e * y * z; G[14][2] = K.c3e * (x * x - y * y);
         G[15][0] = -K.c3a * (3.0 * x * x - 3.0 * y * y);
         G[15][1] = 6.0 * K.c3a * x * y;
+    }
+}
+
+// Loads the (DEG+1)^2 x 3 SH coefficients of one primitive into registers,
+// every load issued before the first use (16-byte loads for degree 3).
+template <int DEG>
+__device__ inline void load_sh(const float* __restrict__ p, float out[48]) {
+    constexpr int NF = 3 * (DEG + 1) * (DEG + 1);
+    if (NF % 4 == 0) {
+        const float4* p4 = reinterpret_cast<const float4*>(p);
+#pragma unroll
+        for (int k = 0; k < NF / 4; ++k) {
+            const float4 x = p4[k];
+            out[4 * k] = x.x;
+            out[4 * k + 1] = x.y;
+            out[4 * k + 2] = x.z;
+            out[4 * k + 3] = x.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < NF; ++k) out[k] = p[k];
     }
 }
 

@@ -12,6 +12,7 @@ import ctypes
 import os
 from typing import List, Optional, Sequence
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +29,7 @@ ERR_HIP = -4
 ERR_DEVICE = -5
 
 FLAG_COUNTERS = 1
+FLAG_VIEWS_RESIDENT = 2
 
 
 class linprim_prims(ctypes.Structure):
@@ -47,10 +49,17 @@ class linprim_tuning(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class linprim_adam_group(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("exp_avg", ctypes.c_void_p),
+                ("exp_avg_sq", ctypes.c_void_p), ("numel", ctypes.c_int64), ("lr", ctypes.c_float),
+                ("lo", ctypes.c_float), ("hi", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
 EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linprim_preprocess",
            "linprim_pair_count", "linprim_bin_sort", "linprim_render_fwd", "linprim_render_fwd_counted",
            "linprim_render_bwd", "linprim_raster_bwd", "linprim_preprocess_bwd", "linprim_read_status",
-           "linprim_strerror", "linprim_debug_pointers")
+           "linprim_strerror", "linprim_debug_pointers", "linprim_upload_views", "linprim_l1_grad",
+           "linprim_adam_step", "linprim_adam_step_dev")
 
 _lib = None
 
@@ -76,6 +85,12 @@ def load(path: str = LIB_PATH):
     lib.linprim_pair_workspace_size.argtypes = [I64, cm, I32, tu]
     lib.linprim_preprocess.argtypes = [pr, cm, I32, tu, P, SZ, P]
     lib.linprim_pair_count.argtypes = [P, ctypes.POINTER(I64), P]
+    lib.linprim_upload_views.argtypes = [cm, I32, tu, P, SZ, I64, I32, P]
+    lib.linprim_l1_grad.argtypes = [P, P, I64, ctypes.c_float, P, P, P]
+    lib.linprim_adam_step.argtypes = [ctypes.POINTER(linprim_adam_group), I32, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, I32, P]
+    lib.linprim_adam_step_dev.argtypes = [ctypes.POINTER(linprim_adam_group), I32, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_float, P, P]
     lib.linprim_bin_sort.argtypes = [pr, cm, I32, tu, P, SZ, P, SZ, I64, P]
     lib.linprim_render_fwd.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ, I64,
                                        P, P, P, P]
@@ -92,7 +107,8 @@ def load(path: str = LIB_PATH):
     lib.linprim_debug_pointers.argtypes = [pr, cm, I32, tu, P, P, I64] + [ctypes.POINTER(P)] * 7
     for f in (lib.linprim_preprocess, lib.linprim_pair_count, lib.linprim_bin_sort, lib.linprim_render_fwd,
               lib.linprim_render_fwd_counted, lib.linprim_render_bwd, lib.linprim_raster_bwd,
-              lib.linprim_preprocess_bwd, lib.linprim_read_status,
+              lib.linprim_preprocess_bwd, lib.linprim_read_status, lib.linprim_upload_views,
+              lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev,
               lib.linprim_debug_pointers):
         f.restype = ctypes.c_int
     _lib = lib
@@ -182,6 +198,54 @@ def linprim_preprocess(prims: Prims, cams, tune, view_ws: torch.Tensor, stream=N
     p = prims.c()
     _check(load().linprim_preprocess(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _ptr(view_ws),
                                      view_ws.numel(), _stream(stream)), "linprim_preprocess")
+
+
+def linprim_upload_views(cams, tune, view_ws, n: int, kind: int, stream=None):
+    _check(load().linprim_upload_views(cams, len(cams), ctypes.byref(tune), _ptr(view_ws), view_ws.numel(), n, kind,
+                                       _stream(stream)), "linprim_upload_views")
+
+
+def linprim_l1_grad(rgb, target, scale: float, grad, partial, stream=None):
+    _check(load().linprim_l1_grad(_ptr(rgb), _ptr(target), rgb.numel(), float(scale), _ptr(grad), _ptr(partial),
+                                  _stream(stream)), "linprim_l1_grad")
+
+
+def _adam_groups(groups: list):
+    arr = (linprim_adam_group * len(groups))()
+    for k, g in enumerate(groups):
+        arr[k].param = g["param"].data_ptr()
+        arr[k].grad = g["grad"].data_ptr()
+        arr[k].exp_avg = g["exp_avg"].data_ptr()
+        arr[k].exp_avg_sq = g["exp_avg_sq"].data_ptr()
+        arr[k].numel = g["param"].numel()
+        arr[k].lr = float(g["lr"])
+        arr[k].lo = float(g.get("lo", float("-inf")))
+        arr[k].hi = float(g.get("hi", float("inf")))
+    return arr
+
+
+def linprim_adam_step(groups: list, beta1: float, beta2: float, eps: float, step: int, stream=None):
+    """groups: list of dicts param, grad, exp_avg, exp_avg_sq (CUDA float32
+    tensors of equal size), lr, and optional lo / hi projection bounds."""
+    arr = _adam_groups(groups)
+    _check(load().linprim_adam_step(arr, len(groups), float(beta1), float(beta2), float(eps), int(step),
+                                    _stream(stream)), "linprim_adam_step")
+
+
+def adam_bias_corrections(beta1: float, beta2: float, step: int):
+    """(1 - beta1^t, 1 - beta2^t) as float32, formed exactly as
+    linprim_adam_step forms them (the float32 betas widened to double, the
+    power and difference in double, one rounding to float32), so that a
+    linprim_adam_step_dev fed these values updates bit-identically."""
+    b1 = float(np.float32(beta1))
+    b2 = float(np.float32(beta2))
+    return np.float32(1.0 - b1 ** int(step)), np.float32(1.0 - b2 ** int(step))
+
+
+def linprim_adam_step_dev(groups: list, beta1: float, beta2: float, eps: float, bias_corr, stream=None):
+    arr = _adam_groups(groups)
+    _check(load().linprim_adam_step_dev(arr, len(groups), float(beta1), float(beta2), float(eps), _ptr(bias_corr),
+                                        _stream(stream)), "linprim_adam_step_dev")
 
 
 def linprim_pair_count(view_ws: torch.Tensor, stream=None) -> int:
