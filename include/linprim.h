@@ -206,7 +206,15 @@ int linprim_l1_grad(const float *rgb, const float *target, int64_t count, float 
  * p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps), then p is clamped to
  * [lo, hi] (use -inf/+inf for none; e.g. distances stay positive and
  * opacities inside [0, 1]).  groups: HOST array; the tensors are DEVICE
- * float32 arrays of `numel` elements; step t >= 1. */
+ * float32 arrays of `numel` elements; step t >= 1.
+ *
+ * period > 0 gives a group two learning rates: element i uses lr_tail when
+ * (i mod period) >= head, else lr.  With the SH array [N][16][3] as one
+ * group, period 48 and head 3 give the colour (degree-0) coefficients and
+ * the higher-degree ones the separate rates of the learning-rate table in
+ * App. G.  period 0 (head, lr_tail ignored): every element uses lr.
+ * Errors: INVALID_ARG for n_groups outside [1, 8], numel < 0, a null array
+ * with numel > 0, head outside [0, period]. */
 typedef struct linprim_adam_group {
     float *param;
     const float *grad;
@@ -215,7 +223,9 @@ typedef struct linprim_adam_group {
     int64_t numel;
     float lr;
     float lo, hi;
-    int32_t reserved;
+    int32_t period;
+    float lr_tail;
+    int32_t head;
 } linprim_adam_group;
 
 int linprim_adam_step(const linprim_adam_group *groups, int32_t n_groups, float beta1, float beta2,

@@ -29,8 +29,9 @@ def l1_grad(rgb, target, scale: float):
 
 def adam_step(param, grad, exp_avg, exp_avg_sq, step: int, lr: float, beta1: float, beta2: float, eps: float,
               lo: float = -np.inf, hi: float = np.inf):
-    """One Adam update at step t = `step` (>= 1).  Returns new
-    (param, exp_avg, exp_avg_sq) as float64 arrays; inputs are not modified."""
+    """One Adam update at step t = `step` (>= 1); `lr` is a scalar or one rate
+    per element.  Returns new (param, exp_avg, exp_avg_sq) as float64 arrays;
+    inputs are not modified."""
     p = np.array(param, dtype=np.float64)
     g = np.asarray(grad, dtype=np.float64)
     m = beta1 * np.asarray(exp_avg, dtype=np.float64) + (1.0 - beta1) * g

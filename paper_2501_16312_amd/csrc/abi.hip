@@ -304,20 +304,29 @@ static int adam_common(const linprim_adam_group* groups, int32_t n_groups, float
     AdamGroups G;
     memset(&G, 0, sizeof(G));
     G.count = n_groups;
-    G.start[0] = 0;
+    G.block0[0] = 0;
+    const int64_t per_block = 256 * 4;
+    auto aligned = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
     for (int k = 0; k < n_groups; ++k) {
         const linprim_adam_group& g = groups[k];
         if (g.numel < 0 || (g.numel > 0 && (!g.param || !g.grad || !g.exp_avg || !g.exp_avg_sq)))
             return LINPRIM_ERR_INVALID_ARG;
+        if (g.period < 0 || (g.period > 0 && (g.head < 0 || g.head > g.period))) return LINPRIM_ERR_INVALID_ARG;
         G.param[k] = g.param;
         G.grad[k] = g.grad;
         G.m[k] = g.exp_avg;
         G.v[k] = g.exp_avg_sq;
+        G.numel[k] = g.numel;
         G.lr[k] = g.lr;
+        G.lr_tail[k] = g.lr_tail;
+        G.period[k] = g.period;
+        G.head[k] = g.head;
         G.lo[k] = g.lo;
         G.hi[k] = g.hi;
-        G.start[k + 1] = G.start[k] + g.numel;
+        G.vec[k] = aligned(g.param) && aligned(g.grad) && aligned(g.exp_avg) && aligned(g.exp_avg_sq);
+        G.block0[k + 1] = G.block0[k] + (g.numel + per_block - 1) / per_block;
     }
+    if (G.block0[n_groups] > 0x7fffffffLL) return LINPRIM_ERR_INVALID_ARG;
     const double bc1 = bias_corr ? 1.0 : 1.0 - pow((double)beta1, (double)step);
     const double bc2 = bias_corr ? 1.0 : 1.0 - pow((double)beta2, (double)step);
     return hip_status(launch_adam(G, beta1, beta2, eps, (float)bc1, (float)bc2, bias_corr, (hipStream_t)stream));

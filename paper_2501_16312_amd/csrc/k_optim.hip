@@ -34,29 +34,59 @@ __global__ __launch_bounds__(256) void k_l1_grad(const float* __restrict__ rgb, 
     if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * scale;
 }
 
-// One thread per 4 consecutive elements of the concatenated groups.
-__global__ __launch_bounds__(256) void k_adam(AdamGroups G, float beta1, float beta2, float eps, float bc1_arg,
-                                              float bc2_arg, const float* __restrict__ bias_corr) {
+constexpr int kAdamBlock = 256;
+constexpr int kAdamPerThread = 4;
+
+__device__ inline void adam_one(float& p, float& m, float& v, float g, float lr, float beta1, float beta2, float eps,
+                                float bc1, float bc2, float lo, float hi) {
+    m = beta1 * m + (1.0f - beta1) * g;
+    v = beta2 * v + (1.0f - beta2) * g * g;
+    const float mh = m / bc1, vh = v / bc2;
+    p = fminf(fmaxf(p - lr * mh / (sqrtf(vh) + eps), lo), hi);
+}
+
+// Each group owns a contiguous range of blocks; a thread updates 4
+// consecutive elements of its group (one 16-byte access per array when the
+// group's arrays are aligned).
+__global__ __launch_bounds__(kAdamBlock) void k_adam(AdamGroups G, float beta1, float beta2, float eps, float bc1_arg,
+                                                     float bc2_arg, const float* __restrict__ bias_corr) {
     const float bc1 = bias_corr ? bias_corr[0] : bc1_arg;
     const float bc2 = bias_corr ? bias_corr[1] : bc2_arg;
-    const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-    if (e0 >= G.start[G.count]) return;
     int gi = 0;
-    while (gi + 1 < G.count && G.start[gi + 1] <= e0) ++gi;
-    for (int k = 0; k < 4; ++k) {
-        const int64_t e = e0 + k;
-        while (gi + 1 < G.count && G.start[gi + 1] <= e) ++gi;
-        if (e >= G.start[G.count]) break;
-        const int64_t i = e - G.start[gi];
-        const float g = G.grad[gi][i];
-        const float m = beta1 * G.m[gi][i] + (1.0f - beta1) * g;
-        const float v = beta2 * G.v[gi][i] + (1.0f - beta2) * g * g;
-        G.m[gi][i] = m;
-        G.v[gi][i] = v;
-        const float mh = m / bc1, vh = v / bc2;
-        float p = G.param[gi][i] - G.lr[gi] * mh / (sqrtf(vh) + eps);
-        p = fminf(fmaxf(p, G.lo[gi]), G.hi[gi]);
-        G.param[gi][i] = p;
+    while (gi + 1 < G.count && G.block0[gi + 1] <= (int64_t)blockIdx.x) ++gi;
+    const int64_t n = G.numel[gi];
+    const int64_t e0 = (((int64_t)blockIdx.x - G.block0[gi]) * kAdamBlock + threadIdx.x) * kAdamPerThread;
+    if (e0 >= n) return;
+    float* __restrict__ P = G.param[gi];
+    const float* __restrict__ Gr = G.grad[gi];
+    float* __restrict__ M = G.m[gi];
+    float* __restrict__ V = G.v[gi];
+    const float lo = G.lo[gi], hi = G.hi[gi];
+    const int period = G.period[gi], head = G.head[gi];
+    float lr[kAdamPerThread];
+#pragma unroll
+    for (int k = 0; k < kAdamPerThread; ++k)
+        lr[k] = (period > 0 && (int)((e0 + k) % period) >= head) ? G.lr_tail[gi] : G.lr[gi];
+    if (G.vec[gi] && e0 + kAdamPerThread <= n) {
+        float4 p = *reinterpret_cast<const float4*>(P + e0);
+        const float4 g = *reinterpret_cast<const float4*>(Gr + e0);
+        float4 m = *reinterpret_cast<const float4*>(M + e0);
+        float4 v = *reinterpret_cast<const float4*>(V + e0);
+        adam_one(p.x, m.x, v.x, g.x, lr[0], beta1, beta2, eps, bc1, bc2, lo, hi);
+        adam_one(p.y, m.y, v.y, g.y, lr[1], beta1, beta2, eps, bc1, bc2, lo, hi);
+        adam_one(p.z, m.z, v.z, g.z, lr[2], beta1, beta2, eps, bc1, bc2, lo, hi);
+        adam_one(p.w, m.w, v.w, g.w, lr[3], beta1, beta2, eps, bc1, bc2, lo, hi);
+        *reinterpret_cast<float4*>(P + e0) = p;
+        *reinterpret_cast<float4*>(M + e0) = m;
+        *reinterpret_cast<float4*>(V + e0) = v;
+    } else {
+        for (int k = 0; k < kAdamPerThread && e0 + k < n; ++k) {
+            float p = P[e0 + k], m = M[e0 + k], v = V[e0 + k];
+            adam_one(p, m, v, Gr[e0 + k], lr[k], beta1, beta2, eps, bc1, bc2, lo, hi);
+            P[e0 + k] = p;
+            M[e0 + k] = m;
+            V[e0 + k] = v;
+        }
     }
 }
 
@@ -70,10 +100,10 @@ hipError_t launch_l1_grad(const float* rgb, const float* target, int64_t count, 
 
 hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,
                        const float* bias_corr, hipStream_t s) {
-    const int64_t total = G.start[G.count];
-    if (total <= 0) return hipSuccess;
-    const int64_t blocks = (total + 1023) / 1024;
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, G, beta1, beta2, eps, bc1, bc2, bias_corr);
+    const int64_t blocks = G.block0[G.count];
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(kAdamBlock), 0, s, G, beta1, beta2, eps, bc1, bc2,
+                       bias_corr);
     return hipGetLastError();
 }
 

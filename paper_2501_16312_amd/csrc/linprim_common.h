@@ -119,9 +119,13 @@ struct AdamGroups {
     const float* grad[8];
     float* m[8];
     float* v[8];
-    int64_t start[9];     // prefix of element counts
+    int64_t numel[8];
+    int64_t block0[9];    // first block of each group (prefix of per-group block counts)
     float lr[8];
+    float lr_tail[8];     // learning rate of positions (i mod period) >= head
+    int period[8], head[8];
     float lo[8], hi[8];   // projection box after the update
+    int vec[8];           // all four arrays 16-byte aligned
     int count;
 };
 hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,

@@ -52,7 +52,8 @@ class linprim_tuning(ctypes.Structure):
 class linprim_adam_group(ctypes.Structure):
     _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("exp_avg", ctypes.c_void_p),
                 ("exp_avg_sq", ctypes.c_void_p), ("numel", ctypes.c_int64), ("lr", ctypes.c_float),
-                ("lo", ctypes.c_float), ("hi", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("lo", ctypes.c_float), ("hi", ctypes.c_float), ("period", ctypes.c_int32),
+                ("lr_tail", ctypes.c_float), ("head", ctypes.c_int32)]
 
 
 EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linprim_preprocess",
@@ -221,12 +222,16 @@ def _adam_groups(groups: list):
         arr[k].lr = float(g["lr"])
         arr[k].lo = float(g.get("lo", float("-inf")))
         arr[k].hi = float(g.get("hi", float("inf")))
+        arr[k].period = int(g.get("period", 0))
+        arr[k].lr_tail = float(g.get("lr_tail", g["lr"]))
+        arr[k].head = int(g.get("head", 0))
     return arr
 
 
 def linprim_adam_step(groups: list, beta1: float, beta2: float, eps: float, step: int, stream=None):
     """groups: list of dicts param, grad, exp_avg, exp_avg_sq (CUDA float32
-    tensors of equal size), lr, and optional lo / hi projection bounds."""
+    tensors of equal size), lr, and optional lo / hi projection bounds and
+    period / head / lr_tail (a second rate for positions i % period >= head)."""
     arr = _adam_groups(groups)
     _check(load().linprim_adam_step(arr, len(groups), float(beta1), float(beta2), float(eps), int(step),
                                     _stream(stream)), "linprim_adam_step")

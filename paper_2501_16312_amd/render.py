@@ -15,12 +15,16 @@ from . import linprim as L
 
 class Rasterizer:
     def __init__(self, kind: int, n: int, cams: Sequence, tile: int = 16, sort_digit_bits: int = 8,
-                 device: str = "cuda", headroom: float = 1.0):
+                 device: str = "cuda", headroom: float = 1.0, views_resident: bool = False):
+        """views_resident: the camera poses live in the view workspace and
+        are replaced with set_views() (same image sizes), so that a captured
+        graph can be replayed on new poses."""
         self.kind = int(kind)
         self.n = int(n)
         self.cams = list(cams)
         self.cams_c = L.cameras(self.cams)
-        self.tune = L.tuning(tile, sort_digit_bits)
+        self.views_resident = bool(views_resident)
+        self.tune = L.tuning(tile, sort_digit_bits, L.FLAG_VIEWS_RESIDENT if views_resident else 0)
         self.device = torch.device(device)
         self.headroom = float(headroom)
         size = L.linprim_view_workspace_size(self.kind, self.n, self.cams_c, self.tune)
@@ -31,6 +35,20 @@ class Rasterizer:
         self.max_pairs = 0
         self.n_pixels = sum(c.width * c.height for c in self.cams)
         self.n_pairs = 0
+        if self.views_resident:
+            L.linprim_upload_views(self.cams_c, self.tune, self.view_ws, self.n, self.kind)
+
+    def set_views(self, cams: Sequence):
+        """New camera poses for a views_resident rasterizer (enqueued on the
+        current stream; image sizes must match the original ones)."""
+        if not self.views_resident:
+            raise L.LinPrimError("set_views needs a views_resident rasterizer")
+        cams = list(cams)
+        if [(c.width, c.height) for c in cams] != [(c.width, c.height) for c in self.cams]:
+            raise L.LinPrimError("set_views: image sizes must stay the same")
+        self.cams = cams
+        self.cams_c = L.cameras(cams)
+        L.linprim_upload_views(self.cams_c, self.tune, self.view_ws, self.n, self.kind)
 
     def reserve_pairs(self, n_pairs: int):
         if n_pairs <= self.max_pairs and self.pair_ws.numel() > 0:

@@ -179,6 +179,26 @@ def test_backward_parity_config0(oracle_mod):
         assert v <= GC.GRAD_TOL, k
 
 
+@pytest.mark.parametrize("kind", [OCTA, TETRA])
+def test_backward_multiview_parity(oracle_mod, kind):
+    """One batched backward over three views of uneven size (tiles 8, with
+    ragged edges) sums each primitive's gradient over the views."""
+    _say(f"backward multiview kind={kind}")
+    sc = _scene_small(kind, 500, seed=31)
+    cams = [scenes.look_at((0, 0, -3), (0, 0, 0), 64, 48), scenes.look_at((3, 0.5, 0), (0, 0, 0), 40, 56),
+            scenes.look_at((-2, 1, -2), (0, 0, 0), 33, 17)]
+    bg = (0.2, 0.0, 0.5)
+    grad = scenes.image_gradient(cams, seed=9)
+    g = GC.gpu_forward(sc, cams, tile=8, bg=bg)
+    gg = GC.gpu_backward(g, grad, bg)
+    rb = oracle_mod.OracleScene(sc, cams, tile=8).backward(grad.astype(np.float64), bg=np.asarray(bg))
+    ok = ~rb["ill"]
+    _say(f"prims ill {rb['ill'].mean() * 100:.2f}%")
+    w = GC.grad_errors(gg, rb, ok, f"multiview kind={kind}")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k
+
+
 def test_backward_tile_sizes_agree(oracle_mod):
     _say("backward tile sizes")
     sc = _scene_small(OCTA, 400, seed=29)

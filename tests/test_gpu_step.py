@@ -49,19 +49,37 @@ def test_l1_grad_parity(torch_cuda, count):
 
 
 def _groups(torch, rng, sizes, bounds):
+    """Five ragged groups; group 1's arrays start one float past a 16-byte
+    boundary (the scalar path), group 4 is an SH-like [n][16][3] array with
+    the degree-0 / higher-degree learning-rate split."""
     gs = []
-    for (n, (lo, hi)), lr in zip(zip(sizes, bounds), (1.6e-4, 1e-3, 5e-2, 2.5e-3, 1e-2)):
+    for k, ((n, (lo, hi)), lr) in enumerate(zip(zip(sizes, bounds), (1.6e-4, 1e-3, 5e-2, 2.5e-3, 2.5e-3))):
         p = rng.uniform(0.0, 1.0, n).astype(np.float32) if lo == 0.0 else rng.normal(size=n).astype(np.float32)
-        gs.append({"param": torch.tensor(p, device="cuda"), "grad": torch.zeros(n, device="cuda"),
-                   "exp_avg": torch.zeros(n, device="cuda"), "exp_avg_sq": torch.zeros(n, device="cuda"),
-                   "lr": lr, "lo": lo, "hi": hi})
+        off = 1 if k == 1 else 0
+
+        def buf(init=None):
+            b = torch.zeros(n + off, device="cuda")
+            if init is not None:
+                b[off:] = torch.tensor(init, device="cuda")
+            return b[off:]
+        g = {"param": buf(p), "grad": buf(), "exp_avg": buf(), "exp_avg_sq": buf(), "lr": lr, "lo": lo, "hi": hi}
+        if k == 4:
+            g.update(period=48, head=3, lr_tail=1.25e-4)
+        gs.append(g)
     return gs
+
+
+def _lr_array(g, n):
+    if g.get("period", 0) > 0:
+        pos = np.arange(n) % g["period"]
+        return np.where(pos >= g["head"], g["lr_tail"], g["lr"])
+    return g["lr"]
 
 
 def test_adam_parity(torch_cuda):
     """Three steps over five ragged groups, with and without projection bounds,
-    against the FP64 oracle; the device-side bias correction variant gives
-    bit-identical results."""
+    aligned and unaligned, with a two-rate group, against the FP64 oracle;
+    the device-side bias correction variant gives bit-identical results."""
     from oracle import optim as O
     from paper_2501_16312_amd import linprim as L
     torch = torch_cuda
@@ -87,7 +105,8 @@ def test_adam_parity(torch_cuda):
         torch.cuda.synchronize()
         for k, (g, h, n) in enumerate(zip(ga, gb, sizes)):
             assert torch.equal(g["param"], h["param"]) and torch.equal(g["exp_avg_sq"], h["exp_avg_sq"])
-            p, m, v = O.adam_step(ref[k][0], g["grad"].cpu().numpy(), ref[k][1], ref[k][2], step, g["lr"], b1, b2,
+            lr = _lr_array(g, n)
+            p, m, v = O.adam_step(ref[k][0], g["grad"].cpu().numpy(), ref[k][1], ref[k][2], step, lr, b1, b2,
                                   eps, *bounds[k])
             # FP32 kernel vs FP64 oracle: m, v to float32 rounding; the update
             # lr * m_hat / sqrt(v_hat) is O(lr), so p to a few ulp plus lr * 1e-5
@@ -96,7 +115,7 @@ def test_adam_parity(torch_cuda):
             m_scale = b1 * np.abs(ref[k][1]) + (1 - b1) * np.abs(gr64)     # m may cancel; v cannot
             assert np.all(np.abs(g["exp_avg"].cpu().numpy() - m) <= 1e-6 * m_scale)
             np.testing.assert_allclose(g["exp_avg_sq"].cpu().numpy(), v, rtol=1e-6, atol=0)
-            assert np.all(np.abs(gp - p) <= 4 * np.spacing(np.abs(p).astype(np.float32)) + g["lr"] * 1e-5)
+            assert np.all(np.abs(gp - p) <= 4 * np.spacing(np.abs(p).astype(np.float32)) + lr * 1e-5)
             assert np.all(gp >= bounds[k][0]) and np.all(gp <= bounds[k][1])
             ref[k] = (gp, g["exp_avg"].cpu().numpy().astype(np.float64), g["exp_avg_sq"].cpu().numpy().astype(np.float64))
 
@@ -199,3 +218,34 @@ def test_captured_training_step_matches_eager(torch_cuda):
         for k in ("means", "quats", "dists", "opacity", "sh"):
             assert torch.equal(getattr(pa, k), getattr(pb, k)), f"step {step}: {k} differs"
         assert abs(float(part.sum()) - cap.loss()) == 0.0
+
+
+def test_graph_replay_new_views(torch_cuda):
+    """A graph captured on one set of camera poses, replayed after
+    set_views() with another, equals eager launches on the new poses."""
+    from paper_2501_16312_amd import linprim as L
+    from paper_2501_16312_amd.graph import CapturedStep, PlainStep
+    from paper_2501_16312_amd.render import Rasterizer
+    torch = torch_cuda
+    sc, _ = _small_scene(1300, seed=5)
+    pos_a = [(0.3, -0.2, -4.0), (4.0, 0.5, 0.2)]
+    pos_b = [(-0.5, 0.4, -3.5), (3.0, -1.0, 2.0)]
+    cams_a = [scenes.look_at(p, (0.0, 0.0, 0.0), w, h) for p, (w, h) in zip(pos_a, [(120, 88), (64, 100)])]
+    cams_b = [scenes.look_at(p, (0.0, 0.0, 0.0), w, h) for p, (w, h) in zip(pos_b, [(120, 88), (64, 100)])]
+    prims = L.Prims.from_scene(sc)
+    grad = torch.tensor(scenes.image_gradient(cams_a, seed=12), device="cuda")
+    rast = Rasterizer(sc.kind, sc.n, cams_a, tile=8, views_resident=True, headroom=3.0)
+    cap = CapturedStep(rast, prims, None, grad_rgb=grad, headroom=3.0)
+    for r, cams in enumerate([cams_b, cams_a, cams_b]):
+        _say(f"replay on new views {r}")
+        rast.set_views(cams)
+        cap.replay()
+        torch.cuda.synchronize()
+        cap.check()
+        eager = PlainStep(Rasterizer(sc.kind, sc.n, cams, tile=8), prims, None, grad)
+        eager.run()
+        torch.cuda.synchronize()
+        for a, b in zip(cap.outs, eager.outs):
+            assert torch.equal(a, b), f"replay {r}: image differs"
+        for k in eager.grads:
+            assert torch.equal(cap.grads[k], eager.grads[k]), f"replay {r}: grad {k} differs"
