@@ -36,6 +36,7 @@ ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, i
     L.offsets = off; off = align256(off + (size_t)vn * 4);
     L.block_sums = off; off = align256(off + (size_t)(L.scan_blocks + 1) * 8);
     L.ranges = off; off = align256(off + (size_t)L.n_tiles_total * 8);
+    L.big = off; off = align256(off + (size_t)vn * 4);
     L.total = off;
     return L;
 }
@@ -157,7 +158,7 @@ int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, i
     if (!(tuning && (tuning->flags & LINPRIM_FLAG_VIEWS_RESIDENT)))
         e = launch_store_views(cams, n_views, tile, reinterpret_cast<ViewInfo*>(ws + L.views), s);
     if (e == hipSuccess) e = launch_preprocess(*prims, n_views, tile, L, ws, s);
-    if (e == hipSuccess) e = launch_scan(L, ws, s);
+    if (e == hipSuccess) e = launch_scan(L, ws, tile, s);
     return hip_status(e);
 }
 

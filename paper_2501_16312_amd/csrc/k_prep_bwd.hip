@@ -24,53 +24,45 @@ __device__ inline bool record_exists(int r, int NQ, int QX, int tile, int4 rect,
     return !(rect.x > gx0 + 7 || rect.z < gx0 || rect.y > gy0 + 7 || rect.w < gy0);
 }
 
-// Sums the gradient records of every (view, primitive) with more than 64
-// records into its first record: the whole wavefront strides over the run
-// and then sums across lanes in a fixed order, so primitives that span
-// thousands of tiles do not hold up a lane.  Shorter runs are summed, in
-// record order, by k_slot_bwd.
-__global__ __launch_bounds__(256) void k_sum_records(const float* __restrict__ payload,
-                                                     const uint32_t* __restrict__ tiles,
-                                                     const uint32_t* __restrict__ offsets, int64_t count, int tile,
-                                                     const Status* __restrict__ status, uint64_t capacity,
-                                                     float* __restrict__ grads) {
+// Sums the gradient records of the slots on the big-slot list (more than
+// kBigRun records: primitives spanning many tiles).  Each slot's run is cut
+// into kBigChunks equal chunks; one wavefront per chunk strides over it,
+// sums across lanes in a fixed order and writes the chunk's sum into the
+// chunk's first record, so no wave holds up the kernel with a long run and
+// the result does not depend on scheduling.  k_slot_bwd adds the chunk sums
+// in chunk order; shorter runs it sums itself.
+__global__ __launch_bounds__(256) void k_sum_big(const float* __restrict__ payload,
+                                                 const uint32_t* __restrict__ tiles,
+                                                 const uint32_t* __restrict__ offsets,
+                                                 const uint32_t* __restrict__ big, int tile,
+                                                 const Status* __restrict__ status, uint64_t capacity,
+                                                 float* __restrict__ grads) {
     if (status->n_pairs > capacity) return;
     const int QX = tile / 8, NQ = QX * QX;
     const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    uint32_t cnt = 0;
-    int4 rect = make_int4(0, 0, -1, -1);
-    uint32_t off = 0;
-    if (slot < count) {
-        cnt = tiles[slot];
-        if (cnt) {
-            rect = *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
-            off = offsets[slot];
-        }
-    }
-    const int nrec = (int)cnt * NQ;
-    // runs of up to 64 records are summed by k_slot_bwd itself
-    uint64_t big = __ballot(nrec > 64);
-    while (big) {
-        const int b = __builtin_ctzll(big);
-        big &= big - 1;
-        const int nr = __builtin_amdgcn_readlane(nrec, b);
-        const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, b);
-        const int4 rc = make_int4(__builtin_amdgcn_readlane(rect.x, b), __builtin_amdgcn_readlane(rect.y, b),
-                                  __builtin_amdgcn_readlane(rect.z, b), __builtin_amdgcn_readlane(rect.w, b));
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t items = (int64_t)status->n_big * kBigChunks;
+    for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); it < items; it += waves) {
+        const int64_t slot = big[it / kBigChunks];
+        const int c = (int)(it % kBigChunks);
+        const int nr = (int)tiles[slot] * NQ;
+        const int r0 = big_chunk_start(c, nr), r1 = big_chunk_start(c + 1, nr);
+        const uint32_t o = offsets[slot];
+        const int4 rc = *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
         const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
         float acc[kGradWords];
+#pragma unroll
         for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
         const float4* g = reinterpret_cast<const float4*>(grads + (int64_t)o * NQ * kGradWords);
-        for (int r0 = lane; r0 < nr; r0 += 128) {
+        for (int rb = r0 + lane; rb < r1; rb += 128) {
             // two records per lane per iteration, all ten loads in flight together
             float4 x[2][kGradWords / 4];
             bool use[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int r = r0 + 64 * h;
-                use[h] = r < nr && (NQ == 1 || record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx));
+                const int r = rb + 64 * h;
+                use[h] = r < r1 && (NQ == 1 || record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx));
 #pragma unroll
                 for (int k = 0; k < kGradWords / 4; ++k)
                     x[h][k] = use[h] ? g[(int64_t)r * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -87,7 +79,7 @@ __global__ __launch_bounds__(256) void k_sum_records(const float* __restrict__ p
         }
         const float outv = wave_reduce20(acc, lane);
         const int ridx = reduce20_index(lane);
-        if (ridx >= 0) grads[(int64_t)o * NQ * kGradWords + ridx] = outv;
+        if (ridx >= 0) grads[((int64_t)o * NQ + r0) * kGradWords + ridx] = outv;
     }
 }
 
@@ -191,7 +183,7 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
     const int nrec = (int)tiles[vs] * nq;
     float r[kGradWords];
-    if (nrec <= 64) {
+    if (nrec <= kBigRun) {
         // sum the run in record order (skipping groups the rectangle misses)
         const int qx = (nq == 1) ? 1 : (nq == 4) ? 2 : 4, tile = 8 * qx;
         const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
@@ -210,13 +202,19 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
             }
         }
     } else {
+        // the chunk sums k_sum_big left in each chunk's first record
 #pragma unroll
-        for (int k = 0; k < kGradWords / 4; ++k) {
-            const float4 x = rp[k];
-            r[4 * k] = x.x;
-            r[4 * k + 1] = x.y;
-            r[4 * k + 2] = x.z;
-            r[4 * k + 3] = x.w;
+        for (int k = 0; k < kGradWords; ++k) r[k] = 0.0f;
+        for (int c = 0; c < kBigChunks; ++c) {
+            const int q = big_chunk_start(c, nrec);
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k) {
+                const float4 x = rp[q * (kGradWords / 4) + k];
+                r[4 * k] += x.x;
+                r[4 * k + 1] += x.y;
+                r[4 * k + 2] += x.z;
+                r[4 * k + 3] += x.w;
+            }
         }
     }
     const ViewInfo& V = views[v];
@@ -476,8 +474,13 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
     const int nq = (tile / 8) * (tile / 8);
     const uint64_t cap = (uint64_t)P.capacity;
     const int64_t vn = p.n * (int64_t)n_views;
-    hipLaunchKernelGGL(k_sum_records, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, stream, payload, tiles, offsets,
-                       vn, tile, st, cap, grads);
+    const uint32_t* big = reinterpret_cast<const uint32_t*>(vws + L.big);
+    // a fixed grid of waves strides over the (big slot, chunk) items, whose
+    // number is only known on the device
+    const int64_t max_waves = (vn * kBigChunks + 3) / 4;
+    const unsigned big_blocks = (unsigned)(max_waves < 1024 ? (max_waves > 0 ? max_waves : 1) : 1024);
+    hipLaunchKernelGGL(k_sum_big, dim3(big_blocks), dim3(256), 0, stream, payload, tiles, offsets, big, tile, st, cap,
+                       grads);
     const dim3 g1((unsigned)((p.n + 127) / 128), (unsigned)n_views);
     const dim3 g2((unsigned)((p.n + 127) / 128));
 #define LP_PRIM(K_, D_)                                                                                        \

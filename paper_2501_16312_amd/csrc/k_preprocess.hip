@@ -266,12 +266,16 @@ __global__ __launch_bounds__(256) void k_scan_totals(uint64_t* __restrict__ bloc
     if (threadIdx.x == 0) {
         status->n_pairs = carry;
         status->overflow = 0;
+        status->n_big = 0;
     }
 }
 
+// Also appends every slot with more than kBigRun gradient records (tile
+// count x groups per tile) to the big-slot list (in no particular order).
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t count,
                                                     const uint64_t* __restrict__ block_sums,
-                                                    uint32_t* __restrict__ out) {
+                                                    uint32_t* __restrict__ out, int nq,
+                                                    Status* __restrict__ status, uint32_t* __restrict__ big) {
     __shared__ uint64_t lds[256];
     // thread t handles the 16 consecutive elements base + 16 t .. 16 t + 15
     const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * 16;
@@ -284,24 +288,37 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
     }
     uint64_t total;
     uint64_t run = block_sums[blockIdx.x] + block_exclusive_scan_u64(s, lds, &total);
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int k = 0; k < 16; ++k) {
         const int64_t idx = base + k;
         if (idx < count) out[idx] = (uint32_t)run;
         run += v[k];
+        const bool is_big = (int64_t)v[k] * nq > kBigRun;
+        const uint64_t m = __ballot(is_big);
+        if (m) {
+            uint32_t first = 0;
+            if (lane == __builtin_ctzll(m)) first = atomicAdd(&status->n_big, (uint32_t)__popcll(m));
+            first = __shfl(first, __builtin_ctzll(m), 64);
+            if (is_big) big[first + __popcll(m & lt_mask)] = (uint32_t)idx;
+        }
     }
 }
 
-hipError_t launch_scan(const ViewLayout& L, char* ws, hipStream_t stream) {
+hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stream) {
     const int64_t count = L.n * L.n_views;
     const uint32_t* tiles = reinterpret_cast<const uint32_t*>(ws + L.tiles);
     uint32_t* offsets = reinterpret_cast<uint32_t*>(ws + L.offsets);
     uint64_t* bsums = reinterpret_cast<uint64_t*>(ws + L.block_sums);
     Status* status = reinterpret_cast<Status*>(ws + L.status);
+    uint32_t* big = reinterpret_cast<uint32_t*>(ws + L.big);
+    const int nq = (tile / 8) * (tile / 8);
     const int64_t nb = L.scan_blocks;
     if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums);
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(256), 0, stream, bsums, nb, status);
     if (nb > 0)
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, offsets);
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, offsets, nq,
+                           status, big);
     return hipGetLastError();
 }
 

@@ -46,6 +46,15 @@ __device__ inline float wave_sum(float v) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// s_waitcnt lgkmcnt(0) (vmcnt and expcnt left at their maxima), fenced so
+// that the scheduler moves no scalar load above it.
+__device__ inline void smem_wait_all() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+}
+__device__ inline void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
 __device__ inline int wave_max_int(int v) {
     for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
     return v;
@@ -268,43 +277,56 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
         if (e1 < rg.y) nxt = load_batch<NQ, false>(base, vals, nullptr, e1, min(64u, rg.y - e1), P.gx0, P.gy0);
         uint64_t mask = cur.mask;
         if (!mask) continue;
-        int b = __builtin_ctzll(mask);
-        Rec Rn;
-        load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)cur.idx, b) * kRecordWords, Rn);
-        while (mask) {
-            const Rec R = Rn;
-            const uint32_t e = e0 + (uint32_t)b;
+        // Two record buffers used in turn: the next surviving entry's record
+        // is loaded into one while the other is blended, with no copies.
+        auto blend = [&](const Rec& R, uint32_t e) {
+            // Branch-free: lanes that do not see the primitive blend with
+            // 1 - o = 1 exactly, which leaves C and T unchanged.
+            const float ki = pxf - R.fi0, kj = pyf - R.fj0;
+            const bool inside = !done && ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj;
+            const float dch = chord_fast<KIND>(R, ki, kj);
+            const bool hitp = inside && dch > 0.0f;
+            if (COUNT) {
+                ev += inside ? 1u : 0u;
+                hit += hitp ? 1u : 0u;
+            }
+            const float ex = hitp ? chord_exp(R.s2, dch) : 1.0f;
+            const float onemo = fmaxf(ex, kOneMinusOMax);
+            const float w = T * (1.0f - onemo);
+            C0 = __builtin_fmaf(w, R.r, C0);
+            C1 = __builtin_fmaf(w, R.g, C1);
+            C2 = __builtin_fmaf(w, R.b, C2);
+            T = T * onemo;
+            last = hitp ? (int)e + 1 : last;
+            const bool stop = hitp && T <= kTStop;
+            term = stop ? e + 1 : term;
+            done = done || stop;
+            return __ballot(!done) != 0;
+        };
+        auto next_rec = [&](Rec& R) {
+            const int b = __builtin_ctzll(mask);
             mask &= mask - 1;
-            if (mask) {
-                b = __builtin_ctzll(mask);
-                load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)cur.idx, b) * kRecordWords, Rn);
-            }
-            if (!done) {
-                const float ki = pxf - R.fi0, kj = pyf - R.fj0;
-                if (ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj) {
-                    if (COUNT) ++ev;
-                    const float delta = chord_fast<KIND>(R, ki, kj);
-                    if (delta > 0.0f) {
-                        if (COUNT) ++hit;
-                        const float ex = chord_exp(R.s2, delta);
-                        const float onemo = fmaxf(ex, kOneMinusOMax);
-                        const float w = T * (1.0f - onemo);
-                        C0 = __builtin_fmaf(w, R.r, C0);
-                        C1 = __builtin_fmaf(w, R.g, C1);
-                        C2 = __builtin_fmaf(w, R.b, C2);
-                        T = T * onemo;
-                        last = (int)e + 1;
-                        if (T <= kTStop) {
-                            done = true;
-                            term = e + 1;
-                        }
-                    }
-                }
-            }
-            if (__ballot(!done) == 0) {
-                alive = false;
-                break;
-            }
+            load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)cur.idx, b) * kRecordWords, R);
+            return e0 + (uint32_t)b;
+        };
+        // Scalar loads complete out of order, so waiting for one buffer means
+        // waiting for every scalar load in flight: wait first, then issue
+        // the next record's load, then blend from the buffer just waited for.
+        Rec RA, RB;
+        uint32_t eA = next_rec(RA), eB = 0;
+        while (true) {
+            smem_wait_all();
+            const bool haveB = mask != 0;
+            if (haveB) eB = next_rec(RB);
+            sched_fence();
+            if (!blend(RA, eA)) { alive = false; break; }
+            if (!haveB) break;
+            smem_wait_all();
+            const bool haveA = mask != 0;
+            if (haveA) eA = next_rec(RA);
+            sched_fence();
+            if (!blend(RB, eB)) { alive = false; break; }
+            if (!haveA) break;
         }
     }
     unsigned long long c_it = 0, c_ev = 0, c_hit = 0;
@@ -413,71 +435,70 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
         const Batch bt = load_batch<NQ, true>(base, vals, offs, e0, nb, P.gx0, P.gy0);
         uint64_t mask = bt.mask;
         if (!mask) continue;
-        int b = 63 - __builtin_clzll(mask);
-        Rec Rn;
-        load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) * kRecordWords, Rn);
-        while (mask) {
-            const Rec R = Rn;
-            const int bcur = b;
+        // Entries in reverse order, two record buffers used in turn (see the
+        // forward for the wait / load order).
+        auto next_rec = [&](Rec& R) {
+            const int b = 63 - __builtin_clzll(mask);
+            mask &= ~(1ull << b);
+            load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) * kRecordWords, R);
+            return b;
+        };
+        auto step = [&](const Rec& R, int bcur) {
             const uint32_t e = e0 + (uint32_t)bcur;
-            mask &= ~(1ull << bcur);
-            if (mask) {
-                b = 63 - __builtin_clzll(mask);
-                load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) * kRecordWords, Rn);
-            }
+            // Branch-free: a lane that does not see the primitive (outside
+            // the rectangle, past its last blended entry, zero chord) runs
+            // the same instructions with delta = 0, o = 0, 1 - o = 1, which
+            // leaves T and the colour behind unchanged exactly and yields
+            // zero gradients.
             float acc[kGradWords];
-#pragma unroll
-            for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
-            bool contributed = false;
             const float ki = pxf - R.fi0, kj = pyf - R.fj0;
-            if ((int)e < last && ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj) {
-                int ih, il;
-                const float delta = chord<KIND>(R, ki, kj, ih, il);
-                if (delta > 0.0f) {
-                    const float ex = chord_exp(R.s2, delta);
-                    const float onemo = fmaxf(ex, kOneMinusOMax);
-                    const float o = 1.0f - onemo;
-                    const float ro = __builtin_amdgcn_rcpf(onemo);
-                    const float Tk = T * ro;                     // transmittance in front of this primitive
-                    // dC/do = T_k rgb - behind / (1 - o)
-                    const float dLdo = G0 * (Tk * R.r - B0 * ro) + G1 * (Tk * R.g - B1 * ro) +
-                                       G2 * (Tk * R.b - B2 * ro);
-                    const float wk = Tk * o;
-                    acc[16] = G0 * wk;
-                    acc[17] = G1 * wk;
-                    acc[18] = G2 * wk;
-                    B0 += wk * R.r;
-                    B1 += wk * R.g;
-                    B2 += wk * R.b;
-                    T = Tk;
-                    contributed = true;
-                    if (ex >= kOneMinusOMax) {                   // not clamped: o = 1 - exp(-sigma chord)
-                        const float gD = dLdo * R.sigma * ex;    // dL/dchord
-                        acc[19] = dLdo * delta * ex;             // dL/dsigma
-                        if (KIND == LINPRIM_OCTAHEDRON) {
+            const bool inside = (int)e < last && ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj;
+            int ih, il;
+            const float dch = chord<KIND>(R, ki, kj, ih, il);
+            const bool contributed = inside && dch > 0.0f;
+            const float delta = contributed ? dch : 0.0f;
+            const float ex = contributed ? chord_exp(R.s2, delta) : 1.0f;
+            const float onemo = fmaxf(ex, kOneMinusOMax);
+            const float o = 1.0f - onemo;
+            const float ro = __builtin_amdgcn_rcpf(onemo);
+            const float Tk = T * ro;                     // transmittance in front of this primitive
+            // dC/do = T_k rgb - behind / (1 - o)
+            const float dLdo = G0 * (Tk * R.r - B0 * ro) + G1 * (Tk * R.g - B1 * ro) + G2 * (Tk * R.b - B2 * ro);
+            const float wk = Tk * o;
+            acc[16] = G0 * wk;
+            acc[17] = G1 * wk;
+            acc[18] = G2 * wk;
+            B0 += wk * R.r;
+            B1 += wk * R.g;
+            B2 += wk * R.b;
+            T = Tk;
+            // not clamped: o = 1 - exp(-sigma chord)
+            const bool open = contributed && ex >= kOneMinusOMax;
+            const float gD = open ? dLdo * R.sigma * ex : 0.0f;    // dL/dchord
+            acc[19] = open ? dLdo * delta * ex : 0.0f;             // dL/dsigma
+            if (KIND == LINPRIM_OCTAHEDRON) {
 #pragma unroll
-                            for (int s = 0; s < 4; ++s) {
-                                const float gh = (ih == s) ? gD : 0.0f;
-                                const float gl = (il == s) ? gD : 0.0f;
-                                const float d = gh - gl;
-                                acc[4 * s + 0] = d * ki;
-                                acc[4 * s + 1] = d * kj;
-                                acc[4 * s + 2] = gh;
-                                acc[4 * s + 3] = -gl;
-                            }
-                        } else {
-                            const int fh = (R.fmap >> (2 * ih)) & 3;
-                            const int fl = (R.fmap >> (2 * (il + 3))) & 3;
-#pragma unroll
-                            for (int f = 0; f < 4; ++f) {
-                                const float d = ((fh == f) ? gD : 0.0f) - ((fl == f) ? gD : 0.0f);
-                                acc[3 * f + 0] = d * ki;
-                                acc[3 * f + 1] = d * kj;
-                                acc[3 * f + 2] = d;
-                            }
-                        }
-                    }
+                for (int s = 0; s < 4; ++s) {
+                    const float gh = (ih == s) ? gD : 0.0f;
+                    const float gl = (il == s) ? gD : 0.0f;
+                    const float d = gh - gl;
+                    acc[4 * s + 0] = d * ki;
+                    acc[4 * s + 1] = d * kj;
+                    acc[4 * s + 2] = gh;
+                    acc[4 * s + 3] = -gl;
                 }
+            } else {
+                const int fh = (R.fmap >> (2 * ih)) & 3;
+                const int fl = (R.fmap >> (2 * (il + 3))) & 3;
+#pragma unroll
+                for (int f = 0; f < 4; ++f) {
+                    const float d = ((fh == f) ? gD : 0.0f) - ((fl == f) ? gD : 0.0f);
+                    acc[3 * f + 0] = d * ki;
+                    acc[3 * f + 1] = d * kj;
+                    acc[3 * f + 2] = d;
+                }
+#pragma unroll
+                for (int k = 12; k < 16; ++k) acc[k] = 0.0f;
             }
             const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, bcur);
             const int64_t slot = record_slot(R, SHIFT, P.tx, P.ty, off, NQ, P.q);
@@ -485,6 +506,22 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             if (__ballot(contributed) != 0) outv = wave_reduce20(acc, lane);
             const int ridx = reduce20_index(lane);
             if (ridx >= 0) grads[slot * kGradWords + ridx] = outv;
+        };
+        Rec RA, RB;
+        int bA = next_rec(RA), bB = 0;
+        while (true) {
+            smem_wait_all();
+            const bool haveB = mask != 0;
+            if (haveB) bB = next_rec(RB);
+            sched_fence();
+            step(RA, bA);
+            if (!haveB) break;
+            smem_wait_all();
+            const bool haveA = mask != 0;
+            if (haveA) bA = next_rec(RA);
+            sched_fence();
+            step(RB, bB);
+            if (!haveA) break;
         }
     }
 }

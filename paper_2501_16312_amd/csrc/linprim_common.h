@@ -63,14 +63,14 @@ struct ViewInfo {
 struct Status {
     uint64_t n_pairs;      // written by the scan
     uint32_t overflow;     // set by bin_sort when n_pairs > capacity
-    uint32_t pad0;
+    uint32_t n_big;        // slots with more than kBigRun gradient records (list in ViewLayout::big)
     uint64_t capacity;
     uint64_t pad[5];
 };
 
 // Offsets into the view workspace (all 256-byte aligned).
 struct ViewLayout {
-    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, total;
+    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, total;
     int64_t n, n_views, n_tiles_total, scan_blocks;
 };
 
@@ -98,7 +98,16 @@ hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int t
                               hipStream_t stream);
 hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L,
                              char* ws, hipStream_t stream);
-hipError_t launch_scan(const ViewLayout& L, char* ws, hipStream_t stream);
+hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stream);
+
+// A (view, primitive) slot whose gradient records number more than kBigRun
+// is listed by the scan; its records are summed by kBigChunks waves, each
+// writing its partial sum over the chunk into the chunk's first record.
+constexpr int kBigRun = 64;
+constexpr int kBigChunks = 16;
+__host__ __device__ inline int big_chunk_start(int c, int nrec) {
+    return (int)(((int64_t)c * nrec) / kBigChunks);
+}
 hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, char* pws,
                            int tile, int digit_bits, int32_t n_views, const linprim_camera* cams,
                            hipStream_t stream, int* result_in_b);
@@ -168,8 +177,14 @@ __device__ inline float wave_reduce20(const float (&v)[20], int lane) {
         b[j] += dpp_mov<0x141>(b[j]);    // row_half_mirror
         b[j] += dpp_mov<0x140>(b[j]);    // row_mirror
     }
+    // branch-free pick of b[lane & 15] (lanes 5..15 of a row return 0)
     const int k = lane & 15;
-    return (k == 0) ? b[0] : (k == 1) ? b[1] : (k == 2) ? b[2] : (k == 3) ? b[3] : (k == 4) ? b[4] : 0.0f;
+    float r = (k == 4) ? b[4] : 0.0f;
+    r = (k == 3) ? b[3] : r;
+    r = (k == 2) ? b[2] : r;
+    r = (k == 1) ? b[1] : r;
+    r = (k == 0) ? b[0] : r;
+    return r;
 }
 
 // Which of the 20 totals lane L returns from wave_reduce20 (-1: none).

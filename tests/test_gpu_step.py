@@ -106,17 +106,20 @@ def test_adam_parity(torch_cuda):
         for k, (g, h, n) in enumerate(zip(ga, gb, sizes)):
             assert torch.equal(g["param"], h["param"]) and torch.equal(g["exp_avg_sq"], h["exp_avg_sq"])
             lr = _lr_array(g, n)
-            p, m, v = O.adam_step(ref[k][0], g["grad"].cpu().numpy(), ref[k][1], ref[k][2], step, lr, b1, b2,
-                                  eps, *bounds[k])
+            # the kernel receives float32 betas and eps: the oracle gets the same numbers
+            f1, f2, fe = (float(np.float32(x)) for x in (b1, b2, eps))
+            p, m, v = O.adam_step(ref[k][0], g["grad"].cpu().numpy(), ref[k][1], ref[k][2], step, lr, f1, f2,
+                                  fe, *(float(np.float32(b)) for b in bounds[k]))
             # FP32 kernel vs FP64 oracle: m, v to float32 rounding; the update
             # lr * m_hat / sqrt(v_hat) is O(lr), so p to a few ulp plus lr * 1e-5
             gp = g["param"].cpu().numpy().astype(np.float64)
             gr64 = g["grad"].cpu().numpy().astype(np.float64)
-            m_scale = b1 * np.abs(ref[k][1]) + (1 - b1) * np.abs(gr64)     # m may cancel; v cannot
+            m_scale = f1 * np.abs(ref[k][1]) + (1 - f1) * np.abs(gr64)     # m may cancel; v cannot
             assert np.all(np.abs(g["exp_avg"].cpu().numpy() - m) <= 1e-6 * m_scale)
             np.testing.assert_allclose(g["exp_avg_sq"].cpu().numpy(), v, rtol=1e-6, atol=0)
             assert np.all(np.abs(gp - p) <= 4 * np.spacing(np.abs(p).astype(np.float32)) + lr * 1e-5)
-            assert np.all(gp >= bounds[k][0]) and np.all(gp <= bounds[k][1])
+            # the bounds reach the kernel as float32
+            assert np.all(gp >= np.float32(bounds[k][0])) and np.all(gp <= np.float32(bounds[k][1]))
             ref[k] = (gp, g["exp_avg"].cpu().numpy().astype(np.float64), g["exp_avg_sq"].cpu().numpy().astype(np.float64))
 
 
