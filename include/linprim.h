@@ -85,7 +85,7 @@ typedef struct linprim_camera {
 /* Launch configuration. */
 typedef struct linprim_tuning {
     int32_t tile;             /* screen tile edge in pixels: 8, 16 or 32 */
-    int32_t sort_digit_bits;  /* radix-sort digit width, 4..8 (0 = 8) */
+    int32_t sort_digit_bits;  /* radix-sort digit width, 4..8 (0 = 8); used with LINPRIM_FLAG_RADIX_SORT */
     int32_t flags;            /* LINPRIM_FLAG_* */
     int32_t reserved;
 } linprim_tuning;
@@ -98,6 +98,11 @@ typedef struct linprim_tuning {
  * captured graph whose camera poses change between replays; image sizes
  * must stay the same). */
 #define LINPRIM_FLAG_VIEWS_RESIDENT 2
+/* linprim_bin_sort orders the pairs with a global LSD radix sort of the
+ * full (tile, depth) keys, sort_digit_bits per pass, instead of the default
+ * per-tile sort (pairs counted and scattered per tile, each tile's list then
+ * sorted by (depth, primitive)).  Both give the same order. */
+#define LINPRIM_FLAG_RADIX_SORT 4
 
 /* Bytes of the per-view workspace (payloads, counts, offsets, tile ranges,
  * status) for n primitives of `type` over n_views cameras. */
@@ -131,14 +136,16 @@ int linprim_upload_views(const linprim_camera *cams, int32_t n_views, const linp
 /* Waits for `stream` and returns the pair count of the last preprocess. */
 int linprim_pair_count(const void *view_ws, int64_t *n_pairs, void *stream);
 
-/* Sec. 3.2 "Global Sorting and Tiling".  Emits key = (global tile << 32) |
- * float32 bits of the centre's camera depth and value = primitive index for
- * every touched tile, sorts the pairs by key with a stable on-device LSD
- * radix sort (ties keep primitive order), and writes every tile's [start,
- * end) range into view_ws.  If the pair count exceeds max_pairs nothing is
- * sorted, the overflow flag in view_ws is set and the render calls leave
- * their outputs untouched; linprim_read_status reports it.  The
- * sorted keys/values stay in pair_ws. */
+/* Sec. 3.2 "Global Sorting and Tiling".  Orders the (tile, primitive)
+ * pairs of every touched tile by key = (global tile << 32) | float32 bits of
+ * the centre's camera depth, ties by primitive index, and writes every
+ * tile's [start, end) range into view_ws.  By default the pairs are counted
+ * per tile, scattered into their tile's segment and each segment is sorted
+ * by (depth, primitive); with LINPRIM_FLAG_RADIX_SORT a stable LSD radix
+ * sort of the emitted keys gives the same order.  If the pair count exceeds
+ * max_pairs nothing is sorted, the overflow flag in view_ws is set and the
+ * render calls leave their outputs untouched; linprim_read_status reports
+ * it.  The sorted keys/values stay in pair_ws. */
 int linprim_bin_sort(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
                      const linprim_tuning *tuning, void *view_ws, size_t view_ws_bytes, void *pair_ws,
                      size_t pair_ws_bytes, int64_t max_pairs, void *stream);

@@ -37,6 +37,7 @@ ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, i
     L.block_sums = off; off = align256(off + (size_t)(L.scan_blocks + 1) * 8);
     L.ranges = off; off = align256(off + (size_t)L.n_tiles_total * 8);
     L.big = off; off = align256(off + (size_t)vn * 4);
+    L.long_list = off; off = align256(off + (size_t)L.n_tiles_total * 4);
     L.total = off;
     return L;
 }
@@ -119,10 +120,10 @@ int hip_status(hipError_t e) { return e == hipSuccess ? LINPRIM_OK : LINPRIM_ERR
 
 // The bin_sort call decides in which buffer the sorted pairs end (the
 // parity of the number of digit passes); the render calls recompute it.
-int result_buffer(const ViewLayout& L, int digit_bits) {
-    const int key_bits = 32 + key_tile_bits(L.n_tiles_total);
-    const int passes = (key_bits + digit_bits - 1) / digit_bits;
-    return passes & 1;
+bool radix_sort(const linprim_tuning* tu) { return tu && (tu->flags & LINPRIM_FLAG_RADIX_SORT); }
+
+int result_buffer(const ViewLayout& L, const linprim_tuning* tu) {
+    return sorted_buffer(L.n_tiles_total, radix_sort(tu), digit_of(tu));
 }
 
 }  // namespace
@@ -206,7 +207,8 @@ int linprim_bin_sort(const linprim_prims* prims, const linprim_camera* cams, int
     PairLayout P;
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
     int in_b = 0;
-    hipError_t e = launch_bin_sort(L, (char*)view_ws, P, (char*)pair_ws, tile_of(tuning), digit_of(tuning), n_views,
+    hipError_t e = launch_bin_sort(L, (char*)view_ws, P, (char*)pair_ws, radix_sort(tuning), tile_of(tuning),
+                                   digit_of(tuning), n_views,
                                    cams, (hipStream_t)stream, &in_b);
     return hip_status(e);
 }
@@ -219,7 +221,7 @@ static int render_fwd_common(const linprim_prims* prims, const linprim_camera* c
     ViewLayout L;
     PairLayout P;
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
-    const int in_b = result_buffer(L, digit_of(tuning));
+    const int in_b = result_buffer(L, tuning);
     hipError_t e = launch_render_fwd_ex(L, (const char*)view_ws, P, (const char*)pair_ws, in_b, prims->type,
                                         tile_of(tuning), n_views, bg, out_rgb, out_T, out_last,
                                         reinterpret_cast<unsigned long long*>(counters), (hipStream_t)stream);
@@ -254,7 +256,7 @@ int linprim_render_bwd(const linprim_prims* prims, const linprim_camera* cams, i
     ViewLayout L;
     PairLayout P;
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
-    const int in_b = result_buffer(L, digit_of(tuning));
+    const int in_b = result_buffer(L, tuning);
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = launch_render_bwd(L, (const char*)view_ws, P, (char*)pair_ws, in_b, prims->type, tile_of(tuning),
                                      n_views, bg, out_T, out_last, grad_rgb, s);
@@ -272,7 +274,7 @@ int linprim_raster_bwd(const linprim_prims* prims, const linprim_camera* cams, i
     ViewLayout L;
     PairLayout P;
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
-    const int in_b = result_buffer(L, digit_of(tuning));
+    const int in_b = result_buffer(L, tuning);
     return hip_status(launch_render_bwd(L, (const char*)view_ws, P, (char*)pair_ws, in_b, prims->type,
                                         tile_of(tuning), n_views, bg, out_T, out_last, grad_rgb,
                                         (hipStream_t)stream));
@@ -377,7 +379,7 @@ int linprim_debug_pointers(const linprim_prims* prims, const linprim_camera* cam
     if (int rc = prepare(prims, cams, n_views, tuning, (size_t)-1, (size_t)-1, max_pairs, L, P)) return rc;
     const char* v = (const char*)view_ws;
     const char* p = (const char*)pair_ws;
-    const int in_b = result_buffer(L, digit_of(tuning));
+    const int in_b = result_buffer(L, tuning);
     if (payload) *payload = (void*)(v + L.payload);
     if (depth_keys) *depth_keys = (void*)(v + L.depth_keys);
     if (tiles_touched) *tiles_touched = (void*)(v + L.tiles);

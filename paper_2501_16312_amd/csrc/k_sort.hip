@@ -12,13 +12,21 @@
 
 namespace linprim {
 
+__device__ inline void emit_pair(uint64_t g, uint32_t depth, uint32_t prim, uint32_t slot,
+                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    keys[slot] = (g << 32) | depth;
+    vals[slot] = prim;
+}
+
+// One thread per (primitive, view) slot; one (key, value) pair per tile of
+// the slot's tile rectangle, row-major, at the slot's offset.
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ depth_keys,
-                                                    const uint32_t* __restrict__ tiles,
-                                                    const uint32_t* __restrict__ offsets,
-                                                    const float* __restrict__ payload, const ViewInfo* __restrict__ views,
-                                                    int64_t n, int tile_shift, Status* __restrict__ status,
-                                                    uint64_t capacity, uint64_t* __restrict__ keys,
-                                                    uint32_t* __restrict__ vals) {
+                                               const uint32_t* __restrict__ tiles,
+                                               const uint32_t* __restrict__ offsets,
+                                               const float* __restrict__ payload, const ViewInfo* __restrict__ views,
+                                               int64_t n, int tile_shift, Status* __restrict__ status,
+                                               uint64_t capacity, uint64_t* __restrict__ keys,
+                                               uint32_t* __restrict__ vals) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int v = blockIdx.y;
     const int lane = threadIdx.x & 63;
@@ -47,8 +55,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
         for (uint32_t t = 0; t < cnt; ++t) {
             const int tx = tx0 + (int)(t % ntx), ty = ty0 + (int)(t / ntx);
             const uint64_t g = (uint64_t)(V.tile_base + (int64_t)ty * V.tiles_x + tx);
-            keys[off + t] = (g << 32) | key;
-            vals[off + t] = (uint32_t)i;
+            emit_pair(g, key, (uint32_t)i, off + t, keys, vals);
         }
     }
     // long runs (near or large primitives): the whole wavefront writes them
@@ -65,9 +72,170 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
         for (uint32_t t = (uint32_t)lane; t < c; t += 64) {
             const int tx = bx0 + (int)(t % bn), ty = by0 + (int)(t / bn);
             const uint64_t g = (uint64_t)(V.tile_base + (int64_t)ty * V.tiles_x + tx);
-            keys[o + t] = (g << 32) | k;
-            vals[o + t] = idx;
+            emit_pair(g, k, idx, o + t, keys, vals);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-tile sort (default).  A stable LSD radix sort of the tile bits alone
+// (bits 32 and up of the keys) groups the pairs by tile and keeps each
+// tile's pairs in emission order; each tile's list is then sorted by
+// (depth bits, primitive index), which is unique within a tile, so the
+// result is the order of the stable sort of the full keys.  Lists of up to
+// kShortList entries are ranked by one wave; longer ones are sorted in LDS
+// by a 256-thread block (bitonic network), and lists longer than kLdsList
+// are sorted in kLdsList chunks that are then merged.
+// ---------------------------------------------------------------------------
+constexpr int kShortList = 256;
+constexpr int kLdsList = 4096;
+
+// Writes the sorted pair e of tile g: the full key and the value.
+__device__ inline void put_sorted(uint64_t g, uint64_t dkey, uint32_t e, uint64_t* __restrict__ keys,
+                                  uint32_t* __restrict__ vals) {
+    keys[e] = (g << 32) | (dkey >> 32);
+    vals[e] = (uint32_t)dkey;
+}
+
+// (depth bits, primitive index) of tile-sorted pair e.
+__device__ inline uint64_t depth_index(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                       int64_t e) {
+    return ((uint64_t)(uint32_t)keys[e] << 32) | vals[e];
+}
+
+// One wave per tile with at most kShortList pairs: every pair's rank is the
+// number of smaller (depth, index) values in the list.  Longer lists are
+// put on the long-list list.
+__global__ __launch_bounds__(64) void k_sort_short_lists(const uint2* __restrict__ ranges, int64_t n_tiles,
+                                                         Status* __restrict__ status, uint64_t capacity,
+                                                         const uint64_t* __restrict__ in_keys,
+                                                         const uint32_t* __restrict__ in_vals,
+                                                         uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                         uint32_t* __restrict__ long_list) {
+    constexpr int PER = kShortList / 64;
+    if (status->n_pairs > capacity) return;
+    const int64_t g = blockIdx.x;
+    if (g >= n_tiles) return;
+    const uint2 rg = ranges[g];
+    const int len = (int)(rg.y - rg.x);
+    if (len == 0) return;
+    const int lane = threadIdx.x;
+    if (len > kShortList) {
+        if (lane == 0) long_list[atomicAdd(&status->n_long, 1u)] = (uint32_t)g;
+        return;
+    }
+    uint64_t k[PER];
+    uint32_t rank[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = q * 64 + lane;
+        k[q] = (e < len) ? depth_index(in_keys, in_vals, rg.x + e) : ~0ull;
+        rank[q] = 0;
+    }
+    const int nq = (len + 63) / 64;
+    for (int q2 = 0; q2 < nq; ++q2) {
+        const int jn = min(64, len - q2 * 64);
+        uint64_t reg = k[0];
+#pragma unroll
+        for (int q = 1; q < PER; ++q)
+            if (q == q2) reg = k[q];
+        for (int j = 0; j < jn; ++j) {
+            const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(reg >> 32), j) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)reg, j);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) rank[q] += (kj < k[q]) ? 1u : 0u;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (q * 64 + lane < len) put_sorted((uint64_t)g, k[q], rg.x + rank[q], keys, vals);
+}
+
+// Bitonic sort of s[0, P) ascending, P a power of two <= kLdsList.
+__device__ inline void lds_bitonic(uint64_t* s, int P) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < (P >> 1); i += blockDim.x) {
+                const int lo = 2 * j * (i / j) + (i % j), hi = lo + j;
+                const uint64_t a = s[lo], b = s[hi];
+                const bool up = (lo & k) == 0;
+                if ((a > b) == up) {
+                    s[lo] = b;
+                    s[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Merge of the sorted runs a[0, la) and b[0, lb) into out[0, la + lb) by the
+// whole block: thread t produces a contiguous slice of the output, finding
+// where it starts by a binary search on the merge path.
+__device__ inline void block_merge(const uint64_t* __restrict__ a, int64_t la, const uint64_t* __restrict__ b,
+                                   int64_t lb, uint64_t* __restrict__ out) {
+    const int64_t m = la + lb;
+    const int64_t per = (m + blockDim.x - 1) / blockDim.x;
+    const int64_t d0 = min(m, (int64_t)threadIdx.x * per), d1 = min(m, d0 + per);
+    if (d0 >= d1) return;
+    // smallest i with a[i] > b[d0 - i - 1] (keys are unique)
+    int64_t lo = max((int64_t)0, d0 - lb), hi = min(d0, la);
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (a[mid] < b[d0 - mid - 1]) lo = mid + 1; else hi = mid;
+    }
+    int64_t i = lo, j = d0 - lo;
+    for (int64_t d = d0; d < d1; ++d) {
+        const bool take_a = j >= lb || (i < la && a[i] < b[j]);
+        out[d] = take_a ? a[i++] : b[j++];
+    }
+}
+
+// Tiles with more than kShortList pairs, one block at a time.  The (depth,
+// index) values are formed in place of the tile-sorted keys, which are no
+// longer needed, and merged through the output key array.
+__global__ __launch_bounds__(256) void k_sort_long_lists(const uint2* __restrict__ ranges,
+                                                         const uint32_t* __restrict__ long_list,
+                                                         const Status* __restrict__ status, uint64_t capacity,
+                                                         uint64_t* __restrict__ in_keys,
+                                                         const uint32_t* __restrict__ in_vals,
+                                                         uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    __shared__ uint64_t s[kLdsList];
+    if (status->n_pairs > capacity) return;
+    const uint32_t n_long = status->n_long;
+    for (uint32_t li = blockIdx.x; li < n_long; li += gridDim.x) {
+        const uint64_t g = long_list[li];
+        const uint2 rg = ranges[g];
+        const int64_t len = (int64_t)rg.y - rg.x;
+        uint64_t* seg = in_keys + rg.x;
+        // sort chunks of kLdsList in LDS, written back in place
+        for (int64_t c0 = 0; c0 < len; c0 += kLdsList) {
+            const int cl = (int)min((int64_t)kLdsList, len - c0);
+            int P = 128;
+            while (P < cl) P <<= 1;
+            for (int i = threadIdx.x; i < P; i += blockDim.x)
+                s[i] = (i < cl) ? depth_index(in_keys, in_vals, (int64_t)rg.x + c0 + i) : ~0ull;
+            __syncthreads();
+            lds_bitonic(s, P);
+            for (int i = threadIdx.x; i < cl; i += blockDim.x) seg[c0 + i] = s[i];
+            __syncthreads();
+        }
+        // merge runs of doubling width, ping-ponging between the segment and
+        // the output key array's segment (scratch until the final write)
+        uint64_t* src = seg;
+        uint64_t* dst = keys + rg.x;
+        for (int64_t w = kLdsList; w < len; w <<= 1) {
+            for (int64_t a0 = 0; a0 < len; a0 += 2 * w) {
+                const int64_t la = min(w, len - a0), lb = min(w, len - a0 - la);
+                block_merge(src + a0, la, src + a0 + la, lb, dst + a0);
+            }
+            __syncthreads();
+            uint64_t* sw = src; src = dst; dst = sw;
+        }
+        // src holds the sorted list; each index is read and then written by
+        // the same thread
+        for (int64_t i = threadIdx.x; i < len; i += blockDim.x) put_sorted(g, src[i], rg.x + (uint32_t)i, keys, vals);
+        __syncthreads();
     }
 }
 
@@ -207,9 +375,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
     }
 }
 
-__global__ __launch_bounds__(256) void k_clear_ranges(uint2* __restrict__ ranges, int64_t count) {
+__global__ __launch_bounds__(256) void k_clear_ranges(uint2* __restrict__ ranges, int64_t count,
+                                                      Status* __restrict__ status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) ranges[i] = make_uint2(0u, 0u);
+    if (i == 0) status->n_long = 0u;
 }
 
 __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict__ keys,
@@ -224,7 +394,22 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
     if (i == (int64_t)np - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[tile].y = (uint32_t)(i + 1);
 }
 
-hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, char* pws, int tile,
+// Passes over the tile bits alone (per-tile sort): at most 8 bits each,
+// spread evenly.
+inline void tile_passes(int tile_bits, int* passes, int* digit) {
+    *passes = (tile_bits + 7) / 8;
+    *digit = (tile_bits + *passes - 1) / *passes;
+}
+
+int sorted_buffer(int64_t n_tiles_total, bool radix, int digit_bits) {
+    const int tb = key_tile_bits(n_tiles_total);
+    if (radix) return ((32 + tb + digit_bits - 1) / digit_bits) & 1;
+    int passes, digit;
+    tile_passes(tb, &passes, &digit);
+    return (passes & 1) ^ 1;   // the per-list sort writes to the other buffer
+}
+
+hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, char* pws, bool radix, int tile,
                            int digit_bits, int32_t n_views, const linprim_camera* cams, hipStream_t stream,
                            int* result_in_b) {
     (void)cams;
@@ -238,40 +423,59 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
     uint32_t* hist = reinterpret_cast<uint32_t*>(pws + P.hist);
     uint32_t* totals = hist + (int64_t)256 * P.sort_blocks;
     uint2* ranges = reinterpret_cast<uint2*>(vws + L.ranges);
+    uint32_t* long_list = reinterpret_cast<uint32_t*>(vws + L.long_list);
     const uint64_t cap = (uint64_t)P.capacity;
+    const int64_t nt = L.n_tiles_total;
     if (L.n > 0) {
         dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)n_views);
         hipLaunchKernelGGL(k_emit_pairs, grid, dim3(256), 0, stream, reinterpret_cast<const uint32_t*>(vws + L.depth_keys),
                            reinterpret_cast<const uint32_t*>(vws + L.tiles),
                            reinterpret_cast<const uint32_t*>(vws + L.offsets),
                            reinterpret_cast<const float*>(vws + L.payload), views, L.n, shift, status, cap, ka, va);
-    } else {
-        // still record the overflow state consistently
     }
-    const int key_bits = 32 + key_tile_bits(L.n_tiles_total);
-    const int passes = (key_bits + digit_bits - 1) / digit_bits;
+    const int tb = key_tile_bits(nt);
+    int passes, digit, key_lo, key_bits;
+    if (radix) {
+        key_lo = 0;
+        key_bits = 32 + tb;
+        digit = digit_bits;
+        passes = (key_bits + digit - 1) / digit;
+    } else {
+        key_lo = 32;
+        key_bits = tb;
+        tile_passes(tb, &passes, &digit);
+    }
     uint64_t *kin = ka, *kout = kb;
     uint32_t *vin = va, *vout = vb;
     const int64_t nb = P.sort_blocks;
     for (int p = 0; p < passes; ++p) {
-        const int sh = p * digit_bits;
-        const int bits = (key_bits - sh) < digit_bits ? (key_bits - sh) : digit_bits;
+        const int sh = p * digit;
+        const int bits = (key_bits - sh) < digit ? (key_bits - sh) : digit;
         if (nb > 0) {
-            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, status, cap, sh, bits,
-                               nb, hist);
+            hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, status, cap,
+                               key_lo + sh, bits, nb, hist);
             hipLaunchKernelGGL(k_radix_scan, dim3(1u << bits), dim3(256), 0, stream, hist, status, cap, nb, totals);
-            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, vin, status, cap,
-                               sh, bits, nb, hist, totals, kout, vout);
+            hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, vin, status,
+                               cap, key_lo + sh, bits, nb, hist, totals, kout, vout);
         }
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
-    *result_in_b = (passes & 1);
-    const int64_t nt = L.n_tiles_total;
-    hipLaunchKernelGGL(k_clear_ranges, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, ranges, nt);
+    hipLaunchKernelGGL(k_clear_ranges, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, ranges, nt, status);
     if (P.capacity > 0)
         hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((P.capacity + 255) / 256)), dim3(256), 0, stream, kin, status,
                            cap, ranges);
+    if (!radix) {
+        // per-list sort from (kin, vin) into (kout, vout)
+        hipLaunchKernelGGL(k_sort_short_lists, dim3((unsigned)nt), dim3(64), 0, stream, ranges, nt, status, cap, kin,
+                           vin, kout, vout, long_list);
+        const int64_t lblocks = nt < 512 ? nt : 512;
+        hipLaunchKernelGGL(k_sort_long_lists, dim3((unsigned)lblocks), dim3(256), 0, stream, ranges, long_list, status,
+                           cap, kin, vin, kout, vout);
+        *result_in_b = (kout == kb) ? 1 : 0;
+    } else {
+        *result_in_b = (kin == kb) ? 1 : 0;
+    }
     return hipGetLastError();
 }
 

@@ -65,12 +65,14 @@ struct Status {
     uint32_t overflow;     // set by bin_sort when n_pairs > capacity
     uint32_t n_big;        // slots with more than kBigRun gradient records (list in ViewLayout::big)
     uint64_t capacity;
-    uint64_t pad[5];
+    uint32_t n_long;       // tiles whose list is sorted by the long-list kernel
+    uint32_t pad1;
+    uint64_t pad[4];
 };
 
 // Offsets into the view workspace (all 256-byte aligned).
 struct ViewLayout {
-    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, total;
+    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, total;
     int64_t n, n_views, n_tiles_total, scan_blocks;
 };
 
@@ -108,7 +110,11 @@ constexpr int kBigChunks = 16;
 __host__ __device__ inline int big_chunk_start(int c, int nrec) {
     return (int)(((int64_t)c * nrec) / kBigChunks);
 }
-hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, char* pws,
+// Pairs are sorted per tile (count, scan, scatter, per-list sort) unless
+// `radix` selects the global LSD radix sort of the full keys.
+// Which pair buffer (0: a, 1: b) holds the sorted pairs after bin_sort.
+int sorted_buffer(int64_t n_tiles_total, bool radix, int digit_bits);
+hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, char* pws, bool radix,
                            int tile, int digit_bits, int32_t n_views, const linprim_camera* cams,
                            hipStream_t stream, int* result_in_b);
 hipError_t launch_render_fwd(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,

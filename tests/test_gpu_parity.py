@@ -43,14 +43,25 @@ def _oracle_render(oracle_mod, sc, cams, tile, bg):
 
 
 # ------------------------------------------------------------ binning
+def _check_sorted(dbg, s, n_pairs):
+    assert n_pairs == len(s["keys"])
+    assert np.array_equal(dbg["keys"].numpy().view(np.uint64), s["keys"])
+    assert np.array_equal(dbg["values"].numpy().view(np.uint32), s["values"])
+    rg = dbg["ranges"].numpy().view(np.uint32).astype(np.int64)
+    nonempty = s["ranges"][:, 1] > s["ranges"][:, 0]
+    assert np.array_equal(rg[nonempty], s["ranges"][nonempty])
+    assert np.all(rg[~nonempty, 0] == rg[~nonempty, 1])
+
+
+@pytest.mark.parametrize("radix", [False, True])
 @pytest.mark.parametrize("kind", [OCTA, TETRA])
 @pytest.mark.parametrize("tile", [8, 16])
-def test_preprocess_and_sort_bit_exact(oracle_mod, kind, tile):
-    _say(f"binning kind={kind} tile={tile}")
+def test_preprocess_and_sort_bit_exact(oracle_mod, kind, tile, radix):
+    _say(f"binning kind={kind} tile={tile} radix={radix}")
     sc = _scene_small(kind, 800, seed=5)
     cams = [scenes.look_at((0.3, -0.2, -3.2), (0, 0, 0), 96, 72),
             scenes.look_at((3.0, 0.4, 0.2), (0, 0, 0), 50, 37)]
-    g = GC.gpu_forward(sc, cams, tile=tile)
+    g = GC.gpu_forward(sc, cams, tile=tile, radix=radix)
     dbg = g["rast"].debug_arrays(g["prims"])
     O = oracle_mod.OracleScene(sc, cams, tile=tile)
     for v in range(len(cams)):
@@ -67,14 +78,7 @@ def test_preprocess_and_sort_bit_exact(oracle_mod, kind, tile):
     tiles_all = dbg["tiles"].numpy().astype(np.int64)
     offs = dbg["offsets"].numpy().view(np.uint32).astype(np.int64)
     assert np.array_equal(offs, np.concatenate([[0], np.cumsum(tiles_all)[:-1]]))
-    s = O.sort()
-    assert g["n_pairs"] == len(s["keys"])
-    assert np.array_equal(dbg["keys"].numpy().view(np.uint64), s["keys"])
-    assert np.array_equal(dbg["values"].numpy().view(np.uint32), s["values"])
-    rg = dbg["ranges"].numpy().view(np.uint32).astype(np.int64)
-    nonempty = s["ranges"][:, 1] > s["ranges"][:, 0]
-    assert np.array_equal(rg[nonempty], s["ranges"][nonempty])
-    assert np.all(rg[~nonempty, 0] == rg[~nonempty, 1])
+    _check_sorted(dbg, O.sort(), g["n_pairs"])
 
 
 @pytest.mark.parametrize("digit", [4, 5, 7, 8])
@@ -82,11 +86,26 @@ def test_sort_digit_widths(oracle_mod, digit):
     _say(f"sort digit={digit}")
     sc = _scene_small(OCTA, 500, seed=9)
     cams = [scenes.look_at((0, 0, -3.0), (0, 0, 0), 64, 64)]
-    g = GC.gpu_forward(sc, cams, tile=8, digit=digit)
+    g = GC.gpu_forward(sc, cams, tile=8, digit=digit, radix=True)
     dbg = g["rast"].debug_arrays(g["prims"])
-    s = oracle_mod.OracleScene(sc, cams, tile=8).sort()
-    assert np.array_equal(dbg["keys"].numpy().view(np.uint64), s["keys"])
-    assert np.array_equal(dbg["values"].numpy().view(np.uint32), s["values"])
+    _check_sorted(dbg, oracle_mod.OracleScene(sc, cams, tile=8).sort(), g["n_pairs"])
+
+
+@pytest.mark.parametrize("n", [300, 3000, 9500])
+def test_sort_long_lists(oracle_mod, n):
+    """Tile lists of a few hundred (sorted in LDS) and of more than 4096
+    pairs (LDS-sorted chunks, then merged): large primitives seen at close
+    range on a small image with 32-pixel tiles, two views of uneven size."""
+    _say(f"sort long lists n={n}")
+    sc = scenes.uniform_octahedra(n, seed=n, box=0.6, dmin=0.3, dmax=0.6)
+    cams = [scenes.look_at((0.1, 0.2, -3.0), (0, 0, 0), 70, 50), scenes.look_at((2.5, 0.3, 1.5), (0, 0, 0), 40, 33)]
+    for radix in (False, True):
+        g = GC.gpu_forward(sc, cams, tile=32, radix=radix)
+        dbg = g["rast"].debug_arrays(g["prims"])
+        s = oracle_mod.OracleScene(sc, cams, tile=32).sort()
+        lens = s["ranges"][:, 1] - s["ranges"][:, 0]
+        _say(f"  radix={radix} longest list {lens.max()}")
+        _check_sorted(dbg, s, g["n_pairs"])
 
 
 # ------------------------------------------------------------ forward
