@@ -85,8 +85,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
     double dx = (double)means[3 * i + 0] - V.cam_pos[0];
     double dy = (double)means[3 * i + 1] - V.cam_pos[1];
     double dz = (double)means[3 * i + 2] - V.cam_pos[2];
-    const double dn = sqrt(dx * dx + dy * dy + dz * dz);
-    dx /= dn; dy /= dn; dz /= dn;
+    const double idn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    dx *= idn; dy *= idn; dz *= idn;
     constexpr int K = (DEG + 1) * (DEG + 1);
     float shv[48];
     load_sh<DEG>(sh + (int64_t)i * K * 3, shv);
@@ -134,7 +134,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
                 nu[c] = kSlab[s][0] * N[c] + kSlab[s][1] * N[3 + c] + kSlab[s][2] * N[6 + c];
             const double nl = sqrt(nu[0] * nu[0] + nu[1] * nu[1] + nu[2] * nu[2]);
             const double nz = clamp_nz(nu[2], nl);
-            const double A = -nu[0] / nz, B = -nu[1] / nz, W = 1.0 / fabs(nz);
+            const double inz = 1.0 / nz;
+            const double A = -nu[0] * inz, B = -nu[1] * inz, W = fabs(inz);
             const double ctr = A * ox + B * oy;
             out[R_PLANES + 4 * s + 0] = (float)A;
             out[R_PLANES + 4 * s + 1] = (float)B;
@@ -158,7 +159,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
             if (to_f > 0.0) { nv[0] = -nv[0]; nv[1] = -nv[1]; nv[2] = -nv[2]; }
             const double nlen = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
             const double nz = clamp_nz(nv[2], nlen);
-            const double A = -nv[0] / nz, B = -nv[1] / nz;
+            const double inz = 1.0 / nz;
+            const double A = -nv[0] * inz, B = -nv[1] * inz;
             pA[f] = A;
             pB[f] = B;
             pD[f] = P0[2] - A * P0[0] - B * P0[1] + A * ox + B * oy;

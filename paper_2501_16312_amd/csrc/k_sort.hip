@@ -124,6 +124,18 @@ __global__ __launch_bounds__(64) void k_sort_short_lists(const uint2* __restrict
         if (lane == 0) long_list[atomicAdd(&status->n_long, 1u)] = (uint32_t)g;
         return;
     }
+    if (len <= 64) {
+        // one pair per lane
+        const uint64_t k = (lane < len) ? depth_index(in_keys, in_vals, rg.x + lane) : ~0ull;
+        uint32_t rank = 0;
+        for (int j = 0; j < len; ++j) {
+            const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(k >> 32), j) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k, j);
+            rank += (kj < k) ? 1u : 0u;
+        }
+        if (lane < len) put_sorted((uint64_t)g, k, rg.x + rank, keys, vals);
+        return;
+    }
     uint64_t k[PER];
     uint32_t rank[PER];
 #pragma unroll
