@@ -105,7 +105,8 @@ typedef struct linprim_tuning {
 #define LINPRIM_FLAG_RADIX_SORT 4
 
 /* Bytes of the per-view workspace (payloads, counts, offsets, tile ranges,
- * status) for n primitives of `type` over n_views cameras. */
+ * status) for n primitives of `type` over n_views cameras; 0 for invalid
+ * arguments, including n * n_views >= 2^32. */
 size_t linprim_view_workspace_size(int32_t type, int64_t n, const linprim_camera *cams,
                                    int32_t n_views, const linprim_tuning *tuning);
 

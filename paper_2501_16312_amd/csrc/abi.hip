@@ -34,10 +34,11 @@ ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, i
     L.depth_keys = off; off = align256(off + (size_t)vn * 4);
     L.tiles = off; off = align256(off + (size_t)vn * 4);
     L.offsets = off; off = align256(off + (size_t)vn * 4);
-    L.block_sums = off; off = align256(off + (size_t)(L.scan_blocks + 1) * 8);
+    L.block_sums = off; off = align256(off + (size_t)(L.scan_blocks + 1) * 16);   // tile sums, visible counts
     L.ranges = off; off = align256(off + (size_t)L.n_tiles_total * 8);
     L.big = off; off = align256(off + (size_t)vn * 4);
     L.long_list = off; off = align256(off + (size_t)L.n_tiles_total * 4);
+    L.vis = off; off = align256(off + (size_t)vn * 4);
     L.total = off;
     return L;
 }
@@ -92,6 +93,10 @@ bool valid_cams(const linprim_camera* cams, int32_t n_views) {
     return true;
 }
 
+// (view, primitive) slots are indexed with 32-bit integers in the lists the
+// scan builds.
+bool valid_slots(int64_t n, int32_t n_views) { return n * (int64_t)n_views < (int64_t(1) << 32); }
+
 bool valid_prims(const linprim_prims* p) {
     if (!p) return false;
     if (p->type != LINPRIM_OCTAHEDRON && p->type != LINPRIM_TETRAHEDRON) return false;
@@ -133,7 +138,7 @@ extern "C" {
 size_t linprim_view_workspace_size(int32_t type, int64_t n, const linprim_camera* cams, int32_t n_views,
                                    const linprim_tuning* tuning) {
     if ((type != LINPRIM_OCTAHEDRON && type != LINPRIM_TETRAHEDRON) || n < 0 || !valid_cams(cams, n_views) ||
-        !valid_tuning(tuning))
+        !valid_tuning(tuning) || !valid_slots(n, n_views))
         return 0;
     return view_layout(n, cams, n_views, tile_of(tuning)).total;
 }
@@ -147,7 +152,8 @@ size_t linprim_pair_workspace_size(int64_t max_pairs, const linprim_camera* cams
 
 int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
                        const linprim_tuning* tuning, void* view_ws, size_t view_ws_bytes, void* stream) {
-    if (!valid_prims(prims) || !valid_cams(cams, n_views) || !valid_tuning(tuning) || !view_ws)
+    if (!valid_prims(prims) || !valid_cams(cams, n_views) || !valid_tuning(tuning) || !view_ws ||
+        !valid_slots(prims->n, n_views))
         return LINPRIM_ERR_INVALID_ARG;
     const int tile = tile_of(tuning);
     const ViewLayout L = view_layout(prims->n, cams, n_views, tile);
@@ -165,7 +171,7 @@ int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, i
 
 int linprim_upload_views(const linprim_camera* cams, int32_t n_views, const linprim_tuning* tuning, void* view_ws,
                          size_t view_ws_bytes, int64_t n, int32_t type, void* stream) {
-    if (!valid_cams(cams, n_views) || !valid_tuning(tuning) || !view_ws || n < 0 ||
+    if (!valid_cams(cams, n_views) || !valid_tuning(tuning) || !view_ws || n < 0 || !valid_slots(n, n_views) ||
         (type != LINPRIM_OCTAHEDRON && type != LINPRIM_TETRAHEDRON))
         return LINPRIM_ERR_INVALID_ARG;
     const int tile = tile_of(tuning);
@@ -191,7 +197,7 @@ static int prepare(const linprim_prims* prims, const linprim_camera* cams, int32
                    const linprim_tuning* tuning, size_t view_ws_bytes, size_t pair_ws_bytes, int64_t max_pairs,
                    ViewLayout& L, PairLayout& P) {
     if (!valid_prims(prims) || !valid_cams(cams, n_views) || !valid_tuning(tuning) || max_pairs < 0 ||
-        max_pairs >= (int64_t(1) << 31))
+        max_pairs >= (int64_t(1) << 31) || !valid_slots(prims->n, n_views))
         return LINPRIM_ERR_INVALID_ARG;
     L = view_layout(prims->n, cams, n_views, tile_of(tuning));
     P = pair_layout(max_pairs, digit_of(tuning), tile_of(tuning));

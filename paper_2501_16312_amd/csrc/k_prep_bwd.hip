@@ -170,14 +170,16 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
                                                   int64_t n, const ViewInfo* __restrict__ views,
                                                   const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
                                                   const uint32_t* __restrict__ offsets, float* __restrict__ grads,
-                                                  int nq, const Status* __restrict__ status, uint64_t capacity) {
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                  int nq, const Status* __restrict__ status, uint64_t capacity,
+                                                  const uint32_t* __restrict__ vis) {
+    // one thread per (view, primitive) slot that touches a tile, taken from
+    // the list the scan built, so that no lane idles on a culled slot
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (status->n_pairs > capacity) return;
-    const int v = blockIdx.y;
-    if (slot >= n) return;
-    const int64_t vs = (int64_t)v * n + slot;
-    if (tiles[vs] == 0) return;
-    const int64_t i = slot;
+    if (t >= (int64_t)status->n_vis) return;
+    const int64_t vs = vis[t];
+    const int v = (int)(vs / n);
+    const int64_t i = vs - (int64_t)v * n;
     constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
     float4* rp = reinterpret_cast<float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
     const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
@@ -481,7 +483,8 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
     const unsigned big_blocks = (unsigned)(max_waves < 1024 ? (max_waves > 0 ? max_waves : 1) : 1024);
     hipLaunchKernelGGL(k_sum_big, dim3(big_blocks), dim3(256), 0, stream, payload, tiles, offsets, big, tile, st, cap,
                        grads);
-    const dim3 g1((unsigned)((p.n + 127) / 128), (unsigned)n_views);
+    const dim3 g1((unsigned)((vn + 127) / 128));
+    const uint32_t* vis = reinterpret_cast<const uint32_t*>(vws + L.vis);
     const dim3 g2((unsigned)((p.n + 127) / 128));
 #define LP_PRIM(K_, D_)                                                                                        \
     hipLaunchKernelGGL((k_prim_bwd<K_, D_>), g2, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, p.sh, \
@@ -496,11 +499,11 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
     }
     if (p.type == LINPRIM_OCTAHEDRON) {
         hipLaunchKernelGGL(k_slot_bwd<LINPRIM_OCTAHEDRON>, g1, dim3(128), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap);
+                           p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap, vis);
         LP_PRIM_DEG(LINPRIM_OCTAHEDRON)
     } else {
         hipLaunchKernelGGL(k_slot_bwd<LINPRIM_TETRAHEDRON>, g1, dim3(128), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap);
+                           p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap, vis);
         LP_PRIM_DEG(LINPRIM_TETRAHEDRON)
     }
 #undef LP_PRIM_DEG

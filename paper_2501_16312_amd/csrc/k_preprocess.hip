@@ -239,71 +239,106 @@ __device__ inline uint64_t block_exclusive_scan_u64(uint64_t x, uint64_t* lds, u
     return incl - x;
 }
 
+// Per block of kScanItems slots: the sum of the tile counts and the number
+// of slots that touch a tile (block_sums[b] and vis_sums[b]).
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t count,
-                                                     uint64_t* __restrict__ block_sums) {
-    __shared__ uint64_t lds[256];
+                                                     uint64_t* __restrict__ block_sums,
+                                                     uint64_t* __restrict__ vis_sums) {
+    __shared__ uint64_t part[2][4];
     const int64_t base = (int64_t)blockIdx.x * kScanItems;
-    uint64_t s = 0;
+    uint64_t s = 0, c = 0;
     for (int k = 0; k < kScanItems / 256; ++k) {
         const int64_t idx = base + k * 256 + threadIdx.x;
-        if (idx < count) s += in[idx];
+        const uint32_t x = (idx < count) ? in[idx] : 0u;
+        s += x;
+        c += x ? 1u : 0u;
     }
-    uint64_t total;
-    block_exclusive_scan_u64(s, lds, &total);
-    if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+    for (int off = 32; off >= 1; off >>= 1) {
+        s += __shfl_xor(s, off, 64);
+        c += __shfl_xor(c, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[0][threadIdx.x >> 6] = s;
+        part[1][threadIdx.x >> 6] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        block_sums[blockIdx.x] = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        vis_sums[blockIdx.x] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+    }
 }
 
-__global__ __launch_bounds__(256) void k_scan_totals(uint64_t* __restrict__ block_sums, int64_t nblocks,
+__global__ __launch_bounds__(256) void k_scan_totals(uint64_t* __restrict__ block_sums,
+                                                     uint64_t* __restrict__ vis_sums, int64_t nblocks,
                                                      Status* __restrict__ status) {
     __shared__ uint64_t lds[256];
-    uint64_t carry = 0;
+    uint64_t carry = 0, vcarry = 0;
     for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
         const int64_t idx = b0 + threadIdx.x;
         const uint64_t x = (idx < nblocks) ? block_sums[idx] : 0;
-        uint64_t total;
+        const uint64_t y = (idx < nblocks) ? vis_sums[idx] : 0;
+        uint64_t total, vtotal;
         const uint64_t ex = block_exclusive_scan_u64(x, lds, &total);
-        if (idx < nblocks) block_sums[idx] = carry + ex;
+        const uint64_t vex = block_exclusive_scan_u64(y, lds, &vtotal);
+        if (idx < nblocks) {
+            block_sums[idx] = carry + ex;
+            vis_sums[idx] = vcarry + vex;
+        }
         carry += total;
+        vcarry += vtotal;
     }
     if (threadIdx.x == 0) {
         status->n_pairs = carry;
         status->overflow = 0;
         status->n_big = 0;
+        status->n_vis = (uint32_t)vcarry;
     }
 }
 
-// Also appends every slot with more than kBigRun gradient records (tile
-// count x groups per tile) to the big-slot list (in no particular order).
+// Appends a slot to a list (in no particular order) with one atomic per
+// wave and item.
+__device__ inline void wave_append(bool take, uint32_t value, uint32_t* __restrict__ counter,
+                                   uint32_t* __restrict__ list, int lane, uint64_t lt_mask) {
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int leader = __builtin_ctzll(m);
+    uint32_t first = 0;
+    if (lane == leader) first = atomicAdd(counter, (uint32_t)__popcll(m));
+    first = __shfl(first, leader, 64);
+    if (take) list[first + __popcll(m & lt_mask)] = value;
+}
+
+// Also lists, in slot order, the slots that touch a tile (for the
+// preprocessing backward), and, in no particular order, those with more than
+// kBigRun gradient records (tile count x groups per tile).
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t count,
                                                     const uint64_t* __restrict__ block_sums,
+                                                    const uint64_t* __restrict__ vis_sums,
                                                     uint32_t* __restrict__ out, int nq,
-                                                    Status* __restrict__ status, uint32_t* __restrict__ big) {
+                                                    Status* __restrict__ status, uint32_t* __restrict__ big,
+                                                    uint32_t* __restrict__ vis) {
     __shared__ uint64_t lds[256];
     // thread t handles the 16 consecutive elements base + 16 t .. 16 t + 15
     const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * 16;
     uint32_t v[16];
-    uint64_t s = 0;
+    uint64_t s = 0, c = 0;
     for (int k = 0; k < 16; ++k) {
         const int64_t idx = base + k;
         v[k] = (idx < count) ? in[idx] : 0u;
         s += v[k];
+        c += v[k] ? 1u : 0u;
     }
     uint64_t total;
     uint64_t run = block_sums[blockIdx.x] + block_exclusive_scan_u64(s, lds, &total);
+    uint64_t vrun = vis_sums[blockIdx.x] + block_exclusive_scan_u64(c, lds, &total);
     const int lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int k = 0; k < 16; ++k) {
         const int64_t idx = base + k;
         if (idx < count) out[idx] = (uint32_t)run;
         run += v[k];
-        const bool is_big = (int64_t)v[k] * nq > kBigRun;
-        const uint64_t m = __ballot(is_big);
-        if (m) {
-            uint32_t first = 0;
-            if (lane == __builtin_ctzll(m)) first = atomicAdd(&status->n_big, (uint32_t)__popcll(m));
-            first = __shfl(first, __builtin_ctzll(m), 64);
-            if (is_big) big[first + __popcll(m & lt_mask)] = (uint32_t)idx;
-        }
+        if (v[k]) vis[vrun++] = (uint32_t)idx;
+        wave_append((int64_t)v[k] * nq > kBigRun, (uint32_t)idx, &status->n_big, big, lane, lt_mask);
     }
 }
 
@@ -316,11 +351,13 @@ hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stre
     uint32_t* big = reinterpret_cast<uint32_t*>(ws + L.big);
     const int nq = (tile / 8) * (tile / 8);
     const int64_t nb = L.scan_blocks;
-    if (nb > 0) hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(256), 0, stream, bsums, nb, status);
+    uint64_t* vsums = bsums + (nb + 1);
     if (nb > 0)
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, offsets, nq,
-                           status, big);
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums);
+    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(256), 0, stream, bsums, vsums, nb, status);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums,
+                           offsets, nq, status, big, reinterpret_cast<uint32_t*>(ws + L.vis));
     return hipGetLastError();
 }
 

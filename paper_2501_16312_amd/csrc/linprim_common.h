@@ -66,13 +66,13 @@ struct Status {
     uint32_t n_big;        // slots with more than kBigRun gradient records (list in ViewLayout::big)
     uint64_t capacity;
     uint32_t n_long;       // tiles whose list is sorted by the long-list kernel
-    uint32_t pad1;
+    uint32_t n_vis;        // (view, primitive) slots that touch a tile (list in ViewLayout::vis)
     uint64_t pad[4];
 };
 
 // Offsets into the view workspace (all 256-byte aligned).
 struct ViewLayout {
-    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, total;
+    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, vis, total;
     int64_t n, n_views, n_tiles_total, scan_blocks;
 };
 
