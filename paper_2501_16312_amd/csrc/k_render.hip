@@ -402,7 +402,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
     const float* base = payload + (size_t)P.v * (size_t)n * kRecordWords;
     const uint32_t* offs = offsets + (size_t)P.v * (size_t)n;
 
-    float T = 1.0f, B0 = 0.0f, B1 = 0.0f, B2 = 0.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
+    // GB = dL/dC . (colour behind the current step), kept as one running
+    // dot product (the colour behind itself is not needed)
+    float T = 1.0f, GB = 0.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
     int last = (int)rg.x;
     if (valid) {
         const int64_t p = (int64_t)y * P.W + x;
@@ -414,10 +416,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
         G0 = gi[p];
         G1 = gi[hw + p];
         G2 = gi[2 * hw + p];
-        // colour behind the current step (absolute); starts with T_final bg
-        B0 = T * bg0;
-        B1 = T * bg1;
-        B2 = T * bg2;
+        // the colour behind starts as T_final bg
+        GB = T * (G0 * bg0 + G1 * bg1 + G2 * bg2);
     }
     const uint32_t walk_end = (uint32_t)wave_max_int(last);
 
@@ -462,8 +462,37 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             float acc[kGradWords];
             const float ki = pxf - R.fi0, kj = pyf - R.fj0;
             const bool inside = (int)e < last && ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj;
-            int ih, il;
-            const float dch = chord<KIND>(R, ki, kj, ih, il);
+            // chord and the active (lowest upper, highest lower) planes,
+            // the first one in plane order on ties; the chord is the same
+            // number the forward computed
+            float dch;
+            bool eh[4], el[4];
+            int ih = 0, il = 0;
+            if (KIND == LINPRIM_OCTAHEDRON) {
+#pragma clang fp contract(off)
+                float h[4], l[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float u = __builtin_fmaf(R.p[4 * s + 0], ki, R.p[4 * s + 1] * kj);
+                    h[s] = u + R.p[4 * s + 2];
+                    l[s] = u + R.p[4 * s + 3];
+                }
+                const float hi = fminf(fminf(h[0], h[1]), fminf(h[2], h[3]));
+                const float lo = fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3]));
+                dch = hi - lo;
+                bool fh = false, fl = false;
+#pragma unroll
+                for (int s = 0; s < 3; ++s) {
+                    eh[s] = !fh && h[s] == hi;
+                    el[s] = !fl && l[s] == lo;
+                    fh = fh || eh[s];
+                    fl = fl || el[s];
+                }
+                eh[3] = !fh;
+                el[3] = !fl;
+            } else {
+                dch = chord<KIND>(R, ki, kj, ih, il);
+            }
             const bool contributed = inside && dch > 0.0f;
             const float delta = contributed ? dch : 0.0f;
             const float ex = contributed ? chord_exp(R.s2, delta) : 1.0f;
@@ -471,30 +500,30 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             const float o = 1.0f - onemo;
             const float ro = __builtin_amdgcn_rcpf(onemo);
             const float Tk = T * ro;                     // transmittance in front of this primitive
-            // dC/do = T_k rgb - behind / (1 - o)
-            const float dLdo = G0 * (Tk * R.r - B0 * ro) + G1 * (Tk * R.g - B1 * ro) + G2 * (Tk * R.b - B2 * ro);
+            // dL/do = G . (T_k rgb - behind / (1 - o))
+            const float Grgb = G0 * R.r + G1 * R.g + G2 * R.b;
+            const float dLdo = Tk * Grgb - ro * GB;
             const float wk = Tk * o;
             acc[16] = G0 * wk;
             acc[17] = G1 * wk;
             acc[18] = G2 * wk;
-            B0 += wk * R.r;
-            B1 += wk * R.g;
-            B2 += wk * R.b;
+            GB += wk * Grgb;
             T = Tk;
             // not clamped: o = 1 - exp(-sigma chord)
             const bool open = contributed && ex >= kOneMinusOMax;
-            const float gD = open ? dLdo * R.sigma * ex : 0.0f;    // dL/dchord
-            acc[19] = open ? dLdo * delta * ex : 0.0f;             // dL/dsigma
+            const float q = dLdo * ex;
+            const float gD = open ? q * R.sigma : 0.0f;    // dL/dchord
+            acc[19] = open ? q * delta : 0.0f;             // dL/dsigma
             if (KIND == LINPRIM_OCTAHEDRON) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float gh = (ih == s) ? gD : 0.0f;
-                    const float gl = (il == s) ? gD : 0.0f;
+                    const float gh = eh[s] ? gD : 0.0f;
+                    const float gl = el[s] ? gD : 0.0f;
                     const float d = gh - gl;
                     acc[4 * s + 0] = d * ki;
                     acc[4 * s + 1] = d * kj;
                     acc[4 * s + 2] = gh;
-                    acc[4 * s + 3] = -gl;
+                    acc[4 * s + 3] = gl;                   // negated after the reduction
                 }
             } else {
                 const int fh = (R.fmap >> (2 * ih)) & 3;
@@ -514,6 +543,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             float outv = 0.0f;
             if (__ballot(contributed) != 0) outv = wave_reduce20(acc, lane);
             const int ridx = reduce20_index(lane);
+            // octahedra: words 4 s + 3 are dL/dDlo = -sum of the lower-plane terms
+            if (KIND == LINPRIM_OCTAHEDRON && ridx < 16 && (ridx & 3) == 3) outv = -outv;
             if (ridx >= 0) grads[slot * kGradWords + ridx] = outv;
         };
         Rec RA, RB;
