@@ -11,6 +11,8 @@ comparison (500,000 octahedra, 16 views of mixed resolution: one
 graph-captured multi-view step against 16 per-view plain launches) unless
 --no-batched is given.
 
+--workload batched runs only the batched-views comparison.
+
 --workload copy times a plain device copy of known size (the calibration
 of the HBM byte counters).
 
@@ -61,7 +63,7 @@ def _traffic(kernel_key, src_file):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, cams, grad, band_rows, threads, min_seconds=10.0, max_repeats=3):
+def cpu_baseline(scene, cams, grad, band_rows, threads, min_seconds=10.0, max_repeats=10):
     """FP64 oracle on a bounded sample: every primitive preprocessed and
     sorted, then a band of image rows (the whole frame by default)
     composited and back-propagated, repeated until about min_seconds of CPU
@@ -182,10 +184,10 @@ def batched_comparison(args, log):
     grad = torch.as_tensor(scenes.image_gradient(cams, seed=2), device="cuda")
     mp = sum(c.width * c.height for c in cams) / 1e6
     tuned = autotune(prims, cams, grad, None)
-    tile, digit = tuned["tile"], tuned["sort_digit_bits"]
-    log(f"batched: autotuned tile {tile}, digit {digit} ({tuned['table']})")
+    tile, digit, radix = tuned["tile"], tuned["sort_digit_bits"], tuned["radix_sort"]
+    log(f"batched: autotuned tile {tile}, radix sort {radix}, digit {digit} ({tuned['table']})")
 
-    rast = Rasterizer(scene.kind, scene.n, cams, tile=tile, sort_digit_bits=digit, headroom=1.05)
+    rast = Rasterizer(scene.kind, scene.n, cams, tile=tile, sort_digit_bits=digit, headroom=1.05, radix_sort=radix)
     cap = CapturedStep(rast, prims, None, grad_rgb=grad, headroom=1.05)
     for _ in range(args.warmup):
         cap.replay()
@@ -200,7 +202,7 @@ def batched_comparison(args, log):
 
     per = []
     for c, g in zip(cams, split_views(grad, cams)):
-        r = Rasterizer(scene.kind, scene.n, [c], tile=tile, sort_digit_bits=digit, headroom=1.05)
+        r = Rasterizer(scene.kind, scene.n, [c], tile=tile, sort_digit_bits=digit, headroom=1.05, radix_sort=radix)
         per.append(Staged(r, prims, None, g))
     acc = {k: torch.empty_like(v) for k, v in per[0].grads.items()}
 
@@ -229,7 +231,9 @@ def batched_comparison(args, log):
     img = float((torch.cat([s.outs[0] for s in per]) - cap.outs[0]).abs().max())
     return {"workload": f"500,000 room-scale octahedra, 16 views on a circle of radius 8, "
                         f"{'/'.join(sorted({f'{c.width}x{c.height}' for c in cams}))}, {mp:.2f} MP per step",
-            "tile": tile, "sort_digit_bits": digit, "graph_ms": round(graph_ms, 3), "per_view_ms": round(per_ms, 3),
+            "megapixels": round(mp, 3), "tile": tile, "radix_sort": radix, "sort_digit_bits": digit,
+            "graph_ms": round(graph_ms, 3),
+            "per_view_ms": round(per_ms, 3),
             "speedup": round(per_ms / graph_ms, 3), "batched_megapixels_per_s": round(mp / (graph_ms * 1e-3), 1),
             "per_view_megapixels_per_s": round(mp / (per_ms * 1e-3), 1), "max_image_diff": img,
             "max_grad_rel_diff": rel, "autotune_ms": {k: round(v, 3) for k, v in tuned["table"].items()}}
@@ -247,7 +251,8 @@ def single(args, log):
     grad_np = scenes.image_gradient(cams, seed=1)
     prims = L.Prims.from_scene(scene)
     grad = torch.as_tensor(grad_np, device="cuda")
-    rast = Rasterizer(scene.kind, scene.n, cams, tile=args.tile, sort_digit_bits=args.digit, headroom=1.05)
+    rast = Rasterizer(scene.kind, scene.n, cams, tile=args.tile, sort_digit_bits=args.digit, headroom=1.05,
+                      radix_sort=args.radix_sort)
     st = Staged(rast, prims, (0.0, 0.0, 0.0), grad)
     log(f"pairs {rast.n_pairs}, capacity {rast.max_pairs}")
     for _ in range(args.warmup):
@@ -283,7 +288,7 @@ def single(args, log):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "1,000,000 octahedra (256-component room-scale mixture, extent 20), one "
                                "1920x1080 view, 60 deg vertical fov, forward + backward", "tile": args.tile,
-                   "sort_digit_bits": args.digit, "pairs": int(n_pairs)},
+                   "sort": f"radix{args.digit}" if args.radix_sort else "per-tile", "pairs": int(n_pairs)},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "pair_counts": {"iterated": counts[0], "evaluated": counts[1], "intersected": counts[2]},
         "roofline": roofline,
@@ -317,7 +322,8 @@ def steploop(args, log):
     pp = L.Prims.from_scene(pert)
     targets, max_pairs = [], 0
     for cams in pool:
-        tr = Rasterizer(scene.kind, scene.n, cams, tile=args.tile, sort_digit_bits=args.digit)
+        tr = Rasterizer(scene.kind, scene.n, cams, tile=args.tile, sort_digit_bits=args.digit,
+                        radix_sort=args.radix_sort)
         targets.append(tr.forward(pp, None)[0].clone())
         max_pairs = max(max_pairs, tr.n_pairs)
         del tr
@@ -342,6 +348,7 @@ def steploop(args, log):
         groups.append(grp)
     n_params = sum(g.numel() for g in grads.values())
     rast = Rasterizer(scene.kind, scene.n, pool[0], tile=args.tile, sort_digit_bits=args.digit,
+                      radix_sort=args.radix_sort,
                       views_resident=True, headroom=1.3)
     rast.reserve_pairs(max_pairs)
     target = targets[0].clone()
@@ -399,7 +406,8 @@ def steploop(args, log):
         "config": {"workload": f"3,000,000 room-scale octahedra (extent 40); per step a batch of 8 random "
                                f"1920x1080 views from a pool of {len(pool)}, L1 to targets rendered from a "
                                f"perturbed copy; fwd + bwd + L1 + fused Adam in one graph",
-                   "tile": args.tile, "sort_digit_bits": args.digit, "pairs_last": int(n_pairs),
+                   "tile": args.tile, "sort": f"radix{args.digit}" if args.radix_sort else "per-tile",
+                   "pairs_last": int(n_pairs),
                    "params": n_params},
         "megapixels_per_s": round(mp / (ms * 1e-3), 1),
         "peak_hbm_gb": round(peak / 1e9, 3),
@@ -410,6 +418,17 @@ def steploop(args, log):
         "roofline": roofline_of(scene.kind, stage_ms, counts),
         "cpu_baseline": None,
     }
+
+
+def batched(args, log):
+    """The batched-views comparison on its own (500k octahedra, 16 views)."""
+    b = batched_comparison(args, log)
+    mp = b["megapixels"]
+    return {"metric": "batched vs per-view speedup, 500k octahedra x 16 views", "value": b["speedup"],
+            "unit": "x", "n_gpus": 1, "steps": max(args.batched_steps, 1), "warmup": args.warmup,
+            "ms_per_step": b["graph_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic", "config": {"workload": b["workload"], "megapixels": mp},
+            "batched": b}
 
 
 def copy_calibration(args, log):
@@ -439,11 +458,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=("single", "steploop", "copy"), default="single")
+    ap.add_argument("--workload", choices=("single", "batched", "steploop", "copy"), default="single")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--view-batches", type=int, default=4)
     ap.add_argument("--tile", type=int, default=8)
     ap.add_argument("--digit", type=int, default=8)
+    ap.add_argument("--radix-sort", action="store_true", help="global LSD radix sort instead of the per-tile sort")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=10)
@@ -460,7 +480,7 @@ def main():
     import torch
     log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
     torch.cuda.set_device(0)
-    run = {"single": single, "steploop": steploop, "copy": copy_calibration}[args.workload]
+    run = {"single": single, "batched": batched, "steploop": steploop, "copy": copy_calibration}[args.workload]
     out = run(args, log)
     print(json.dumps(out), flush=True)
 

@@ -1,9 +1,10 @@
 """Autotuner for the rasterizer's launch configuration.
 
-Times the full forward + backward step for each candidate (screen tile edge
-in {8, 16, 32}, radix-sort digit width) on the caller's own primitives,
-cameras and loss gradient, and keeps the fastest.  Results are cached in
-memory and, optionally, in a JSON file, keyed by device, primitive type,
+Times the full forward + backward step for each candidate -- screen tile
+edge in {8, 16, 32} and the pair sort (per-tile sort, or the global LSD
+radix sort with its digit width) -- on the caller's own primitives, cameras
+and loss gradient, and keeps the fastest.  Results are cached in memory
+and, optionally, in a JSON file, keyed by device, primitive type,
 primitive-count bucket and the list of image sizes.
 
 The list walk of the render kernels is batched 64 entries at a time (one
@@ -22,7 +23,8 @@ from . import linprim as L
 from .graph import PlainStep
 from .render import Rasterizer
 
-DEFAULT_CANDIDATES = ((8, 8), (16, 8), (32, 8), (16, 7), (8, 7))
+# (tile, radix sort?, digit bits)
+DEFAULT_CANDIDATES = ((8, False, 8), (16, False, 8), (32, False, 8), (8, True, 8), (16, True, 7))
 
 _memo: dict = {}
 
@@ -34,8 +36,8 @@ def cache_key(kind: int, n: int, cams: Sequence) -> str:
     return f"{dev}|{kind}|2^{bucket}|{sizes}"
 
 
-def _time_config(prims: L.Prims, cams, tile: int, digit: int, grad, bg, reps: int) -> float:
-    rast = Rasterizer(prims.kind, prims.n, cams, tile=tile, sort_digit_bits=digit, headroom=1.05)
+def _time_config(prims: L.Prims, cams, tile: int, radix: bool, digit: int, grad, bg, reps: int) -> float:
+    rast = Rasterizer(prims.kind, prims.n, cams, tile=tile, sort_digit_bits=digit, headroom=1.05, radix_sort=radix)
     step = PlainStep(rast, prims, bg, grad)
     step.run()
     torch.cuda.synchronize()
@@ -55,7 +57,7 @@ def _time_config(prims: L.Prims, cams, tile: int, digit: int, grad, bg, reps: in
 
 def autotune(prims: L.Prims, cams: Sequence, grad_rgb: torch.Tensor, bg=None, candidates=DEFAULT_CANDIDATES,
              reps: int = 3, cache_file: Optional[str] = None) -> dict:
-    """Returns {"tile": t, "sort_digit_bits": d, "ms": best, "table": {...}}."""
+    """Returns {"tile": t, "radix_sort": r, "sort_digit_bits": d, "ms": best, "table": {...}}."""
     key = cache_key(prims.kind, prims.n, cams)
     if key in _memo:
         return _memo[key]
@@ -65,12 +67,14 @@ def autotune(prims: L.Prims, cams: Sequence, grad_rgb: torch.Tensor, bg=None, ca
         if key in disk:
             _memo[key] = disk[key]
             return disk[key]
-    table = {}
-    for tile, digit in candidates:
-        table[f"{tile}/{digit}"] = _time_config(prims, cams, tile, digit, grad_rgb, bg, reps)
+    table, conf = {}, {}
+    for tile, radix, digit in candidates:
+        name = f"{tile}/{'radix' + str(digit) if radix else 'tiles'}"
+        table[name] = _time_config(prims, cams, tile, radix, digit, grad_rgb, bg, reps)
+        conf[name] = (tile, radix, digit)
     best = min(table, key=table.get)
-    tile, digit = (int(x) for x in best.split("/"))
-    res = {"tile": tile, "sort_digit_bits": digit, "ms": table[best], "table": table}
+    tile, radix, digit = conf[best]
+    res = {"tile": tile, "radix_sort": radix, "sort_digit_bits": digit, "ms": table[best], "table": table}
     _memo[key] = res
     if cache_file:
         disk = {}
