@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_sum_big(const float* __restrict__ paylo
 
 // Colour backward along the viewing direction, one basis function at a
 // time (single precision): gsh_k += grgb Y_k, gdir += sum_ch grgb sh_k
-// dY_k/ddir.  The basis polynomials are those of sh_eval.
+// dY_k/ddir.  The basis polynomials are those of sh_eval_f.
 struct ShBack {
     int K;
     const float* sh;     // [48] coefficients (registers)

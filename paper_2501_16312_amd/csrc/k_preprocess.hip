@@ -90,15 +90,15 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
     constexpr int K = (DEG + 1) * (DEG + 1);
     float shv[48];
     load_sh<DEG>(sh + (int64_t)i * K * 3, shv);
-    double Y[16];
-    sh_eval(DEG, dx, dy, dz, Y);
+    float Y[16];
+    sh_eval_f<DEG>((float)dx, (float)dy, (float)dz, Y);
     float rgb[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double acc = 0.0;
+        float acc = 0.0f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc += (double)shv[3 * k + c] * Y[k];
-        rgb[c] = (float)fmax(acc + 0.5, 0.0);
+        for (int k = 0; k < K; ++k) acc = __builtin_fmaf(shv[3 * k + c], Y[k], acc);
+        rgb[c] = fmaxf(acc + 0.5f, 0.0f);
     }
 
     float out[kRecordWords];

@@ -337,68 +337,39 @@ __device__ inline ShConst sh_constants() {
     return K;
 }
 
-__device__ inline void sh_eval(int deg, double x, double y, double z, double Y[16]) {
+// The basis in single precision, degree fixed at compile time (the colour
+// only needs float accuracy; the constants are computed in double from
+// their closed forms and rounded once).
+template <int DEG>
+__device__ inline void sh_eval_f(float x, float y, float z, float Y[16]) {
     const ShConst K = sh_constants();
-    for (int k = 0; k < 16; ++k) Y[k] = 0.0;
-    Y[0] = K.c0;
-    if (deg >= 1) {
-        Y[1] = -K.c1 * y;
-        Y[2] = K.c1 * z;
-        Y[3] = -K.c1 * x;
+    const float c0 = (float)K.c0, c1 = (float)K.c1, c2a = (float)K.c2a, c2b = (float)K.c2b, c2c = (float)K.c2c;
+    const float c3a = (float)K.c3a, c3b = (float)K.c3b, c3c = (float)K.c3c, c3d = (float)K.c3d, c3e = (float)K.c3e;
+    Y[0] = c0;
+    if (DEG >= 1) {
+        Y[1] = -c1 * y;
+        Y[2] = c1 * z;
+        Y[3] = -c1 * x;
     }
-    if (deg >= 2) {
-        Y[4] = K.c2a * x * y;
-        Y[5] = -K.c2a * y * z;
-        Y[6] = K.c2b * (2.0 * z * z - x * x - y * y);
-        Y[7] = -K.c2a * x * z;
-        Y[8] = K.c2c * (x * x - y * y);
-    }
-    if (deg >= 3) {
-        Y[9] = -K.c3a * y * (3.0 * x * x - y * y);
-        Y[10] = K.c3b * x * y * z;
-        Y[11] = -K.c3c * y * (4.0 * z * z - x * x - y * y);
-        Y[12] = K.c3d * z * (2.0 * z * z - 3.0 * x * x - 3.0 * y * y);
-        Y[13] = -K.c3c * x * (4.0 * z * z - x * x - y * y);
-        Y[14] = K.c3e * z * (x * x - y * y);
-        Y[15] = -K.c3a * x * (x * x - 3.0 * y * y);
+    if (DEG >= 2) {
+        const float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = c2a * x * y;
+        Y[5] = -c2a * y * z;
+        Y[6] = c2b * (2.0f * zz - xx - yy);
+        Y[7] = -c2a * x * z;
+        Y[8] = c2c * (xx - yy);
+        if (DEG >= 3) {
+            Y[9] = -c3a * y * (3.0f * xx - yy);
+            Y[10] = c3b * x * y * z;
+            Y[11] = -c3c * y * (4.0f * zz - xx - yy);
+            Y[12] = c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -c3c * x * (4.0f * zz - xx - yy);
+            Y[14] = c3e * z * (xx - yy);
+            Y[15] = -c3a * x * (xx - 3.0f * yy);
+        }
     }
 }
 
-// Gradient of every basis function with respect to the (unnormalised)
-// direction components, used by the backward pass.
-__device__ inline void sh_eval_grad(int deg, double x, double y, double z, double G[16][3]) {
-    const ShConst K = sh_constants();
-    for (int k = 0; k < 16; ++k) G[k][0] = G[k][1] = G[k][2] = 0.0;
-    if (deg >= 1) {
-        G[1][1] = -K.c1;
-        G[2][2] = K.c1;
-        G[3][0] = -K.c1;
-    }
-    if (deg >= 2) {
-        G[4][0] = K.c2a * y; G[4][1] = K.c2a * x;
-        G[5][1] = -K.c2a * z; G[5][2] = -K.c2a * y;
-        G[6][0] = -2.0 * K.c2b * x; G[6][1] = -2.0 * K.c2b * y; G[6][2] = 4.0 * K.c2b * z;
-        G[7][0] = -K.c2a * z; G[7][2] = -K.c2a * x;
-        G[8][0] = 2.0 * K.c2c * x; G[8][1] = -2.0 * K.c2c * y;
-    }
-    if (deg >= 3) {
-        G[9][0] = -6.0 * K.c3a * x * y;
-        G[9][1] = -K.c3a * (3.0 * x * x - 3.0 * y * y);
-        G[10][0] = K.c3b * y * z; G[10][1] = K.c3b * x * z; G[10][2] = K.c3b * x * y;
-        G[11][0] = 2.0 * K.c3c * x * y;
-        G[11][1] = -K.c3c * (4.0 * z * z - x * x - 3.0 * y * y);
-        G[11][2] = -8.0 * K.c3c * y * z;
-        G[12][0] = -6.0 * K.c3d * x * z;
-        G[12][1] = -6.0 * K.c3d * y * z;
-        G[12][2] = K.c3d * (6.0 * z * z - 3.0 * x * x - 3.0 * y * y);
-        G[13][0] = -K.c3c * (4.0 * z * z - 3.0 * x * x - y * y);
-        G[13][1] = 2.0 * K.c3c * x * y;
-        G[13][2] = -8.0 * K.c3c * x * z;
-        G[14][0] = 2.0 * K.c3e * x * z; G[14][1] = -2.0 * K.c3e * y * z; G[14][2] = K.c3e * (x * x - y * y);
-        G[15][0] = -K.c3a * (3.0 * x * x - 3.0 * y * y);
-        G[15][1] = 6.0 * K.c3a * x * y;
-    }
-}
 
 // Loads the (DEG+1)^2 x 3 SH coefficients of one primitive into registers,
 // every load issued before the first use (16-byte loads for degree 3).
