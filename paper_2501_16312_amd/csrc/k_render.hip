@@ -291,7 +291,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
             // Branch-free: lanes that do not see the primitive blend with
             // 1 - o = 1 exactly, which leaves C and T unchanged.
             const float ki = pxf - R.fi0, kj = pyf - R.fj0;
-            const bool inside = !done && ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj;
+            // bitwise &: every test is a plain compare, no short-circuit branches
+            const bool inside = !done & (ki >= 0.0f) & (ki <= R.fwi) & (kj >= 0.0f) & (kj <= R.fwj);
             const float dch = chord_fast<KIND>(R, ki, kj);
             const bool hitp = inside && dch > 0.0f;
             if (COUNT) {
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             // zero gradients.
             float acc[kGradWords];
             const float ki = pxf - R.fi0, kj = pyf - R.fj0;
-            const bool inside = (int)e < last && ki >= 0.0f && ki <= R.fwi && kj >= 0.0f && kj <= R.fwj;
+            const bool inside = ((int)e < last) & (ki >= 0.0f) & (ki <= R.fwi) & (kj >= 0.0f) & (kj <= R.fwj);
             // chord and the active (lowest upper, highest lower) planes,
             // the first one in plane order on ties; the chord is the same
             // number the forward computed

@@ -18,44 +18,47 @@ __device__ inline void emit_pair(uint64_t g, uint32_t depth, uint32_t prim, uint
     vals[slot] = prim;
 }
 
-// One thread per (primitive, view) slot; one (key, value) pair per tile of
-// the slot's tile rectangle, row-major, at the slot's offset.
+// One thread per (view, primitive) slot that touches a tile (from the
+// scan's list, in slot order); one (key, value) pair per tile of the slot's
+// tile rectangle, row-major, at the slot's offset.
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ depth_keys,
-                                               const uint32_t* __restrict__ tiles,
-                                               const uint32_t* __restrict__ offsets,
-                                               const float* __restrict__ payload, const ViewInfo* __restrict__ views,
-                                               int64_t n, int tile_shift, Status* __restrict__ status,
-                                               uint64_t capacity, uint64_t* __restrict__ keys,
-                                               uint32_t* __restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y;
+                                                    const uint32_t* __restrict__ tiles,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    const float* __restrict__ payload,
+                                                    const ViewInfo* __restrict__ views, const uint32_t* __restrict__ vis,
+                                                    int64_t n, int tile_shift, Status* __restrict__ status,
+                                                    uint64_t capacity, uint64_t* __restrict__ keys,
+                                                    uint32_t* __restrict__ vals) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const uint64_t npairs = status->n_pairs;
     if (npairs > capacity) {
-        if (i == 0 && v == 0) status->overflow = 1;
+        if (t == 0) status->overflow = 1;
         return;
     }
-    const ViewInfo& V = views[v];
-    const int64_t slot = (int64_t)v * n + i;
-    uint32_t cnt = 0;
+    const int64_t n_vis = status->n_vis;
+    if (t - lane >= n_vis) return;    // whole wave past the list
+    uint32_t cnt = 0, key = 0, off = 0, prim = 0;
+    int v = 0;
     int4 r = make_int4(0, 0, 0, 0);
-    uint32_t key = 0, off = 0;
-    if (i < n) {
-        cnt = tiles[slot];
-        if (cnt) {
-            r = reinterpret_cast<const int4*>(payload + slot * kRecordWords)[0];
-            key = depth_keys[slot];
-            off = offsets[slot];
-        }
+    if (t < n_vis) {
+        const int64_t vs = vis[t];
+        v = (int)(vs / n);
+        prim = (uint32_t)(vs - (int64_t)v * n);
+        cnt = tiles[vs];
+        r = reinterpret_cast<const int4*>(payload + vs * kRecordWords)[0];
+        key = depth_keys[vs];
+        off = offsets[vs];
     }
     const int tx0 = r.x >> tile_shift, ty0 = r.y >> tile_shift;
     const int ntx = (r.z >> tile_shift) - tx0 + 1;
     // short runs: one lane writes them in row-major tile order
     if (cnt > 0 && cnt <= 32) {
-        for (uint32_t t = 0; t < cnt; ++t) {
-            const int tx = tx0 + (int)(t % ntx), ty = ty0 + (int)(t / ntx);
+        const ViewInfo& V = views[v];
+        for (uint32_t q = 0; q < cnt; ++q) {
+            const int tx = tx0 + (int)(q % ntx), ty = ty0 + (int)(q / ntx);
             const uint64_t g = (uint64_t)(V.tile_base + (int64_t)ty * V.tiles_x + tx);
-            emit_pair(g, key, (uint32_t)i, off + t, keys, vals);
+            emit_pair(g, key, prim, off + q, keys, vals);
         }
     }
     // long runs (near or large primitives): the whole wavefront writes them
@@ -66,13 +69,16 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
         const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cnt, b);
         const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, b);
         const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, b);
+        const uint32_t pb = (uint32_t)__builtin_amdgcn_readlane((int)prim, b);
+        const int vb = __builtin_amdgcn_readlane(v, b);
         const int bx0 = __builtin_amdgcn_readlane(tx0, b), by0 = __builtin_amdgcn_readlane(ty0, b);
         const int bn = __builtin_amdgcn_readlane(ntx, b);
-        const uint32_t idx = (uint32_t)(i - (threadIdx.x & 63) + b);
-        for (uint32_t t = (uint32_t)lane; t < c; t += 64) {
-            const int tx = bx0 + (int)(t % bn), ty = by0 + (int)(t / bn);
-            const uint64_t g = (uint64_t)(V.tile_base + (int64_t)ty * V.tiles_x + tx);
-            emit_pair(g, k, idx, o + t, keys, vals);
+        const int64_t tile_base = views[vb].tile_base;
+        const int tiles_x = views[vb].tiles_x;
+        for (uint32_t q = (uint32_t)lane; q < c; q += 64) {
+            const int tx = bx0 + (int)(q % bn), ty = by0 + (int)(q / bn);
+            const uint64_t g = (uint64_t)(tile_base + (int64_t)ty * tiles_x + tx);
+            emit_pair(g, k, pb, o + q, keys, vals);
         }
     }
 }
@@ -439,11 +445,13 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
     const uint64_t cap = (uint64_t)P.capacity;
     const int64_t nt = L.n_tiles_total;
     if (L.n > 0) {
-        dim3 grid((unsigned)((L.n + 255) / 256), (unsigned)n_views);
-        hipLaunchKernelGGL(k_emit_pairs, grid, dim3(256), 0, stream, reinterpret_cast<const uint32_t*>(vws + L.depth_keys),
+        const int64_t vn = L.n * (int64_t)n_views;
+        hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, stream,
+                           reinterpret_cast<const uint32_t*>(vws + L.depth_keys),
                            reinterpret_cast<const uint32_t*>(vws + L.tiles),
                            reinterpret_cast<const uint32_t*>(vws + L.offsets),
-                           reinterpret_cast<const float*>(vws + L.payload), views, L.n, shift, status, cap, ka, va);
+                           reinterpret_cast<const float*>(vws + L.payload), views,
+                           reinterpret_cast<const uint32_t*>(vws + L.vis), L.n, shift, status, cap, ka, va);
     }
     const int tb = key_tile_bits(nt);
     int passes, digit, key_lo, key_bits;
