@@ -324,8 +324,10 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
                                                                 uint64_t* __restrict__ keys_out,
                                                                 uint32_t* __restrict__ vals_out) {
     __shared__ uint32_t base[256];       // global start of each digit for this block
-    __shared__ uint32_t running[256];    // keys of each digit already placed by this block
+    __shared__ uint32_t running[256];    // keys of each digit ranked so far in this block
     __shared__ uint32_t wave_cnt[kSortThreads / 64][256];
+    __shared__ uint64_t lkey[kSortTile];  // the block's keys in digit order
+    __shared__ uint32_t lval[kSortTile];
     const uint64_t np = status->n_pairs;
     if (np > capacity) return;
     const int radix = 1 << bits;
@@ -352,19 +354,24 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
         for (int w = 0; w < kSortThreads / 64; ++w) wave_cnt[w][d] = 0;
     }
     __syncthreads();
+    // 1. rank of every key among the block's keys of its digit, in index order
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t blk = (int64_t)blockIdx.x * kSortTile;
+    uint64_t key[kSortItems];
+    uint32_t val[kSortItems], dig[kSortItems], rnk[kSortItems];
+#pragma unroll
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = blk + (int64_t)k * kSortThreads + t;
         const bool valid = idx < (int64_t)np;
-        uint64_t key = 0;
-        uint32_t val = 0;
-        uint32_t d = 0;
-        if (valid) {
-            key = keys_in[idx];
-            val = vals_in[idx];
-            d = (uint32_t)(key >> shift) & (uint32_t)(radix - 1);
-        }
+        key[k] = valid ? keys_in[idx] : 0ull;
+        val[k] = valid ? vals_in[idx] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t idx = blk + (int64_t)k * kSortThreads + t;
+        const bool valid = idx < (int64_t)np;
+        const uint32_t d = valid ? (uint32_t)(key[k] >> shift) & (uint32_t)(radix - 1) : 0u;
+        dig[k] = d;
         // lanes of this wave holding the same digit
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) {
@@ -374,22 +381,55 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
         if (valid && rank == 0) wave_cnt[wave][d] = (uint32_t)__popcll(peers);
         __syncthreads();
-        if (valid) {
-            uint32_t pos = base[d] + running[d] + rank;
-            for (int w = 0; w < wave; ++w) pos += wave_cnt[w][d];
-            keys_out[pos] = key;
-            vals_out[pos] = val;
-        }
+        uint32_t pre = running[d] + rank;
+        for (int w = 0; w < wave; ++w) pre += wave_cnt[w][d];
+        rnk[k] = pre;
         __syncthreads();
         for (int dd = t; dd < radix; dd += kSortThreads) {
-            uint32_t s = 0;
+            uint32_t sum = 0;
             for (int w = 0; w < kSortThreads / 64; ++w) {
-                s += wave_cnt[w][dd];
+                sum += wave_cnt[w][dd];
                 wave_cnt[w][dd] = 0;
             }
-            running[dd] += s;
+            running[dd] += sum;
         }
         __syncthreads();
+    }
+    // 2. the block's digit starts (exclusive scan of its digit counts, one
+    //    wave; wave_cnt[0] holds them), keys placed in LDS in digit order
+    if (t < 64) {
+        uint32_t carry = 0;
+        for (int d0 = 0; d0 < radix; d0 += 64) {
+            const int d = d0 + lane;
+            const uint32_t x = (d < radix) ? running[d] : 0u;
+            uint32_t incl = x;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            if (d < radix) wave_cnt[0][d] = carry + incl - x;
+            carry += __shfl(incl, 63, 64);
+        }
+    }
+    __syncthreads();
+    const int nk = (int)min((int64_t)kSortTile, (int64_t)np - blk);
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) {
+        const int64_t idx = blk + (int64_t)k * kSortThreads + t;
+        if (idx < (int64_t)np) {
+            const uint32_t lp = wave_cnt[0][dig[k]] + rnk[k];
+            lkey[lp] = key[k];
+            lval[lp] = val[k];
+        }
+    }
+    __syncthreads();
+    // 3. consecutive threads write consecutive positions of each digit's run
+    for (int i = t; i < nk; i += kSortThreads) {
+        const uint64_t kk = lkey[i];
+        const uint32_t d = (uint32_t)(kk >> shift) & (uint32_t)(radix - 1);
+        const uint32_t pos = base[d] + (uint32_t)i - wave_cnt[0][d];
+        keys_out[pos] = kk;
+        vals_out[pos] = lval[i];
     }
 }
 
