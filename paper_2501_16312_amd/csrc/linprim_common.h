@@ -157,12 +157,15 @@ __device__ inline float dpp_mov(float src) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(src), CTRL, ROW_MASK, 0xF, false));
 }
 
-// Sums 20 per-lane values over the 64 lanes of a wavefront (every lane must
-// be active).  Reduce-scatter: gfx950's permlane32 / permlane16 swaps pair
-// the two halves and then the two rows of each half, so that register j of
-// row r carries value j + 5 r summed over four lanes; four DPP steps finish
-// each row.  Lane L with k = L % 16 < 5 returns the total of value
-// k + 5 (L / 16) (see reduce20_index); other lanes return 0.
+// Sums 20 values over the 64 lanes of a wave and leaves each total in one
+// lane: two cross-half swaps (permlane32 / permlane16) pair the values so
+// that every 16-lane row holds 5 of them, then four DPP steps inside the
+// row each halve the values a lane keeps while doubling the set of lanes
+// they are summed over (row mirror: lane i with 15 - i; half-row mirror:
+// i with 7 - i; quad swaps: i with i ^ 2, then i with i ^ 1).  Lane L of row
+// r = L / 16 ends with the total of value v + 5 r, v = 4 b1 + 2 b2 + b3 from
+// the bits b1, b2, b3 of L; lanes with v >= 5, and the odd lane of each pair
+// that holds a duplicate, do not write (see reduce20_index).
 __device__ inline float wave_reduce20(const float (&v)[20], int lane) {
     float a[10];
 #pragma unroll
@@ -170,33 +173,41 @@ __device__ inline float wave_reduce20(const float (&v)[20], int lane) {
         const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[j + 10]), false, false);
         a[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
-    float b[5];
+    float b[6];
 #pragma unroll
     for (int j = 0; j < 5; ++j) {
         const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[j]), __float_as_uint(a[j + 5]), false, false);
         b[j] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
+    b[5] = 0.0f;
+    const bool h3 = (lane >> 3) & 1, h2 = (lane >> 2) & 1, h1 = (lane >> 1) & 1;
+    float c[4];
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-        b[j] += dpp_mov<0xB1>(b[j]);     // quad_perm(1,0,3,2)
-        b[j] += dpp_mov<0x4E>(b[j]);     // quad_perm(2,3,0,1)
-        b[j] += dpp_mov<0x141>(b[j]);    // row_half_mirror
-        b[j] += dpp_mov<0x140>(b[j]);    // row_mirror
+    for (int p = 0; p < 3; ++p) {                       // lanes i and 15 - i
+        const float keep = h3 ? b[2 * p + 1] : b[2 * p];
+        const float give = h3 ? b[2 * p] : b[2 * p + 1];
+        c[p] = keep + dpp_mov<0x140>(give);
     }
-    // branch-free pick of b[lane & 15] (lanes 5..15 of a row return 0)
-    const int k = lane & 15;
-    float r = (k == 4) ? b[4] : 0.0f;
-    r = (k == 3) ? b[3] : r;
-    r = (k == 2) ? b[2] : r;
-    r = (k == 1) ? b[1] : r;
-    r = (k == 0) ? b[0] : r;
-    return r;
+    c[3] = 0.0f;
+    float d[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {                       // lanes i and 7 - i of a half row
+        const float keep = h2 ? c[2 * q + 1] : c[2 * q];
+        const float give = h2 ? c[2 * q] : c[2 * q + 1];
+        d[q] = keep + dpp_mov<0x141>(give);
+    }
+    const float keep = h1 ? d[1] : d[0];               // lanes i and i ^ 2
+    const float give = h1 ? d[0] : d[1];
+    float e = keep + dpp_mov<0x4E>(give);
+    e += dpp_mov<0xB1>(e);                              // lanes i and i ^ 1
+    return e;
 }
 
-// Which of the 20 totals lane L returns from wave_reduce20 (-1: none).
+// Which of the 20 totals lane L writes after wave_reduce20 (-1: none).
 __device__ inline int reduce20_index(int lane) {
-    const int k = lane & 15;
-    return k < 5 ? k + 5 * (lane >> 4) : -1;
+    const int i = lane & 15;
+    const int v = 4 * ((i >> 1) & 1) + 2 * ((i >> 2) & 1) + ((i >> 3) & 1);
+    return ((i & 1) == 0 && v < 5) ? v + 5 * (lane >> 4) : -1;
 }
 
 // Rotation of q / |q| written with s = 2 / |q|^2 (no square root).  The
