@@ -65,6 +65,8 @@ def _load():
     lib.orc_chord.restype = ctypes.c_double
     lib.orc_chord.argtypes = [P, ctypes.c_int, I64, ctypes.c_double, ctypes.c_double, ctypes.c_int]
     lib.orc_mtia.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+    lib.orc_mtia_ray.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.orc_set_exact.argtypes = [P, ctypes.c_int]
     lib.orc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_backward.argtypes = [P] + [ctypes.c_void_p] * 8
     lib.orc_num_threads.restype = ctypes.c_int
@@ -100,14 +102,28 @@ def mtia(corners, rx: float, ry: float) -> dict:
             "dV": out[5:].reshape(3, 3)}
 
 
+def mtia_ray(corners, direction) -> dict:
+    """Moeller-Trumbore for the ray t * direction from the origin (exact
+    variant) and the derivatives of t with respect to the corners."""
+    V = _f64(corners).reshape(9)
+    D = _f64(direction).reshape(3)
+    out = np.zeros(14)
+    _load().orc_mtia_ray(_ptr(V), _ptr(D), _ptr(out))
+    return {"hit": bool(out[0]), "t": out[1], "u": out[2], "v": out[3], "det": out[4],
+            "dV": out[5:].reshape(3, 3)}
+
+
 def camera_rows(cams) -> np.ndarray:
     return np.stack([c.as_row() for c in cams]).astype(np.float64)
 
 
 class OracleScene:
-    """One scene and a set of views, rendered in double precision."""
+    """One scene and a set of views, rendered in double precision.
 
-    def __init__(self, scene, cams, tile: int = 16, inputs64: Optional[dict] = None):
+    ``exact`` selects the variant without the ray-space approximation: pixel
+    rays from the camera centre meet the camera-space primitives."""
+
+    def __init__(self, scene, cams, tile: int = 16, inputs64: Optional[dict] = None, exact: bool = False):
         lib = _load()
         self.kind = int(scene.kind)
         self.n = int(scene.n)
@@ -136,6 +152,8 @@ class OracleScene:
         if lib.orc_set_views(self.h, len(self.cams), rows.ctypes.data_as(D), self.tile) != 0:
             raise ValueError("oracle rejected the cameras")
         self._sorted = False
+        self.exact = bool(exact)
+        lib.orc_set_exact(self.h, 1 if self.exact else 0)
         lib.orc_preprocess(self.h)
 
     def __del__(self):
@@ -250,5 +268,5 @@ class OracleScene:
         return out
 
 
-def render(scene, cams, bg=None, tile: int = 16, mode: str = "tiled") -> dict:
-    return OracleScene(scene, cams, tile).render(bg, mode)
+def render(scene, cams, bg=None, tile: int = 16, mode: str = "tiled", exact: bool = False) -> dict:
+    return OracleScene(scene, cams, tile, exact=exact).render(bg, mode)

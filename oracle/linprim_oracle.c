@@ -22,7 +22,13 @@
  *   - opacity o = min(1 - exp(-sigma * chord), 0.99);
  *   - compositing stops after the primitive that brings the transmittance
  *     to 1e-3 or below;
- *   - no gradient through min(d) of Eq. 1 (App. G).
+ *   - no gradient through min(d) of Eq. 1 (App. G);
+ *   - exact variant (the appendix on the ray-space approximation): the same
+ *     pipeline without ray space; each pixel ray leaves the camera centre and
+ *     the chord is the Euclidean length of its segment inside the camera-space
+ *     primitive; the bounding box is that of the perspective-projected
+ *     corners, and a primitive with a corner at or in front of the near plane
+ *     is culled (its projection is undefined there).
  *
  * The binning quantities (pixel rectangle, tile rectangle, depth key) are
  * integer decisions.  They are computed in double precision with a fixed
@@ -79,6 +85,8 @@ typedef struct {
     double tc[3];    /* camera-space centre */
     double c[3];     /* ray-space centre */
     double a[4][3];  /* ray-space offsets: octahedron a0..a2, tetrahedron a0..a3 */
+    double oc[4][3]; /* camera-space offsets from the centre to the axes / corners */
+    double vc[6][3]; /* camera-space corners (exact variant) */
     double sigma;
     double rgb[3];
     double raw[3];   /* colour before the clamp at zero */
@@ -86,6 +94,7 @@ typedef struct {
 
 typedef struct {
     int type, deg, K, nd;
+    int exact;               /* 0: EWA ray space (Sec. 3.2); 1: pixel rays in camera space (App. "Ray Space Approximation") */
     int64_t n;
     double *means, *quats, *dists, *opac, *sh;
     int n_views, tile;
@@ -268,6 +277,7 @@ static void preprocess_one(const orc_scene *S, const orc_view *V, int64_t n, orc
     world_offsets(S->type, R, d, o);
     const int na = (S->type == ORC_OCTA) ? 3 : 4;
     for (int k = 0; k < na; ++k) mat3_vec(V->Rw, o[k], oc[k]);
+    memcpy(P->oc, oc, sizeof(oc));
 
     /* ray space: centre c = phi(tc), offsets a_k = J(tc) * oc_k */
     const double iz = 1.0 / tc[2];
@@ -291,6 +301,31 @@ static void preprocess_one(const orc_scene *S, const orc_view *V, int64_t n, orc
             if (xs[s] > xmax) xmax = xs[s];
             if (ys[s] < ymin) ymin = ys[s];
             if (ys[s] > ymax) ymax = ys[s];
+        }
+    }
+    if (S->exact) {
+        /* Without the ray-space approximation the footprint is the
+         * perspective projection of the corners themselves.  A corner at or
+         * behind the near plane has no projection, so such a primitive is
+         * culled; otherwise every point of it lies in front of the camera and
+         * each pixel ray meets it at positive depth only. */
+        const int nc = (S->type == ORC_OCTA) ? 6 : 4;
+        for (int k = 0; k < nc; ++k)
+            for (int r = 0; r < 3; ++r) {
+                if (S->type == ORC_OCTA)
+                    P->vc[k][r] = (k & 1) ? tc[r] - oc[k >> 1][r] : tc[r] + oc[k >> 1][r];
+                else
+                    P->vc[k][r] = tc[r] + oc[k][r];
+            }
+        xmin = INFINITY; xmax = -INFINITY; ymin = INFINITY; ymax = -INFINITY;
+        for (int k = 0; k < nc; ++k) {
+            if (!(P->vc[k][2] > V->near_z)) return;
+            const double xp = V->fx * P->vc[k][0] / P->vc[k][2] + V->cx;
+            const double yp = V->fy * P->vc[k][1] / P->vc[k][2] + V->cy;
+            if (xp < xmin) xmin = xp;
+            if (xp > xmax) xmax = xp;
+            if (yp < ymin) ymin = yp;
+            if (yp > ymax) ymax = yp;
         }
     }
     if (!isfinite(xmin) || !isfinite(xmax) || !isfinite(ymin) || !isfinite(ymax)) return;
@@ -493,71 +528,61 @@ static double l1_of(const double s0[3], const double m[3], double z)
     return fabs(s0[0] + z * m[0]) + fabs(s0[1] + z * m[1]) + fabs(s0[2] + z * m[2]);
 }
 
-static double chord_clip(int type, const orc_prep *P, double rx, double ry)
+/* Length of the interval of z where |s0 + z m|_1 <= 1 (a convex piecewise
+ * linear function): from its smallest breakpoint value walk outwards to the
+ * two crossings of 1. */
+static double l1_chord(const double s0[3], const double m[3])
 {
-    if (type == ORC_OCTA) {
-        double M[3][3];
-        for (int r = 0; r < 3; ++r) for (int k = 0; k < 3; ++k) M[r][k] = P->a[k][r];
-        const double b0[3] = {rx - P->c[0], ry - P->c[1], 0.0};
-        const double ez[3] = {0.0, 0.0, 1.0};
-        double s0[3], m[3];
-        if (!solve3(M, b0, s0) || !solve3(M, ez, m)) return 0.0;
-        double bp[3];
-        int nb = 0;
-        for (int k = 0; k < 3; ++k) if (m[k] != 0.0) bp[nb++] = -s0[k] / m[k];
-        /* sort breakpoints */
-        for (int i = 0; i < nb; ++i)
-            for (int j = i + 1; j < nb; ++j) if (bp[j] < bp[i]) { double t = bp[i]; bp[i] = bp[j]; bp[j] = t; }
-        int best = 0;
-        for (int i = 1; i < nb; ++i) if (l1_of(s0, m, bp[i]) < l1_of(s0, m, bp[best])) best = i;
-        const double zb = bp[best], fb = l1_of(s0, m, zb);
-        if (fb > 1.0) return 0.0;
-        /* walk right from the minimum to the crossing f = 1 */
-        double hi;
-        {
-            double z0 = zb, f0 = fb;
-            int i = best + 1;
-            for (;;) {
-                if (i < nb) {
-                    const double f1 = l1_of(s0, m, bp[i]);
-                    if (f1 > 1.0) { hi = z0 + (1.0 - f0) * (bp[i] - z0) / (f1 - f0); break; }
-                    z0 = bp[i]; f0 = f1; ++i;
-                } else {
-                    const double slope = fabs(m[0]) + fabs(m[1]) + fabs(m[2]);
-                    hi = z0 + (1.0 - f0) / slope;
-                    break;
-                }
+    double bp[3];
+    int nb = 0;
+    for (int k = 0; k < 3; ++k) if (m[k] != 0.0) bp[nb++] = -s0[k] / m[k];
+    /* sort breakpoints */
+    for (int i = 0; i < nb; ++i)
+        for (int j = i + 1; j < nb; ++j) if (bp[j] < bp[i]) { double t = bp[i]; bp[i] = bp[j]; bp[j] = t; }
+    int best = 0;
+    for (int i = 1; i < nb; ++i) if (l1_of(s0, m, bp[i]) < l1_of(s0, m, bp[best])) best = i;
+    const double zb = bp[best], fb = l1_of(s0, m, zb);
+    if (fb > 1.0) return 0.0;
+    /* walk right from the minimum to the crossing f = 1 */
+    double hi;
+    {
+        double z0 = zb, f0 = fb;
+        int i = best + 1;
+        for (;;) {
+            if (i < nb) {
+                const double f1 = l1_of(s0, m, bp[i]);
+                if (f1 > 1.0) { hi = z0 + (1.0 - f0) * (bp[i] - z0) / (f1 - f0); break; }
+                z0 = bp[i]; f0 = f1; ++i;
+            } else {
+                const double slope = fabs(m[0]) + fabs(m[1]) + fabs(m[2]);
+                hi = z0 + (1.0 - f0) / slope;
+                break;
             }
         }
-        double lo;
-        {
-            double z0 = zb, f0 = fb;
-            int i = best - 1;
-            for (;;) {
-                if (i >= 0) {
-                    const double f1 = l1_of(s0, m, bp[i]);
-                    if (f1 > 1.0) { lo = z0 - (1.0 - f0) * (z0 - bp[i]) / (f1 - f0); break; }
-                    z0 = bp[i]; f0 = f1; --i;
-                } else {
-                    const double slope = fabs(m[0]) + fabs(m[1]) + fabs(m[2]);
-                    lo = z0 - (1.0 - f0) / slope;
-                    break;
-                }
-            }
-        }
-        return hi - lo;
     }
-    /* tetrahedron: corners V_i = c + a_i; barycentrics lambda solve
-     * sum_i lambda_i V_i = X, sum_i lambda_i = 1.  Use lambda_1..3 from the
-     * 3x3 system with V_0 as origin, lambda_0 = 1 - sum. */
-    double E[3][3];
-    for (int r = 0; r < 3; ++r) for (int k = 0; k < 3; ++k) E[r][k] = P->a[k + 1][r] - P->a[0][r];
-    const double b0[3] = {rx - P->c[0] - P->a[0][0], ry - P->c[1] - P->a[0][1], -P->c[2] - P->a[0][2]};
-    const double ez[3] = {0.0, 0.0, 1.0};
-    double l0[3], l1[3];
-    if (!solve3(E, b0, l0) || !solve3(E, ez, l1)) return 0.0;
-    double lam0[4] = {1.0 - l0[0] - l0[1] - l0[2], l0[0], l0[1], l0[2]};
-    double lam1[4] = {-l1[0] - l1[1] - l1[2], l1[0], l1[1], l1[2]};
+    double lo;
+    {
+        double z0 = zb, f0 = fb;
+        int i = best - 1;
+        for (;;) {
+            if (i >= 0) {
+                const double f1 = l1_of(s0, m, bp[i]);
+                if (f1 > 1.0) { lo = z0 - (1.0 - f0) * (z0 - bp[i]) / (f1 - f0); break; }
+                z0 = bp[i]; f0 = f1; --i;
+            } else {
+                const double slope = fabs(m[0]) + fabs(m[1]) + fabs(m[2]);
+                lo = z0 - (1.0 - f0) / slope;
+                break;
+            }
+        }
+    }
+    return hi - lo;
+}
+
+/* Length of the interval of z where every barycentric coordinate
+ * lam0_i + z lam1_i is non-negative (Cyrus-Beck). */
+static double bary_chord(const double lam0[4], const double lam1[4])
+{
     double zlo = -INFINITY, zhi = INFINITY;
     for (int i = 0; i < 4; ++i) {
         if (lam1[i] > 0.0) { const double z = -lam0[i] / lam1[i]; if (z > zlo) zlo = z; }
@@ -565,6 +590,123 @@ static double chord_clip(int type, const orc_prep *P, double rx, double ry)
         else if (lam0[i] < 0.0) return 0.0;
     }
     return (zhi > zlo) ? (zhi - zlo) : 0.0;
+}
+
+/* Interval length along the line p0 + z dir through the primitive with
+ * centre c and offsets a (octahedron: c + [a0 a1 a2] s, |s|_1 <= 1;
+ * tetrahedron: corners c + a_i). */
+static double clip_line(int type, const double c[3], const double a[4][3], const double b0[3],
+                        const double dir[3])
+{
+    if (type == ORC_OCTA) {
+        double M[3][3];
+        for (int r = 0; r < 3; ++r) for (int k = 0; k < 3; ++k) M[r][k] = a[k][r];
+        double s0[3], m[3];
+        if (!solve3(M, b0, s0) || !solve3(M, dir, m)) return 0.0;
+        return l1_chord(s0, m);
+    }
+    /* corners V_i = c + a_i; barycentrics lambda solve sum_i lambda_i V_i = X,
+     * sum_i lambda_i = 1.  Use lambda_1..3 from the 3x3 system with V_0 as
+     * origin, lambda_0 = 1 - sum.  b0 is the line origin relative to c. */
+    double E[3][3];
+    for (int r = 0; r < 3; ++r) for (int k = 0; k < 3; ++k) E[r][k] = a[k + 1][r] - a[0][r];
+    const double rel[3] = {b0[0] - a[0][0], b0[1] - a[0][1], b0[2] - a[0][2]};
+    double l0[3], l1[3];
+    if (!solve3(E, rel, l0) || !solve3(E, dir, l1)) return 0.0;
+    const double lam0[4] = {1.0 - l0[0] - l0[1] - l0[2], l0[0], l0[1], l0[2]};
+    const double lam1[4] = {-l1[0] - l1[1] - l1[2], l1[0], l1[1], l1[2]};
+    (void)c;
+    return bary_chord(lam0, lam1);
+}
+
+static double chord_clip(int type, const orc_prep *P, double rx, double ry)
+{
+    const double ez[3] = {0.0, 0.0, 1.0};
+    if (type == ORC_OCTA) {
+        const double b0[3] = {rx - P->c[0], ry - P->c[1], 0.0};
+        return clip_line(type, P->c, P->a, b0, ez);
+    }
+    const double b0[3] = {rx - P->c[0], ry - P->c[1], -P->c[2]};
+    return clip_line(type, P->c, P->a, b0, ez);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact variant (appendix "Ray Space Approximation"): no affine ray space.  */
+/* The pixel ray leaves the camera centre along                              */
+/* D = ((px - cx) / fx, (py - cy) / fy, 1) and crosses the camera-space      */
+/* primitive; the chord is the Euclidean length of the segment inside it.    */
+/* ------------------------------------------------------------------------ */
+static void pixel_ray(const orc_view *V, double px, double py, double D[3])
+{
+    D[0] = (px - V->cx) / V->fx;
+    D[1] = (py - V->cy) / V->fy;
+    D[2] = 1.0;
+}
+
+static double norm3(const double v[3]) { return sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); }
+
+/* Moeller-Trumbore for the ray t D (t real) from the camera centre; the hit
+ * parameter t is also the hit's camera z because D_z = 1. */
+static orc_hit mtia_ray(const double V0[3], const double V1[3], const double V2[3], const double D[3])
+{
+    orc_hit H = {0, 0, 0, 0, 0};
+    const double e1[3] = {V1[0] - V0[0], V1[1] - V0[1], V1[2] - V0[2]};
+    const double e2[3] = {V2[0] - V0[0], V2[1] - V0[1], V2[2] - V0[2]};
+    const double h[3] = {D[1] * e2[2] - D[2] * e2[1], D[2] * e2[0] - D[0] * e2[2], D[0] * e2[1] - D[1] * e2[0]};
+    const double a = e1[0] * h[0] + e1[1] * h[1] + e1[2] * h[2];
+    if (a == 0.0) return H;
+    const double f = 1.0 / a;
+    const double s[3] = {-V0[0], -V0[1], -V0[2]};              /* ray origin (0,0,0) - V0 */
+    const double u = f * (s[0] * h[0] + s[1] * h[1] + s[2] * h[2]);
+    if (u < 0.0 || u > 1.0) return H;
+    const double q[3] = {s[1] * e1[2] - s[2] * e1[1], s[2] * e1[0] - s[0] * e1[2], s[0] * e1[1] - s[1] * e1[0]};
+    const double v = f * (D[0] * q[0] + D[1] * q[1] + D[2] * q[2]);
+    if (v < 0.0 || u + v > 1.0) return H;
+    H.hit = 1;
+    H.t = f * (e2[0] * q[0] + e2[1] * q[1] + e2[2] * q[2]);
+    H.u = u; H.v = v; H.det = a;
+    return H;
+}
+
+static orc_chord_t chord_mtia_exact(int type, const orc_prep *P, const double D[3])
+{
+    orc_chord_t C;
+    memset(&C, 0, sizeof(C));
+    C.f_in = C.f_out = -1;
+    int F[8][3];
+    const int nf = prim_faces(type, F);
+    for (int f = 0; f < nf; ++f) {
+        orc_hit H = mtia_ray(P->vc[F[f][0]], P->vc[F[f][1]], P->vc[F[f][2]], D);
+        if (!H.hit) continue;
+        if (C.nhit == 0 || H.t < C.h_in.t) { C.h_in = H; C.f_in = f; }
+        if (C.nhit == 0 || H.t > C.h_out.t) { C.h_out = H; C.f_out = f; }
+        C.nhit++;
+    }
+    C.delta = (C.nhit >= 1) ? (C.h_out.t - C.h_in.t) * norm3(D) : 0.0;
+    return C;
+}
+
+/* Independent formulation of the exact chord: the same clipping as
+ * chord_clip along the line t D in camera space. */
+static double chord_clip_exact(int type, const orc_prep *P, const double D[3])
+{
+    const double b0[3] = {-P->tc[0], -P->tc[1], -P->tc[2]};
+    return clip_line(type, P->tc, P->oc, b0, D) * norm3(D);
+}
+
+/* App. E's rule for a general ray direction: moving corner j of the hit
+ * triangle by dV moves the hit parameter by w_j (n . dV) / (n . D), with w
+ * the hit's barycentric weights (1 - u - v, u, v) and n the face normal. */
+static void mtia_ray_grad(const double V0[3], const double V1[3], const double V2[3], const double D[3],
+                          const orc_hit *H, double dV[3][3])
+{
+    const double e1[3] = {V1[0] - V0[0], V1[1] - V0[1], V1[2] - V0[2]};
+    const double e2[3] = {V2[0] - V0[0], V2[1] - V0[1], V2[2] - V0[2]};
+    const double n[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double nd = n[0] * D[0] + n[1] * D[1] + n[2] * D[2];
+    const double w[3] = {1.0 - H->u - H->v, H->u, H->v};
+    for (int j = 0; j < 3; ++j)
+        for (int r = 0; r < 3; ++r) dV[j][r] = w[j] * n[r] / nd;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -643,6 +785,16 @@ int orc_set_views(void *h, int n_views, const double *cams, int tile)
     }
     S->n_tiles_total = tb;
     S->prep = (orc_prep *)calloc((size_t)n_views * (size_t)(S->n > 0 ? S->n : 1), sizeof(orc_prep));
+    return 0;
+}
+
+/* Selects the chord model for the following orc_preprocess: 0 = EWA ray
+ * space (Sec. 3.2), 1 = exact pixel rays in camera space. */
+int orc_set_exact(void *h, int exact)
+{
+    orc_scene *S = (orc_scene *)h;
+    if (!S) return -1;
+    S->exact = exact ? 1 : 0;
     return 0;
 }
 
@@ -781,7 +933,8 @@ static int in_rect(const orc_prep *P, int i, int j)
 }
 
 /* Conditioning of one blended step with respect to float32 evaluation. */
-static int step_ill(int type, const orc_prep *P, const orc_step *st, double Tafter, double *cond)
+static int step_ill(int type, const orc_prep *P, const orc_step *st, double Tafter, double *cond,
+                    const orc_view *V, const double *D)
 {
     int ill = 0;
     if (fabs(Tafter - ORC_T_STOP) <= ORC_ILL_T) ill |= 1;
@@ -792,6 +945,31 @@ static int step_ill(int type, const orc_prep *P, const orc_step *st, double Taft
         const orc_hit *H = hs[s];
         const double b = fmin(fmin(H->u, H->v), 1.0 - H->u - H->v);
         if (b < ORC_ILL_BARY) ill |= 2;
+    }
+    if (D) {
+        /* exact variant: a float32 evaluation of a face's hit depth along the
+         * pixel ray errs by about 2^-23 times (its change per pixel across the
+         * rectangle + its distance from the centre's depth) */
+        const int fs[2] = {st->ch.f_in, st->ch.f_out};
+        int F[8][3];
+        prim_faces(type, F);
+        const double span = (double)(P->rect[2] - P->rect[0] + P->rect[3] - P->rect[1] + 2);
+        double err = 0.0;
+        for (int s = 0; s < 2; ++s) {
+            const double *A = P->vc[F[fs[s]][0]], *B = P->vc[F[fs[s]][1]], *C = P->vc[F[fs[s]][2]];
+            const double n0 = (B[1] - A[1]) * (C[2] - A[2]) - (B[2] - A[2]) * (C[1] - A[1]);
+            const double n1 = (B[2] - A[2]) * (C[0] - A[0]) - (B[0] - A[0]) * (C[2] - A[2]);
+            const double n2 = (B[0] - A[0]) * (C[1] - A[1]) - (B[1] - A[1]) * (C[0] - A[0]);
+            const double nd = n0 * D[0] + n1 * D[1] + n2 * D[2];
+            if (nd == 0.0) { ill |= 3; continue; }
+            const double t = hs[s]->t;
+            const double slope = fabs(t) * (fabs(n0) / V->fx + fabs(n1) / V->fy) / fabs(nd);
+            err += slope * span + fabs(t - P->tc[2]);
+        }
+        const double est = P->sigma * st->e * norm3(D) * err * 1.1920928955078125e-7;
+        if (cond && est > *cond) *cond = est;
+        if (est > ORC_ILL_STEEP) ill |= 3;
+        return ill;
     }
     /* sensitivity of the chord to a float32-sized perturbation of the faces'
      * planes over the primitive's pixel rectangle */
@@ -827,6 +1005,8 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
 {
     const orc_prep *Pv = S->prep + (int64_t)v * S->n;
     const double rx = i + 0.5, ry = j + 0.5;
+    double D[3];
+    pixel_ray(&S->views[v], rx, ry, D);
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
     int64_t last = last_default, it = 0, ev = 0, hit = 0, ns = 0;
     int ill = 0;
@@ -840,9 +1020,9 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
         double delta;
         if (use_clip) {
             memset(&ch, 0, sizeof(ch));
-            delta = chord_clip(S->type, P, rx, ry);
+            delta = S->exact ? chord_clip_exact(S->type, P, D) : chord_clip(S->type, P, rx, ry);
         } else {
-            ch = chord_mtia(S->type, P, rx, ry);
+            ch = S->exact ? chord_mtia_exact(S->type, P, D) : chord_mtia(S->type, P, rx, ry);
             delta = ch.delta;
         }
         if (!(delta > 0.0)) continue;
@@ -857,7 +1037,7 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
         st.delta = delta; st.e = e; st.o = o; st.T = T; st.clamped = clamped; st.ch = ch;
         for (int c = 0; c < 3; ++c) C[c] += T * o * P->rgb[c];
         T = T * (1.0 - o);
-        if (!use_clip) ill |= step_ill(S->type, P, &st, T, &cond);
+        if (!use_clip) ill |= step_ill(S->type, P, &st, T, &cond, &S->views[v], S->exact ? D : NULL);
         if (steps) steps[ns] = st;
         ++ns;
         last = pos ? pos[k] + 1 : k + 1;
@@ -1016,7 +1196,25 @@ double orc_chord(void *h, int v, int64_t n, double px, double py, int method)
     orc_scene *S = (orc_scene *)h;
     const orc_prep *P = S->prep + (int64_t)v * S->n + n;
     if (!P->valid) return 0.0;
+    if (S->exact) {
+        double D[3];
+        pixel_ray(&S->views[v], px, py, D);
+        return method == 0 ? chord_mtia_exact(S->type, P, D).delta : chord_clip_exact(S->type, P, D);
+    }
     return method == 0 ? chord_mtia(S->type, P, px, py).delta : chord_clip(S->type, P, px, py);
+}
+
+/* One exact-variant ray hit and its corner derivatives, for tests:
+ * V: 9 doubles (three camera-space corners), D: ray direction;
+ * out: hit, t, u, v, det, dt/dV (9). */
+void orc_mtia_ray(const double *V, const double *D, double *out)
+{
+    orc_hit H = mtia_ray(V, V + 3, V + 6, D);
+    out[0] = H.hit; out[1] = H.t; out[2] = H.u; out[3] = H.v; out[4] = H.det;
+    double dV[3][3];
+    memset(dV, 0, sizeof(dV));
+    if (H.hit) mtia_ray_grad(V, V + 3, V + 6, D, &H, dV);
+    for (int k = 0; k < 9; ++k) out[5 + k] = dV[k / 3][k % 3];
 }
 
 /* One MTIA evaluation and its App. E depth derivatives, for tests:
@@ -1050,6 +1248,9 @@ static int pixel_backward(const orc_scene *S, int v, int i, int j, const orc_ste
 {
     const orc_prep *Pv = S->prep + (int64_t)v * S->n;
     const double rx = i + 0.5, ry = j + 0.5;
+    double D[3];
+    pixel_ray(&S->views[v], rx, ry, D);
+    const double nD = norm3(D);
     double behind[3];
     int ill = 0;
     for (int c = 0; c < 3; ++c) behind[c] = Tfinal * bg[c];
@@ -1066,18 +1267,29 @@ static int pixel_backward(const orc_scene *S, int v, int i, int j, const orc_ste
         }
         for (int c = 0; c < 3; ++c) behind[c] += s->T * s->o * P->rgb[c];
         const double Tafter = s->T * (1.0 - s->o);
-        const int sill = step_ill(S->type, P, s, Tafter, NULL);
+        const int sill = step_ill(S->type, P, s, Tafter, NULL, &S->views[v], S->exact ? D : NULL);
         if (sill) pg->ill = 1;
         ill |= sill;
         if (s->clamped) continue;
         /* App. E: o = 1 - exp(-sigma (i2 - i1)) */
         const double dLdDelta = dLdo * P->sigma * s->e;
         pg->gsigma += dLdo * s->delta * s->e;
-        double Vc[6][3];
-        prim_corners(S->type, P, Vc);
         const int fs[2] = {s->ch.f_in, s->ch.f_out};
         const orc_hit *hs[2] = {&s->ch.h_in, &s->ch.h_out};
         const double sgn[2] = {-1.0, 1.0};
+        if (S->exact) {
+            /* chord = |D| (t_out - t_in); gradients onto camera-space corners */
+            for (int q = 0; q < 2; ++q) {
+                const int *tri = F[fs[q]];
+                double dV[3][3];
+                mtia_ray_grad(P->vc[tri[0]], P->vc[tri[1]], P->vc[tri[2]], D, hs[q], dV);
+                for (int m = 0; m < 3; ++m)
+                    for (int r = 0; r < 3; ++r) pg->gV[tri[m]][r] += sgn[q] * dLdDelta * nD * dV[m][r];
+            }
+            continue;
+        }
+        double Vc[6][3];
+        prim_corners(S->type, P, Vc);
         for (int q = 0; q < 2; ++q) {
             const int *tri = F[fs[q]];
             double dV[3][3];
@@ -1127,24 +1339,31 @@ static void prim_backward(const orc_scene *S, const orc_view *V, int64_t n, cons
     const double x = t[0], y = t[1], z = t[2];
     const double l = sqrt(x * x + y * y + z * z);
 
-    /* c = phi(t), d phi / d t = J */
     double gt[3];
-    mat3T_vec(J, gc, gt);
-    /* a_k = J(t) oc_k */
     double goc[4][3];
-    for (int k = 0; k < na; ++k) {
-        mat3T_vec(J, ga[k], goc[k]);
-        const double *w = oc[k];
-        const double tw = x * w[0] + y * w[1] + z * w[2];
-        const double l3 = l * l * l;
-        const double fx = V->fx, fy = V->fy;
-        /* d(J w)/dx, d(J w)/dy, d(J w)/dz (columns) */
-        const double dJw[3][3] = {
-            {-fx * w[2] / (z * z), 0.0, -fx * w[0] / (z * z) + 2.0 * fx * x * w[2] / (z * z * z)},
-            {0.0, -fy * w[2] / (z * z), -fy * w[1] / (z * z) + 2.0 * fy * y * w[2] / (z * z * z)},
-            {w[0] / l - tw * x / l3, w[1] / l - tw * y / l3, w[2] / l - tw * z / l3}};
-        for (int c = 0; c < 3; ++c)
-            gt[c] += dJw[0][c] * ga[k][0] + dJw[1][c] * ga[k][1] + dJw[2][c] * ga[k][2];
+    if (S->exact) {
+        /* the corners are camera-space points: centre t, offsets oc_k */
+        for (int r = 0; r < 3; ++r) gt[r] = gc[r];
+        for (int k = 0; k < na; ++k)
+            for (int r = 0; r < 3; ++r) goc[k][r] = ga[k][r];
+    } else {
+        /* c = phi(t), d phi / d t = J */
+        mat3T_vec(J, gc, gt);
+        /* a_k = J(t) oc_k */
+        for (int k = 0; k < na; ++k) {
+            mat3T_vec(J, ga[k], goc[k]);
+            const double *w = oc[k];
+            const double tw = x * w[0] + y * w[1] + z * w[2];
+            const double l3 = l * l * l;
+            const double fx = V->fx, fy = V->fy;
+            /* d(J w)/dx, d(J w)/dy, d(J w)/dz (columns) */
+            const double dJw[3][3] = {
+                {-fx * w[2] / (z * z), 0.0, -fx * w[0] / (z * z) + 2.0 * fx * x * w[2] / (z * z * z)},
+                {0.0, -fy * w[2] / (z * z), -fy * w[1] / (z * z) + 2.0 * fy * y * w[2] / (z * z * z)},
+                {w[0] / l - tw * x / l3, w[1] / l - tw * y / l3, w[2] / l - tw * z / l3}};
+            for (int c = 0; c < 3; ++c)
+                gt[c] += dJw[0][c] * ga[k][0] + dJw[1][c] * ga[k][1] + dJw[2][c] * ga[k][2];
+        }
     }
     /* camera -> world */
     double gmu[3], go_w[4][3];

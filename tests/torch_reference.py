@@ -14,6 +14,11 @@ reference gradients for tiny scenes:
 
 No pixel rectangle is needed: the footprint lies inside it, so the chord is
 zero wherever the rectangle test would reject the pixel.
+
+``exact=True`` renders the variant without ray space: the same slab and
+barycentric clipping along the camera-space pixel ray t D,
+D = ((px - cx)/fx, (py - cy)/fy, 1), with the chord t-interval scaled by |D|;
+primitives with a corner at or in front of the near plane are skipped.
 """
 import math
 
@@ -72,7 +77,7 @@ TET_DIRS = np.array([[1, 1, 1], [1, -1, -1], [-1, 1, -1], [-1, -1, 1]], np.float
 SLABS = torch.tensor([[1, 1, 1], [1, 1, -1], [1, -1, 1], [-1, 1, 1]], dtype=torch.float64)
 
 
-def render(kind, params, cam, bg, sh_degree=3):
+def render(kind, params, cam, bg, sh_degree=3, exact=False):
     """params: dict of float64 tensors means [N,3], quats [N,4], dists [N,k],
     opacity [N], sh [N,K,3].  Returns the image [3,H,W]."""
     means, quats, dists, opac, sh = (params[k] for k in ("means", "quats", "dists", "opacity", "sh"))
@@ -109,7 +114,43 @@ def render(kind, params, cam, bg, sh_degree=3):
     pix = torch.stack([ii.reshape(-1), jj.reshape(-1)], -1)        # [P,2]
     P = pix.shape[0]
     deltas = []
-    for k in range(n):
+    offc = offs @ Rw.T                                            # camera-space offsets
+    near32 = float(np.float32(cam.near))
+    culled = set()
+    if exact:
+        D = torch.stack([(pix[:, 0] - cx) / fx, (pix[:, 1] - cy) / fy,
+                         torch.ones(P, dtype=torch.float64)], -1)   # [P,3]
+        Dn = D.norm(dim=1)
+        for k in range(n):
+            if kind == 0:
+                corners = torch.cat([tc[k] + offc[k], tc[k] - offc[k]], 0)
+            else:
+                corners = tc[k] + offc[k]
+            if bool((corners[:, 2] <= near32).any()):
+                culled.add(k)
+            if kind == 0:
+                Minv = torch.linalg.inv(offc[k].T)
+                s0 = Minv @ (-tc[k])                          # local coords of the camera centre
+                m = D @ Minv.T                                # [P,3] local direction
+                num = SLABS @ s0                              # [4]
+                den = m @ SLABS.T                             # [P,4]
+                e1 = (-1 - num) / den
+                e2 = (1 - num) / den
+                lo = torch.minimum(e1, e2).max(dim=1).values
+                hi = torch.maximum(e1, e2).min(dim=1).values
+            else:
+                E = torch.stack([offc[k, 1] - offc[k, 0], offc[k, 2] - offc[k, 0], offc[k, 3] - offc[k, 0]], 1)
+                Einv = torch.linalg.inv(E)
+                l0 = Einv @ (-tc[k] - offc[k, 0])             # lambda_1..3 at t = 0
+                l1 = D @ Einv.T                               # [P,3]
+                L0 = torch.cat([(1 - l0.sum()).reshape(1), l0])
+                L1 = torch.cat([-l1.sum(1, keepdim=True), l1], 1)
+                big = torch.tensor(1e30, dtype=torch.float64)
+                roots = -L0 / L1
+                lo = torch.where(L1 > 0, roots, -big).max(dim=1).values
+                hi = torch.where(L1 < 0, roots, big).min(dim=1).values
+            deltas.append(torch.relu(hi - lo) * Dn)
+    for k in range(n if not exact else 0):
         rel = torch.cat([pix - c[k, :2], torch.zeros(P, 1, dtype=torch.float64)], 1)   # X - c at z = c_z
         if kind == 0:
             M = a[k].T                                        # columns = axis offsets
@@ -140,7 +181,7 @@ def render(kind, params, cam, bg, sh_degree=3):
     alive = torch.ones(P, dtype=torch.bool)
     C = torch.zeros(3, P, dtype=torch.float64)
     for k in order:
-        if tc[k, 2].item() <= float(np.float32(cam.near)):
+        if tc[k, 2].item() <= near32 or k in culled:
             continue
         o = torch.minimum(1 - torch.exp(-sigma[k] * deltas[k]), torch.tensor(O_MAX, dtype=torch.float64))
         o = torch.where(alive, o, torch.zeros_like(o))
