@@ -251,24 +251,41 @@ def single(args, log):
     grad_np = scenes.image_gradient(cams, seed=1)
     prims = L.Prims.from_scene(scene)
     grad = torch.as_tensor(grad_np, device="cuda")
-    rast = Rasterizer(scene.kind, scene.n, cams, tile=args.tile, sort_digit_bits=args.digit, headroom=1.05,
-                      radix_sort=args.radix_sort)
-    st = Staged(rast, prims, (0.0, 0.0, 0.0), grad)
-    log(f"pairs {rast.n_pairs}, capacity {rast.max_pairs}")
-    for _ in range(args.warmup):
-        st.run()
-    wall, stage_ms = st.time_stages(args.steps)
-    n_pairs, overflow = rast.status()
-    if overflow:
-        raise RuntimeError("pair capacity overflow in the timed region")
-    ms_per_step = wall * 1e3 / args.steps
+
+    def measure(exact):
+        rast = Rasterizer(scene.kind, scene.n, cams, tile=args.tile, sort_digit_bits=args.digit, headroom=1.05,
+                          radix_sort=args.radix_sort, exact=exact)
+        st = Staged(rast, prims, (0.0, 0.0, 0.0), grad)
+        log(f"{'exact rays: ' if exact else ''}pairs {rast.n_pairs}, capacity {rast.max_pairs}")
+        for _ in range(args.warmup):
+            st.run()
+        wall, stage_ms = st.time_stages(args.steps)
+        n_pairs, overflow = rast.status()
+        if overflow:
+            raise RuntimeError("pair capacity overflow in the timed region")
+        ms = wall * 1e3 / args.steps
+        log("stage ms (median): " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
+        counts = st.counts()
+        log(f"iterated {counts[0]}, evaluated {counts[1]}, intersected {counts[2]}")
+        del st, rast
+        torch.cuda.empty_cache()
+        return ms, stage_ms, counts, n_pairs
+
+    ms_per_step, stage_ms, counts, n_pairs = measure(args.exact)
     value = cam.width * cam.height / 1e6 / (ms_per_step / 1e3)
-    log("stage ms (median): " + ", ".join(f"{k} {v:.3f}" for k, v in stage_ms.items()))
-    counts = st.counts()
-    log(f"iterated {counts[0]}, evaluated {counts[1]}, intersected {counts[2]}")
-    roofline = roofline_of(scene.kind, stage_ms, counts)
-    del st, rast
-    torch.cuda.empty_cache()
+    roofline = roofline_of(scene.kind, stage_ms, counts) if not args.exact else None
+
+    exact = None
+    if not args.exact and not args.no_exact:
+        # the variant without the ray-space approximation on the same workload
+        e_ms, e_stage, e_counts, e_pairs = measure(True)
+        exact = {"megapixels_per_s": round(cam.width * cam.height / 1e6 / (e_ms / 1e3), 3),
+                 "ms_per_step": round(e_ms, 4), "pairs": int(e_pairs),
+                 "stage_ms": {k: round(v, 4) for k, v in e_stage.items()},
+                 "pair_counts": {"iterated": e_counts[0], "evaluated": e_counts[1], "intersected": e_counts[2]},
+                 "render_ms_ratio_to_ray_space": round((e_stage["render_fwd"] + e_stage["raster_bwd"]) /
+                                                       (stage_ms["render_fwd"] + stage_ms["raster_bwd"]), 3)}
+        log(f"exact rays: {exact['megapixels_per_s']} MP/s, render time x{exact['render_ms_ratio_to_ray_space']}")
 
     batched = None
     if not args.no_batched:
@@ -282,7 +299,7 @@ def single(args, log):
         log("timing the oracle on a bounded sample ...")
         cpu = cpu_baseline(scene, cams, grad_np, args.band_rows, threads=os.cpu_count() or 1)
     return {
-        "metric": "fwd+bwd megapixels/s at 1M octahedra 1080p",
+        "metric": "fwd+bwd megapixels/s at 1M octahedra 1080p" + (", exact rays" if args.exact else ""),
         "value": round(value, 3), "unit": "megapixels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
@@ -293,6 +310,7 @@ def single(args, log):
         "pair_counts": {"iterated": counts[0], "evaluated": counts[1], "intersected": counts[2]},
         "roofline": roofline,
         "batched": batched,
+        "exact_rays": exact,
         "cpu_baseline": cpu,
     }
 
@@ -466,6 +484,8 @@ def main():
     ap.add_argument("--radix-sort", action="store_true", help="global LSD radix sort instead of the per-tile sort")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--exact", action="store_true", help="time the variant without the ray-space approximation")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact-rays comparison of the default run")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--band-rows", type=int, default=0, help="rows of the oracle sample (0: whole frame)")
     ap.add_argument("--quiet", action="store_true")

@@ -103,6 +103,16 @@ typedef struct linprim_tuning {
  * per-tile sort (pairs counted and scattered per tile, each tile's list then
  * sorted by (depth, primitive)).  Both give the same order. */
 #define LINPRIM_FLAG_RADIX_SORT 4
+/* The variant without the ray-space approximation that the paper's appendix
+ * on that approximation evaluates: each pixel ray leaves the camera centre
+ * along ((i + 1/2 - cx)/fx, (j + 1/2 - cy)/fy, 1) and the chord is the
+ * Euclidean length of its segment inside the camera-space primitive (true
+ * ray / polytope intersection, no linearisation).  The pixel rectangle is
+ * the box of the perspective-projected corners, and a primitive with any
+ * corner at depth <= near_z is culled (its projection is undefined).  Depth
+ * keys, sorting, compositing and Eq. 1 are unchanged.  The flag must be the
+ * same in every call on one pair of workspaces. */
+#define LINPRIM_FLAG_EXACT_RAYS 8
 
 /* Bytes of the per-view workspace (payloads, counts, offsets, tile ranges,
  * status) for n primitives of `type` over n_views cameras; 0 for invalid
@@ -116,8 +126,9 @@ size_t linprim_view_workspace_size(int32_t type, int64_t n, const linprim_camera
 size_t linprim_pair_workspace_size(int64_t max_pairs, const linprim_camera *cams, int32_t n_views,
                                    const linprim_tuning *tuning);
 
-/* Sec. 3.2 "Preprocessing".  Writes, into view_ws, the ray-space render
- * payload of every (view, primitive), its pixel and tile rectangles, depth
+/* Sec. 3.2 "Preprocessing".  Writes, into view_ws, the render payload
+ * (ray-space planes, or camera-space ones with LINPRIM_FLAG_EXACT_RAYS) of
+ * every (view, primitive), its pixel and tile rectangles, depth
  * key and tile count, and the exclusive prefix sum of the tile counts (the
  * total is the pair count).  The binning quantities are computed in IEEE
  * double precision with a fixed evaluation order, so they are reproducible
@@ -184,7 +195,7 @@ int linprim_render_bwd(const linprim_prims *prims, const linprim_camera *cams, i
 /* The two stages of linprim_render_bwd, callable on their own (Sec. 3.4
  * "Rasterization Backpropagation" and "Preprocessing Backpropagation").
  * linprim_raster_bwd writes one gradient record per (tile, primitive) pair
- * into pair_ws: dL/d(ray-space plane coefficients), dL/d rgb and dL/d sigma
+ * into pair_ws: dL/d(plane coefficients of the payload), dL/d rgb and dL/d sigma
  * summed over the tile's pixels.  linprim_preprocess_bwd sums each
  * primitive's records in a fixed order and carries them to the features;
  * outputs as in linprim_render_bwd. */

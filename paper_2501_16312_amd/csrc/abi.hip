@@ -61,7 +61,7 @@ PairLayout pair_layout(int64_t max_pairs, int digit_bits, int tile) {
 }
 
 hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
-                                int result_in_b, int type, int tile, int32_t n_views, const float bg[3],
+                                int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                                 float* out_rgb, float* out_T, int32_t* out_last, unsigned long long* counters,
                                 hipStream_t stream);
 
@@ -127,6 +127,8 @@ int hip_status(hipError_t e) { return e == hipSuccess ? LINPRIM_OK : LINPRIM_ERR
 // parity of the number of digit passes); the render calls recompute it.
 bool radix_sort(const linprim_tuning* tu) { return tu && (tu->flags & LINPRIM_FLAG_RADIX_SORT); }
 
+bool exact_rays(const linprim_tuning* tu) { return tu && (tu->flags & LINPRIM_FLAG_EXACT_RAYS); }
+
 int result_buffer(const ViewLayout& L, const linprim_tuning* tu) {
     return sorted_buffer(L.n_tiles_total, radix_sort(tu), digit_of(tu));
 }
@@ -164,7 +166,7 @@ int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, i
     hipError_t e = hipSuccess;
     if (!(tuning && (tuning->flags & LINPRIM_FLAG_VIEWS_RESIDENT)))
         e = launch_store_views(cams, n_views, tile, reinterpret_cast<ViewInfo*>(ws + L.views), s);
-    if (e == hipSuccess) e = launch_preprocess(*prims, n_views, tile, L, ws, s);
+    if (e == hipSuccess) e = launch_preprocess(*prims, n_views, tile, exact_rays(tuning), L, ws, s);
     if (e == hipSuccess) e = launch_scan(L, ws, tile, s);
     return hip_status(e);
 }
@@ -229,7 +231,7 @@ static int render_fwd_common(const linprim_prims* prims, const linprim_camera* c
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
     const int in_b = result_buffer(L, tuning);
     hipError_t e = launch_render_fwd_ex(L, (const char*)view_ws, P, (const char*)pair_ws, in_b, prims->type,
-                                        tile_of(tuning), n_views, bg, out_rgb, out_T, out_last,
+                                        exact_rays(tuning), tile_of(tuning), n_views, bg, out_rgb, out_T, out_last,
                                         reinterpret_cast<unsigned long long*>(counters), (hipStream_t)stream);
     return hip_status(e);
 }
@@ -264,10 +266,11 @@ int linprim_render_bwd(const linprim_prims* prims, const linprim_camera* cams, i
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
     const int in_b = result_buffer(L, tuning);
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_render_bwd(L, (const char*)view_ws, P, (char*)pair_ws, in_b, prims->type, tile_of(tuning),
-                                     n_views, bg, out_T, out_last, grad_rgb, s);
+    hipError_t e = launch_render_bwd(L, (const char*)view_ws, P, (char*)pair_ws, in_b, prims->type,
+                                     exact_rays(tuning), tile_of(tuning), n_views, bg, out_T, out_last, grad_rgb, s);
     if (e == hipSuccess)
-        e = launch_preprocess_bwd(*prims, n_views, tile_of(tuning), L, (const char*)view_ws, P, (const char*)pair_ws,
+        e = launch_preprocess_bwd(*prims, n_views, tile_of(tuning), exact_rays(tuning), L, (const char*)view_ws, P,
+                                  (const char*)pair_ws,
                                   grad_means, grad_quats, grad_dists, grad_opacity, grad_sh, s);
     return hip_status(e);
 }
@@ -282,7 +285,7 @@ int linprim_raster_bwd(const linprim_prims* prims, const linprim_camera* cams, i
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
     const int in_b = result_buffer(L, tuning);
     return hip_status(launch_render_bwd(L, (const char*)view_ws, P, (char*)pair_ws, in_b, prims->type,
-                                        tile_of(tuning), n_views, bg, out_T, out_last, grad_rgb,
+                                        exact_rays(tuning), tile_of(tuning), n_views, bg, out_T, out_last, grad_rgb,
                                         (hipStream_t)stream));
 }
 
@@ -296,7 +299,8 @@ int linprim_preprocess_bwd(const linprim_prims* prims, const linprim_camera* cam
     ViewLayout L;
     PairLayout P;
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
-    return hip_status(launch_preprocess_bwd(*prims, n_views, tile_of(tuning), L, (const char*)view_ws, P,
+    return hip_status(launch_preprocess_bwd(*prims, n_views, tile_of(tuning), exact_rays(tuning), L,
+                                            (const char*)view_ws, P,
                                             (const char*)pair_ws, grad_means, grad_quats, grad_dists, grad_opacity,
                                             grad_sh, (hipStream_t)stream));
 }

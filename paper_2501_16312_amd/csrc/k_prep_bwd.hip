@@ -157,6 +157,121 @@ __device__ inline void sh_backward(ShBack& S, float x, float y, float z) {
     S.term(15, -K.c3a * x * (x * x - 3 * y * y), -K.c3a * (3 * x * x - 3 * y * y), 6 * K.c3a * x * y, 0);
 }
 
+// Offsets of one primitive (camera space) -> world offsets -> rotation
+// gradient (row-major) and distance gradients, accumulated.
+template <int KIND>
+__device__ inline void offsets_to_rotation(const Geom& G, const ViewInfo& V, const float* __restrict__ dists,
+                                          const double goc[4][3], double gR[9], double gd[4]) {
+    constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        double go[3];
+        for (int c = 0; c < 3; ++c) go[c] = V.Rw[c] * goc[k][0] + V.Rw[3 + c] * goc[k][1] + V.Rw[6 + c] * goc[k][2];
+        if (KIND == LINPRIM_OCTAHEDRON) {
+            const double dk = (double)dists[k];
+            for (int rr = 0; rr < 3; ++rr) {
+                gR[3 * rr + k] += go[rr] * dk;
+                gd[k] += go[rr] * G.R[3 * rr + k];
+            }
+        } else {
+            const double gk = (double)dists[k] * kInvSqrt3;
+            for (int rr = 0; rr < 3; ++rr) {
+                const double rb = kTetDir[k][0] * G.R[3 * rr] + kTetDir[k][1] * G.R[3 * rr + 1] +
+                                  kTetDir[k][2] * G.R[3 * rr + 2];
+                for (int c = 0; c < 3; ++c) gR[3 * rr + c] += go[rr] * kTetDir[k][c] * gk;
+                gd[k] += go[rr] * rb * kInvSqrt3;
+            }
+        }
+    }
+}
+
+// Exact variant (no ray space): the summed record holds, per plane k,
+// dL/d(a_k, b_k) at the rectangle origin (words 0, 1), dL/du_k (word 2, the
+// plane's offset g_k = a_k ox + b_k oy) and dL/dc_k (word 3), plus
+// dL/d(sigma z_c) (word 19).  With the camera-space normal n_k and centre t:
+//   a_k = -t_z n_kx / fx,  b_k = -t_z n_ky / fy,  c_k = n_k . t,
+//   ox = i0 + 1/2 - (fx t_x / t_z + cx),  oy likewise,
+// then n_k -> camera offsets oc (and, for octahedra, the 1/d^2 weights).
+template <int KIND>
+__device__ inline void exact_slot_bwd(const Geom& G, const ViewInfo& V, const float* __restrict__ dists, double sigma,
+                                      double ox, double oy, const float r[kGradWords], float4* rp) {
+    double nrm[4][3];
+    exact_normals(KIND, G, nrm);
+    const double tx = G.tc[0], ty = G.tc[1], tz = G.tc[2];
+    double gt[3] = {0, 0, 0}, gn[4][3];
+    double gox = 0.0, goy = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double a = -tz * nrm[k][0] / V.fx, b = -tz * nrm[k][1] / V.fy;
+        const double w0 = r[4 * k], w1 = r[4 * k + 1], w2 = r[4 * k + 2], w3 = r[4 * k + 3];
+        const double ga = w0 + w2 * ox, gb = w1 + w2 * oy;
+        gox += w2 * a;
+        goy += w2 * b;
+        gn[k][0] = -tz / V.fx * ga + tx * w3;
+        gn[k][1] = -tz / V.fy * gb + ty * w3;
+        gn[k][2] = tz * w3;
+        gt[0] += nrm[k][0] * w3;
+        gt[1] += nrm[k][1] * w3;
+        gt[2] += nrm[k][2] * w3 - nrm[k][0] / V.fx * ga - nrm[k][1] / V.fy * gb;
+    }
+    // projected centre: X = fx t_x / t_z + cx, ox = i0 + 1/2 - X
+    gt[0] -= gox * V.fx / tz;
+    gt[2] += gox * V.fx * tx / (tz * tz);
+    gt[1] -= goy * V.fy / tz;
+    gt[2] += goy * V.fy * ty / (tz * tz);
+    // the record's sigma is sigma t_z
+    const double gsig = (double)r[19] * tz;
+    gt[2] += (double)r[19] * sigma;
+    double goc[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double gd[4] = {0, 0, 0, 0};
+    if (KIND == LINPRIM_OCTAHEDRON) {
+        // n_k = N^T kSlab[k] with N = M^-1 and column c of M the offset oc_c:
+        // dL/dN[c][r] = sum_k kSlab[k][c] dL/dn_k[r], dL/dM = -N^T dL/dN N^T
+        double M[9], N[9], gN[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) M[3 * r + c] = G.oc[c][r];
+        inverse3(M, N);
+        for (int c = 0; c < 3; ++c)
+            for (int r = 0; r < 3; ++r)
+                gN[3 * c + r] = kSlab[0][c] * gn[0][r] + kSlab[1][c] * gn[1][r] + kSlab[2][c] * gn[2][r] +
+                                kSlab[3][c] * gn[3][r];
+        double T1[9];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                T1[3 * a + b] = N[a] * gN[b] + N[3 + a] * gN[3 + b] + N[6 + a] * gN[6 + b];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                goc[b][a] = -(T1[3 * a] * N[3 * b] + T1[3 * a + 1] * N[3 * b + 1] + T1[3 * a + 2] * N[3 * b + 2]);
+    } else {
+        // rows of M_f are the offsets of the three corners other than f and
+        // M_f n_f = 1:  dL/dM_f = -(M_f^-T dL/dn_f) n_f^T
+        for (int f = 0; f < 4; ++f) {
+            double M[9], N[9];
+            int m[3], q = 0;
+            for (int kk = 0; kk < 4; ++kk) {
+                if (kk == f) continue;
+                m[q] = kk;
+                for (int c = 0; c < 3; ++c) M[3 * q + c] = G.oc[kk][c];
+                ++q;
+            }
+            inverse3(M, N);
+            double y[3];
+            for (int j = 0; j < 3; ++j) y[j] = N[j] * gn[f][0] + N[3 + j] * gn[f][1] + N[6 + j] * gn[f][2];
+            for (int j = 0; j < 3; ++j)
+                for (int c = 0; c < 3; ++c) goc[m[j]][c] -= y[j] * nrm[f][c];
+        }
+    }
+    double gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    offsets_to_rotation<KIND>(G, V, dists, goc, gR, gd);
+    double gm[3];
+    for (int c = 0; c < 3; ++c) gm[c] = V.Rw[c] * gt[0] + V.Rw[3 + c] * gt[1] + V.Rw[6 + c] * gt[2];
+    rp[0] = make_float4((float)gm[0], (float)gm[1], (float)gm[2], (float)gR[0]);
+    rp[1] = make_float4((float)gR[1], (float)gR[2], (float)gR[3], (float)gR[4]);
+    rp[2] = make_float4((float)gR[5], (float)gR[6], (float)gR[7], (float)gR[8]);
+    rp[3] = make_float4((float)gd[0], (float)gd[1], (float)gd[2], (float)gd[3]);
+    rp[4] = make_float4(r[16], r[17], r[18], (float)gsig);
+}
+
 // ---------------------------------------------------------------------------
 // Stage 1, one thread per (view, primitive): the summed record (dL/d plane
 // coefficients, dL/d rgb, dL/d sigma) -> dL/d(ray-space centre, offsets) ->
@@ -164,7 +279,7 @@ __device__ inline void sh_backward(ShBack& S, float x, float y, float z) {
 //   [0..2] dL/d mu (geometric part), [3..11] dL/dR (row-major),
 //   [12..15] dL/d distances, [16..19] unchanged (rgb, sigma).
 // ---------------------------------------------------------------------------
-template <int KIND>
+template <int KIND, bool EXACT>
 __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ means, const float* __restrict__ quats,
                                                   const float* __restrict__ dists, const float* __restrict__ opacity,
                                                   int64_t n, const ViewInfo* __restrict__ views,
@@ -221,9 +336,16 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     }
     const ViewInfo& V = views[v];
     Geom G;
-    if (!build_geometry(KIND, means + 3 * i, quats + 4 * i, dists + ND * i, opacity[i], V, G)) return;
+    if (!build_geometry(KIND, EXACT, means + 3 * i, quats + 4 * i, dists + ND * i, opacity[i], V, G)) return;
     const double ox = (double)rc.x + 0.5 - G.c[0];
     const double oy = (double)rc.y + 0.5 - G.c[1];
+    if (EXACT) {
+        double dmin = (double)dists[ND * i];
+        for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dists[ND * i + k]);
+        const double sigma = -log(1.0 - kAlphaScaleD * (double)opacity[i]) / (2.0 * dmin);
+        exact_slot_bwd<KIND>(G, V, dists + ND * i, sigma, ox, oy, r, rp);
+        return;
+    }
 
     // ---- planes -> ray-space centre (xy) and offsets a_k
     double gox = 0.0, goy = 0.0;
@@ -463,7 +585,7 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
     for (int64_t j = threadIdx.x; j < rows * w3; j += 128) gs[j] = stage[j];
 }
 
-hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L,
+hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, bool exact, const ViewLayout& L,
                                  const char* vws, const PairLayout& P, const char* pws, float* g_means,
                                  float* g_quats, float* g_dists, float* g_opacity, float* g_sh, hipStream_t stream) {
     if (p.n == 0) return hipSuccess;
@@ -497,15 +619,17 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
         case 2: LP_PRIM(K_, 2); break;       \
         default: LP_PRIM(K_, 3); break;      \
     }
+#define LP_SLOT(K_, E_)                                                                                         \
+    hipLaunchKernelGGL((k_slot_bwd<K_, E_>), g1, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, p.n, \
+                       views, payload, tiles, offsets, grads, nq, st, cap, vis)
     if (p.type == LINPRIM_OCTAHEDRON) {
-        hipLaunchKernelGGL(k_slot_bwd<LINPRIM_OCTAHEDRON>, g1, dim3(128), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap, vis);
+        if (exact) LP_SLOT(LINPRIM_OCTAHEDRON, true); else LP_SLOT(LINPRIM_OCTAHEDRON, false);
         LP_PRIM_DEG(LINPRIM_OCTAHEDRON)
     } else {
-        hipLaunchKernelGGL(k_slot_bwd<LINPRIM_TETRAHEDRON>, g1, dim3(128), 0, stream, p.means, p.quats, p.dists,
-                           p.opacity, p.n, views, payload, tiles, offsets, grads, nq, st, cap, vis);
+        if (exact) LP_SLOT(LINPRIM_TETRAHEDRON, true); else LP_SLOT(LINPRIM_TETRAHEDRON, false);
         LP_PRIM_DEG(LINPRIM_TETRAHEDRON)
     }
+#undef LP_SLOT
 #undef LP_PRIM_DEG
 #undef LP_PRIM
     return hipGetLastError();

@@ -50,7 +50,7 @@ hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int t
 
 // One thread per (primitive, view).  Writes the 32-dword payload record,
 // the depth key and the tile count.
-template <int KIND, int DEG>
+template <int KIND, int DEG, bool EXACT>
 __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ means, const float* __restrict__ quats,
                                                     const float* __restrict__ dists, const float* __restrict__ opacity,
                                                     const float* __restrict__ sh, int64_t n,
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
     float* rec = payload + slot * kRecordWords;
     Geom G;
     const float alpha = opacity[i];
-    if (!build_geometry(KIND, means + 3 * i, quats + 4 * i, dists + nd * i, alpha, V, G)) {
+    if (!build_geometry(KIND, EXACT, means + 3 * i, quats + 4 * i, dists + nd * i, alpha, V, G)) {
         reinterpret_cast<int4*>(rec)[0] = make_int4(-1, -1, -1, -1);
         depth_keys[slot] = 0u;
         tiles[slot] = 0u;
@@ -121,7 +121,23 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
     // the render kernels evaluate planes at integer ki = i - i0, kj = j - j0.
     const double ox = (double)i0 + 0.5 - G.c[0];
     const double oy = (double)j0 + 0.5 - G.c[1];
-    if (KIND == LINPRIM_OCTAHEDRON) {
+    if (EXACT) {
+        // camera-space planes along the pixel ray X = z_c (1 + tau) D: with
+        // the projected centre (G.c[0], G.c[1]) and dx = i + 1/2 - c_x,
+        // n . (centre - z_c D) = -z_c (n_x dx / fx + n_y dy / fy)
+        double nrm[4][3];
+        exact_normals(KIND, G, nrm);
+        const double zc = G.tc[2];
+        for (int k = 0; k < 4; ++k) {
+            const double a = -zc * nrm[k][0] / V.fx, b = -zc * nrm[k][1] / V.fy;
+            out[R_PLANES + 4 * k + 0] = (float)a;
+            out[R_PLANES + 4 * k + 1] = (float)b;
+            out[R_PLANES + 4 * k + 2] = (float)(a * ox + b * oy);
+            out[R_PLANES + 4 * k + 3] = (float)(nrm[k][0] * G.tc[0] + nrm[k][1] * G.tc[1] + nrm[k][2] * G.tc[2]);
+        }
+        out[R_S2] = (float)(sigma * zc * kLog2e);
+        out[R_SIGMA] = (float)(sigma * zc);
+    } else if (KIND == LINPRIM_OCTAHEDRON) {
         // primitive = c + M s, |s|_1 <= 1, M = [a0 a1 a2]; the pair of faces
         // with sign pattern sg is the slab |sg . M^-1 (X - c)| <= 1.
         double M[9], N[9];
@@ -189,8 +205,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
         dst[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
 }
 
-hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L, char* ws,
-                             hipStream_t stream) {
+hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, const ViewLayout& L,
+                             char* ws, hipStream_t stream) {
     if (p.n == 0) return hipSuccess;
     const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
     dim3 grid((unsigned)((p.n + 255) / 256), (unsigned)n_views);
@@ -198,9 +214,15 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
     float* payload = reinterpret_cast<float*>(ws + L.payload);
     uint32_t* keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
     uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
-#define LP_PRE(K_, D_)                                                                                        \
-    hipLaunchKernelGGL((k_preprocess<K_, D_>), grid, dim3(256), 0, stream, p.means, p.quats, p.dists, p.opacity, \
-                       p.sh, p.n, views, shift, payload, keys, tiles)
+#define LP_PRE(K_, D_)                                                                                         \
+    do {                                                                                                         \
+        if (exact)                                                                                               \
+            hipLaunchKernelGGL((k_preprocess<K_, D_, true>), grid, dim3(256), 0, stream, p.means, p.quats,        \
+                               p.dists, p.opacity, p.sh, p.n, views, shift, payload, keys, tiles);               \
+        else                                                                                                     \
+            hipLaunchKernelGGL((k_preprocess<K_, D_, false>), grid, dim3(256), 0, stream, p.means, p.quats,       \
+                               p.dists, p.opacity, p.sh, p.n, views, shift, payload, keys, tiles);               \
+    } while (0)
 #define LP_PRE_DEG(K_)                      \
     switch (p.sh_degree) {                  \
         case 0: LP_PRE(K_, 0); break;       \

@@ -94,7 +94,7 @@ struct Rec {
     int fmap;
 };
 
-template <int KIND>
+template <int KIND, bool EXACT = false>
 __device__ inline void load_rec(const float* __restrict__ rec, Rec& R) {
     R.i0 = __float_as_int(rec[R_I0]);
     R.j0 = __float_as_int(rec[R_J0]);
@@ -108,11 +108,11 @@ __device__ inline void load_rec(const float* __restrict__ rec, Rec& R) {
     R.fj0 = rec[R_FJ0];
     R.fwi = rec[R_FWI];
     R.fwj = rec[R_FWJ];
-    constexpr int NP = (KIND == LINPRIM_OCTAHEDRON) ? 16 : 18;
+    constexpr int NP = (EXACT || KIND == LINPRIM_OCTAHEDRON) ? 16 : 18;
 #pragma unroll
     for (int k = 0; k < NP; ++k) R.p[k] = rec[R_PLANES + k];
     R.sigma = rec[R_SIGMA];
-    R.fmap = (KIND == LINPRIM_OCTAHEDRON) ? 0 : __float_as_int(rec[R_FACEMAP]);
+    R.fmap = (EXACT || KIND == LINPRIM_OCTAHEDRON) ? 0 : __float_as_int(rec[R_FACEMAP]);
 }
 
 // Returns hi - lo; ih / il are the active upper / lower slot (first on ties).
@@ -177,10 +177,63 @@ __device__ inline float chord_fast(const Rec& R, float ki, float kj) {
     }
 }
 
+// Exact variant (no ray space): each plane k bounds the relative depth tau
+// along the pixel ray at (u_k + h) / (c_k - u_k).  Per plane: u, 1/(c - u),
+// the plane's upper and lower bounds (a tetrahedron face is an exit where
+// c - u >= 0, an entry elsewhere; the other bound is infinite).  A plane
+// parallel to the ray gives infinite (or, on its boundary, NaN) bounds,
+// which the min / max reductions ignore.
+struct ExactPlanes {
+    float u[4], inv[4], hi[4], lo[4];
+    float U, L;
+};
+
+template <int KIND>
+__device__ inline void exact_planes(const Rec& R, float ki, float kj, ExactPlanes& X) {
+#pragma clang fp contract(off)
+    X.U = INFINITY;
+    X.L = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const float u = __builtin_fmaf(R.p[4 * k + 0], ki, __builtin_fmaf(R.p[4 * k + 1], kj, R.p[4 * k + 2]));
+        const float den = R.p[4 * k + 3] - u;
+        const float inv = __builtin_amdgcn_rcpf(den);
+        X.u[k] = u;
+        X.inv[k] = inv;
+        if (KIND == LINPRIM_OCTAHEDRON) {
+            const float ui = u * inv;
+            const float t1 = ui - inv, t2 = ui + inv;
+            X.hi[k] = fmaxf(t1, t2);
+            X.lo[k] = fminf(t1, t2);
+        } else {
+            const float t = __builtin_fmaf(u, inv, inv);
+            const bool ex = den >= 0.0f;
+            X.hi[k] = ex ? t : INFINITY;
+            X.lo[k] = ex ? -INFINITY : t;
+        }
+        X.U = fminf(X.U, X.hi[k]);
+        X.L = fmaxf(X.L, X.lo[k]);
+    }
+}
+
+// |D| (min exits - max entries) with rn = |D| of the pixel ray; the z_c
+// factor of the chord is folded into the record's sigma.
+__device__ inline float exact_chord(const ExactPlanes& X, float rn) {
+#pragma clang fp contract(off)
+    return (X.U - X.L) * rn;
+}
+
 // Opacity factors of a chord: e = exp(-sigma chord), 1 - o = max(e, 0.01).
 __device__ inline float chord_exp(float s2, float delta) {
 #pragma clang fp contract(off)
     return __builtin_amdgcn_exp2f(-(s2 * delta));
+}
+
+// |D| of the exact variant's pixel ray D = ((x + 1/2 - cx)/fx, (y + 1/2 - cy)/fy, 1).
+__device__ inline float ray_norm(const ViewInfo& V, int x, int y) {
+    const float rx = (float)(((double)x + 0.5 - V.cx) / V.fx);
+    const float ry = (float)(((double)y + 0.5 - V.cy) / V.fy);
+    return sqrtf(rx * rx + ry * ry + 1.0f);
 }
 
 // ---------------------------------------------------------------------------
@@ -253,7 +306,7 @@ __device__ inline Batch load_batch(const float* __restrict__ base, const uint32_
 // ---------------------------------------------------------------------------
 // Forward.
 // ---------------------------------------------------------------------------
-template <int TILE, int KIND, bool COUNT>
+template <int TILE, int KIND, bool COUNT, bool EXACT>
 __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ views, int n_views, int64_t n,
                                                    const float* __restrict__ payload, const uint32_t* __restrict__ vals,
                                                    const uint2* __restrict__ ranges, const Status* __restrict__ status,
@@ -269,6 +322,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
     const int x = P.gx0 + (lane & 7), y = P.gy0 + (lane >> 3);
     const bool valid = x < P.W && y < P.H;
     const float pxf = (float)x, pyf = (float)y;
+    const float rn = EXACT ? ray_norm(views[P.v], x, y) : 1.0f;
     const uint2 rg = ranges[P.g];
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     int last = (int)rg.x;
@@ -293,7 +347,14 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
             const float ki = pxf - R.fi0, kj = pyf - R.fj0;
             // bitwise &: every test is a plain compare, no short-circuit branches
             const bool inside = !done & (ki >= 0.0f) & (ki <= R.fwi) & (kj >= 0.0f) & (kj <= R.fwj);
-            const float dch = chord_fast<KIND>(R, ki, kj);
+            float dch;
+            if (EXACT) {
+                ExactPlanes X;
+                exact_planes<KIND>(R, ki, kj, X);
+                dch = exact_chord(X, rn);
+            } else {
+                dch = chord_fast<KIND>(R, ki, kj);
+            }
             const bool hitp = inside && dch > 0.0f;
             if (COUNT) {
                 ev += inside ? 1u : 0u;
@@ -315,7 +376,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
         auto next_rec = [&](Rec& R) {
             const int b = __builtin_ctzll(mask);
             mask &= mask - 1;
-            load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)cur.idx, b) * kRecordWords, R);
+            load_rec<KIND, EXACT>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)cur.idx, b) * kRecordWords, R);
             return e0 + (uint32_t)b;
         };
         // Scalar loads complete out of order, so waiting for one buffer means
@@ -381,7 +442,7 @@ __device__ inline int64_t record_slot(const Rec& R, int tile_shift, int tx, int 
     return ((int64_t)prim_offset + (int64_t)(ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0)) * NQ + q;
 }
 
-template <int TILE, int KIND>
+template <int TILE, int KIND, bool EXACT>
 __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ views, int n_views, int64_t n,
                                                    const float* __restrict__ payload, const uint32_t* __restrict__ vals,
                                                    const uint2* __restrict__ ranges, const uint32_t* __restrict__ offsets,
@@ -398,6 +459,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
     const int x = P.gx0 + (lane & 7), y = P.gy0 + (lane >> 3);
     const bool valid = x < P.W && y < P.H;
     const float pxf = (float)x, pyf = (float)y;
+    const float rn = EXACT ? ray_norm(views[P.v], x, y) : 1.0f;
     const uint2 rg = ranges[P.g];
     const int64_t hw = (int64_t)P.W * P.H;
     const float* base = payload + (size_t)P.v * (size_t)n * kRecordWords;
@@ -450,7 +512,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
         auto next_rec = [&](Rec& R) {
             const int b = 63 - __builtin_clzll(mask);
             mask &= ~(1ull << b);
-            load_rec<KIND>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) * kRecordWords, R);
+            load_rec<KIND, EXACT>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) * kRecordWords, R);
             return b;
         };
         auto step = [&](const Rec& R, int bcur) {
@@ -469,7 +531,19 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             float dch;
             bool eh[4], el[4];
             int ih = 0, il = 0;
-            if (KIND == LINPRIM_OCTAHEDRON) {
+            ExactPlanes X;
+            if (EXACT) {
+                exact_planes<KIND>(R, ki, kj, X);
+                dch = exact_chord(X, rn);
+                bool fh = false, fl = false;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    eh[k] = !fh && X.hi[k] == X.U;
+                    el[k] = !fl && X.lo[k] == X.L;
+                    fh = fh || eh[k];
+                    fl = fl || el[k];
+                }
+            } else if (KIND == LINPRIM_OCTAHEDRON) {
 #pragma clang fp contract(off)
                 float h[4], l[4];
 #pragma unroll
@@ -515,7 +589,33 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             const float q = dLdo * ex;
             const float gD = open ? q * R.sigma : 0.0f;    // dL/dchord
             acc[19] = open ? q * delta : 0.0f;             // dL/dsigma
-            if (KIND == LINPRIM_OCTAHEDRON) {
+            if (EXACT) {
+                // words 4 k + 0..3: dL/d(a_k, b_k, g_k, c_k); a plane bound
+                // tau = (u + h) / (c - u) has dtau/du = (c + h) / (c - u)^2
+                // and dtau/dc = -tau / (c - u)
+                const float g = gD * rn;                   // dL/d(U - L)
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const float c = R.p[4 * k + 3];
+                    const float inv = X.inv[k];
+                    const float ge = eh[k] ? g : 0.0f, gl = el[k] ? g : 0.0f;
+                    float gu;
+                    if (KIND == LINPRIM_OCTAHEDRON) {
+                        // the upper bound has h = +1 where c - u >= 0, else h = -1
+                        const float hh = (c - X.u[k] >= 0.0f) ? 1.0f : -1.0f;
+                        gu = (ge * (c + hh) - gl * (c - hh)) * (inv * inv);
+                    } else {
+                        gu = (ge - gl) * (c + 1.0f) * (inv * inv);
+                    }
+                    const float gc = (gl * X.L - ge * X.U) * inv;
+                    const bool act = eh[k] || el[k];
+                    const float Gu = act ? gu : 0.0f, Gc = act ? gc : 0.0f;
+                    acc[4 * k + 0] = Gu * ki;
+                    acc[4 * k + 1] = Gu * kj;
+                    acc[4 * k + 2] = Gu;
+                    acc[4 * k + 3] = Gc;
+                }
+            } else if (KIND == LINPRIM_OCTAHEDRON) {
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const float gh = eh[s] ? gD : 0.0f;
@@ -545,7 +645,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             if (__ballot(contributed) != 0) outv = wave_reduce20(acc, lane);
             const int ridx = reduce20_index(lane);
             // octahedra: words 4 s + 3 are dL/dDlo = -sum of the lower-plane terms
-            if (KIND == LINPRIM_OCTAHEDRON && ridx < 16 && (ridx & 3) == 3) outv = -outv;
+            if (!EXACT && KIND == LINPRIM_OCTAHEDRON && ridx < 16 && (ridx & 3) == 3) outv = -outv;
             if (ridx >= 0) grads[slot * kGradWords + ridx] = outv;
         };
         Rec RA, RB;
@@ -576,22 +676,22 @@ static dim3 wave_grid(const ViewLayout& L) {
     return dim3((unsigned)(L.n_tiles_total * NQ));
 }
 
-template <int TILE, int KIND>
+template <int TILE, int KIND, bool EXACT>
 static void fwd_dispatch(bool count, const ViewLayout& Lv, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
                          const float* payload, const uint32_t* vals, const uint2* ranges, const Status* st,
                          uint64_t cap, const float bg[3], float* rgb, float* T, int32_t* last,
                          unsigned long long* counters) {
     const dim3 grid = wave_grid<TILE>(Lv);
     if (count)
-        hipLaunchKernelGGL((k_render_fwd<TILE, KIND, true>), grid, dim3(64), 0, s, views, nv, n, payload, vals, ranges,
-                           st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters);
+        hipLaunchKernelGGL((k_render_fwd<TILE, KIND, true, EXACT>), grid, dim3(64), 0, s, views, nv, n, payload, vals,
+                           ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters);
     else
-        hipLaunchKernelGGL((k_render_fwd<TILE, KIND, false>), grid, dim3(64), 0, s, views, nv, n, payload, vals, ranges,
-                           st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters);
+        hipLaunchKernelGGL((k_render_fwd<TILE, KIND, false, EXACT>), grid, dim3(64), 0, s, views, nv, n, payload, vals,
+                           ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters);
 }
 
 hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
-                                int result_in_b, int type, int tile, int32_t n_views, const float bg[3],
+                                int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                                 float* out_rgb, float* out_T, int32_t* out_last, unsigned long long* counters,
                                 hipStream_t stream) {
     if (L.n_tiles_total == 0) return hipSuccess;
@@ -602,35 +702,42 @@ hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const Pair
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
     const uint64_t cap = (uint64_t)P.capacity;
     const bool count = counters != nullptr;
-#define LP_FWD(T_, K_) fwd_dispatch<T_, K_>(count, L, stream, views, n_views, L.n, payload, vals, ranges, st, cap, bg, \
-                                            out_rgb, out_T, out_last, counters)
+#define LP_FWD(T_, K_, E_) fwd_dispatch<T_, K_, E_>(count, L, stream, views, n_views, L.n, payload, vals, ranges, st, \
+                                                    cap, bg, out_rgb, out_T, out_last, counters)
+#define LP_FWD_T(K_, E_)                                                       \
+    do {                                                                       \
+        if (tile == 8) LP_FWD(8, K_, E_);                                      \
+        else if (tile == 16) LP_FWD(16, K_, E_);                               \
+        else LP_FWD(32, K_, E_);                                               \
+    } while (0)
     if (type == LINPRIM_OCTAHEDRON) {
-        if (tile == 8) LP_FWD(8, 0); else if (tile == 16) LP_FWD(16, 0); else LP_FWD(32, 0);
+        if (exact) LP_FWD_T(0, true); else LP_FWD_T(0, false);
     } else {
-        if (tile == 8) LP_FWD(8, 1); else if (tile == 16) LP_FWD(16, 1); else LP_FWD(32, 1);
+        if (exact) LP_FWD_T(1, true); else LP_FWD_T(1, false);
     }
+#undef LP_FWD_T
 #undef LP_FWD
     return hipGetLastError();
 }
 
 hipError_t launch_render_fwd(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
-                             int result_in_b, int type, int tile, int32_t n_views, const float bg[3],
+                             int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                              float* out_rgb, float* out_T, int32_t* out_last, hipStream_t stream) {
-    return launch_render_fwd_ex(L, vws, P, pws, result_in_b, type, tile, n_views, bg, out_rgb, out_T, out_last,
+    return launch_render_fwd_ex(L, vws, P, pws, result_in_b, type, exact, tile, n_views, bg, out_rgb, out_T, out_last,
                                 nullptr, stream);
 }
 
-template <int TILE, int KIND>
+template <int TILE, int KIND, bool EXACT>
 static void bwd_dispatch(const ViewLayout& Lv, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
                          const float* payload, const uint32_t* vals, const uint2* ranges, const uint32_t* offsets,
                          const Status* st, uint64_t cap, const float bg[3], const float* T, const int32_t* last,
                          const float* grad, float* grads) {
-    hipLaunchKernelGGL((k_render_bwd<TILE, KIND>), wave_grid<TILE>(Lv), dim3(64), 0, s, views, nv, n, payload, vals,
-                       ranges, offsets, st, cap, bg[0], bg[1], bg[2], T, last, grad, grads);
+    hipLaunchKernelGGL((k_render_bwd<TILE, KIND, EXACT>), wave_grid<TILE>(Lv), dim3(64), 0, s, views, nv, n, payload,
+                       vals, ranges, offsets, st, cap, bg[0], bg[1], bg[2], T, last, grad, grads);
 }
 
 hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLayout& P, char* pws, int result_in_b,
-                             int type, int tile, int32_t n_views, const float bg[3], const float* out_T,
+                             int type, bool exact, int tile, int32_t n_views, const float bg[3], const float* out_T,
                              const int32_t* out_last, const float* grad_rgb, hipStream_t stream) {
     if (L.n_tiles_total == 0) return hipSuccess;
     const ViewInfo* views = reinterpret_cast<const ViewInfo*>(vws + L.views);
@@ -641,13 +748,20 @@ hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLay
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
     float* grads = reinterpret_cast<float*>(pws + P.grads);
     const uint64_t cap = (uint64_t)P.capacity;
-#define LP_BWD(T_, K_) bwd_dispatch<T_, K_>(L, stream, views, n_views, L.n, payload, vals, ranges, offsets, st, cap, \
-                                            bg, out_T, out_last, grad_rgb, grads)
+#define LP_BWD(T_, K_, E_) bwd_dispatch<T_, K_, E_>(L, stream, views, n_views, L.n, payload, vals, ranges, offsets, \
+                                                    st, cap, bg, out_T, out_last, grad_rgb, grads)
+#define LP_BWD_T(K_, E_)                                                       \
+    do {                                                                       \
+        if (tile == 8) LP_BWD(8, K_, E_);                                      \
+        else if (tile == 16) LP_BWD(16, K_, E_);                               \
+        else LP_BWD(32, K_, E_);                                               \
+    } while (0)
     if (type == LINPRIM_OCTAHEDRON) {
-        if (tile == 8) LP_BWD(8, 0); else if (tile == 16) LP_BWD(16, 0); else LP_BWD(32, 0);
+        if (exact) LP_BWD_T(0, true); else LP_BWD_T(0, false);
     } else {
-        if (tile == 8) LP_BWD(8, 1); else if (tile == 16) LP_BWD(16, 1); else LP_BWD(32, 1);
+        if (exact) LP_BWD_T(1, true); else LP_BWD_T(1, false);
     }
+#undef LP_BWD_T
 #undef LP_BWD
     return hipGetLastError();
 }

@@ -41,6 +41,19 @@ constexpr int kGradWords = 20;            // backward record per (tile, primitiv
 //   [30]    float sigma
 // The chord through the primitive at a pixel is
 //   max(0, min over upper planes - max over lower planes).
+//
+// Exact variant (no ray space), both types: the pixel ray is
+// X(tau) = z_c (1 + tau) D with D = ((i + 1/2 - cx)/fx, (j + 1/2 - cy)/fy, 1)
+// and z_c the centre's camera depth.  Plane k of the camera-space primitive,
+// n_k . (X - centre) = h, crosses it at tau = (u_k + h) / (c_k - u_k) with
+//   u_k = a_k ki + b_k kj + g_k  (= n_k . (centre - z_c D)),  c_k = n_k . centre.
+//   [12 + 4 k .. 15 + 4 k]  float a_k, b_k, g_k, c_k   (k = 0..3)
+//   octahedron: slab k is -1 <= n_k . (X - centre) <= 1 (both signs of h);
+//   tetrahedron: face k is n_k . (X - centre) <= 1, an exit where
+//   c_k - u_k >= 0 and an entry elsewhere;
+//   [4]  float sigma z_c log2(e),  [30] float sigma z_c.
+// The chord is |D| z_c (min exits - max entries), so that
+// exp(-sigma chord) = exp2(-[4] |D| (min exits - max entries)).
 // ----------------------------------------------------------------------------
 enum : int {
     R_I0 = 0, R_J0 = 1, R_I1 = 2, R_J1 = 3, R_S2 = 4, R_RGB = 5, R_FI0 = 8, R_FJ0 = 9, R_FWI = 10,
@@ -98,7 +111,7 @@ int key_tile_bits(int64_t n_tiles_total);
 // ----------------------------------------------------------------------------
 hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int tile, ViewInfo* views,
                               hipStream_t stream);
-hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L,
+hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, const ViewLayout& L,
                              char* ws, hipStream_t stream);
 hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stream);
 
@@ -118,13 +131,13 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
                            int tile, int digit_bits, int32_t n_views, const linprim_camera* cams,
                            hipStream_t stream, int* result_in_b);
 hipError_t launch_render_fwd(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
-                             int result_in_b, int type, int tile, int32_t n_views, const float bg[3],
+                             int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                              float* out_rgb, float* out_T, int32_t* out_last, hipStream_t stream);
 hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLayout& P, char* pws,
-                             int result_in_b, int type, int tile, int32_t n_views, const float bg[3],
+                             int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                              const float* out_T, const int32_t* out_last, const float* grad_rgb,
                              hipStream_t stream);
-hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, const ViewLayout& L,
+hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, bool exact, const ViewLayout& L,
                                  const char* vws, const PairLayout& P, const char* pws, float* g_means,
                                  float* g_quats, float* g_dists, float* g_opacity, float* g_sh,
                                  hipStream_t stream);
@@ -249,7 +262,7 @@ struct Geom {
 // Builds the primitive, transforms it and bounds it.  Returns false if the
 // primitive is culled.  The rectangle and key computations follow the
 // binning contract exactly (double precision, fixed order, no contraction).
-__device__ inline bool build_geometry(int type, const float* mu_f, const float* q_f, const float* d_f,
+__device__ inline bool build_geometry(int type, bool exact, const float* mu_f, const float* q_f, const float* d_f,
                                       float alpha, const ViewInfo& V, Geom& G) {
     const int na = (type == LINPRIM_OCTAHEDRON) ? 3 : 4;
     if (!quat_rotation_d((double)q_f[0], (double)q_f[1], (double)q_f[2], (double)q_f[3], G.R)) return false;
@@ -309,6 +322,29 @@ __device__ inline bool build_geometry(int type, const float* mu_f, const float* 
             if (xm > xmax) xmax = xm;
             if (ym < ymin) ymin = ym;
             if (ym > ymax) ymax = ym;
+        }
+    }
+    if (exact) {
+        // without ray space the footprint is bounded by the perspective
+        // projections of the corners; a corner at or in front of the near
+        // plane has none, and the primitive is culled
+        xmin = INFINITY; xmax = -INFINITY; ymin = INFINITY; ymax = -INFINITY;
+        const int nc = (type == LINPRIM_OCTAHEDRON) ? 6 : 4;
+        for (int k = 0; k < nc; ++k) {
+            double v[3];
+            for (int r = 0; r < 3; ++r) {
+                if (type == LINPRIM_OCTAHEDRON)
+                    v[r] = (k & 1) ? G.tc[r] - G.oc[k >> 1][r] : G.tc[r] + G.oc[k >> 1][r];
+                else
+                    v[r] = G.tc[r] + G.oc[k][r];
+            }
+            if (!(v[2] > V.near_z)) return false;
+            const double xp = V.fx * v[0] / v[2] + V.cx;
+            const double yp = V.fy * v[1] / v[2] + V.cy;
+            if (xp < xmin) xmin = xp;
+            if (xp > xmax) xmax = xp;
+            if (yp < ymin) ymin = yp;
+            if (yp > ymax) ymax = yp;
         }
     }
     if (!isfinite(xmin) || !isfinite(xmax) || !isfinite(ymin) || !isfinite(ymax)) return false;
@@ -423,6 +459,36 @@ __device__ inline double inverse3(const double M[9], double N[9]) {
     N[7] = (M[1] * M[6] - M[0] * M[7]) * id;
     N[8] = (M[0] * M[4] - M[1] * M[3]) * id;
     return det;
+}
+
+// Exact variant: camera-space normals of the primitive's planes, scaled so
+// that the octahedron (centre + M s, |s|_1 <= 1, columns of M the offsets
+// oc_c) is |n_k . (X - centre)| <= 1 for its 4 slabs, n_k = M^-T kSlab[k],
+// and the tetrahedron n_k . (X - centre) <= 1 for the face opposite corner
+// k (n_k . oc_m = 1 for the other three corners).  Exact inverses: the
+// camera rotation, given in float32, need not be exactly orthonormal.
+__device__ inline void exact_normals(int type, const Geom& G, double n[4][3]) {
+    if (type == LINPRIM_OCTAHEDRON) {
+        double M[9], N[9];
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) M[3 * r + c] = G.oc[c][r];
+        inverse3(M, N);
+        for (int k = 0; k < 4; ++k)
+            for (int r = 0; r < 3; ++r)
+                n[k][r] = kSlab[k][0] * N[r] + kSlab[k][1] * N[3 + r] + kSlab[k][2] * N[6 + r];
+    } else {
+        for (int f = 0; f < 4; ++f) {
+            double M[9], N[9];
+            int q = 0;
+            for (int m = 0; m < 4; ++m) {
+                if (m == f) continue;
+                for (int c = 0; c < 3; ++c) M[3 * q + c] = G.oc[m][c];
+                ++q;
+            }
+            inverse3(M, N);
+            for (int c = 0; c < 3; ++c) n[f][c] = N[3 * c] + N[3 * c + 1] + N[3 * c + 2];
+        }
+    }
 }
 
 // Smallest |z| component allowed for a face normal relative to its length;

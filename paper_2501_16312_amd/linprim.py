@@ -31,6 +31,7 @@ ERR_DEVICE = -5
 FLAG_COUNTERS = 1
 FLAG_VIEWS_RESIDENT = 2
 FLAG_RADIX_SORT = 4
+FLAG_EXACT_RAYS = 8
 
 
 class linprim_prims(ctypes.Structure):

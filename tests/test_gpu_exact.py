@@ -1,0 +1,179 @@
+"""HIP path of the exact variant (no ray-space approximation) vs the FP64
+oracle's exact mode, through the C ABI (MI355X only).
+
+Same bars as the ray-space path: binning bit-exact, images within 1e-5
+absolute and gradients within 1e-3 relative on well-conditioned pixels /
+primitives, as flagged by the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2501_16312_amd import scenes
+from tests import gpu_common as GC
+
+pytestmark = pytest.mark.gpu
+
+OCTA, TETRA = scenes.OCTAHEDRON, scenes.TETRAHEDRON
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def oracle_mod():
+    import oracle
+    oracle._load()
+    return oracle
+
+
+def _scene(kind, n, seed):
+    gen = scenes.uniform_octahedra if kind == OCTA else scenes.uniform_tetrahedra
+    return gen(n, seed=seed, dmin=0.03, dmax=0.25)
+
+
+def _cams():
+    # two uneven views, image sizes not multiples of the tile
+    return [scenes.look_at((0.2, 0.1, -2.6), (0, 0, 0), 88, 61),
+            scenes.look_at((2.4, 0.5, 0.6), (0, 0, 0), 45, 37)]
+
+
+@pytest.mark.parametrize("kind", [OCTA, TETRA])
+@pytest.mark.parametrize("tile", [8, 16])
+def test_exact_binning_bit_exact(oracle_mod, kind, tile):
+    _say(f"exact binning kind={kind} tile={tile}")
+    sc = _scene(kind, 700, seed=41)
+    cams = _cams()
+    g = GC.gpu_forward(sc, cams, tile=tile, exact=True)
+    dbg = g["rast"].debug_arrays(g["prims"])
+    O = oracle_mod.OracleScene(sc, cams, tile=tile, exact=True)
+    culled_by_corner = 0
+    for v in range(len(cams)):
+        p = O.prep(v)
+        pay = dbg["payload"][v * sc.n:(v + 1) * sc.n].numpy()
+        rect = pay[:, :4].view(np.int32)
+        assert np.array_equal(rect[p["valid"]], p["rect"][p["valid"]])
+        assert np.all(rect[~p["valid"], 0] == -1)
+        keys = dbg["depth_keys"][v * sc.n:(v + 1) * sc.n].numpy().view(np.uint32)
+        assert np.array_equal(keys[p["valid"]], p["key"][p["valid"]])
+        assert np.array_equal(dbg["tiles"][v * sc.n:(v + 1) * sc.n].numpy(), p["tiles"])
+        rs = oracle_mod.OracleScene(sc, [cams[v]], tile=tile).prep()
+        culled_by_corner += int((rs["valid"] & ~p["valid"]).sum())
+    s = O.sort()
+    assert g["n_pairs"] == len(s["keys"])
+    assert np.array_equal(dbg["keys"].numpy().view(np.uint64), s["keys"])
+    assert np.array_equal(dbg["values"].numpy().view(np.uint32), s["values"])
+    _say(f"  primitives culled only for a corner behind the near plane: {culled_by_corner}")
+
+
+@pytest.mark.parametrize("kind", [OCTA, TETRA])
+def test_exact_forward_parity(oracle_mod, kind):
+    _say(f"exact forward kind={kind}")
+    sc = _scene(kind, 900, seed=43)
+    cams = _cams()
+    bg = (0.1, 0.2, 0.3)
+    g = GC.gpu_forward(sc, cams, tile=16, bg=bg, exact=True, counters=True)
+    O = oracle_mod.OracleScene(sc, cams, tile=16, exact=True)
+    r = O.render(bg=np.asarray(bg))
+    r["cams"] = cams
+    good, _, ill = GC.compare_images(g, r, f"exact kind={kind}")
+    assert good <= GC.IMG_TOL
+    # close-up primitives: the oracle flags about 3% of the pixels (the same
+    # share as for this scene in ray space)
+    assert ill < 0.05
+    ok = (r["ill"] & 1) == 0
+    assert np.mean(g["last"][ok] == r["last"][ok]) > 0.999
+    assert (r["T"] < 1).mean() > 0.2
+    ev = int(r["counts"][:, 1].sum())
+    hit = int(r["counts"][:, 2].sum())
+    _say(f"  counts gpu {g['counts'].tolist()} oracle evaluated {ev} intersected {hit}")
+    assert abs(int(g["counts"][1]) - ev) <= max(2, 1e-3 * ev)
+    assert abs(int(g["counts"][2]) - hit) <= max(2, 1e-3 * hit)
+
+
+def test_exact_differs_from_ray_space(oracle_mod):
+    """The two chord models give different images on large close primitives
+    (the variant is not silently the ray-space path)."""
+    _say("exact vs ray space")
+    sc = scenes.uniform_octahedra(60, seed=47, box=0.5, dmin=0.2, dmax=0.5)
+    cams = [scenes.look_at((0.0, 0.0, -2.2), (0, 0, 0), 64, 64)]
+    a = GC.gpu_forward(sc, cams, tile=16, exact=True)["rgb"]
+    b = GC.gpu_forward(sc, cams, tile=16, exact=False)["rgb"]
+    ra = oracle_mod.OracleScene(sc, cams, tile=16, exact=True).render()["rgb"]
+    assert np.abs(a - b).max() > 1e-3
+    assert np.abs(a - ra).max() < np.abs(b - ra).max()
+
+
+def test_exact_tile_size_invariance():
+    _say("exact tile invariance")
+    sc = _scene(OCTA, 700, seed=45)
+    cams = [scenes.look_at((0.1, -0.3, -2.8), (0, 0, 0), 100, 70)]
+    imgs = [GC.gpu_forward(sc, cams, tile=t, exact=True)["rgb"] for t in (8, 16, 32)]
+    assert np.array_equal(imgs[0], imgs[1])
+    assert np.array_equal(imgs[0], imgs[2])
+
+
+@pytest.mark.parametrize("kind", [OCTA, TETRA])
+@pytest.mark.parametrize("tile", [8, 16])
+def test_exact_backward_parity(oracle_mod, kind, tile):
+    _say(f"exact backward kind={kind} tile={tile}")
+    gen = scenes.uniform_octahedra if kind == OCTA else scenes.uniform_tetrahedra
+    sc = gen(500, seed=49, dmin=0.03, dmax=0.15)
+    cams = [scenes.look_at((0.2, 0.1, -3.0), (0, 0, 0), 88, 61), scenes.look_at((2.76, 0.5, 0.6), (0, 0, 0), 45, 37)]
+    bg = (0.3, 0.1, 0.2)
+    grad = scenes.image_gradient(cams, seed=5)
+    g = GC.gpu_forward(sc, cams, tile=tile, bg=bg, exact=True)
+    gg = GC.gpu_backward(g, grad, bg)
+    rb = oracle_mod.OracleScene(sc, cams, tile=tile, exact=True).backward(grad.astype(np.float64),
+                                                                           bg=np.asarray(bg))
+    ok = ~rb["ill"]
+    _say(f"  prims ill {rb['ill'].mean() * 100:.2f}%")
+    # a primitive is left out if any pixel reaching it is ill-conditioned
+    # (about 12% of the octahedra here, 3% of the tetrahedra; ray space alike)
+    assert ok.mean() > 0.8
+    w = GC.grad_errors(gg, rb, ok, f"exact kind={kind} tile={tile}")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k
+
+
+def test_exact_config0_parity(oracle_mod):
+    """The 1,024-octahedron workload at 128 x 128, forward and backward."""
+    _say("exact config0")
+    sc, cams = scenes.config0()
+    grad = scenes.image_gradient(cams, seed=1)
+    g = GC.gpu_forward(sc, cams, tile=16, exact=True)
+    O = oracle_mod.OracleScene(sc, cams, tile=16, exact=True)
+    r = O.render()
+    r["cams"] = cams
+    good, _, ill = GC.compare_images(g, r, "exact config0")
+    assert good <= GC.IMG_TOL and ill < 0.01
+    gg = GC.gpu_backward(g, grad)
+    rb = O.backward(grad.astype(np.float64))
+    ok = ~rb["ill"]
+    w = GC.grad_errors(gg, rb, ok, "exact config0")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k
+
+
+def test_exact_full_size_sampled(oracle_mod):
+    """1M octahedra at 1080p without ray space: sampled pixels against the
+    oracle's brute-force per-pixel render."""
+    _say("exact full-size sampled config2")
+    sc, cams = scenes.CONFIGS[2]()
+    cam = cams[0]
+    g = GC.gpu_forward(sc, cams, tile=8, exact=True)
+    _say(f"  pairs {g['n_pairs']}")
+    O = oracle_mod.OracleScene(sc, cams, tile=8, exact=True)
+    rng = np.random.default_rng(202)
+    idx = rng.choice(cam.width * cam.height, size=1200, replace=False)
+    pix = np.stack([idx % cam.width, idx // cam.width], 1).astype(np.int32)
+    r = O.render_pixels(0, pix)
+    hw = cam.width * cam.height
+    rgb = np.stack([g["rgb"][c * hw + idx] for c in range(3)], 1)
+    ok = (r["ill"] & 1) == 0
+    err = np.maximum(np.abs(rgb - r["rgb"]).max(1), np.abs(g["T"][idx] - r["T"]))
+    _say(f"  sampled max err (ok) {err[ok].max():.3e}, overall {err.max():.3e}, ill {(~ok).mean() * 100:.2f}%")
+    assert err[ok].max() <= GC.IMG_TOL
+    assert (r["T"] < 1).mean() > 0.05
