@@ -128,6 +128,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
         double nrm[4][3];
         exact_normals(KIND, G, nrm);
         const double zc = G.tc[2];
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
             const double a = -zc * nrm[k][0] / V.fx, b = -zc * nrm[k][1] / V.fy;
             out[R_PLANES + 4 * k + 0] = (float)a;

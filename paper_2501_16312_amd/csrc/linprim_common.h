@@ -330,8 +330,11 @@ __device__ inline bool build_geometry(int type, bool exact, const float* mu_f, c
         // plane has none, and the primitive is culled
         xmin = INFINITY; xmax = -INFINITY; ymin = INFINITY; ymax = -INFINITY;
         const int nc = (type == LINPRIM_OCTAHEDRON) ? 6 : 4;
-        for (int k = 0; k < nc; ++k) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            if (k >= nc) break;
             double v[3];
+#pragma unroll
             for (int r = 0; r < 3; ++r) {
                 if (type == LINPRIM_OCTAHEDRON)
                     v[r] = (k & 1) ? G.tc[r] - G.oc[k >> 1][r] : G.tc[r] + G.oc[k >> 1][r];
@@ -473,19 +476,23 @@ __device__ inline void exact_normals(int type, const Geom& G, double n[4][3]) {
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) M[3 * r + c] = G.oc[c][r];
         inverse3(M, N);
+#pragma unroll
         for (int k = 0; k < 4; ++k)
+#pragma unroll
             for (int r = 0; r < 3; ++r)
                 n[k][r] = kSlab[k][0] * N[r] + kSlab[k][1] * N[3 + r] + kSlab[k][2] * N[6 + r];
     } else {
+#pragma unroll
         for (int f = 0; f < 4; ++f) {
             double M[9], N[9];
-            int q = 0;
-            for (int m = 0; m < 4; ++m) {
-                if (m == f) continue;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                const int m = q + (q >= f ? 1 : 0);     // the corners other than f
+#pragma unroll
                 for (int c = 0; c < 3; ++c) M[3 * q + c] = G.oc[m][c];
-                ++q;
             }
             inverse3(M, N);
+#pragma unroll
             for (int c = 0; c < 3; ++c) n[f][c] = N[3 * c] + N[3 * c + 1] + N[3 * c + 2];
         }
     }
