@@ -67,6 +67,7 @@ def _load():
     lib.orc_mtia.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
     lib.orc_mtia_ray.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_set_exact.argtypes = [P, ctypes.c_int]
+    lib.orc_set_antialias.argtypes = [P, ctypes.c_int]
     lib.orc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_backward.argtypes = [P] + [ctypes.c_void_p] * 8
     lib.orc_num_threads.restype = ctypes.c_int
@@ -121,9 +122,13 @@ class OracleScene:
     """One scene and a set of views, rendered in double precision.
 
     ``exact`` selects the variant without the ray-space approximation: pixel
-    rays from the camera centre meet the camera-space primitives."""
+    rays from the camera centre meet the camera-space primitives.
+    ``antialias`` applies the 2D anti-aliasing filter (ray space only)."""
 
-    def __init__(self, scene, cams, tile: int = 16, inputs64: Optional[dict] = None, exact: bool = False):
+    def __init__(self, scene, cams, tile: int = 16, inputs64: Optional[dict] = None, exact: bool = False,
+                 antialias: bool = False):
+        if exact and antialias:
+            raise ValueError("the anti-aliasing filter belongs to the ray-space model")
         lib = _load()
         self.kind = int(scene.kind)
         self.n = int(scene.n)
@@ -154,6 +159,8 @@ class OracleScene:
         self._sorted = False
         self.exact = bool(exact)
         lib.orc_set_exact(self.h, 1 if self.exact else 0)
+        self.antialias = bool(antialias)
+        lib.orc_set_antialias(self.h, 1 if self.antialias else 0)
         lib.orc_preprocess(self.h)
 
     def __del__(self):

@@ -95,6 +95,7 @@ typedef struct {
 typedef struct {
     int type, deg, K, nd;
     int exact;               /* 0: EWA ray space (Sec. 3.2); 1: pixel rays in camera space (App. "Ray Space Approximation") */
+    int aa;                  /* 2D anti-aliasing filter (App. "Anti-Aliasing"), ray space only */
     int64_t n;
     double *means, *quats, *dists, *opac, *sh;
     int n_views, tile;
@@ -251,6 +252,40 @@ static void ray_jacobian(const orc_view *V, const double t[3], double J[3][3])
     J[2][0] = t[0] / l; J[2][1] = t[1] / l; J[2][2] = t[2] / l;
 }
 
+/* The 2D anti-aliasing filter (appendix "Anti-Aliasing", filter size in
+ * App. G): the corners that lie on the tiling box move outward, parallel to
+ * the screen, by the filter size of 0.1 pixel.  An octahedron's ray-space
+ * axis vector a_k carries the two corners c +/- a_k, so it moves by half the
+ * size (both corners move out by 0.05); a tetrahedron's corner c + a_i moves
+ * by the full size.  A corner on two sides of the box moves along both axes.
+ * The selection is piecewise constant, so gradients pass through unchanged. */
+#define ORC_AA_SIZE 0.1
+static void antialias_shift(int type, double a[4][3])
+{
+    for (int ax = 0; ax < 2; ++ax) {
+        if (type == ORC_OCTA) {
+            double ext = 0.0;
+            for (int k = 0; k < 3; ++k) if (fabs(a[k][ax]) > ext) ext = fabs(a[k][ax]);
+            double shift[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < 3; ++k)
+                if (fabs(a[k][ax]) == ext) shift[k] = copysign(0.5 * ORC_AA_SIZE, a[k][ax]);
+            for (int k = 0; k < 3; ++k) a[k][ax] += shift[k];
+        } else {
+            double lo = a[0][ax], hi = a[0][ax];
+            for (int i = 1; i < 4; ++i) {
+                if (a[i][ax] < lo) lo = a[i][ax];
+                if (a[i][ax] > hi) hi = a[i][ax];
+            }
+            double shift[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int i = 0; i < 4; ++i) {
+                if (a[i][ax] == lo) shift[i] -= ORC_AA_SIZE;
+                if (a[i][ax] == hi) shift[i] += ORC_AA_SIZE;
+            }
+            for (int i = 0; i < 4; ++i) a[i][ax] += shift[i];
+        }
+    }
+}
+
 /* Sec. 3.2 "Preprocessing": build the primitive, transform it to the camera,
  * colour it from the viewing direction, project it into ray space and bound
  * it on screen. */
@@ -287,12 +322,15 @@ static void preprocess_one(const orc_scene *S, const orc_view *V, int64_t n, orc
     const double l = sqrt(tc[0] * tc[0] + tc[1] * tc[1] + tc[2] * tc[2]);
     P->tc[0] = tc[0]; P->tc[1] = tc[1]; P->tc[2] = tc[2];
     P->c[0] = cxp; P->c[1] = cyp; P->c[2] = l;
+    for (int k = 0; k < na; ++k) {
+        P->a[k][0] = J00 * oc[k][0] + J02 * oc[k][2];
+        P->a[k][1] = J11 * oc[k][1] + J12 * oc[k][2];
+        P->a[k][2] = tc[0] / l * oc[k][0] + tc[1] / l * oc[k][1] + tc[2] / l * oc[k][2];
+    }
+    if (S->aa) antialias_shift(S->type, P->a);
     double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
     for (int k = 0; k < na; ++k) {
-        const double ax = J00 * oc[k][0] + J02 * oc[k][2];
-        const double ay = J11 * oc[k][1] + J12 * oc[k][2];
-        const double az = tc[0] / l * oc[k][0] + tc[1] / l * oc[k][1] + tc[2] / l * oc[k][2];
-        P->a[k][0] = ax; P->a[k][1] = ay; P->a[k][2] = az;
+        const double ax = P->a[k][0], ay = P->a[k][1];
         /* corners: c + a_k, and for the octahedron also c - a_k */
         const double xs[2] = {cxp + ax, cxp - ax}, ys[2] = {cyp + ay, cyp - ay};
         const int nsign = (S->type == ORC_OCTA) ? 2 : 1;
@@ -785,6 +823,16 @@ int orc_set_views(void *h, int n_views, const double *cams, int tile)
     }
     S->n_tiles_total = tb;
     S->prep = (orc_prep *)calloc((size_t)n_views * (size_t)(S->n > 0 ? S->n : 1), sizeof(orc_prep));
+    return 0;
+}
+
+/* Selects the 2D anti-aliasing filter for the following orc_preprocess
+ * (ray space only). */
+int orc_set_antialias(void *h, int aa)
+{
+    orc_scene *S = (orc_scene *)h;
+    if (!S) return -1;
+    S->aa = aa ? 1 : 0;
     return 0;
 }
 
