@@ -113,6 +113,16 @@ typedef struct linprim_tuning {
  * keys, sorting, compositing and Eq. 1 are unchanged.  The flag must be the
  * same in every call on one pair of workspaces. */
 #define LINPRIM_FLAG_EXACT_RAYS 8
+/* The 2D anti-aliasing filter of the paper's appendix on anti-aliasing
+ * (filter size 0.1 pixel, App. G): in ray space, the corners that lie on
+ * the primitive's tiling box move outward, parallel to the screen, by
+ * 0.1 pixel (an octahedron's axis vector, which carries two mirrored
+ * corners, by 0.05); every corner attaining an extreme moves, along both
+ * axes if it attains two.  This enlarges the footprint and the chords of
+ * small primitives; gradients pass through the constant shift.  Not
+ * combinable with LINPRIM_FLAG_EXACT_RAYS (INVALID_ARG).  Same flag in
+ * every call on one pair of workspaces. */
+#define LINPRIM_FLAG_ANTIALIAS 16
 
 /* Bytes of the per-view workspace (payloads, counts, offsets, tile ranges,
  * status) for n primitives of `type` over n_views cameras; 0 for invalid

@@ -82,6 +82,8 @@ int digit_of(const linprim_tuning* tu) {
 
 bool valid_tuning(const linprim_tuning* tu) {
     if (!valid_tile(tile_of(tu))) return false;
+    // the anti-aliasing filter belongs to the ray-space model
+    if (tu && (tu->flags & LINPRIM_FLAG_EXACT_RAYS) && (tu->flags & LINPRIM_FLAG_ANTIALIAS)) return false;
     const int d = digit_of(tu);
     return d >= 4 && d <= 8;
 }
@@ -129,6 +131,8 @@ bool radix_sort(const linprim_tuning* tu) { return tu && (tu->flags & LINPRIM_FL
 
 bool exact_rays(const linprim_tuning* tu) { return tu && (tu->flags & LINPRIM_FLAG_EXACT_RAYS); }
 
+bool antialias(const linprim_tuning* tu) { return tu && (tu->flags & LINPRIM_FLAG_ANTIALIAS); }
+
 int result_buffer(const ViewLayout& L, const linprim_tuning* tu) {
     return sorted_buffer(L.n_tiles_total, radix_sort(tu), digit_of(tu));
 }
@@ -166,7 +170,7 @@ int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, i
     hipError_t e = hipSuccess;
     if (!(tuning && (tuning->flags & LINPRIM_FLAG_VIEWS_RESIDENT)))
         e = launch_store_views(cams, n_views, tile, reinterpret_cast<ViewInfo*>(ws + L.views), s);
-    if (e == hipSuccess) e = launch_preprocess(*prims, n_views, tile, exact_rays(tuning), L, ws, s);
+    if (e == hipSuccess) e = launch_preprocess(*prims, n_views, tile, exact_rays(tuning), antialias(tuning), L, ws, s);
     if (e == hipSuccess) e = launch_scan(L, ws, tile, s);
     return hip_status(e);
 }
@@ -269,7 +273,7 @@ int linprim_render_bwd(const linprim_prims* prims, const linprim_camera* cams, i
     hipError_t e = launch_render_bwd(L, (const char*)view_ws, P, (char*)pair_ws, in_b, prims->type,
                                      exact_rays(tuning), tile_of(tuning), n_views, bg, out_T, out_last, grad_rgb, s);
     if (e == hipSuccess)
-        e = launch_preprocess_bwd(*prims, n_views, tile_of(tuning), exact_rays(tuning), L, (const char*)view_ws, P,
+        e = launch_preprocess_bwd(*prims, n_views, tile_of(tuning), exact_rays(tuning), antialias(tuning), L, (const char*)view_ws, P,
                                   (const char*)pair_ws,
                                   grad_means, grad_quats, grad_dists, grad_opacity, grad_sh, s);
     return hip_status(e);
@@ -299,7 +303,7 @@ int linprim_preprocess_bwd(const linprim_prims* prims, const linprim_camera* cam
     ViewLayout L;
     PairLayout P;
     if (int rc = prepare(prims, cams, n_views, tuning, view_ws_bytes, pair_ws_bytes, max_pairs, L, P)) return rc;
-    return hip_status(launch_preprocess_bwd(*prims, n_views, tile_of(tuning), exact_rays(tuning), L,
+    return hip_status(launch_preprocess_bwd(*prims, n_views, tile_of(tuning), exact_rays(tuning), antialias(tuning), L,
                                             (const char*)view_ws, P,
                                             (const char*)pair_ws, grad_means, grad_quats, grad_dists, grad_opacity,
                                             grad_sh, (hipStream_t)stream));

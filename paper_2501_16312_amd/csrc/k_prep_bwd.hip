@@ -286,7 +286,7 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
                                                   const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
                                                   const uint32_t* __restrict__ offsets, float* __restrict__ grads,
                                                   int nq, const Status* __restrict__ status, uint64_t capacity,
-                                                  const uint32_t* __restrict__ vis) {
+                                                  const uint32_t* __restrict__ vis, int aa) {
     // one thread per (view, primitive) slot that touches a tile, taken from
     // the list the scan built, so that no lane idles on a culled slot
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -336,7 +336,8 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     }
     const ViewInfo& V = views[v];
     Geom G;
-    if (!build_geometry(KIND, EXACT, means + 3 * i, quats + 4 * i, dists + ND * i, opacity[i], V, G)) return;
+    if (!build_geometry(KIND, EXACT, aa != 0, means + 3 * i, quats + 4 * i, dists + ND * i, opacity[i], V, G))
+        return;
     const double ox = (double)rc.x + 0.5 - G.c[0];
     const double oy = (double)rc.y + 0.5 - G.c[1];
     if (EXACT) {
@@ -585,7 +586,8 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
     for (int64_t j = threadIdx.x; j < rows * w3; j += 128) gs[j] = stage[j];
 }
 
-hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, bool exact, const ViewLayout& L,
+hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, bool exact, bool aa,
+                                 const ViewLayout& L,
                                  const char* vws, const PairLayout& P, const char* pws, float* g_means,
                                  float* g_quats, float* g_dists, float* g_opacity, float* g_sh, hipStream_t stream) {
     if (p.n == 0) return hipSuccess;
@@ -621,7 +623,7 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
     }
 #define LP_SLOT(K_, E_)                                                                                         \
     hipLaunchKernelGGL((k_slot_bwd<K_, E_>), g1, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, p.n, \
-                       views, payload, tiles, offsets, grads, nq, st, cap, vis)
+                       views, payload, tiles, offsets, grads, nq, st, cap, vis, aa ? 1 : 0)
     if (p.type == LINPRIM_OCTAHEDRON) {
         if (exact) LP_SLOT(LINPRIM_OCTAHEDRON, true); else LP_SLOT(LINPRIM_OCTAHEDRON, false);
         LP_PRIM_DEG(LINPRIM_OCTAHEDRON)

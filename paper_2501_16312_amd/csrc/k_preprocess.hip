@@ -54,7 +54,7 @@ template <int KIND, int DEG, bool EXACT>
 __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ means, const float* __restrict__ quats,
                                                     const float* __restrict__ dists, const float* __restrict__ opacity,
                                                     const float* __restrict__ sh, int64_t n,
-                                                    const ViewInfo* __restrict__ views, int tile_shift,
+                                                    const ViewInfo* __restrict__ views, int tile_shift, int aa,
                                                     float* __restrict__ payload, uint32_t* __restrict__ depth_keys,
                                                     uint32_t* __restrict__ tiles) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
     float* rec = payload + slot * kRecordWords;
     Geom G;
     const float alpha = opacity[i];
-    if (!build_geometry(KIND, EXACT, means + 3 * i, quats + 4 * i, dists + nd * i, alpha, V, G)) {
+    if (!build_geometry(KIND, EXACT, aa != 0, means + 3 * i, quats + 4 * i, dists + nd * i, alpha, V, G)) {
         reinterpret_cast<int4*>(rec)[0] = make_int4(-1, -1, -1, -1);
         depth_keys[slot] = 0u;
         tiles[slot] = 0u;
@@ -206,8 +206,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
         dst[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
 }
 
-hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, const ViewLayout& L,
-                             char* ws, hipStream_t stream) {
+hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, bool aa,
+                             const ViewLayout& L, char* ws, hipStream_t stream) {
     if (p.n == 0) return hipSuccess;
     const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
     dim3 grid((unsigned)((p.n + 255) / 256), (unsigned)n_views);
@@ -215,14 +215,14 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
     float* payload = reinterpret_cast<float*>(ws + L.payload);
     uint32_t* keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
     uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
-#define LP_PRE(K_, D_)                                                                                         \
-    do {                                                                                                         \
-        if (exact)                                                                                               \
-            hipLaunchKernelGGL((k_preprocess<K_, D_, true>), grid, dim3(256), 0, stream, p.means, p.quats,        \
-                               p.dists, p.opacity, p.sh, p.n, views, shift, payload, keys, tiles);               \
-        else                                                                                                     \
-            hipLaunchKernelGGL((k_preprocess<K_, D_, false>), grid, dim3(256), 0, stream, p.means, p.quats,       \
-                               p.dists, p.opacity, p.sh, p.n, views, shift, payload, keys, tiles);               \
+#define LP_PRE(K_, D_)                                                                                     \
+    do {                                                                                                     \
+        if (exact)                                                                                           \
+            hipLaunchKernelGGL((k_preprocess<K_, D_, true>), grid, dim3(256), 0, stream, p.means, p.quats,    \
+                               p.dists, p.opacity, p.sh, p.n, views, shift, aa ? 1 : 0, payload, keys, tiles); \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_preprocess<K_, D_, false>), grid, dim3(256), 0, stream, p.means, p.quats,   \
+                               p.dists, p.opacity, p.sh, p.n, views, shift, aa ? 1 : 0, payload, keys, tiles); \
     } while (0)
 #define LP_PRE_DEG(K_)                      \
     switch (p.sh_degree) {                  \

@@ -111,8 +111,8 @@ int key_tile_bits(int64_t n_tiles_total);
 // ----------------------------------------------------------------------------
 hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int tile, ViewInfo* views,
                               hipStream_t stream);
-hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, const ViewLayout& L,
-                             char* ws, hipStream_t stream);
+hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, bool aa,
+                             const ViewLayout& L, char* ws, hipStream_t stream);
 hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stream);
 
 // A (view, primitive) slot whose gradient records number more than kBigRun
@@ -137,7 +137,8 @@ hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLay
                              int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                              const float* out_T, const int32_t* out_last, const float* grad_rgb,
                              hipStream_t stream);
-hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, bool exact, const ViewLayout& L,
+hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, bool exact, bool aa,
+                                 const ViewLayout& L,
                                  const char* vws, const PairLayout& P, const char* pws, float* g_means,
                                  float* g_quats, float* g_dists, float* g_opacity, float* g_sh,
                                  hipStream_t stream);
@@ -262,8 +263,49 @@ struct Geom {
 // Builds the primitive, transforms it and bounds it.  Returns false if the
 // primitive is culled.  The rectangle and key computations follow the
 // binning contract exactly (double precision, fixed order, no contraction).
-__device__ inline bool build_geometry(int type, bool exact, const float* mu_f, const float* q_f, const float* d_f,
-                                      float alpha, const ViewInfo& V, Geom& G) {
+// The 2D anti-aliasing filter (appendix "Anti-Aliasing"; filter size 0.1
+// pixel, App. G): the ray-space corners on the tiling box move outward,
+// parallel to the screen, by the filter size; an octahedron's axis vector
+// carries two mirrored corners and moves by half of it.  All corners that
+// attain an extreme move.  The shift is a constant, so gradients with
+// respect to the offsets pass through unchanged.
+constexpr double kAaSize = 0.1;
+
+__device__ inline void antialias_shift(int type, double a[4][3]) {
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+        if (type == LINPRIM_OCTAHEDRON) {
+            double ext = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (fabs(a[k][ax]) > ext) ext = fabs(a[k][ax]);
+            double sh[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) sh[k] = (fabs(a[k][ax]) == ext) ? copysign(0.5 * kAaSize, a[k][ax]) : 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) a[k][ax] += sh[k];
+        } else {
+            double lo = a[0][ax], hi = a[0][ax];
+#pragma unroll
+            for (int i = 1; i < 4; ++i) {
+                if (a[i][ax] < lo) lo = a[i][ax];
+                if (a[i][ax] > hi) hi = a[i][ax];
+            }
+            double sh[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                sh[i] = 0.0;
+                if (a[i][ax] == lo) sh[i] -= kAaSize;
+                if (a[i][ax] == hi) sh[i] += kAaSize;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i][ax] += sh[i];
+        }
+    }
+}
+
+__device__ inline bool build_geometry(int type, bool exact, bool aa, const float* mu_f, const float* q_f,
+                                      const float* d_f, float alpha, const ViewInfo& V, Geom& G) {
     const int na = (type == LINPRIM_OCTAHEDRON) ? 3 : 4;
     if (!quat_rotation_d((double)q_f[0], (double)q_f[1], (double)q_f[2], (double)q_f[3], G.R)) return false;
     double d[4];
@@ -304,13 +346,19 @@ __device__ inline bool build_geometry(int type, bool exact, const float* mu_f, c
     G.J[3] = 0.0; G.J[4] = J11; G.J[5] = J12;
     G.J[6] = G.tc[0] / l; G.J[7] = G.tc[1] / l; G.J[8] = G.tc[2] / l;
     G.c[0] = cxp; G.c[1] = cyp; G.c[2] = l;
-    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
-    for (int k = 0; k < na; ++k) {
-        const double ax = J00 * G.oc[k][0] + J02 * G.oc[k][2];
-        const double ay = J11 * G.oc[k][1] + J12 * G.oc[k][2];
-        G.a[k][0] = ax;
-        G.a[k][1] = ay;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= na) break;
+        G.a[k][0] = J00 * G.oc[k][0] + J02 * G.oc[k][2];
+        G.a[k][1] = J11 * G.oc[k][1] + J12 * G.oc[k][2];
         G.a[k][2] = G.J[6] * G.oc[k][0] + G.J[7] * G.oc[k][1] + G.J[8] * G.oc[k][2];
+    }
+    if (aa) antialias_shift(type, G.a);
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= na) break;
+        const double ax = G.a[k][0], ay = G.a[k][1];
         const double xp = cxp + ax, yp = cyp + ay;
         if (xp < xmin) xmin = xp;
         if (xp > xmax) xmax = xp;

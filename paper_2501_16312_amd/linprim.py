@@ -32,6 +32,7 @@ FLAG_COUNTERS = 1
 FLAG_VIEWS_RESIDENT = 2
 FLAG_RADIX_SORT = 4
 FLAG_EXACT_RAYS = 8
+FLAG_ANTIALIAS = 16
 
 
 class linprim_prims(ctypes.Structure):

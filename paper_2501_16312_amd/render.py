@@ -16,20 +16,21 @@ from . import linprim as L
 class Rasterizer:
     def __init__(self, kind: int, n: int, cams: Sequence, tile: int = 16, sort_digit_bits: int = 8,
                  device: str = "cuda", headroom: float = 1.0, views_resident: bool = False,
-                 radix_sort: bool = False, exact: bool = False):
+                 radix_sort: bool = False, exact: bool = False, antialias: bool = False):
         """views_resident: the camera poses live in the view workspace and
         are replaced with set_views() (same image sizes), so that a captured
         graph can be replayed on new poses.  radix_sort: order the pairs with
         the global LSD radix sort (sort_digit_bits per pass) instead of the
         per-tile sort.  exact: render without the ray-space approximation
-        (pixel rays meet the camera-space primitives)."""
+        (pixel rays meet the camera-space primitives).  antialias: the 2D
+        anti-aliasing filter of the ray-space model."""
         self.kind = int(kind)
         self.n = int(n)
         self.cams = list(cams)
         self.cams_c = L.cameras(self.cams)
         self.views_resident = bool(views_resident)
         flags = ((L.FLAG_VIEWS_RESIDENT if views_resident else 0) | (L.FLAG_RADIX_SORT if radix_sort else 0)
-                 | (L.FLAG_EXACT_RAYS if exact else 0))
+                 | (L.FLAG_EXACT_RAYS if exact else 0) | (L.FLAG_ANTIALIAS if antialias else 0))
         self.exact = bool(exact)
         self.tune = L.tuning(tile, sort_digit_bits, flags)
         self.device = torch.device(device)

@@ -11,10 +11,12 @@ IMG_TOL = 1e-5          # absolute, per colour channel and transmittance
 GRAD_TOL = 1e-3         # relative, with a floor of 1e-2 x rms of the tensor
 
 
-def gpu_forward(scene, cams, tile=16, bg=(0.0, 0.0, 0.0), digit=8, counters=False, radix=False, exact=False):
+def gpu_forward(scene, cams, tile=16, bg=(0.0, 0.0, 0.0), digit=8, counters=False, radix=False, exact=False,
+                antialias=False):
     torch.cuda.synchronize()
     prims = L.Prims.from_scene(scene)
-    rast = Rasterizer(scene.kind, scene.n, cams, tile=tile, sort_digit_bits=digit, radix_sort=radix, exact=exact)
+    rast = Rasterizer(scene.kind, scene.n, cams, tile=tile, sort_digit_bits=digit, radix_sort=radix, exact=exact,
+                      antialias=antialias)
     cnt = torch.zeros(3, dtype=torch.int64, device="cuda") if counters else None
     rgb, T, last = rast.forward(prims, bg, counters=cnt)
     torch.cuda.synchronize()

@@ -52,6 +52,11 @@ def test_workspace_sizes_and_validation(lib):
     assert p2 >= 100000 * (8 + 8 + 4 + 4 + 80)
     assert lib.linprim_pair_workspace_size(1 << 31, cams, t16) == 0
     assert lib.linprim_pair_workspace_size(10, cams, lib.tuning(16, 9)) == 0
+    # the anti-aliasing filter belongs to the ray-space model
+    assert lib.linprim_view_workspace_size(0, 10, cams, lib.tuning(16, 8, lib.FLAG_ANTIALIAS)) > 0
+    assert lib.linprim_view_workspace_size(0, 10, cams, lib.tuning(16, 8, lib.FLAG_EXACT_RAYS)) > 0
+    assert lib.linprim_view_workspace_size(
+        0, 10, cams, lib.tuning(16, 8, lib.FLAG_EXACT_RAYS | lib.FLAG_ANTIALIAS)) == 0
 
 
 def test_null_arguments_rejected_without_device(lib):
