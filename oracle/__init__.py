@@ -68,6 +68,7 @@ def _load():
     lib.orc_mtia_ray.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_set_exact.argtypes = [P, ctypes.c_int]
     lib.orc_set_antialias.argtypes = [P, ctypes.c_int]
+    lib.orc_render_depth.argtypes = [P] + [ctypes.c_void_p] * 3
     lib.orc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_backward.argtypes = [P] + [ctypes.c_void_p] * 8
     lib.orc_num_threads.restype = ctypes.c_int
@@ -226,6 +227,18 @@ class OracleScene:
         if rc != 0:
             raise RuntimeError("oracle render failed")
         return {"rgb": rgb, "T": T, "last": last, "ill": ill, "cond": cond, "counts": counts}
+
+    def render_depth(self, bg=None) -> dict:
+        """Depth map (centre camera z of the primitive at which cumulative
+        opacity first exceeds 0.5; 0 where it never does), packed like T."""
+        self._ensure_sorted()
+        npx = sum(c.width * c.height for c in self.cams)
+        depth = np.zeros(npx)
+        ill = np.zeros(npx, np.uint8)
+        b = self._bg(bg)
+        if _load().orc_render_depth(self.h, _ptr(b), _ptr(depth), _ptr(ill)) != 0:
+            raise RuntimeError("oracle depth render failed")
+        return {"depth": depth, "ill": ill.astype(bool)}
 
     def render_band(self, j0: int, j1: int, bg=None) -> dict:
         """Tiled render of the rows [j0, j1) of every view only (others zero)."""

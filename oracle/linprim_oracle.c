@@ -973,7 +973,15 @@ typedef struct {
     int64_t iterated, evaluated, intersected;
     int ill;           /* bit 0: value ill-conditioned; bit 1: gradient ill-conditioned */
     double cond;       /* largest float32 error estimate of a blended opacity */
+    double depth;      /* depth of the primitive where cumulative opacity first exceeds 0.5 (0: never) */
+    int depth_ill;     /* a step leaves T within 1e-6 of 0.5 (the crossing may move in float32) */
 } orc_pix;
+
+/* Appendix "Depth and Surface Reconstruction": a pixel's depth is that of
+ * the first primitive along its ray at which the cumulative opacity 1 - T
+ * exceeds 0.5.  The primitive's depth is read as its centre's camera z, the
+ * value the method sorts by (the float32 depth key). */
+#define ORC_DEPTH_T 0.5
 
 static int in_rect(const orc_prep *P, int i, int j)
 {
@@ -1057,8 +1065,8 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
     pixel_ray(&S->views[v], rx, ry, D);
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
     int64_t last = last_default, it = 0, ev = 0, hit = 0, ns = 0;
-    int ill = 0;
-    double cond = 0.0;
+    int ill = 0, depth_ill = 0;
+    double cond = 0.0, depth = 0.0;
     for (int64_t k = 0; k < len; ++k) {
         ++it;
         const orc_prep *P = Pv + list[k];
@@ -1084,7 +1092,14 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
         st.prim = list[k];
         st.delta = delta; st.e = e; st.o = o; st.T = T; st.clamped = clamped; st.ch = ch;
         for (int c = 0; c < 3; ++c) C[c] += T * o * P->rgb[c];
+        const double Tbefore = T;
         T = T * (1.0 - o);
+        if (Tbefore >= ORC_DEPTH_T && T < ORC_DEPTH_T) {
+            float zf;
+            memcpy(&zf, &P->key, 4);
+            depth = (double)zf;
+        }
+        if (fabs(T - ORC_DEPTH_T) <= ORC_ILL_T) depth_ill = 1;
         if (!use_clip) ill |= step_ill(S->type, P, &st, T, &cond, &S->views[v], S->exact ? D : NULL);
         if (steps) steps[ns] = st;
         ++ns;
@@ -1094,6 +1109,8 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
     for (int c = 0; c < 3; ++c) out->rgb[c] = C[c] + T * bg[c];
     out->T = T;
     out->last = last;
+    out->depth = depth;
+    out->depth_ill = depth_ill;
     out->iterated = it; out->evaluated = ev; out->intersected = hit;
     out->ill = ill;
     out->cond = cond;
@@ -1206,6 +1223,35 @@ static int render_rows(orc_scene *S, int mode, const double *bg, double *rgb, do
         }
         counts[4 * v + 0] = it; counts[4 * v + 1] = ev; counts[4 * v + 2] = hit; counts[4 * v + 3] = fr;
         rgb_base += 3 * HW;
+    }
+    return 0;
+}
+
+/* Depth map of every view (tiled walk), packed like T; depth_ill[p] = 1
+ * where the crossing of 0.5 may move under float32 evaluation (a step ends
+ * within 1e-6 of it) or the pixel's value is ill-conditioned. */
+int orc_render_depth(void *h, const double *bg, double *depth, uint8_t *depth_ill)
+{
+    orc_scene *S = (orc_scene *)h;
+    if (!S || !S->prep || !S->rlo) return -1;
+    for (int v = 0; v < S->n_views; ++v) {
+        const orc_view *V = &S->views[v];
+#pragma omp parallel
+        {
+            int64_t *list = NULL, *pos = NULL, cap = 0, start = 0;
+#pragma omp for schedule(dynamic, 1)
+            for (int j = 0; j < V->H; ++j)
+                for (int i = 0; i < V->W; ++i) {
+                    const int64_t len = pixel_list(S, v, i, j, 0, &list, &pos, &cap, &start);
+                    orc_pix px;
+                    composite(S, v, list, pos, len, i, j, bg + 3 * v, 0, &px, NULL, NULL, start);
+                    const int64_t p = V->pix_base + (int64_t)j * V->W + i;
+                    depth[p] = px.depth;
+                    depth_ill[p] = (uint8_t)(px.depth_ill || (px.ill & 1));
+                }
+            free(list);
+            free(pos);
+        }
     }
     return 0;
 }
