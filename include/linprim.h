@@ -284,6 +284,19 @@ int linprim_render_fwd_counted(const linprim_prims *prims, const linprim_camera 
                                int64_t max_pairs, float *out_rgb, float *out_T, int32_t *out_last,
                                uint64_t *counters, void *stream);
 
+/* linprim_render_fwd plus the depth map of the paper's appendix "Depth and
+ * Surface Reconstruction": out_depth [sum_v H_v W_v] (DEVICE float,
+ * layout of out_T) receives, per pixel, the depth of the first primitive
+ * at whose blending the cumulative opacity 1 - T exceeds 0.5 (T drops
+ * below 0.5), read as that primitive's centre camera depth (the float32
+ * depth key the lists are sorted by), and 0 where 1 - T never exceeds
+ * 0.5.  The accumulated-opacity (alpha) channel is 1 - out_T. */
+int linprim_render_fwd_depth(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                             const linprim_tuning *tuning, const float *bg, const void *view_ws,
+                             size_t view_ws_bytes, const void *pair_ws, size_t pair_ws_bytes,
+                             int64_t max_pairs, float *out_rgb, float *out_T, int32_t *out_last,
+                             float *out_depth, void *stream);
+
 /* Static description of an error code. */
 const char *linprim_strerror(int code);
 

@@ -62,8 +62,8 @@ PairLayout pair_layout(int64_t max_pairs, int digit_bits, int tile) {
 
 hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
                                 int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
-                                float* out_rgb, float* out_T, int32_t* out_last, unsigned long long* counters,
-                                hipStream_t stream);
+                                float* out_rgb, float* out_T, int32_t* out_last, float* out_depth,
+                                unsigned long long* counters, hipStream_t stream);
 
 }  // namespace linprim
 
@@ -228,7 +228,7 @@ int linprim_bin_sort(const linprim_prims* prims, const linprim_camera* cams, int
 static int render_fwd_common(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
                              const linprim_tuning* tuning, const float* bg, const void* view_ws, size_t view_ws_bytes,
                              const void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float* out_rgb,
-                             float* out_T, int32_t* out_last, uint64_t* counters, void* stream) {
+                             float* out_T, int32_t* out_last, float* out_depth, uint64_t* counters, void* stream) {
     if (!bg || !view_ws || !pair_ws || !out_rgb || !out_T || !out_last) return LINPRIM_ERR_INVALID_ARG;
     ViewLayout L;
     PairLayout P;
@@ -236,7 +236,8 @@ static int render_fwd_common(const linprim_prims* prims, const linprim_camera* c
     const int in_b = result_buffer(L, tuning);
     hipError_t e = launch_render_fwd_ex(L, (const char*)view_ws, P, (const char*)pair_ws, in_b, prims->type,
                                         exact_rays(tuning), tile_of(tuning), n_views, bg, out_rgb, out_T, out_last,
-                                        reinterpret_cast<unsigned long long*>(counters), (hipStream_t)stream);
+                                        out_depth, reinterpret_cast<unsigned long long*>(counters),
+                                        (hipStream_t)stream);
     return hip_status(e);
 }
 
@@ -245,7 +246,16 @@ int linprim_render_fwd(const linprim_prims* prims, const linprim_camera* cams, i
                        const void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float* out_rgb, float* out_T,
                        int32_t* out_last, void* stream) {
     return render_fwd_common(prims, cams, n_views, tuning, bg, view_ws, view_ws_bytes, pair_ws, pair_ws_bytes,
-                             max_pairs, out_rgb, out_T, out_last, nullptr, stream);
+                             max_pairs, out_rgb, out_T, out_last, nullptr, nullptr, stream);
+}
+
+int linprim_render_fwd_depth(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                             const linprim_tuning* tuning, const float* bg, const void* view_ws, size_t view_ws_bytes,
+                             const void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float* out_rgb,
+                             float* out_T, int32_t* out_last, float* out_depth, void* stream) {
+    if (!out_depth) return LINPRIM_ERR_INVALID_ARG;
+    return render_fwd_common(prims, cams, n_views, tuning, bg, view_ws, view_ws_bytes, pair_ws, pair_ws_bytes,
+                             max_pairs, out_rgb, out_T, out_last, out_depth, nullptr, stream);
 }
 
 int linprim_render_fwd_counted(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
@@ -254,7 +264,7 @@ int linprim_render_fwd_counted(const linprim_prims* prims, const linprim_camera*
                                float* out_rgb, float* out_T, int32_t* out_last, uint64_t* counters, void* stream) {
     if (!counters) return LINPRIM_ERR_INVALID_ARG;
     return render_fwd_common(prims, cams, n_views, tuning, bg, view_ws, view_ws_bytes, pair_ws, pair_ws_bytes,
-                             max_pairs, out_rgb, out_T, out_last, counters, stream);
+                             max_pairs, out_rgb, out_T, out_last, nullptr, counters, stream);
 }
 
 int linprim_render_bwd(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,

@@ -306,14 +306,20 @@ __device__ inline Batch load_batch(const float* __restrict__ base, const uint32_
 // ---------------------------------------------------------------------------
 // Forward.
 // ---------------------------------------------------------------------------
-template <int TILE, int KIND, bool COUNT, bool EXACT>
+// Cumulative opacity beyond which a pixel's depth is taken (depth maps of
+// the appendix "Depth and Surface Reconstruction").
+constexpr float kDepthT = 0.5f;
+
+template <int TILE, int KIND, bool COUNT, bool EXACT, bool DEPTH>
 __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ views, int n_views, int64_t n,
                                                    const float* __restrict__ payload, const uint32_t* __restrict__ vals,
                                                    const uint2* __restrict__ ranges, const Status* __restrict__ status,
                                                    uint64_t capacity, float bg0, float bg1, float bg2,
                                                    float* __restrict__ out_rgb, float* __restrict__ out_T,
                                                    int32_t* __restrict__ out_last,
-                                                   unsigned long long* __restrict__ counters) {
+                                                   unsigned long long* __restrict__ counters,
+                                                   const uint32_t* __restrict__ depth_keys,
+                                                   float* __restrict__ out_depth) {
     if (status->n_pairs > capacity) return;
     constexpr int QX = TILE / 8, NQ = QX * QX;
     const Place P = place_wave<TILE>(views, n_views);
@@ -328,6 +334,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
     int last = (int)rg.x;
     bool done = !valid;
     uint32_t ev = 0, hit = 0, term = rg.y;
+    uint32_t half = 0xffffffffu;   // list position at which 1 - T first exceeds 0.5
     const float* base = payload + (size_t)P.v * (size_t)n * kRecordWords;
     bool alive = true;
     uint32_t sink = 0;   // keeps the L2-warming loads alive; never stored
@@ -366,6 +373,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
             C0 = __builtin_fmaf(w, R.r, C0);
             C1 = __builtin_fmaf(w, R.g, C1);
             C2 = __builtin_fmaf(w, R.b, C2);
+            if (DEPTH) half = (T >= kDepthT && T * onemo < kDepthT) ? e : half;
             T = T * onemo;
             last = hitp ? (int)e + 1 : last;
             const bool stop = hitp && T <= kTStop;
@@ -411,6 +419,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
         o[2 * hw + p] = C2 + T * bg2;
         out_T[pix] = T;
         out_last[pix] = last;
+        if (DEPTH) {
+            float dz = 0.0f;
+            if (half != 0xffffffffu) dz = __uint_as_float(depth_keys[(size_t)P.v * (size_t)n + vals[half]]);
+            out_depth[pix] = dz;
+        }
         if (COUNT) {
             c_it = term - rg.x;
             c_ev = ev;
@@ -680,30 +693,34 @@ template <int TILE, int KIND, bool EXACT>
 static void fwd_dispatch(bool count, const ViewLayout& Lv, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
                          const float* payload, const uint32_t* vals, const uint2* ranges, const Status* st,
                          uint64_t cap, const float bg[3], float* rgb, float* T, int32_t* last,
-                         unsigned long long* counters) {
+                         unsigned long long* counters, const uint32_t* keys, float* depth) {
     const dim3 grid = wave_grid<TILE>(Lv);
-    if (count)
-        hipLaunchKernelGGL((k_render_fwd<TILE, KIND, true, EXACT>), grid, dim3(64), 0, s, views, nv, n, payload, vals,
-                           ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters);
-    else
-        hipLaunchKernelGGL((k_render_fwd<TILE, KIND, false, EXACT>), grid, dim3(64), 0, s, views, nv, n, payload, vals,
-                           ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters);
+#define LP_K(C_, D_)                                                                                              \
+    hipLaunchKernelGGL((k_render_fwd<TILE, KIND, C_, EXACT, D_>), grid, dim3(64), 0, s, views, nv, n, payload, vals, \
+                       ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters, keys, depth)
+    if (depth) {
+        if (count) LP_K(true, true); else LP_K(false, true);
+    } else {
+        if (count) LP_K(true, false); else LP_K(false, false);
+    }
+#undef LP_K
 }
 
 hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
                                 int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
-                                float* out_rgb, float* out_T, int32_t* out_last, unsigned long long* counters,
-                                hipStream_t stream) {
+                                float* out_rgb, float* out_T, int32_t* out_last, float* out_depth,
+                                unsigned long long* counters, hipStream_t stream) {
     if (L.n_tiles_total == 0) return hipSuccess;
     const ViewInfo* views = reinterpret_cast<const ViewInfo*>(vws + L.views);
     const float* payload = reinterpret_cast<const float*>(vws + L.payload);
     const uint32_t* vals = reinterpret_cast<const uint32_t*>(pws + (result_in_b ? P.vals_b : P.vals_a));
     const uint2* ranges = reinterpret_cast<const uint2*>(vws + L.ranges);
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
+    const uint32_t* keys = reinterpret_cast<const uint32_t*>(vws + L.depth_keys);
     const uint64_t cap = (uint64_t)P.capacity;
     const bool count = counters != nullptr;
 #define LP_FWD(T_, K_, E_) fwd_dispatch<T_, K_, E_>(count, L, stream, views, n_views, L.n, payload, vals, ranges, st, \
-                                                    cap, bg, out_rgb, out_T, out_last, counters)
+                                                    cap, bg, out_rgb, out_T, out_last, counters, keys, out_depth)
 #define LP_FWD_T(K_, E_)                                                       \
     do {                                                                       \
         if (tile == 8) LP_FWD(8, K_, E_);                                      \
@@ -724,7 +741,7 @@ hipError_t launch_render_fwd(const ViewLayout& L, const char* vws, const PairLay
                              int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                              float* out_rgb, float* out_T, int32_t* out_last, hipStream_t stream) {
     return launch_render_fwd_ex(L, vws, P, pws, result_in_b, type, exact, tile, n_views, bg, out_rgb, out_T, out_last,
-                                nullptr, stream);
+                                nullptr, nullptr, stream);
 }
 
 template <int TILE, int KIND, bool EXACT>

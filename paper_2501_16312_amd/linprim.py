@@ -61,6 +61,7 @@ class linprim_adam_group(ctypes.Structure):
 
 EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linprim_preprocess",
            "linprim_pair_count", "linprim_bin_sort", "linprim_render_fwd", "linprim_render_fwd_counted",
+           "linprim_render_fwd_depth",
            "linprim_render_bwd", "linprim_raster_bwd", "linprim_preprocess_bwd", "linprim_read_status",
            "linprim_strerror", "linprim_debug_pointers", "linprim_upload_views", "linprim_l1_grad",
            "linprim_adam_step", "linprim_adam_step_dev")
@@ -100,6 +101,8 @@ def load(path: str = LIB_PATH):
                                        P, P, P, P]
     lib.linprim_render_fwd_counted.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ,
                                                I64, P, P, P, P, P]
+    lib.linprim_render_fwd_depth.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ,
+                                             I64, P, P, P, P, P]
     lib.linprim_render_bwd.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ, I64,
                                        P, P, P, P, P, P, P, P, P]
     lib.linprim_raster_bwd.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ, I64,
@@ -110,7 +113,8 @@ def load(path: str = LIB_PATH):
     lib.linprim_strerror.argtypes = [ctypes.c_int]
     lib.linprim_debug_pointers.argtypes = [pr, cm, I32, tu, P, P, I64] + [ctypes.POINTER(P)] * 7
     for f in (lib.linprim_preprocess, lib.linprim_pair_count, lib.linprim_bin_sort, lib.linprim_render_fwd,
-              lib.linprim_render_fwd_counted, lib.linprim_render_bwd, lib.linprim_raster_bwd,
+              lib.linprim_render_fwd_counted, lib.linprim_render_fwd_depth, lib.linprim_render_bwd,
+              lib.linprim_raster_bwd,
               lib.linprim_preprocess_bwd, lib.linprim_read_status, lib.linprim_upload_views,
               lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev,
               lib.linprim_debug_pointers):
@@ -275,10 +279,18 @@ def _bg(bg):
 
 
 def linprim_render_fwd(prims: Prims, cams, tune, bg, view_ws, pair_ws, max_pairs, out_rgb, out_T, out_last,
-                       stream=None, counters: Optional[torch.Tensor] = None):
+                       stream=None, counters: Optional[torch.Tensor] = None,
+                       out_depth: Optional[torch.Tensor] = None):
     p = prims.c()
     lib = load()
-    if counters is None:
+    if out_depth is not None:
+        if counters is not None:
+            raise LinPrimError("counters and the depth map are separate entry points")
+        rc = lib.linprim_render_fwd_depth(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _bg(bg),
+                                          _ptr(view_ws), view_ws.numel(), _ptr(pair_ws), pair_ws.numel(), max_pairs,
+                                          _ptr(out_rgb), _ptr(out_T), _ptr(out_last), _ptr(out_depth),
+                                          _stream(stream))
+    elif counters is None:
         rc = lib.linprim_render_fwd(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _bg(bg), _ptr(view_ws),
                                     view_ws.numel(), _ptr(pair_ws), pair_ws.numel(), max_pairs, _ptr(out_rgb),
                                     _ptr(out_T), _ptr(out_last), _stream(stream))

@@ -85,10 +85,14 @@ class Rasterizer:
         last = torch.empty(self.n_pixels, dtype=torch.int32, device=self.device)
         return rgb, T, last
 
-    def render(self, prims: L.Prims, bg=None, out=None, counters: Optional[torch.Tensor] = None):
+    def render(self, prims: L.Prims, bg=None, out=None, counters: Optional[torch.Tensor] = None,
+               depth: Optional[torch.Tensor] = None):
+        """depth: optional float32 [n_pixels] tensor that receives the depth
+        map (centre depth of the primitive at which cumulative opacity first
+        exceeds 0.5, 0 elsewhere)."""
         rgb, T, last = out if out is not None else self.alloc_outputs()
         L.linprim_render_fwd(prims, self.cams_c, self.tune, bg, self.view_ws, self.pair_ws, self.max_pairs, rgb,
-                             T, last, counters=counters)
+                             T, last, counters=counters, out_depth=depth)
         return rgb, T, last
 
     def forward(self, prims: L.Prims, bg=None, counters: Optional[torch.Tensor] = None):
