@@ -69,6 +69,7 @@ def _load():
     lib.orc_set_exact.argtypes = [P, ctypes.c_int]
     lib.orc_set_antialias.argtypes = [P, ctypes.c_int]
     lib.orc_render_depth.argtypes = [P] + [ctypes.c_void_p] * 3
+    lib.orc_get_stats.argtypes = [P] + [ctypes.c_void_p] * 3
     lib.orc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_backward.argtypes = [P] + [ctypes.c_void_p] * 8
     lib.orc_num_threads.restype = ctypes.c_int
@@ -239,6 +240,19 @@ class OracleScene:
         if _load().orc_render_depth(self.h, _ptr(b), _ptr(depth), _ptr(ill)) != 0:
             raise RuntimeError("oracle depth render failed")
         return {"depth": depth, "ill": ill.astype(bool)}
+
+    def stats(self) -> dict:
+        """Screen-space statistics of the last backward(): per view and
+        primitive, sgrad [V,n,2] = dL/d(projected centre, pixels) with the
+        ray-space offsets held fixed, radius [V,n] (half the larger side of
+        the projected box, pixels) and visible [V,n] (touches a tile)."""
+        V, n = len(self.cams), self.n
+        sg = np.zeros((V, n, 2))
+        rad = np.zeros((V, n))
+        vis = np.zeros((V, n), np.uint8)
+        if _load().orc_get_stats(self.h, _ptr(sg), _ptr(rad), _ptr(vis)) != 0:
+            raise RuntimeError("call backward() first")
+        return {"sgrad": sg, "radius": rad, "visible": vis.astype(bool)}
 
     def render_band(self, j0: int, j1: int, bg=None) -> dict:
         """Tiled render of the rows [j0, j1) of every view only (others zero)."""

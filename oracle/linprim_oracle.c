@@ -90,6 +90,7 @@ typedef struct {
     double sigma;
     double rgb[3];
     double raw[3];   /* colour before the clamp at zero */
+    double radius;   /* half the larger side of the projected bounding box (pixels) */
 } orc_prep;
 
 typedef struct {
@@ -106,6 +107,7 @@ typedef struct {
     uint32_t *vals;
     int64_t n_tiles_total;
     int64_t *rlo, *rhi;
+    double *sgrad;           /* [n_views][n][2] dL/d(projected centre) of the last backward */
 } orc_scene;
 
 /* ------------------------------------------------------------------------ */
@@ -367,6 +369,7 @@ static void preprocess_one(const orc_scene *S, const orc_view *V, int64_t n, orc
         }
     }
     if (!isfinite(xmin) || !isfinite(xmax) || !isfinite(ymin) || !isfinite(ymax)) return;
+    P->radius = 0.5 * fmax(xmax - xmin, ymax - ymin);
 
     /* projected bounding box -> pixel rectangle (centres inside the box) */
     double fi0 = ceil(xmin - 0.5), fi1 = floor(xmax - 0.5);
@@ -780,6 +783,7 @@ static void free_views(orc_scene *S)
     free(S->keys); S->keys = NULL;
     free(S->vals); S->vals = NULL;
     free(S->rlo); S->rlo = NULL;
+    free(S->sgrad); S->sgrad = NULL;
     free(S->rhi); S->rhi = NULL;
     S->n_pairs = 0;
 }
@@ -1558,6 +1562,8 @@ int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, 
 #ifdef _OPENMP
     nthreads = omp_get_max_threads();
 #endif
+    free(S->sgrad);
+    S->sgrad = (double *)calloc((size_t)S->n_views * (size_t)(n > 0 ? n : 1) * 2, sizeof(double));
     orc_pgrad *acc = (orc_pgrad *)malloc(sizeof(orc_pgrad) * (size_t)(n > 0 ? n : 1));
     orc_pgrad *tacc = (orc_pgrad *)calloc((size_t)nthreads * (size_t)(n > 0 ? n : 1), sizeof(orc_pgrad));
     int64_t rgb_base = 0;
@@ -1616,7 +1622,16 @@ int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, 
         const orc_prep *Pv = S->prep + (int64_t)v * n;
 #pragma omp parallel for schedule(static)
         for (int64_t m = 0; m < n; ++m) {
+            double *sg = S->sgrad + 2 * ((int64_t)v * n + m);
+            sg[0] = sg[1] = 0.0;
             if (!Pv[m].valid) continue;
+            /* Sec. 3.4 "Adaptive Population Control": the view-space positional
+             * gradient, dL/d(ray-space centre x, y) with the offsets held
+             * fixed, i.e. the sum of the corner gradients (ray space only) */
+            if (!S->exact) {
+                const int nc = (S->type == ORC_OCTA) ? 6 : 4;
+                for (int k = 0; k < nc; ++k) { sg[0] += acc[m].gV[k][0]; sg[1] += acc[m].gV[k][1]; }
+            }
             if (acc[m].ill) prim_ill[m] = 1;
             for (int c = 0; c < 3; ++c)
                 if (fabs(Pv[m].raw[c]) <= ORC_ILL_RGB && acc[m].grgb[c] != 0.0) prim_ill[m] = 1;
@@ -1627,6 +1642,23 @@ int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, 
     }
     free(acc);
     free(tacc);
+    return 0;
+}
+
+/* Per (view, primitive) screen-space statistics of the last orc_backward:
+ * sgrad [n_views][n][2] = dL/d(projected centre, pixels), radius
+ * [n_views][n] = half the larger side of the projected box, visible
+ * [n_views][n] = 1 where the primitive touches a tile. */
+int orc_get_stats(void *h, double *sgrad, double *radius, uint8_t *visible)
+{
+    orc_scene *S = (orc_scene *)h;
+    if (!S || !S->prep || !S->sgrad) return -1;
+    const int64_t vn = (int64_t)S->n_views * S->n;
+    memcpy(sgrad, S->sgrad, sizeof(double) * 2 * (size_t)vn);
+    for (int64_t k = 0; k < vn; ++k) {
+        radius[k] = S->prep[k].valid ? S->prep[k].radius : 0.0;
+        visible[k] = (uint8_t)S->prep[k].valid;
+    }
     return 0;
 }
 
