@@ -196,7 +196,7 @@ int linprim_render_fwd(const linprim_prims *prims, const linprim_camera *cams, i
  * are OVERWRITTEN; grad_sh has the layout of prims->sh.  Deterministic: no
  * floating-point atomics. */
 int linprim_render_bwd(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
-                       const linprim_tuning *tuning, const float *bg, const void *view_ws,
+                       const linprim_tuning *tuning, const float *bg, void *view_ws,
                        size_t view_ws_bytes, void *pair_ws, size_t pair_ws_bytes, int64_t max_pairs,
                        const float *out_T, const int32_t *out_last, const float *grad_rgb,
                        float *grad_means, float *grad_quats, float *grad_dists, float *grad_opacity,
@@ -207,15 +207,17 @@ int linprim_render_bwd(const linprim_prims *prims, const linprim_camera *cams, i
  * linprim_raster_bwd writes one gradient record per (tile, primitive) pair
  * into pair_ws: dL/d(plane coefficients of the payload), dL/d rgb and dL/d sigma
  * summed over the tile's pixels.  linprim_preprocess_bwd sums each
- * primitive's records in a fixed order and carries them to the features;
- * outputs as in linprim_render_bwd. */
+ * primitive's records in a fixed order (in place, in pair_ws) and carries
+ * them to the features; outputs as in linprim_render_bwd.  It also leaves,
+ * in view_ws, each visible (view, primitive)'s screen statistics that
+ * linprim_accumulate_stats reads. */
 int linprim_raster_bwd(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
                        const linprim_tuning *tuning, const float *bg, const void *view_ws,
                        size_t view_ws_bytes, void *pair_ws, size_t pair_ws_bytes, int64_t max_pairs,
                        const float *out_T, const int32_t *out_last, const float *grad_rgb, void *stream);
 int linprim_preprocess_bwd(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
-                           const linprim_tuning *tuning, const void *view_ws, size_t view_ws_bytes,
-                           const void *pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float *grad_means,
+                           const linprim_tuning *tuning, void *view_ws, size_t view_ws_bytes,
+                           void *pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float *grad_means,
                            float *grad_quats, float *grad_dists, float *grad_opacity, float *grad_sh,
                            void *stream);
 
@@ -296,6 +298,83 @@ int linprim_render_fwd_depth(const linprim_prims *prims, const linprim_camera *c
                              size_t view_ws_bytes, const void *pair_ws, size_t pair_ws_bytes,
                              int64_t max_pairs, float *out_rgb, float *out_T, int32_t *out_last,
                              float *out_depth, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Adaptive population control (Sec. 3.4 "Adaptive Population Control";
+ * thresholds in App. G).
+ * ------------------------------------------------------------------------ */
+
+/* Adds, for every primitive, the statistics of the last backward pass on
+ * these workspaces (linprim_render_bwd or linprim_preprocess_bwd, ray-space
+ * model): over the views in which it touches a tile, the norm of its
+ * view-space positional gradient (dL/d ray-space centre x, y with the
+ * primitive's ray-space offsets held fixed, per unit of normalised device
+ * coordinates: x scaled by W/2, y by H/2) into grad_accum, the number of
+ * such views into count, and the largest screen radius (half the larger
+ * side of the projected bounding box, pixels) into max_radius.  All three
+ * DEVICE arrays [n] are read-modify-written (zero them to start).  With
+ * LINPRIM_FLAG_EXACT_RAYS the gradient norms are 0 (the quantity belongs to
+ * the ray-space model); counts and radii are still kept. */
+int linprim_accumulate_stats(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                             const linprim_tuning *tuning, const void *view_ws, size_t view_ws_bytes,
+                             float *grad_accum, int32_t *count, float *max_radius, void *stream);
+
+/* Thresholds of the densify / prune pass (App. G's values in brackets).
+ * Every decision is taken in float32. */
+typedef struct linprim_densify_params {
+    float grad_threshold;      /* mean positional gradient above which a primitive densifies [1.5e-4] */
+    float min_opacity;         /* primitives with a smaller opacity are removed [0.025] */
+    float max_size_frac;       /* primitives larger than this fraction of the extent are removed [0.4] */
+    float max_screen_radius;   /* originals whose largest screen radius exceeds this are removed [20 px] */
+    float clone_size_frac;     /* candidates smaller than this fraction of the extent are cloned [0.01] */
+    float split_shrink;        /* split children's distances are divided by this [1.2] */
+    float extent;              /* scene extent, world units */
+    int32_t reserved;
+} linprim_densify_params;
+
+/* The primitives and, optionally, their Adam moments: DEVICE arrays with
+ * the layouts of linprim_prims (means [n,3], quats [n,4], dists [n,3|4],
+ * opacity [n], sh [n,(deg+1)^2,3]); exp_avg / exp_avg_sq in the same order
+ * and shapes, all NULL for none. */
+typedef struct linprim_state {
+    float *means, *quats, *dists, *opacity, *sh;
+    float *exp_avg[5];
+    float *exp_avg_sq[5];
+} linprim_state;
+
+/* Bytes of the densify workspace for n primitives. */
+size_t linprim_densify_workspace_size(int64_t n);
+
+/* Decides, per primitive, from its size (octahedron: longest axis 2 max d;
+ * tetrahedron: sqrt(2) times the distance to the furthest corner), its mean
+ * positional gradient grad_accum / count, its opacity and max_radius:
+ *   candidate: mean gradient > grad_threshold;
+ *   a candidate with size < clone_size_frac * extent is cloned (same
+ *   features, zero moments), a larger one is replaced by two children
+ *   (distances / split_shrink, zero moments, positions drawn as below);
+ *   removed: opacity < min_opacity, size > max_size_frac * extent (a split
+ *   child with its reduced size), or, for originals, max_radius >
+ *   max_screen_radius.
+ * Writes the plan into ws and returns, in *n_out (HOST), the number of
+ * primitives after the pass.  Waits for `stream`. */
+int linprim_densify_plan(int32_t type, int64_t n, const float *dists, const float *opacity,
+                         const float *grad_accum, const int32_t *count, const float *max_radius,
+                         const linprim_densify_params *params, void *ws, size_t ws_bytes, int64_t *n_out,
+                         void *stream);
+
+/* Writes the n_out primitives of the plan into dst (DEVICE arrays sized
+ * for n_out rows, not overlapping src): for each input primitive in order,
+ * the original (with its moments) or its two split children, then its
+ * clone.  Split child c of primitive i is placed at mu + R (d * z) for an
+ * octahedron (standard deviations equal to its distances along its own
+ * axes, then rotated) or at mu + (max d / 2) z for a tetrahedron, with z =
+ * normals[i][c][0..2] (DEVICE float [n][2][3], standard normal draws the
+ * caller provides).  dst moments are written when dst.exp_avg[0] is not
+ * NULL (zero for new primitives, copied otherwise). */
+int linprim_densify_apply(int32_t type, int32_t sh_degree, int64_t n, const linprim_state *src,
+                          const float *normals, const float *grad_accum, const int32_t *count,
+                          const float *max_radius, const linprim_densify_params *params, const void *ws,
+                          size_t ws_bytes, const linprim_state *dst, int64_t n_out, void *stream);
 
 /* Static description of an error code. */
 const char *linprim_strerror(int code);

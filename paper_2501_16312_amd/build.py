@@ -26,6 +26,7 @@ SOURCES = {
     "k_render.hip": [],
     "k_prep_bwd.hip": ["-ffp-contract=off"],
     "k_optim.hip": [],
+    "k_population.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

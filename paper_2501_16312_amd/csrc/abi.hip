@@ -39,6 +39,7 @@ ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, i
     L.big = off; off = align256(off + (size_t)vn * 4);
     L.long_list = off; off = align256(off + (size_t)L.n_tiles_total * 4);
     L.vis = off; off = align256(off + (size_t)vn * 4);
+    L.stats = off; off = align256(off + (size_t)vn * 8);
     L.total = off;
     return L;
 }
@@ -268,7 +269,7 @@ int linprim_render_fwd_counted(const linprim_prims* prims, const linprim_camera*
 }
 
 int linprim_render_bwd(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
-                       const linprim_tuning* tuning, const float* bg, const void* view_ws, size_t view_ws_bytes,
+                       const linprim_tuning* tuning, const float* bg, void* view_ws, size_t view_ws_bytes,
                        void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, const float* out_T,
                        const int32_t* out_last, const float* grad_rgb, float* grad_means, float* grad_quats,
                        float* grad_dists, float* grad_opacity, float* grad_sh, void* stream) {
@@ -304,8 +305,8 @@ int linprim_raster_bwd(const linprim_prims* prims, const linprim_camera* cams, i
 }
 
 int linprim_preprocess_bwd(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
-                           const linprim_tuning* tuning, const void* view_ws, size_t view_ws_bytes,
-                           const void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float* grad_means,
+                           const linprim_tuning* tuning, void* view_ws, size_t view_ws_bytes,
+                           void* pair_ws, size_t pair_ws_bytes, int64_t max_pairs, float* grad_means,
                            float* grad_quats, float* grad_dists, float* grad_opacity, float* grad_sh, void* stream) {
     if (!view_ws || !pair_ws) return LINPRIM_ERR_INVALID_ARG;
     if (prims && prims->n > 0 && (!grad_means || !grad_quats || !grad_dists || !grad_opacity || !grad_sh))
@@ -317,6 +318,97 @@ int linprim_preprocess_bwd(const linprim_prims* prims, const linprim_camera* cam
                                             (const char*)view_ws, P,
                                             (const char*)pair_ws, grad_means, grad_quats, grad_dists, grad_opacity,
                                             grad_sh, (hipStream_t)stream));
+}
+
+int linprim_accumulate_stats(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                             const linprim_tuning* tuning, const void* view_ws, size_t view_ws_bytes,
+                             float* grad_accum, int32_t* count, float* max_radius, void* stream) {
+    if (!valid_prims(prims) || !valid_cams(cams, n_views) || !valid_tuning(tuning) || !view_ws ||
+        !valid_slots(prims->n, n_views))
+        return LINPRIM_ERR_INVALID_ARG;
+    if (prims->n > 0 && (!grad_accum || !count || !max_radius)) return LINPRIM_ERR_INVALID_ARG;
+    const ViewLayout L = view_layout(prims->n, cams, n_views, tile_of(tuning));
+    if (view_ws_bytes < L.total) return LINPRIM_ERR_WORKSPACE;
+    return hip_status(launch_accumulate_stats(prims->n, n_views, L, (const char*)view_ws, grad_accum, count,
+                                              max_radius, (hipStream_t)stream));
+}
+
+size_t linprim_densify_workspace_size(int64_t n) {
+    if (n < 0 || n >= (int64_t(1) << 31)) return 0;
+    const int64_t nb = (n + kDensifyItems - 1) / kDensifyItems;
+    return align256((size_t)(nb + 1) * 8);
+}
+
+static bool finite_f(float x) { return x - x == 0.0f; }   // false for inf and NaN
+
+static bool valid_densify(const linprim_densify_params* dp) {
+    return dp && dp->split_shrink > 0.0f && dp->extent > 0.0f && finite_f(dp->extent) &&
+           finite_f(dp->split_shrink) && finite_f(dp->grad_threshold) && finite_f(dp->min_opacity) &&
+           finite_f(dp->max_size_frac) && finite_f(dp->max_screen_radius) && finite_f(dp->clone_size_frac);
+}
+
+static DensifyParams densify_params(const linprim_densify_params* dp) {
+    return {dp->grad_threshold, dp->min_opacity, dp->max_size_frac, dp->max_screen_radius, dp->clone_size_frac,
+            dp->split_shrink};
+}
+
+int linprim_densify_plan(int32_t type, int64_t n, const float* dists, const float* opacity, const float* grad_accum,
+                         const int32_t* count, const float* max_radius, const linprim_densify_params* params,
+                         void* ws, size_t ws_bytes, int64_t* n_out, void* stream) {
+    if ((type != LINPRIM_OCTAHEDRON && type != LINPRIM_TETRAHEDRON) || n < 0 || n >= (int64_t(1) << 31) || !ws ||
+        !n_out || !valid_densify(params))
+        return LINPRIM_ERR_INVALID_ARG;
+    if (n > 0 && (!dists || !opacity || !grad_accum || !count || !max_radius)) return LINPRIM_ERR_INVALID_ARG;
+    if (ws_bytes < linprim_densify_workspace_size(n)) return LINPRIM_ERR_WORKSPACE;
+    if (int rc = check_device()) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t* bs = (int64_t*)ws;
+    hipError_t e = launch_densify_plan(type, n, dists, opacity, grad_accum, count, max_radius,
+                                       densify_params(params), params->extent, bs, s);
+    if (e != hipSuccess) return LINPRIM_ERR_HIP;
+    const int64_t nb = (n + kDensifyItems - 1) / kDensifyItems;
+    int64_t total = 0;
+    if (hipMemcpyAsync(&total, bs + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess) return LINPRIM_ERR_HIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return LINPRIM_ERR_HIP;
+    *n_out = total;
+    return LINPRIM_OK;
+}
+
+static bool state_ok(const linprim_state* st, int64_t rows) {
+    if (!st) return false;
+    if (rows == 0) return true;
+    if (!st->means || !st->quats || !st->dists || !st->opacity || !st->sh) return false;
+    const bool any = st->exp_avg[0] != nullptr;
+    for (int f = 0; f < 5; ++f)
+        if ((st->exp_avg[f] != nullptr) != any || (st->exp_avg_sq[f] != nullptr) != any) return false;
+    return true;
+}
+
+static StateSet state_set(const linprim_state* st) {
+    StateSet S;
+    float* p[5] = {st->means, st->quats, st->dists, st->opacity, st->sh};
+    for (int f = 0; f < 5; ++f) {
+        S.p[f] = p[f];
+        S.m[f] = st->exp_avg[f];
+        S.v[f] = st->exp_avg_sq[f];
+    }
+    return S;
+}
+
+int linprim_densify_apply(int32_t type, int32_t sh_degree, int64_t n, const linprim_state* src, const float* normals,
+                          const float* grad_accum, const int32_t* count, const float* max_radius,
+                          const linprim_densify_params* params, const void* ws, size_t ws_bytes,
+                          const linprim_state* dst, int64_t n_out, void* stream) {
+    if ((type != LINPRIM_OCTAHEDRON && type != LINPRIM_TETRAHEDRON) || sh_degree < 0 || sh_degree > 3 || n < 0 ||
+        n >= (int64_t(1) << 31) || n_out < 0 || n_out > 3 * n || !ws || !valid_densify(params) ||
+        !state_ok(src, n) || !state_ok(dst, n_out))
+        return LINPRIM_ERR_INVALID_ARG;
+    if (n > 0 && (!normals || !grad_accum || !count || !max_radius)) return LINPRIM_ERR_INVALID_ARG;
+    if (ws_bytes < linprim_densify_workspace_size(n)) return LINPRIM_ERR_WORKSPACE;
+    if (int rc = check_device()) return rc;
+    return hip_status(launch_densify_apply(type, sh_degree, n, state_set(src), normals, grad_accum, count,
+                                           max_radius, densify_params(params), params->extent,
+                                           (const int64_t*)ws, state_set(dst), (hipStream_t)stream));
 }
 
 int linprim_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad, float* partial,

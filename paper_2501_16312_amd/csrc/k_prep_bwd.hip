@@ -286,7 +286,8 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
                                                   const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
                                                   const uint32_t* __restrict__ offsets, float* __restrict__ grads,
                                                   int nq, const Status* __restrict__ status, uint64_t capacity,
-                                                  const uint32_t* __restrict__ vis, int aa) {
+                                                  const uint32_t* __restrict__ vis, int aa,
+                                                  float2* __restrict__ stats) {
     // one thread per (view, primitive) slot that touches a tile, taken from
     // the list the scan built, so that no lane idles on a culled slot
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -341,6 +342,8 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     const double ox = (double)rc.x + 0.5 - G.c[0];
     const double oy = (double)rc.y + 0.5 - G.c[1];
     if (EXACT) {
+        // the view-space positional gradient is a ray-space quantity: none here
+        stats[vs] = make_float2(0.0f, (float)G.radius);
         double dmin = (double)dists[ND * i];
         for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dists[ND * i + k]);
         const double sigma = -log(1.0 - kAlphaScaleD * (double)opacity[i]) / (2.0 * dmin);
@@ -420,6 +423,13 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     }
     // ox = i0 + 1/2 - c_x, oy = j0 + 1/2 - c_y; c_z does not enter a chord
     const double gc0 = -gox, gc1 = -goy;
+    // Sec. 3.4 "Adaptive Population Control": the view-space positional
+    // gradient (dL/d centre x, y with the offsets fixed) per unit of
+    // normalised device coordinates, and the screen radius
+    {
+        const double ex = gc0 * 0.5 * (double)V.width, ey = gc1 * 0.5 * (double)V.height;
+        stats[vs] = make_float2((float)sqrt(ex * ex + ey * ey), (float)G.radius);
+    }
 
     // ---- ray space -> camera: c = phi(t) with d phi/dt = J; a_k = J(t) oc_k
     const double* J = G.J;
@@ -609,6 +619,7 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
                        grads);
     const dim3 g1((unsigned)((vn + 127) / 128));
     const uint32_t* vis = reinterpret_cast<const uint32_t*>(vws + L.vis);
+    float2* stats = reinterpret_cast<float2*>(const_cast<char*>(vws) + L.stats);
     const dim3 g2((unsigned)((p.n + 127) / 128));
 #define LP_PRIM(K_, D_)                                                                                        \
     hipLaunchKernelGGL((k_prim_bwd<K_, D_>), g2, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, p.sh, \
@@ -623,7 +634,7 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
     }
 #define LP_SLOT(K_, E_)                                                                                         \
     hipLaunchKernelGGL((k_slot_bwd<K_, E_>), g1, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, p.n, \
-                       views, payload, tiles, offsets, grads, nq, st, cap, vis, aa ? 1 : 0)
+                       views, payload, tiles, offsets, grads, nq, st, cap, vis, aa ? 1 : 0, stats)
     if (p.type == LINPRIM_OCTAHEDRON) {
         if (exact) LP_SLOT(LINPRIM_OCTAHEDRON, true); else LP_SLOT(LINPRIM_OCTAHEDRON, false);
         LP_PRIM_DEG(LINPRIM_OCTAHEDRON)

@@ -85,7 +85,7 @@ struct Status {
 
 // Offsets into the view workspace (all 256-byte aligned).
 struct ViewLayout {
-    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, vis, total;
+    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, vis, stats, total;
     int64_t n, n_views, n_tiles_total, scan_blocks;
 };
 
@@ -157,6 +157,26 @@ struct AdamGroups {
     int vec[8];           // all four arrays 16-byte aligned
     int count;
 };
+// Adaptive population control (Sec. 3.4; thresholds of App. G).
+struct DensifyParams {
+    float grad_threshold, min_opacity, max_size_frac, max_radius, clone_size_frac, shrink;
+};
+struct StateSet {
+    float* p[5];     // means, quats, dists, opacity, sh
+    float* m[5];     // Adam first moments (all null: none)
+    float* v[5];     // Adam second moments
+};
+constexpr int kDensifyItems = 1024;   // primitives per scan block
+hipError_t launch_accumulate_stats(int64_t n, int32_t n_views, const ViewLayout& L, const char* vws,
+                                   float* grad_accum, int32_t* count, float* max_radius, hipStream_t s);
+hipError_t launch_densify_plan(int type, int64_t n, const float* dists, const float* opacity,
+                               const float* grad_accum, const int32_t* count, const float* max_radius,
+                               const DensifyParams& dp, float extent, int64_t* block_sums, hipStream_t s);
+hipError_t launch_densify_apply(int type, int sh_degree, int64_t n, const StateSet& src, const float* normals,
+                                const float* grad_accum, const int32_t* count, const float* max_radius,
+                                const DensifyParams& dp, float extent, const int64_t* block_sums,
+                                const StateSet& dst, hipStream_t s);
+
 hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,
                        const float* bias_corr, hipStream_t s);
 hipError_t launch_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad,
@@ -258,6 +278,7 @@ struct Geom {
     double J[9];        // ray-space Jacobian at tc (row-major)
     int rect[4];
     uint32_t key;
+    double radius;      // half the larger side of the projected bounding box (pixels)
 };
 
 // Builds the primitive, transforms it and bounds it.  Returns false if the
@@ -399,6 +420,7 @@ __device__ inline bool build_geometry(int type, bool exact, bool aa, const float
         }
     }
     if (!isfinite(xmin) || !isfinite(xmax) || !isfinite(ymin) || !isfinite(ymax)) return false;
+    G.radius = 0.5 * fmax(xmax - xmin, ymax - ymin);
     double fi0 = ceil(xmin - 0.5), fi1 = floor(xmax - 0.5);
     double fj0 = ceil(ymin - 0.5), fj1 = floor(ymax - 0.5);
     if (fi0 < 0.0) fi0 = 0.0;

@@ -59,12 +59,26 @@ class linprim_adam_group(ctypes.Structure):
                 ("lr_tail", ctypes.c_float), ("head", ctypes.c_int32)]
 
 
+class linprim_densify_params(ctypes.Structure):
+    _fields_ = [("grad_threshold", ctypes.c_float), ("min_opacity", ctypes.c_float),
+                ("max_size_frac", ctypes.c_float), ("max_screen_radius", ctypes.c_float),
+                ("clone_size_frac", ctypes.c_float), ("split_shrink", ctypes.c_float),
+                ("extent", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+class linprim_state(ctypes.Structure):
+    _fields_ = [("means", ctypes.c_void_p), ("quats", ctypes.c_void_p), ("dists", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p), ("exp_avg", ctypes.c_void_p * 5),
+                ("exp_avg_sq", ctypes.c_void_p * 5)]
+
+
 EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linprim_preprocess",
            "linprim_pair_count", "linprim_bin_sort", "linprim_render_fwd", "linprim_render_fwd_counted",
            "linprim_render_fwd_depth",
            "linprim_render_bwd", "linprim_raster_bwd", "linprim_preprocess_bwd", "linprim_read_status",
            "linprim_strerror", "linprim_debug_pointers", "linprim_upload_views", "linprim_l1_grad",
-           "linprim_adam_step", "linprim_adam_step_dev")
+           "linprim_adam_step", "linprim_adam_step_dev", "linprim_accumulate_stats",
+           "linprim_densify_workspace_size", "linprim_densify_plan", "linprim_densify_apply")
 
 _lib = None
 
@@ -109,6 +123,12 @@ def load(path: str = LIB_PATH):
                                        P, P, P, P]
     lib.linprim_preprocess_bwd.argtypes = [pr, cm, I32, tu, P, SZ, P, SZ, I64, P, P, P, P, P, P]
     lib.linprim_read_status.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I32), P]
+    dpp, stp = ctypes.POINTER(linprim_densify_params), ctypes.POINTER(linprim_state)
+    lib.linprim_accumulate_stats.argtypes = [pr, cm, I32, tu, P, SZ, P, P, P, P]
+    lib.linprim_densify_workspace_size.restype = SZ
+    lib.linprim_densify_workspace_size.argtypes = [I64]
+    lib.linprim_densify_plan.argtypes = [I32, I64, P, P, P, P, P, dpp, P, SZ, ctypes.POINTER(I64), P]
+    lib.linprim_densify_apply.argtypes = [I32, I32, I64, stp, P, P, P, P, dpp, P, SZ, stp, I64, P]
     lib.linprim_strerror.restype = ctypes.c_char_p
     lib.linprim_strerror.argtypes = [ctypes.c_int]
     lib.linprim_debug_pointers.argtypes = [pr, cm, I32, tu, P, P, I64] + [ctypes.POINTER(P)] * 7
@@ -117,7 +137,8 @@ def load(path: str = LIB_PATH):
               lib.linprim_raster_bwd,
               lib.linprim_preprocess_bwd, lib.linprim_read_status, lib.linprim_upload_views,
               lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev,
-              lib.linprim_debug_pointers):
+              lib.linprim_debug_pointers, lib.linprim_accumulate_stats, lib.linprim_densify_plan,
+              lib.linprim_densify_apply):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -345,3 +366,55 @@ def linprim_debug_pointers(prims: Prims, cams, tune, view_ws, pair_ws, max_pairs
            "linprim_debug_pointers")
     names = ("payload", "depth_keys", "tiles", "offsets", "keys", "values", "ranges")
     return {k: int(o.value or 0) for k, o in zip(names, outs)}
+
+
+# ---------------------------------------------------------------------------
+# Adaptive population control.
+# ---------------------------------------------------------------------------
+FIELDS = ("means", "quats", "dists", "opacity", "sh")
+
+
+def densify_params(extent: float, grad_threshold: float = 1.5e-4, min_opacity: float = 0.025,
+                   max_size_frac: float = 0.4, max_screen_radius: float = 20.0, clone_size_frac: float = 0.01,
+                   split_shrink: float = 1.2) -> linprim_densify_params:
+    """App. G's thresholds by default."""
+    return linprim_densify_params(grad_threshold, min_opacity, max_size_frac, max_screen_radius, clone_size_frac,
+                                  split_shrink, float(extent), 0)
+
+
+def state(params: dict, exp_avg: Optional[dict] = None, exp_avg_sq: Optional[dict] = None) -> linprim_state:
+    st = linprim_state()
+    for k in FIELDS:
+        setattr(st, k, params[k].data_ptr() if params[k].numel() else None)
+    for f, k in enumerate(FIELDS):
+        st.exp_avg[f] = exp_avg[k].data_ptr() if exp_avg is not None and exp_avg[k].numel() else None
+        st.exp_avg_sq[f] = exp_avg_sq[k].data_ptr() if exp_avg_sq is not None and exp_avg_sq[k].numel() else None
+    return st
+
+
+def linprim_accumulate_stats(prims: Prims, cams, tune, view_ws, grad_accum, count, max_radius, stream=None):
+    p = prims.c()
+    _check(load().linprim_accumulate_stats(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _ptr(view_ws),
+                                           view_ws.numel(), _ptr(grad_accum), _ptr(count), _ptr(max_radius),
+                                           _stream(stream)), "linprim_accumulate_stats")
+
+
+def linprim_densify_workspace_size(n: int) -> int:
+    return int(load().linprim_densify_workspace_size(int(n)))
+
+
+def linprim_densify_plan(kind: int, dists, opacity, grad_accum, count, max_radius, dp: linprim_densify_params,
+                         ws, stream=None) -> int:
+    out = ctypes.c_int64(0)
+    _check(load().linprim_densify_plan(int(kind), int(opacity.numel()), _ptr(dists), _ptr(opacity),
+                                       _ptr(grad_accum), _ptr(count), _ptr(max_radius), ctypes.byref(dp), _ptr(ws),
+                                       ws.numel(), ctypes.byref(out), _stream(stream)), "linprim_densify_plan")
+    return int(out.value)
+
+
+def linprim_densify_apply(kind: int, sh_degree: int, n: int, src: linprim_state, normals, grad_accum, count,
+                          max_radius, dp: linprim_densify_params, ws, dst: linprim_state, n_out: int, stream=None):
+    _check(load().linprim_densify_apply(int(kind), int(sh_degree), int(n), ctypes.byref(src), _ptr(normals),
+                                        _ptr(grad_accum), _ptr(count), _ptr(max_radius), ctypes.byref(dp), _ptr(ws),
+                                        ws.numel(), ctypes.byref(dst), int(n_out), _stream(stream)),
+           "linprim_densify_apply")

@@ -1,0 +1,56 @@
+"""Adaptive population control over the C ABI (Sec. 3.4 "Adaptive
+Population Control"; thresholds in App. G): statistics accumulated after
+every backward pass, and a densify / prune pass that returns new parameter
+and Adam-moment tensors.  Argument marshalling only; the work runs in
+csrc/k_population.hip and the statistics come from the preprocessing
+backward kernels."""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import linprim as L
+
+
+class PopulationControl:
+    def __init__(self, kind: int, sh_degree: int, n: int, device: str = "cuda", **thresholds):
+        self.kind, self.sh_degree = int(kind), int(sh_degree)
+        self.device = torch.device(device)
+        self.thresholds = thresholds
+        self.reset(n)
+
+    def reset(self, n: int):
+        self.n = int(n)
+        self.grad_accum = torch.zeros(self.n, dtype=torch.float32, device=self.device)
+        self.count = torch.zeros(self.n, dtype=torch.int32, device=self.device)
+        self.max_radius = torch.zeros(self.n, dtype=torch.float32, device=self.device)
+
+    def accumulate(self, rast, prims: L.Prims):
+        """After rast.backward(...) on these primitives."""
+        L.linprim_accumulate_stats(prims, rast.cams_c, rast.tune, rast.view_ws, self.grad_accum, self.count,
+                                   self.max_radius)
+
+    def densify(self, params: dict, extent: float, exp_avg: Optional[dict] = None,
+                exp_avg_sq: Optional[dict] = None, normals: Optional[torch.Tensor] = None,
+                generator: Optional[torch.Generator] = None):
+        """Returns (params, exp_avg, exp_avg_sq) after the pass (new tensors;
+        moments None if none were given) and resets the statistics."""
+        dp = L.densify_params(extent, **self.thresholds)
+        n = self.n
+        ws = torch.empty(max(L.linprim_densify_workspace_size(n), 1), dtype=torch.uint8, device=self.device)
+        n_out = L.linprim_densify_plan(self.kind, params["dists"], params["opacity"], self.grad_accum, self.count,
+                                       self.max_radius, dp, ws)
+        if normals is None:
+            normals = torch.randn((n, 2, 3), generator=generator, dtype=torch.float32, device=self.device)
+        new = {k: torch.empty((n_out,) + tuple(params[k].shape[1:]), dtype=torch.float32, device=self.device)
+               for k in L.FIELDS}
+        m_new = v_new = None
+        if exp_avg is not None:
+            m_new = {k: torch.empty_like(new[k]) for k in L.FIELDS}
+            v_new = {k: torch.empty_like(new[k]) for k in L.FIELDS}
+        L.linprim_densify_apply(self.kind, self.sh_degree, n, L.state(params, exp_avg, exp_avg_sq),
+                                normals.contiguous(), self.grad_accum, self.count, self.max_radius, dp, ws,
+                                L.state(new, m_new, v_new), n_out)
+        self.reset(n_out)
+        return new, m_new, v_new
