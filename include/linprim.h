@@ -376,6 +376,33 @@ int linprim_densify_apply(int32_t type, int32_t sh_degree, int64_t n, const linp
                           const float *max_radius, const linprim_densify_params *params, const void *ws,
                           size_t ws_bytes, const linprim_state *dst, int64_t n_out, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Photometric loss of the optimisation (Sec. 3.4 "Optimization": the loss
+ * of 3DGS, an L1 and an SSIM term).  Per view, with n = 3 H W,
+ *   L_v = (1 - lambda) sum |C - T| / n + lambda (1 - sum s / n),
+ *   s = (2 mx my + C1)(2 sxy + C2) / ((mx^2 + my^2 + C1)(sxx + syy + C2)),
+ * local statistics mx, my, sxx, syy, sxy of each channel by an 11 x 11
+ * Gaussian window (standard deviation 1.5, normalised), zero padding at the
+ * border, C1 = 0.01^2, C2 = 0.03^2; the loss of a batch is sum_v L_v
+ * (3DGS's weight: lambda = 0.2).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the loss workspace (per-block partial sums and three per-pixel
+ * derivative maps of the largest view). */
+size_t linprim_loss_workspace_size(const linprim_camera *cams, int32_t n_views);
+
+/* dL/dC for the packed view-major images rgb and target (DEVICE, layout of
+ * linprim_render_fwd's out_rgb) into grad (DEVICE, same layout; may not
+ * alias the inputs); the partial sums of the loss stay in ws.  sign(0) = 0
+ * in the L1 term.  Graph-capturable. */
+int linprim_loss_grad(const float *rgb, const float *target, const linprim_camera *cams, int32_t n_views,
+                      float lambda, void *ws, size_t ws_bytes, float *grad, void *stream);
+
+/* Waits for `stream` and returns, in *loss (HOST), sum_v L_v of the last
+ * linprim_loss_grad on ws, the partial sums added in double precision. */
+int linprim_loss_value(const void *ws, size_t ws_bytes, const linprim_camera *cams, int32_t n_views, float lambda,
+                       double *loss, void *stream);
+
 /* Static description of an error code. */
 const char *linprim_strerror(int code);
 

@@ -27,6 +27,7 @@ SOURCES = {
     "k_prep_bwd.hip": ["-ffp-contract=off"],
     "k_optim.hip": [],
     "k_population.hip": [],
+    "k_loss.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

@@ -1,6 +1,7 @@
 // abi.hip -- the extern "C" entry points of liblinprim.so: argument
 // validation, workspace layouts and launch order.  Every call enqueues on
 // the caller's stream; only linprim_pair_count / linprim_read_status wait.
+#include <stdlib.h>
 #include <string.h>
 
 #include "linprim_common.h"
@@ -409,6 +410,80 @@ int linprim_densify_apply(int32_t type, int32_t sh_degree, int64_t n, const linp
     return hip_status(launch_densify_apply(type, sh_degree, n, state_set(src), normals, grad_accum, count,
                                            max_radius, densify_params(params), params->extent,
                                            (const int64_t*)ws, state_set(dst), (hipStream_t)stream));
+}
+
+// Loss workspace: per view, 2 floats per (channel, 32 x 32 tile) block,
+// then 9 floats per pixel of the largest view.
+static size_t loss_partials(const linprim_camera* cams, int32_t n_views) {
+    size_t t = 0;
+    for (int v = 0; v < n_views; ++v)
+        t += (size_t)2 * 3 * ((cams[v].width + kLossTile - 1) / kLossTile) *
+             ((cams[v].height + kLossTile - 1) / kLossTile);
+    return t;
+}
+
+size_t linprim_loss_workspace_size(const linprim_camera* cams, int32_t n_views) {
+    if (!valid_cams(cams, n_views)) return 0;
+    size_t hw = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const size_t x = (size_t)cams[v].width * (size_t)cams[v].height;
+        if (x > hw) hw = x;
+    }
+    return align256(loss_partials(cams, n_views) * 4) + align256(hw * 9 * 4);
+}
+
+int linprim_loss_grad(const float* rgb, const float* target, const linprim_camera* cams, int32_t n_views,
+                      float lambda, void* ws, size_t ws_bytes, float* grad, void* stream) {
+    if (!rgb || !target || !grad || !ws || !valid_cams(cams, n_views) || !(lambda >= 0.0f && lambda <= 1.0f) ||
+        grad == rgb || grad == target)
+        return LINPRIM_ERR_INVALID_ARG;
+    if (ws_bytes < linprim_loss_workspace_size(cams, n_views)) return LINPRIM_ERR_WORKSPACE;
+    if (int rc = check_device()) return rc;
+    float* partial = (float*)ws;
+    float* dmaps = (float*)((char*)ws + align256(loss_partials(cams, n_views) * 4));
+    int64_t px = 0;
+    size_t po = 0;
+    hipError_t e = hipSuccess;
+    for (int v = 0; v < n_views && e == hipSuccess; ++v) {
+        const int W = cams[v].width, H = cams[v].height;
+        e = launch_ssim_l1(rgb + 3 * px, target + 3 * px, W, H, lambda, dmaps, partial + po, grad + 3 * px,
+                           (hipStream_t)stream);
+        px += (int64_t)W * H;
+        po += (size_t)2 * 3 * ((W + kLossTile - 1) / kLossTile) * ((H + kLossTile - 1) / kLossTile);
+    }
+    return hip_status(e);
+}
+
+int linprim_loss_value(const void* ws, size_t ws_bytes, const linprim_camera* cams, int32_t n_views, float lambda,
+                       double* loss, void* stream) {
+    if (!ws || !loss || !valid_cams(cams, n_views)) return LINPRIM_ERR_INVALID_ARG;
+    if (ws_bytes < linprim_loss_workspace_size(cams, n_views)) return LINPRIM_ERR_WORKSPACE;
+    const size_t np = loss_partials(cams, n_views);
+    float* host = (float*)malloc(np * sizeof(float) + 1);
+    if (!host) return LINPRIM_ERR_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    if (hipMemcpyAsync(host, ws, np * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        free(host);
+        return LINPRIM_ERR_HIP;
+    }
+    double total = 0.0;
+    size_t po = 0;
+    for (int v = 0; v < n_views; ++v) {
+        const int W = cams[v].width, H = cams[v].height;
+        const size_t nb = (size_t)3 * ((W + kLossTile - 1) / kLossTile) * ((H + kLossTile - 1) / kLossTile);
+        double ssum = 0.0, l1 = 0.0;
+        for (size_t b = 0; b < nb; ++b) {
+            ssum += host[po + 2 * b];
+            l1 += host[po + 2 * b + 1];
+        }
+        const double n = 3.0 * (double)W * (double)H;
+        total += (1.0 - (double)lambda) * l1 / n + (double)lambda * (1.0 - ssum / n);
+        po += 2 * nb;
+    }
+    free(host);
+    *loss = total;
+    return LINPRIM_OK;
 }
 
 int linprim_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad, float* partial,

@@ -1,0 +1,198 @@
+// k_loss.hip -- the photometric loss of the optimisation (Sec. 3.4
+// "Optimization": 3DGS's L1 + SSIM) and its gradient with respect to the
+// rendered image, fused: per view and channel,
+//   L = (1 - lam) mean |x - y| + lam (1 - mean s),
+//   s = (2 mx my + C1)(2 sxy + C2) / ((mx^2 + my^2 + C1)(sxx + syy + C2)),
+// local statistics by an 11 x 11 Gaussian window (sigma 1.5, zero padding).
+//
+// Two passes over 32 x 32 output tiles, each staging a 42 x 42 input tile
+// (5-pixel halo) in LDS and applying the separable window as a row pass then
+// a column pass:
+//   k_ssim_fwd  five statistics -> s and its partial derivatives with respect
+//               to mx, E[x^2], E[xy] (written per pixel), block sums of s and
+//               |x - y|;
+//   k_ssim_bwd  the window applied to those three derivative maps (the window
+//               is symmetric, so it is its own adjoint) ->
+//               dL/dx = (1 - lam) sign(x - y) / n - lam / n (G*A + 2 x G*B + y G*C).
+#include "linprim_common.h"
+
+namespace linprim {
+
+constexpr int kSsimTile = 32;
+constexpr int kSsimHalo = 5;
+constexpr int kSsimIn = kSsimTile + 2 * kSsimHalo;   // 42
+constexpr float kC1 = 0.0001f;                       // 0.01^2
+constexpr float kC2 = 0.0009f;                       // 0.03^2
+
+struct SsimWindow {
+    float w[11];
+};
+
+// Loads a 42 x 42 tile of `src` (zero outside the image) into `dst`.
+__device__ inline void load_tile(const float* __restrict__ src, int W, int H, int x0, int y0, float* dst) {
+    for (int k = threadIdx.x; k < kSsimIn * kSsimIn; k += blockDim.x) {
+        const int r = k / kSsimIn, c = k % kSsimIn;
+        const int y = y0 - kSsimHalo + r, x = x0 - kSsimHalo + c;
+        dst[k] = (x >= 0 && x < W && y >= 0 && y < H) ? src[(int64_t)y * W + x] : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ rgb, const float* __restrict__ target,
+                                                  int W, int H, SsimWindow win, float* __restrict__ dmaps,
+                                                  float* __restrict__ partial) {
+    __shared__ float xs[kSsimIn * kSsimIn], ys[kSsimIn * kSsimIn];
+    __shared__ float hs[5][kSsimIn * kSsimTile];
+    __shared__ float red[2][256];
+    const int ch = blockIdx.z;
+    const int x0 = blockIdx.x * kSsimTile, y0 = blockIdx.y * kSsimTile;
+    const int64_t hw = (int64_t)W * H;
+    const float* X = rgb + ch * hw;
+    const float* Y = target + ch * hw;
+    load_tile(X, W, H, x0, y0, xs);
+    load_tile(Y, W, H, x0, y0, ys);
+    __syncthreads();
+    // row pass: 42 rows x 32 output columns, five statistics
+    for (int k = threadIdx.x; k < kSsimIn * kSsimTile; k += blockDim.x) {
+        const int r = k / kSsimTile, c = k % kSsimTile;
+        float a = 0.f, b = 0.f, xx = 0.f, yy = 0.f, xy = 0.f;
+#pragma unroll
+        for (int t = 0; t < 11; ++t) {
+            const float xv = xs[r * kSsimIn + c + t], yv = ys[r * kSsimIn + c + t], wt = win.w[t];
+            a += wt * xv;
+            b += wt * yv;
+            xx += wt * xv * xv;
+            yy += wt * yv * yv;
+            xy += wt * xv * yv;
+        }
+        hs[0][k] = a;
+        hs[1][k] = b;
+        hs[2][k] = xx;
+        hs[3][k] = yy;
+        hs[4][k] = xy;
+    }
+    __syncthreads();
+    float ssum = 0.f, l1 = 0.f;
+    for (int k = threadIdx.x; k < kSsimTile * kSsimTile; k += blockDim.x) {
+        const int r = k / kSsimTile, c = k % kSsimTile;
+        const int x = x0 + c, y = y0 + r;
+        if (x >= W || y >= H) continue;
+        float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+#pragma unroll
+        for (int t = 0; t < 11; ++t) {
+            const int q = (r + t) * kSsimTile + c;
+            const float wt = win.w[t];
+            mx += wt * hs[0][q];
+            my += wt * hs[1][q];
+            exx += wt * hs[2][q];
+            eyy += wt * hs[3][q];
+            exy += wt * hs[4][q];
+        }
+        const float A = 2.f * mx * my + kC1;
+        const float B = 2.f * (exy - mx * my) + kC2;
+        const float Cc = mx * mx + my * my + kC1;
+        const float D = (exx - mx * mx) + (eyy - my * my) + kC2;
+        const float icd = 1.0f / (Cc * D);
+        const float s = A * B * icd;
+        const int64_t p = (int64_t)y * W + x;
+        float* dm = dmaps + (int64_t)ch * 3 * hw;
+        dm[p] = 2.f * my * (B - A) * icd - 2.f * mx * s / Cc + 2.f * mx * s / D;   // ds/dmx
+        dm[hw + p] = -s / D;                                                      // ds/dE[x^2]
+        dm[2 * hw + p] = 2.f * A * icd;                                           // ds/dE[xy]
+        ssum += s;
+        l1 += fabsf(X[p] - Y[p]);
+    }
+    // block sums, fixed order
+    red[0][threadIdx.x] = ssum;
+    red[1][threadIdx.x] = l1;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + off];
+            red[1][threadIdx.x] += red[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t b = ((int64_t)ch * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        partial[2 * b] = red[0][0];
+        partial[2 * b + 1] = red[1][0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ rgb, const float* __restrict__ target,
+                                                  int W, int H, SsimWindow win, const float* __restrict__ dmaps,
+                                                  float l1_scale, float ssim_scale, float* __restrict__ grad) {
+    __shared__ float ts[3][kSsimIn * kSsimIn];
+    __shared__ float hs[3][kSsimIn * kSsimTile];
+    const int ch = blockIdx.z;
+    const int x0 = blockIdx.x * kSsimTile, y0 = blockIdx.y * kSsimTile;
+    const int64_t hw = (int64_t)W * H;
+    const float* dm = dmaps + (int64_t)ch * 3 * hw;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) load_tile(dm + m * hw, W, H, x0, y0, ts[m]);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kSsimIn * kSsimTile; k += blockDim.x) {
+        const int r = k / kSsimTile, c = k % kSsimTile;
+        float a = 0.f, b = 0.f, d = 0.f;
+#pragma unroll
+        for (int t = 0; t < 11; ++t) {
+            const int q = r * kSsimIn + c + t;
+            const float wt = win.w[t];
+            a += wt * ts[0][q];
+            b += wt * ts[1][q];
+            d += wt * ts[2][q];
+        }
+        hs[0][k] = a;
+        hs[1][k] = b;
+        hs[2][k] = d;
+    }
+    __syncthreads();
+    const float* X = rgb + ch * hw;
+    const float* Y = target + ch * hw;
+    float* G = grad + ch * hw;
+    for (int k = threadIdx.x; k < kSsimTile * kSsimTile; k += blockDim.x) {
+        const int r = k / kSsimTile, c = k % kSsimTile;
+        const int x = x0 + c, y = y0 + r;
+        if (x >= W || y >= H) continue;
+        float ga = 0.f, gb = 0.f, gc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 11; ++t) {
+            const int q = (r + t) * kSsimTile + c;
+            const float wt = win.w[t];
+            ga += wt * hs[0][q];
+            gb += wt * hs[1][q];
+            gc += wt * hs[2][q];
+        }
+        const int64_t p = (int64_t)y * W + x;
+        const float xv = X[p], yv = Y[p];
+        const float d = xv - yv;
+        const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+        G[p] = l1_scale * sg - ssim_scale * (ga + 2.f * xv * gb + yv * gc);
+    }
+}
+
+SsimWindow ssim_window() {
+    SsimWindow S;
+    double g[11], tot = 0.0;
+    for (int t = 0; t < 11; ++t) {
+        const double r = t - 5;
+        g[t] = exp(-(r * r) / (2.0 * 1.5 * 1.5));
+        tot += g[t];
+    }
+    for (int t = 0; t < 11; ++t) S.w[t] = (float)(g[t] / tot);
+    return S;
+}
+
+// One view [3, H, W]: dmaps [3][3][H][W] scratch, partial [2 * 3 * tiles].
+hipError_t launch_ssim_l1(const float* rgb, const float* target, int W, int H, float lam, float* dmaps,
+                          float* partial, float* grad, hipStream_t s) {
+    const SsimWindow win = ssim_window();
+    const dim3 grid((unsigned)((W + kSsimTile - 1) / kSsimTile), (unsigned)((H + kSsimTile - 1) / kSsimTile), 3);
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, rgb, target, W, H, win, dmaps, partial);
+    const float n = 3.0f * (float)W * (float)H;
+    hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, rgb, target, W, H, win, dmaps, (1.0f - lam) / n, lam / n,
+                       grad);
+    return hipGetLastError();
+}
+
+}  // namespace linprim

@@ -177,6 +177,11 @@ hipError_t launch_densify_apply(int type, int sh_degree, int64_t n, const StateS
                                 const DensifyParams& dp, float extent, const int64_t* block_sums,
                                 const StateSet& dst, hipStream_t s);
 
+// Photometric loss (Sec. 3.4 "Optimization"), one view [3, H, W].
+constexpr int kLossTile = 32;
+hipError_t launch_ssim_l1(const float* rgb, const float* target, int W, int H, float lam, float* dmaps,
+                          float* partial, float* grad, hipStream_t s);
+
 hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,
                        const float* bias_corr, hipStream_t s);
 hipError_t launch_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad,

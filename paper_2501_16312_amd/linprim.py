@@ -78,7 +78,8 @@ EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linpri
            "linprim_render_bwd", "linprim_raster_bwd", "linprim_preprocess_bwd", "linprim_read_status",
            "linprim_strerror", "linprim_debug_pointers", "linprim_upload_views", "linprim_l1_grad",
            "linprim_adam_step", "linprim_adam_step_dev", "linprim_accumulate_stats",
-           "linprim_densify_workspace_size", "linprim_densify_plan", "linprim_densify_apply")
+           "linprim_densify_workspace_size", "linprim_densify_plan", "linprim_densify_apply",
+           "linprim_loss_workspace_size", "linprim_loss_grad", "linprim_loss_value")
 
 _lib = None
 
@@ -129,6 +130,10 @@ def load(path: str = LIB_PATH):
     lib.linprim_densify_workspace_size.argtypes = [I64]
     lib.linprim_densify_plan.argtypes = [I32, I64, P, P, P, P, P, dpp, P, SZ, ctypes.POINTER(I64), P]
     lib.linprim_densify_apply.argtypes = [I32, I32, I64, stp, P, P, P, P, dpp, P, SZ, stp, I64, P]
+    lib.linprim_loss_workspace_size.restype = SZ
+    lib.linprim_loss_workspace_size.argtypes = [cm, I32]
+    lib.linprim_loss_grad.argtypes = [P, P, cm, I32, ctypes.c_float, P, SZ, P, P]
+    lib.linprim_loss_value.argtypes = [P, SZ, cm, I32, ctypes.c_float, ctypes.POINTER(ctypes.c_double), P]
     lib.linprim_strerror.restype = ctypes.c_char_p
     lib.linprim_strerror.argtypes = [ctypes.c_int]
     lib.linprim_debug_pointers.argtypes = [pr, cm, I32, tu, P, P, I64] + [ctypes.POINTER(P)] * 7
@@ -138,7 +143,7 @@ def load(path: str = LIB_PATH):
               lib.linprim_preprocess_bwd, lib.linprim_read_status, lib.linprim_upload_views,
               lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev,
               lib.linprim_debug_pointers, lib.linprim_accumulate_stats, lib.linprim_densify_plan,
-              lib.linprim_densify_apply):
+              lib.linprim_densify_apply, lib.linprim_loss_grad, lib.linprim_loss_value):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -418,3 +423,25 @@ def linprim_densify_apply(kind: int, sh_degree: int, n: int, src: linprim_state,
                                         _ptr(grad_accum), _ptr(count), _ptr(max_radius), ctypes.byref(dp), _ptr(ws),
                                         ws.numel(), ctypes.byref(dst), int(n_out), _stream(stream)),
            "linprim_densify_apply")
+
+
+# ---------------------------------------------------------------------------
+# Photometric loss (3DGS's L1 + SSIM).
+# ---------------------------------------------------------------------------
+SSIM_LAMBDA = 0.2
+
+
+def linprim_loss_workspace_size(cams) -> int:
+    return int(load().linprim_loss_workspace_size(cams, len(cams)))
+
+
+def linprim_loss_grad(rgb, target, cams, ws, grad, lam: float = SSIM_LAMBDA, stream=None):
+    _check(load().linprim_loss_grad(_ptr(rgb), _ptr(target), cams, len(cams), float(lam), _ptr(ws), ws.numel(),
+                                    _ptr(grad), _stream(stream)), "linprim_loss_grad")
+
+
+def linprim_loss_value(ws, cams, lam: float = SSIM_LAMBDA, stream=None) -> float:
+    out = ctypes.c_double(0.0)
+    _check(load().linprim_loss_value(_ptr(ws), ws.numel(), cams, len(cams), float(lam), ctypes.byref(out),
+                                     _stream(stream)), "linprim_loss_value")
+    return float(out.value)
