@@ -18,9 +18,9 @@ of the HBM byte counters).
 
 --workload steploop times the optimisation loop instead: 3,000,000
 octahedra, per step a batch of 8 random 1920x1080 views (from a pool of
-batches whose L1 targets were rendered once from a perturbed copy of the
-scene), forward + backward + L1 + fused Adam captured in one graph and
-replayed on each batch's poses.
+batches whose targets were rendered once from a perturbed copy of the
+scene), forward + backward + the L1 + SSIM loss gradient + fused Adam
+captured in one graph and replayed on each batch's poses.
 
 Prints one JSON line.
 """
@@ -316,7 +316,7 @@ def single(args, log):
 
 
 def steploop(args, log):
-    """Optimisation loop: fwd + bwd + L1 + Adam, one graph replayed per step
+    """Optimisation loop: fwd + bwd + loss + Adam, one graph replayed per step
     on a new batch of 8 random 1080p views (a pool of batches whose targets
     are rendered once, up front, from a perturbed copy of the scene)."""
     import numpy as np
@@ -372,7 +372,7 @@ def steploop(args, log):
     target = targets[0].clone()
     cap = CapturedStep(rast, prims, None, target=target, l1_scale=1.0 / target.numel(),
                        adam={"groups": groups, "beta1": 0.9, "beta2": 0.999, "eps": 1e-15}, headroom=1.3,
-                       grads=grads)
+                       grads=grads, loss=args.loss)
     log(f"pair capacity {rast.max_pairs} (largest batch {max_pairs}), {n_params} parameters")
 
     def step(k):
@@ -416,20 +416,32 @@ def steploop(args, log):
     adam_gbs = n_params * ADAM_BYTES_PER_PARAM / (adam_ms * 1e-3) / 1e9
     mp = sum(c.width * c.height for c in pool[0]) / 1e6
     ms = wall * 1e3 / args.steps
+    loss_name = "L1 + 0.2 (1 - SSIM) per view" if args.loss == "l1_ssim" else "mean L1"
+    loss_ms = None
+    if args.loss == "l1_ssim":
+        # the fused loss kernels timed alone on the last batch
+        e0l, e1l = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0l.record()
+        for _ in range(5):
+            L.linprim_loss_grad(cap.outs[0], target, rast.cams_c, cap.loss_ws, cap.grad_rgb)
+        e1l.record()
+        e1l.synchronize()
+        loss_ms = round(e0l.elapsed_time(e1l) / 5, 4)
     return {
         "metric": "optimisation steps/s at 3M octahedra, 8 x 1080p views",
         "value": round(1e3 / ms, 3), "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"3,000,000 room-scale octahedra (extent 40); per step a batch of 8 random "
-                               f"1920x1080 views from a pool of {len(pool)}, L1 to targets rendered from a "
-                               f"perturbed copy; fwd + bwd + L1 + fused Adam in one graph",
+                               f"1920x1080 views from a pool of {len(pool)}, {loss_name} to targets rendered "
+                               f"from a perturbed copy; fwd + bwd + loss + fused Adam in one graph",
+                   "loss": args.loss,
                    "tile": args.tile, "sort": f"radix{args.digit}" if args.radix_sort else "per-tile",
                    "pairs_last": int(n_pairs),
                    "params": n_params},
         "megapixels_per_s": round(mp / (ms * 1e-3), 1),
         "peak_hbm_gb": round(peak / 1e9, 3),
-        "loss": {"before": loss0, "after": loss1},
+        "loss": {"before": loss0, "after": loss1, "kernel_ms": loss_ms},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "adam": {"ms": round(adam_ms, 4), "achieved_gbs": round(adam_gbs, 1), "peak_gbs": PEAK_HBM_GBS,
                  "frac": round(adam_gbs / PEAK_HBM_GBS, 4), "bytes_per_param": ADAM_BYTES_PER_PARAM},
@@ -479,6 +491,8 @@ def main():
     ap.add_argument("--workload", choices=("single", "batched", "steploop", "copy"), default="single")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--view-batches", type=int, default=4)
+    ap.add_argument("--loss", choices=("l1_ssim", "l1"), default="l1_ssim",
+                    help="step-loop loss: 3DGS's L1 + SSIM (default) or mean L1")
     ap.add_argument("--tile", type=int, default=8)
     ap.add_argument("--digit", type=int, default=8)
     ap.add_argument("--radix-sort", action="store_true", help="global LSD radix sort instead of the per-tile sort")

@@ -28,12 +28,32 @@ struct SsimWindow {
     float w[11];
 };
 
-// Loads a 42 x 42 tile of `src` (zero outside the image) into `dst`.
-__device__ inline void load_tile(const float* __restrict__ src, int W, int H, int x0, int y0, float* dst) {
-    for (int k = threadIdx.x; k < kSsimIn * kSsimIn; k += blockDim.x) {
-        const int r = k / kSsimIn, c = k % kSsimIn;
+// Loads 42 x 42 tiles of NT images (zero outside the image) into LDS.  All
+// of a thread's global loads are issued before the first LDS store, so the
+// block waits for memory once rather than once per element.
+constexpr int kTileElems = kSsimIn * kSsimIn;             // 1764
+constexpr int kLoadIters = (kTileElems + 255) / 256;      // 7 for 256 threads
+template <int NT>
+__device__ inline void load_tiles(const float* const (&src)[NT], int W, int H, int x0, int y0,
+                                  float* const (&dst)[NT]) {
+    float v[NT][kLoadIters];
+#pragma unroll
+    for (int it = 0; it < kLoadIters; ++it) {
+        const int k = (int)threadIdx.x + it * 256;
+        const int r = k / kSsimIn, c = k - r * kSsimIn;
         const int y = y0 - kSsimHalo + r, x = x0 - kSsimHalo + c;
-        dst[k] = (x >= 0 && x < W && y >= 0 && y < H) ? src[(int64_t)y * W + x] : 0.0f;
+        const bool in = k < kTileElems && x >= 0 && x < W && y >= 0 && y < H;
+        const int64_t off = in ? (int64_t)y * W + x : 0;
+#pragma unroll
+        for (int m = 0; m < NT; ++m) v[m][it] = in ? src[m][off] : 0.0f;
+    }
+#pragma unroll
+    for (int it = 0; it < kLoadIters; ++it) {
+        const int k = (int)threadIdx.x + it * 256;
+        if (k < kTileElems) {
+#pragma unroll
+            for (int m = 0; m < NT; ++m) dst[m][k] = v[m][it];
+        }
     }
 }
 
@@ -48,11 +68,14 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ rgb,
     const int64_t hw = (int64_t)W * H;
     const float* X = rgb + ch * hw;
     const float* Y = target + ch * hw;
-    load_tile(X, W, H, x0, y0, xs);
-    load_tile(Y, W, H, x0, y0, ys);
+    {
+        const float* const srcs[2] = {X, Y};
+        float* const dsts[2] = {xs, ys};
+        load_tiles<2>(srcs, W, H, x0, y0, dsts);
+    }
     __syncthreads();
     // row pass: 42 rows x 32 output columns, five statistics
-    for (int k = threadIdx.x; k < kSsimIn * kSsimTile; k += blockDim.x) {
+    for (int k = threadIdx.x; k < kSsimIn * kSsimTile; k += 256) {
         const int r = k / kSsimTile, c = k % kSsimTile;
         float a = 0.f, b = 0.f, xx = 0.f, yy = 0.f, xy = 0.f;
 #pragma unroll
@@ -72,7 +95,8 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ rgb,
     }
     __syncthreads();
     float ssum = 0.f, l1 = 0.f;
-    for (int k = threadIdx.x; k < kSsimTile * kSsimTile; k += blockDim.x) {
+#pragma unroll
+    for (int k = threadIdx.x; k < kSsimTile * kSsimTile; k += 256) {
         const int r = k / kSsimTile, c = k % kSsimTile;
         const int x = x0 + c, y = y0 + r;
         if (x >= W || y >= H) continue;
@@ -99,7 +123,7 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ rgb,
         dm[hw + p] = -s / D;                                                      // ds/dE[x^2]
         dm[2 * hw + p] = 2.f * A * icd;                                           // ds/dE[xy]
         ssum += s;
-        l1 += fabsf(X[p] - Y[p]);
+        l1 += fabsf(xs[(r + kSsimHalo) * kSsimIn + c + kSsimHalo] - ys[(r + kSsimHalo) * kSsimIn + c + kSsimHalo]);
     }
     // block sums, fixed order
     red[0][threadIdx.x] = ssum;
@@ -128,10 +152,13 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ rgb,
     const int x0 = blockIdx.x * kSsimTile, y0 = blockIdx.y * kSsimTile;
     const int64_t hw = (int64_t)W * H;
     const float* dm = dmaps + (int64_t)ch * 3 * hw;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) load_tile(dm + m * hw, W, H, x0, y0, ts[m]);
+    {
+        const float* const srcs[3] = {dm, dm + hw, dm + 2 * hw};
+        float* const dsts[3] = {ts[0], ts[1], ts[2]};
+        load_tiles<3>(srcs, W, H, x0, y0, dsts);
+    }
     __syncthreads();
-    for (int k = threadIdx.x; k < kSsimIn * kSsimTile; k += blockDim.x) {
+    for (int k = threadIdx.x; k < kSsimIn * kSsimTile; k += 256) {
         const int r = k / kSsimTile, c = k % kSsimTile;
         float a = 0.f, b = 0.f, d = 0.f;
 #pragma unroll
@@ -150,7 +177,8 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ rgb,
     const float* X = rgb + ch * hw;
     const float* Y = target + ch * hw;
     float* G = grad + ch * hw;
-    for (int k = threadIdx.x; k < kSsimTile * kSsimTile; k += blockDim.x) {
+#pragma unroll
+    for (int k = threadIdx.x; k < kSsimTile * kSsimTile; k += 256) {
         const int r = k / kSsimTile, c = k % kSsimTile;
         const int x = x0 + c, y = y0 + r;
         if (x >= W || y >= H) continue;

@@ -1,5 +1,5 @@
-"""Graph-captured steps: the whole forward + backward (and optionally the L1
-loss gradient and the Adam update) of all views recorded once into a HIP
+"""Graph-captured steps: the whole forward + backward (and optionally the loss
+gradient and the Adam update) of all views recorded once into a HIP
 graph and replayed, with no host work or synchronisation inside a step.
 
 The pair count is data-dependent; the pair workspace is sized once, with
@@ -22,7 +22,10 @@ class CapturedStep:
     """fwd + bwd over every view of `rast`, captured in one graph.
 
     grad_rgb: a fixed dL/dC buffer, or None with `target` given, in which
-    case the step computes the L1 gradient scale * sign(C - target) itself.
+    case the step computes the loss gradient itself: loss="l1" gives
+    scale * sign(C - target); loss="l1_ssim" gives the gradient of 3DGS's
+    per-view (1 - lam) L1 + lam (1 - SSIM) summed over the views (Sec. 3.4
+    "Optimization"), lam = ssim_lambda.
     adam: optional dict (groups, beta1, beta2, eps) -- the update then runs
     inside the graph, reading its bias corrections from a device buffer; its
     groups' "grad" tensors must be the ones in `grads`.
@@ -32,19 +35,28 @@ class CapturedStep:
 
     def __init__(self, rast: Rasterizer, prims: L.Prims, bg=None, grad_rgb: Optional[torch.Tensor] = None,
                  target: Optional[torch.Tensor] = None, l1_scale: Optional[float] = None,
-                 adam: Optional[dict] = None, headroom: float = 1.25, grads: Optional[dict] = None):
+                 adam: Optional[dict] = None, headroom: float = 1.25, grads: Optional[dict] = None,
+                 loss: str = "l1", ssim_lambda: float = L.SSIM_LAMBDA):
         self.rast, self.prims, self.bg = rast, prims, bg
         rast.headroom = max(rast.headroom, headroom)
         rast.preprocess(prims, sync_count=True)          # sizes the pair workspace
         self.outs = rast.alloc_outputs()
         self.grads = grads if grads is not None else rast.alloc_grads(prims)
         self.target = target
+        self.loss_kind = "l1"
         if grad_rgb is None:
             if target is None:
                 raise ValueError("need grad_rgb or target")
+            if loss not in ("l1", "l1_ssim"):
+                raise ValueError(f"unknown loss {loss}")
+            self.loss_kind = loss
+            self.ssim_lambda = float(ssim_lambda)
             self.grad_rgb = torch.empty_like(self.outs[0])
             self.partial = torch.zeros((self.outs[0].numel() + 1023) // 1024, device=self.outs[0].device)
             self.l1_scale = float(l1_scale if l1_scale is not None else 1.0 / self.outs[0].numel())
+            if loss == "l1_ssim":
+                self.loss_ws = torch.empty(L.linprim_loss_workspace_size(rast.cams_c), dtype=torch.uint8,
+                                           device=self.outs[0].device)
         else:
             self.grad_rgb = grad_rgb.contiguous()
         self.adam = adam
@@ -64,7 +76,10 @@ class CapturedStep:
         r.bin_sort(p)
         r.render(p, self.bg, out=self.outs)
         if self.target is not None:
-            L.linprim_l1_grad(rgb, self.target, self.l1_scale, self.grad_rgb, self.partial)
+            if self.loss_kind == "l1_ssim":
+                L.linprim_loss_grad(rgb, self.target, r.cams_c, self.loss_ws, self.grad_rgb, self.ssim_lambda)
+            else:
+                L.linprim_l1_grad(rgb, self.target, self.l1_scale, self.grad_rgb, self.partial)
         L.linprim_raster_bwd(p, r.cams_c, r.tune, self.bg, r.view_ws, r.pair_ws, r.max_pairs, T, last, self.grad_rgb)
         L.linprim_preprocess_bwd(p, r.cams_c, r.tune, r.view_ws, r.pair_ws, r.max_pairs, self.grads)
         if self.adam is not None:
@@ -88,7 +103,9 @@ class CapturedStep:
         self.graph.replay()
 
     def loss(self) -> float:
-        """L1 loss of the last replay (host sync; for logging only)."""
+        """Loss of the last replay (host sync; for logging only)."""
+        if self.loss_kind == "l1_ssim":
+            return L.linprim_loss_value(self.loss_ws, self.rast.cams_c, self.ssim_lambda)
         return float(self.partial.sum().item())
 
     def check(self):

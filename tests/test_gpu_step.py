@@ -165,9 +165,11 @@ def test_graph_replay_matches_eager(torch_cuda, tile):
     assert npx == cap.outs[1].numel()
 
 
-def test_captured_training_step_matches_eager(torch_cuda):
-    """L1 + Adam inside the graph: three replays follow the eager sequence
-    (fwd, L1 gradient, bwd, Adam) step for step, bit for bit."""
+@pytest.mark.parametrize("loss", ["l1", "l1_ssim"])
+def test_captured_training_step_matches_eager(torch_cuda, loss):
+    """Loss gradient + Adam inside the graph: three replays follow the eager
+    sequence (fwd, loss gradient, bwd, Adam) step for step, bit for bit,
+    for the mean L1 and for 3DGS's L1 + SSIM."""
     from paper_2501_16312_amd import linprim as L
     from paper_2501_16312_amd.graph import CapturedStep
     from paper_2501_16312_amd.render import Rasterizer
@@ -201,15 +203,20 @@ def test_captured_training_step_matches_eager(torch_cuda):
     outs = ra.alloc_outputs()
     g_rgb = torch.empty_like(outs[0])
     part = torch.zeros((outs[0].numel() + 1023) // 1024, device="cuda")
+    lws = torch.empty(L.linprim_loss_workspace_size(ra.cams_c), dtype=torch.uint8, device="cuda")
     # captured
     cap = CapturedStep(Rasterizer(sc.kind, sc.n, cams, tile=16), pb, None, target=target, l1_scale=scale,
-                       adam={"groups": groups_b, "beta1": b1, "beta2": b2, "eps": eps}, headroom=1.5, grads=gb)
+                       adam={"groups": groups_b, "beta1": b1, "beta2": b2, "eps": eps}, headroom=1.5, grads=gb,
+                       loss=loss)
     for step in range(1, 4):
         _say(f"captured training step {step}")
         L.linprim_preprocess(pa, ra.cams_c, ra.tune, ra.view_ws)
         ra.bin_sort(pa)
         ra.render(pa, None, out=outs)
-        L.linprim_l1_grad(outs[0], target, scale, g_rgb, part)
+        if loss == "l1_ssim":
+            L.linprim_loss_grad(outs[0], target, ra.cams_c, lws, g_rgb)
+        else:
+            L.linprim_l1_grad(outs[0], target, scale, g_rgb, part)
         L.linprim_raster_bwd(pa, ra.cams_c, ra.tune, None, ra.view_ws, ra.pair_ws, ra.max_pairs, outs[1], outs[2],
                              g_rgb)
         L.linprim_preprocess_bwd(pa, ra.cams_c, ra.tune, ra.view_ws, ra.pair_ws, ra.max_pairs, ga)
@@ -220,7 +227,8 @@ def test_captured_training_step_matches_eager(torch_cuda):
         assert torch.equal(outs[0], cap.outs[0]), f"step {step}: image differs"
         for k in ("means", "quats", "dists", "opacity", "sh"):
             assert torch.equal(getattr(pa, k), getattr(pb, k)), f"step {step}: {k} differs"
-        assert abs(float(part.sum()) - cap.loss()) == 0.0
+        eager_loss = L.linprim_loss_value(lws, ra.cams_c) if loss == "l1_ssim" else float(part.sum())
+        assert eager_loss == cap.loss() and eager_loss > 0
 
 
 def test_graph_replay_new_views(torch_cuda):
