@@ -377,6 +377,40 @@ int linprim_densify_apply(int32_t type, int32_t sh_degree, int64_t n, const linp
                           size_t ws_bytes, const linprim_state *dst, int64_t n_out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * LinPrim-MCMC (Sec. 3.4 "LinPrim-MCMC"): GS-MCMC's relocation and noise
+ * steps for octahedra treated as Gaussians with standard deviations d / 2.6.
+ * Octahedra only (other types: INVALID_ARG).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of the relocation workspace for n primitives. */
+size_t linprim_mcmc_workspace_size(int64_t n);
+
+/* In place on `state` (DEVICE, moments optional): every dead primitive
+ * (opacity <= 0.005) becomes a copy of a live source drawn with probability
+ * proportional to its opacity -- integer weights floor(alpha 2^32), the k-th
+ * dead primitive (index order) taking the first index whose inclusive
+ * weight prefix exceeds floor(total * rand[k] / 2^32), rand DEVICE uint32[n]
+ * from the caller.  A source drawn c times first becomes one of
+ * N = min(c + 1, 51) copies: opacity 1 - (1 - alpha)^(1/N) (clamped to
+ * [0.005, 1 - 2^-23]) and distances times
+ * alpha / sum_{i=1}^{N} sum_{k=0}^{i-1} C(i-1,k) (-1)^k alpha_new^(k+1) / sqrt(k+1).
+ * Moments of sources and relocated primitives are reset to zero.  Nothing
+ * happens if no primitive is alive. */
+int linprim_mcmc_relocate(int32_t type, int32_t sh_degree, int64_t n, const linprim_state *state,
+                          const uint32_t *rand, void *ws, size_t ws_bytes, void *stream);
+
+/* Waits for `stream` and returns the number of dead primitives the last
+ * linprim_mcmc_relocate on ws found (all of them were relocated if any
+ * primitive was alive). */
+int linprim_mcmc_dead_count(const void *ws, size_t ws_bytes, int64_t n, int64_t *n_dead, void *stream);
+
+/* means += noise_lr * lr_means * s(1 - alpha) * R S^2 R^T eps, S = diag(d / 2.6),
+ * s(x) = 1 / (1 + exp(-100 (x - 0.995))), eps = normals (DEVICE float [n][3],
+ * standard normal draws from the caller). */
+int linprim_mcmc_noise(int32_t type, int64_t n, const linprim_state *state, const float *normals, float lr_means,
+                       float noise_lr, void *stream);
+
+/* ------------------------------------------------------------------------
  * Photometric loss of the optimisation (Sec. 3.4 "Optimization": the loss
  * of 3DGS, an L1 and an SSIM term).  Per view, with n = 3 H W,
  *   L_v = (1 - lambda) sum |C - T| / n + lambda (1 - sum s / n),

@@ -28,6 +28,7 @@ SOURCES = {
     "k_optim.hip": [],
     "k_population.hip": [],
     "k_loss.hip": [],
+    "k_mcmc.hip": [],
 }
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",

@@ -412,6 +412,47 @@ int linprim_densify_apply(int32_t type, int32_t sh_degree, int64_t n, const linp
                                            (const int64_t*)ws, state_set(dst), (hipStream_t)stream));
 }
 
+size_t linprim_mcmc_workspace_size(int64_t n) {
+    if (n < 0 || n >= (int64_t(1) << 31)) return 0;
+    return mc_workspace_bytes(n);
+}
+
+int linprim_mcmc_relocate(int32_t type, int32_t sh_degree, int64_t n, const linprim_state* state,
+                          const uint32_t* rand, void* ws, size_t ws_bytes, void* stream) {
+    if (type != LINPRIM_OCTAHEDRON || sh_degree < 0 || sh_degree > 3 || n < 0 || n >= (int64_t(1) << 31) || !ws ||
+        !state_ok(state, n) || (n > 0 && !rand))
+        return LINPRIM_ERR_INVALID_ARG;
+    if (ws_bytes < mc_workspace_bytes(n)) return LINPRIM_ERR_WORKSPACE;
+    if (int rc = check_device()) return rc;
+    return hip_status(launch_mc_relocate(n, sh_degree, state_set(state), rand, (char*)ws, (hipStream_t)stream));
+}
+
+int linprim_mcmc_dead_count(const void* ws, size_t ws_bytes, int64_t n, int64_t* n_dead, void* stream) {
+    if (!ws || !n_dead || n < 0 || n >= (int64_t(1) << 31)) return LINPRIM_ERR_INVALID_ARG;
+    if (ws_bytes < mc_workspace_bytes(n)) return LINPRIM_ERR_WORKSPACE;
+    if (n == 0) {
+        *n_dead = 0;
+        return LINPRIM_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int64_t v = 0;
+    if (hipMemcpyAsync(&v, (const char*)ws + mc_dead_offset(n), 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return LINPRIM_ERR_HIP;
+    *n_dead = v;
+    return LINPRIM_OK;
+}
+
+int linprim_mcmc_noise(int32_t type, int64_t n, const linprim_state* state, const float* normals, float lr_means,
+                       float noise_lr, void* stream) {
+    if (type != LINPRIM_OCTAHEDRON || n < 0 || n >= (int64_t(1) << 31) || !state_ok(state, n) ||
+        (n > 0 && !normals) || !finite_f(lr_means) || !finite_f(noise_lr))
+        return LINPRIM_ERR_INVALID_ARG;
+    if (int rc = check_device()) return rc;
+    return hip_status(launch_mc_noise(n, state->means, state->quats, state->dists, state->opacity, normals,
+                                      (double)noise_lr * (double)lr_means, (hipStream_t)stream));
+}
+
 // Loss workspace: per view, 2 floats per (channel, 32 x 32 tile) block,
 // then 9 floats per pixel of the largest view.
 static size_t loss_partials(const linprim_camera* cams, int32_t n_views) {

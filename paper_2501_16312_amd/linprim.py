@@ -79,7 +79,9 @@ EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linpri
            "linprim_strerror", "linprim_debug_pointers", "linprim_upload_views", "linprim_l1_grad",
            "linprim_adam_step", "linprim_adam_step_dev", "linprim_accumulate_stats",
            "linprim_densify_workspace_size", "linprim_densify_plan", "linprim_densify_apply",
-           "linprim_loss_workspace_size", "linprim_loss_grad", "linprim_loss_value")
+           "linprim_loss_workspace_size", "linprim_loss_grad", "linprim_loss_value",
+           "linprim_mcmc_workspace_size", "linprim_mcmc_relocate", "linprim_mcmc_dead_count",
+           "linprim_mcmc_noise")
 
 _lib = None
 
@@ -130,6 +132,11 @@ def load(path: str = LIB_PATH):
     lib.linprim_densify_workspace_size.argtypes = [I64]
     lib.linprim_densify_plan.argtypes = [I32, I64, P, P, P, P, P, dpp, P, SZ, ctypes.POINTER(I64), P]
     lib.linprim_densify_apply.argtypes = [I32, I32, I64, stp, P, P, P, P, dpp, P, SZ, stp, I64, P]
+    lib.linprim_mcmc_workspace_size.restype = SZ
+    lib.linprim_mcmc_workspace_size.argtypes = [I64]
+    lib.linprim_mcmc_relocate.argtypes = [I32, I32, I64, stp, P, P, SZ, P]
+    lib.linprim_mcmc_dead_count.argtypes = [P, SZ, I64, ctypes.POINTER(I64), P]
+    lib.linprim_mcmc_noise.argtypes = [I32, I64, stp, P, ctypes.c_float, ctypes.c_float, P]
     lib.linprim_loss_workspace_size.restype = SZ
     lib.linprim_loss_workspace_size.argtypes = [cm, I32]
     lib.linprim_loss_grad.argtypes = [P, P, cm, I32, ctypes.c_float, P, SZ, P, P]
@@ -143,7 +150,8 @@ def load(path: str = LIB_PATH):
               lib.linprim_preprocess_bwd, lib.linprim_read_status, lib.linprim_upload_views,
               lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev,
               lib.linprim_debug_pointers, lib.linprim_accumulate_stats, lib.linprim_densify_plan,
-              lib.linprim_densify_apply, lib.linprim_loss_grad, lib.linprim_loss_value):
+              lib.linprim_densify_apply, lib.linprim_loss_grad, lib.linprim_loss_value,
+              lib.linprim_mcmc_relocate, lib.linprim_mcmc_dead_count, lib.linprim_mcmc_noise):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -445,3 +453,28 @@ def linprim_loss_value(ws, cams, lam: float = SSIM_LAMBDA, stream=None) -> float
     _check(load().linprim_loss_value(_ptr(ws), ws.numel(), cams, len(cams), float(lam), ctypes.byref(out),
                                      _stream(stream)), "linprim_loss_value")
     return float(out.value)
+
+
+# ---------------------------------------------------------------------------
+# LinPrim-MCMC population steps.
+# ---------------------------------------------------------------------------
+def linprim_mcmc_workspace_size(n: int) -> int:
+    return int(load().linprim_mcmc_workspace_size(int(n)))
+
+
+def linprim_mcmc_relocate(kind: int, sh_degree: int, n: int, st: linprim_state, rand_u32, ws, stream=None):
+    _check(load().linprim_mcmc_relocate(int(kind), int(sh_degree), int(n), ctypes.byref(st), _ptr(rand_u32),
+                                        _ptr(ws), ws.numel(), _stream(stream)), "linprim_mcmc_relocate")
+
+
+def linprim_mcmc_dead_count(ws, n: int, stream=None) -> int:
+    out = ctypes.c_int64(0)
+    _check(load().linprim_mcmc_dead_count(_ptr(ws), ws.numel(), int(n), ctypes.byref(out), _stream(stream)),
+           "linprim_mcmc_dead_count")
+    return int(out.value)
+
+
+def linprim_mcmc_noise(kind: int, n: int, st: linprim_state, normals, lr_means: float, noise_lr: float = 5e5,
+                       stream=None):
+    _check(load().linprim_mcmc_noise(int(kind), int(n), ctypes.byref(st), _ptr(normals), float(lr_means),
+                                     float(noise_lr), _stream(stream)), "linprim_mcmc_noise")

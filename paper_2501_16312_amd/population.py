@@ -54,3 +54,30 @@ class PopulationControl:
                                 L.state(new, m_new, v_new), n_out)
         self.reset(n_out)
         return new, m_new, v_new
+
+
+class MCMC:
+    """LinPrim-MCMC's population steps (Sec. 3.4): relocation of dead
+    octahedra and the opacity-gated position noise, in place."""
+
+    def __init__(self, n: int, sh_degree: int = 3, device: str = "cuda"):
+        self.n, self.sh_degree = int(n), int(sh_degree)
+        self.device = torch.device(device)
+        self.ws = torch.empty(max(L.linprim_mcmc_workspace_size(self.n), 1), dtype=torch.uint8, device=self.device)
+
+    def relocate(self, params: dict, exp_avg: Optional[dict] = None, exp_avg_sq: Optional[dict] = None,
+                 rand_u32: Optional[torch.Tensor] = None, generator: Optional[torch.Generator] = None) -> None:
+        if rand_u32 is None:
+            r = torch.randint(0, 2 ** 32, (self.n,), generator=generator, dtype=torch.int64, device=self.device)
+            rand_u32 = r.to(torch.int32)                 # same 32 bits
+        L.linprim_mcmc_relocate(L.OCTAHEDRON, self.sh_degree, self.n, L.state(params, exp_avg, exp_avg_sq),
+                                rand_u32, self.ws)
+
+    def dead_count(self) -> int:
+        return L.linprim_mcmc_dead_count(self.ws, self.n)
+
+    def noise(self, params: dict, lr_means: float, noise_lr: float = 5e5, normals: Optional[torch.Tensor] = None,
+              generator: Optional[torch.Generator] = None) -> None:
+        if normals is None:
+            normals = torch.randn((self.n, 3), generator=generator, dtype=torch.float32, device=self.device)
+        L.linprim_mcmc_noise(L.OCTAHEDRON, self.n, L.state(params), normals.contiguous(), lr_means, noise_lr)
