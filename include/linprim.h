@@ -399,6 +399,15 @@ size_t linprim_mcmc_workspace_size(int64_t n);
 int linprim_mcmc_relocate(int32_t type, int32_t sh_degree, int64_t n, const linprim_state *state,
                           const uint32_t *rand, void *ws, size_t ws_bytes, void *stream);
 
+/* GS-MCMC's growth step: draws n_add sources (n_add <= n) among the first
+ * n rows of `state` exactly as linprim_mcmc_relocate draws them (rand
+ * DEVICE uint32[n_add]), applies the same source update, and writes the
+ * copies to rows n .. n + n_add - 1 (the arrays must hold n + n_add rows;
+ * the caller copies the first n).  The caller picks n_add (GS-MCMC: grow by
+ * 5% per step up to a cap).  ws: linprim_mcmc_workspace_size(n). */
+int linprim_mcmc_add(int32_t type, int32_t sh_degree, int64_t n, int64_t n_add, const linprim_state *state,
+                     const uint32_t *rand, void *ws, size_t ws_bytes, void *stream);
+
 /* Waits for `stream` and returns the number of dead primitives the last
  * linprim_mcmc_relocate on ws found (all of them were relocated if any
  * primitive was alive). */

@@ -94,6 +94,33 @@ def relocate(params: dict, moments: dict, r_u32):
     return p, m, len(dead)
 
 
+def add(params: dict, moments: dict, n_add: int, r_u32):
+    """GS-MCMC's growth step: n_add sources drawn as in relocate (among all
+    current rows), the same source update, copies appended.  Returns float64
+    (params, moments) with n + n_add rows."""
+    p = {k: np.array(v, np.float64) for k, v in params.items()}
+    m = {k: np.array(v, np.float64) for k, v in moments.items()}
+    op32 = np.asarray(params["opacity"], np.float32)
+    w = weights(op32)
+    if n_add == 0 or w.sum() == 0:
+        return p, m
+    src = sample(w, np.asarray(r_u32)[:n_add])
+    counts = np.bincount(src, minlength=len(op32))
+    for s in np.nonzero(counts)[0]:
+        nn = min(int(counts[s]) + 1, N_MAX)
+        a = float(op32[s])
+        a_new = min(max(1.0 - (1.0 - a) ** (1.0 / nn), MIN_OPACITY), 1.0 - 2.0 ** -23)
+        p["dists"][s] = p["dists"][s] * relocation_scale(a, a_new, nn)
+        p["opacity"][s] = a_new
+        for key in m:
+            m[key][s] = 0.0
+    for k in p:
+        p[k] = np.concatenate([p[k], p[k][src]])
+    for key in m:
+        m[key] = np.concatenate([m[key], np.zeros((n_add,) + m[key].shape[1:])])
+    return p, m
+
+
 def quat_matrix(q):
     w, x, y, z = np.asarray(q, np.float64) / np.linalg.norm(np.asarray(q, np.float64))
     return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],

@@ -424,7 +424,18 @@ int linprim_mcmc_relocate(int32_t type, int32_t sh_degree, int64_t n, const linp
         return LINPRIM_ERR_INVALID_ARG;
     if (ws_bytes < mc_workspace_bytes(n)) return LINPRIM_ERR_WORKSPACE;
     if (int rc = check_device()) return rc;
-    return hip_status(launch_mc_relocate(n, sh_degree, state_set(state), rand, (char*)ws, (hipStream_t)stream));
+    return hip_status(launch_mc_relocate(n, -1, sh_degree, state_set(state), rand, (char*)ws, (hipStream_t)stream));
+}
+
+int linprim_mcmc_add(int32_t type, int32_t sh_degree, int64_t n, int64_t n_add, const linprim_state* state,
+                     const uint32_t* rand, void* ws, size_t ws_bytes, void* stream) {
+    if (type != LINPRIM_OCTAHEDRON || sh_degree < 0 || sh_degree > 3 || n < 0 || n_add < 0 || n_add > n ||
+        n + n_add >= (int64_t(1) << 31) || !ws || !state_ok(state, n + n_add) || (n_add > 0 && !rand))
+        return LINPRIM_ERR_INVALID_ARG;
+    if (ws_bytes < mc_workspace_bytes(n)) return LINPRIM_ERR_WORKSPACE;
+    if (int rc = check_device()) return rc;
+    return hip_status(launch_mc_relocate(n, n_add, sh_degree, state_set(state), rand, (char*)ws,
+                                         (hipStream_t)stream));
 }
 
 int linprim_mcmc_dead_count(const void* ws, size_t ws_bytes, int64_t n, int64_t* n_dead, void* stream) {

@@ -152,14 +152,16 @@ __global__ __launch_bounds__(256) void k_mc_prefix(int64_t n, const float* __res
     }
 }
 
+// n_draws >= 0: that many draws (adding primitives); otherwise one per dead
+// primitive (the device count).
 __global__ __launch_bounds__(256) void k_mc_sample(int64_t n, const uint64_t* __restrict__ prefix,
                                                    const uint64_t* __restrict__ wtotal,
-                                                   const int64_t* __restrict__ dtotal,
+                                                   const int64_t* __restrict__ dtotal, int64_t n_draws,
                                                    const uint32_t* __restrict__ rnd, int32_t* __restrict__ samples,
                                                    int32_t* __restrict__ counts) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t total = *wtotal;
-    if (k >= *dtotal || total == 0) return;
+    if (k >= (n_draws >= 0 ? n_draws : *dtotal) || total == 0) return;
     // floor(total r / 2^32), exactly
     const uint64_t r = rnd[k];
     const uint64_t t = (total >> 32) * r + (((total & 0xffffffffull) * r) >> 32);
@@ -209,13 +211,16 @@ __global__ __launch_bounds__(256) void k_mc_sources(int64_t n, StateSet S, int s
     zero_moments(S, width, i);
 }
 
+// Draw k's target: the k-th dead primitive, or row append_base + k when
+// adding (n_draws >= 0).
 __global__ __launch_bounds__(256) void k_mc_copy(StateSet S, int sh_floats, const int64_t* __restrict__ dtotal,
+                                                 int64_t n_draws, int64_t append_base,
                                                  const uint64_t* __restrict__ wtotal,
                                                  const int32_t* __restrict__ dead_list,
                                                  const int32_t* __restrict__ samples) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= *dtotal || *wtotal == 0) return;
-    const int64_t j = dead_list[k], s = samples[k];
+    if (k >= (n_draws >= 0 ? n_draws : *dtotal) || *wtotal == 0) return;
+    const int64_t j = n_draws >= 0 ? append_base + k : (int64_t)dead_list[k], s = samples[k];
     const int width[5] = {3, 4, 3, 1, sh_floats};
 #pragma unroll
     for (int f = 0; f < 5; ++f)
@@ -248,6 +253,7 @@ __global__ __launch_bounds__(256) void k_mc_noise(int64_t n, float* __restrict__
 }
 
 // Workspace: prefix [n] u64 | wsum [nb+1] u64 | dsum [nb+1] i64 | dead [n] i32 | samples [n] i32 | counts [n] i32
+// (draws when adding are at most n: the workspace of n serves both steps).
 struct McLayout {
     size_t prefix, wsum, dsum, dead, samples, counts, total;
 };
@@ -268,9 +274,11 @@ McLayout mc_layout(int64_t n) {
 
 size_t mc_workspace_bytes(int64_t n) { return mc_layout(n).total; }
 
-hipError_t launch_mc_relocate(int64_t n, int sh_degree, const StateSet& S, const uint32_t* rnd, char* ws,
-                              hipStream_t s) {
-    if (n == 0) return hipSuccess;
+// n_add < 0: relocate the dead in place; n_add >= 0: draw n_add sources
+// among the first n rows and write their copies to rows n .. n + n_add - 1.
+hipError_t launch_mc_relocate(int64_t n, int64_t n_add, int sh_degree, const StateSet& S, const uint32_t* rnd,
+                              char* ws, hipStream_t s) {
+    if (n == 0 || n_add == 0) return hipSuccess;
     const McLayout L = mc_layout(n);
     const int64_t nb = (n + kMcItems - 1) / kMcItems;
     uint64_t* prefix = (uint64_t*)(ws + L.prefix);
@@ -284,9 +292,12 @@ hipError_t launch_mc_relocate(int64_t n, int sh_degree, const StateSet& S, const
     hipLaunchKernelGGL(k_mc_count, dim3((unsigned)nb), dim3(256), 0, s, n, S.p[3], wsum, dsum);
     hipLaunchKernelGGL(k_mc_scan, dim3(1), dim3(1024), 0, s, wsum, dsum, nb);
     hipLaunchKernelGGL(k_mc_prefix, dim3((unsigned)nb), dim3(256), 0, s, n, S.p[3], wsum, dsum, prefix, dead, counts);
-    hipLaunchKernelGGL(k_mc_sample, dim3(g1), dim3(256), 0, s, n, prefix, wsum + nb, dsum + nb, rnd, samples, counts);
+    const int64_t draws_max = n_add >= 0 ? n_add : n;
+    const unsigned gd = (unsigned)((draws_max + 255) / 256);
+    hipLaunchKernelGGL(k_mc_sample, dim3(gd), dim3(256), 0, s, n, prefix, wsum + nb, dsum + nb, n_add, rnd, samples,
+                       counts);
     hipLaunchKernelGGL(k_mc_sources, dim3(g1), dim3(256), 0, s, n, S, shf, counts);
-    hipLaunchKernelGGL(k_mc_copy, dim3(g1), dim3(256), 0, s, S, shf, dsum + nb, wsum + nb, dead, samples);
+    hipLaunchKernelGGL(k_mc_copy, dim3(gd), dim3(256), 0, s, S, shf, dsum + nb, n_add, n, wsum + nb, dead, samples);
     return hipGetLastError();
 }
 

@@ -180,8 +180,8 @@ hipError_t launch_densify_apply(int type, int sh_degree, int64_t n, const StateS
 // LinPrim-MCMC population steps (Sec. 3.4), octahedra.
 size_t mc_workspace_bytes(int64_t n);
 int64_t mc_dead_offset(int64_t n);
-hipError_t launch_mc_relocate(int64_t n, int sh_degree, const StateSet& S, const uint32_t* rnd, char* ws,
-                              hipStream_t s);
+hipError_t launch_mc_relocate(int64_t n, int64_t n_add, int sh_degree, const StateSet& S, const uint32_t* rnd,
+                              char* ws, hipStream_t s);
 hipError_t launch_mc_noise(int64_t n, float* means, const float* quats, const float* dists, const float* opacity,
                            const float* eps, double scale, hipStream_t s);
 

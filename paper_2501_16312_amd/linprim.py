@@ -81,7 +81,7 @@ EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linpri
            "linprim_densify_workspace_size", "linprim_densify_plan", "linprim_densify_apply",
            "linprim_loss_workspace_size", "linprim_loss_grad", "linprim_loss_value",
            "linprim_mcmc_workspace_size", "linprim_mcmc_relocate", "linprim_mcmc_dead_count",
-           "linprim_mcmc_noise")
+           "linprim_mcmc_noise", "linprim_mcmc_add")
 
 _lib = None
 
@@ -136,6 +136,7 @@ def load(path: str = LIB_PATH):
     lib.linprim_mcmc_workspace_size.argtypes = [I64]
     lib.linprim_mcmc_relocate.argtypes = [I32, I32, I64, stp, P, P, SZ, P]
     lib.linprim_mcmc_dead_count.argtypes = [P, SZ, I64, ctypes.POINTER(I64), P]
+    lib.linprim_mcmc_add.argtypes = [I32, I32, I64, I64, stp, P, P, SZ, P]
     lib.linprim_mcmc_noise.argtypes = [I32, I64, stp, P, ctypes.c_float, ctypes.c_float, P]
     lib.linprim_loss_workspace_size.restype = SZ
     lib.linprim_loss_workspace_size.argtypes = [cm, I32]
@@ -151,7 +152,8 @@ def load(path: str = LIB_PATH):
               lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev,
               lib.linprim_debug_pointers, lib.linprim_accumulate_stats, lib.linprim_densify_plan,
               lib.linprim_densify_apply, lib.linprim_loss_grad, lib.linprim_loss_value,
-              lib.linprim_mcmc_relocate, lib.linprim_mcmc_dead_count, lib.linprim_mcmc_noise):
+              lib.linprim_mcmc_relocate, lib.linprim_mcmc_dead_count, lib.linprim_mcmc_noise,
+              lib.linprim_mcmc_add):
         f.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -465,6 +467,11 @@ def linprim_mcmc_workspace_size(n: int) -> int:
 def linprim_mcmc_relocate(kind: int, sh_degree: int, n: int, st: linprim_state, rand_u32, ws, stream=None):
     _check(load().linprim_mcmc_relocate(int(kind), int(sh_degree), int(n), ctypes.byref(st), _ptr(rand_u32),
                                         _ptr(ws), ws.numel(), _stream(stream)), "linprim_mcmc_relocate")
+
+
+def linprim_mcmc_add(kind: int, sh_degree: int, n: int, n_add: int, st: linprim_state, rand_u32, ws, stream=None):
+    _check(load().linprim_mcmc_add(int(kind), int(sh_degree), int(n), int(n_add), ctypes.byref(st), _ptr(rand_u32),
+                                   _ptr(ws), ws.numel(), _stream(stream)), "linprim_mcmc_add")
 
 
 def linprim_mcmc_dead_count(ws, n: int, stream=None) -> int:

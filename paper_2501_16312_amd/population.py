@@ -73,6 +73,26 @@ class MCMC:
         L.linprim_mcmc_relocate(L.OCTAHEDRON, self.sh_degree, self.n, L.state(params, exp_avg, exp_avg_sq),
                                 rand_u32, self.ws)
 
+    def add(self, params: dict, n_add: int, exp_avg: Optional[dict] = None, exp_avg_sq: Optional[dict] = None,
+            rand_u32: Optional[torch.Tensor] = None, generator: Optional[torch.Generator] = None):
+        """Returns new (params, exp_avg, exp_avg_sq) with n_add more rows,
+        copies of sources drawn by opacity (GS-MCMC's growth step)."""
+        n_add = int(min(max(n_add, 0), self.n))
+        grow = lambda t: torch.cat([t, torch.empty((n_add,) + tuple(t.shape[1:]), dtype=t.dtype,
+                                                   device=t.device)]) if t is not None else None
+        newp = {k: grow(v) for k, v in params.items()}
+        newm = {k: grow(v) for k, v in exp_avg.items()} if exp_avg is not None else None
+        newv = {k: grow(v) for k, v in exp_avg_sq.items()} if exp_avg_sq is not None else None
+        if rand_u32 is None:
+            r = torch.randint(0, 2 ** 32, (max(n_add, 1),), generator=generator, dtype=torch.int64,
+                              device=self.device)
+            rand_u32 = r.to(torch.int32)
+        L.linprim_mcmc_add(L.OCTAHEDRON, self.sh_degree, self.n, n_add, L.state(newp, newm, newv), rand_u32,
+                           self.ws)
+        self.n += n_add
+        self.ws = torch.empty(max(L.linprim_mcmc_workspace_size(self.n), 1), dtype=torch.uint8, device=self.device)
+        return newp, newm, newv
+
     def dead_count(self) -> int:
         return L.linprim_mcmc_dead_count(self.ws, self.n)
 

@@ -96,3 +96,25 @@ def test_tetrahedra_rejected():
     ws = torch.empty(L.linprim_mcmc_workspace_size(1), dtype=torch.uint8, device="cuda")
     with pytest.raises(L.LinPrimError):
         L.linprim_mcmc_relocate(L.TETRAHEDRON, 3, 1, st, torch.zeros(1, dtype=torch.int32, device="cuda"), ws)
+
+
+def test_add_parity():
+    _say("mcmc add")
+    n, n_add = 8000, 400
+    params, moments, r = _state(n, seed=21)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a), device="cuda")
+    P = {k: dev(params[k]) for k in FIELDS}
+    M = {k: dev(moments[("m", k)]) for k in FIELDS}
+    V = {k: dev(moments[("v", k)]) for k in FIELDS}
+    mc = MCMC(n)
+    newp, newm, newv = mc.add(P, n_add, M, V, rand_u32=dev(r[:n_add].view(np.int32)))
+    torch.cuda.synchronize()
+    op, om = MC.add(params, moments, n_add, r[:n_add])
+    assert mc.n == n + n_add and newp["means"].shape[0] == n + n_add
+    for k in ("means", "quats", "sh"):
+        assert np.array_equal(newp[k].cpu().numpy().astype(np.float64), op[k]), k
+    for k in ("dists", "opacity"):
+        np.testing.assert_allclose(newp[k].cpu().numpy(), op[k], rtol=1e-6, err_msg=k)
+    for k in FIELDS:
+        assert np.array_equal(newm[k].cpu().numpy().astype(np.float64), om[("m", k)]), k
+        assert np.array_equal(newv[k].cpu().numpy().astype(np.float64), om[("v", k)]), k

@@ -100,3 +100,24 @@ def test_noise_closed_form():
     gate = 1.0 / (1.0 + math.exp(-100.0 * ((1.0 - float(np.float32(0.002))) - 0.995)))
     ref = 5e5 * 1e-4 * gate * (np.array([1.0, 2.0, 3.0]) / 2.6) ** 2 * eps[1]
     np.testing.assert_allclose(mu[1], ref, rtol=1e-12)
+
+
+def test_growth_step_appends_updated_sources():
+    op = np.array([0.4, 0.001, 0.8], np.float32)
+    n = len(op)
+    params = {"means": np.arange(n * 3, dtype=np.float32).reshape(n, 3),
+              "quats": np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)),
+              "dists": np.full((n, 3), 0.2, np.float32), "opacity": op}
+    moments = {("m", k): np.ones_like(v) for k, v in params.items()}
+    w = MC.weights(op)
+    r_last = 2 ** 32 - 1                        # the last live primitive (2)
+    p, m = MC.add(params, moments, 2, [r_last, 0])  # draws: primitive 2, then primitive 0
+    assert p["means"].shape[0] == 5
+    assert list(np.nonzero(w)[0]) == [0, 2]
+    for row, s in ((3, 2), (4, 0)):
+        for k in params:
+            np.testing.assert_array_equal(p[k][row], p[k][s])
+    a0 = 1.0 - (1.0 - float(op[0])) ** 0.5       # each source drawn once: one of 2 copies
+    assert abs(p["opacity"][0] - a0) < 1e-15 and p["opacity"][1] == float(op[1])
+    for key in m:
+        assert np.all(m[key][[0, 2, 3, 4]] == 0) and np.all(m[key][1] == 1)
