@@ -237,7 +237,10 @@ __device__ inline float ray_norm(const ViewInfo& V, int x, int y) {
 }
 
 // ---------------------------------------------------------------------------
-// Wave placement: wave w handles group q = w % NQ of global tile g = w / NQ.
+// Wave placement: wave w (XCD-chunked) handles group q = w % NQ of the tile at
+// position w / NQ of the render order (heavy tiles first, then the others,
+// each part in tile order, so that consecutive positions are mostly
+// neighbouring tiles).
 // ---------------------------------------------------------------------------
 struct Place {
     int v, tx, ty, gx0, gy0, W, H, q;
@@ -245,11 +248,11 @@ struct Place {
 };
 
 template <int TILE>
-__device__ inline Place place_wave(const ViewInfo* __restrict__ views, int n_views) {
+__device__ inline Place place_wave(const ViewInfo* __restrict__ views, int n_views, const uint32_t* __restrict__ order) {
     constexpr int QX = TILE / 8, NQ = QX * QX;
     const int64_t w = xcd_tile(blockIdx.x, gridDim.x);
     Place P;
-    P.g = w / NQ;
+    P.g = order[w / NQ];
     P.q = (int)(w % NQ);
     P.v = find_view(views, n_views, P.g);
     P.W = views[P.v].width;
@@ -319,10 +322,10 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
                                                    int32_t* __restrict__ out_last,
                                                    unsigned long long* __restrict__ counters,
                                                    const uint32_t* __restrict__ depth_keys,
-                                                   float* __restrict__ out_depth) {
+                                                   float* __restrict__ out_depth, const uint32_t* __restrict__ order) {
     if (status->n_pairs > capacity) return;
     constexpr int QX = TILE / 8, NQ = QX * QX;
-    const Place P = place_wave<TILE>(views, n_views);
+    const Place P = place_wave<TILE>(views, n_views, order);
     if (P.gx0 >= P.W || P.gy0 >= P.H) return;
     const int lane = threadIdx.x;
     const int x = P.gx0 + (lane & 7), y = P.gy0 + (lane >> 3);
@@ -462,11 +465,12 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
                                                    const Status* __restrict__ status, uint64_t capacity, float bg0,
                                                    float bg1, float bg2, const float* __restrict__ out_T,
                                                    const int32_t* __restrict__ out_last,
-                                                   const float* __restrict__ grad_rgb, float* __restrict__ grads) {
+                                                   const float* __restrict__ grad_rgb, float* __restrict__ grads,
+                                                   const uint32_t* __restrict__ order) {
     if (status->n_pairs > capacity) return;
     constexpr int QX = TILE / 8, NQ = QX * QX;
     constexpr int SHIFT = (TILE == 8) ? 3 : (TILE == 16) ? 4 : 5;
-    const Place P = place_wave<TILE>(views, n_views);
+    const Place P = place_wave<TILE>(views, n_views, order);
     if (P.gx0 >= P.W || P.gy0 >= P.H) return;
     const int lane = threadIdx.x;
     const int x = P.gx0 + (lane & 7), y = P.gy0 + (lane >> 3);
@@ -693,11 +697,11 @@ template <int TILE, int KIND, bool EXACT>
 static void fwd_dispatch(bool count, const ViewLayout& Lv, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
                          const float* payload, const uint32_t* vals, const uint2* ranges, const Status* st,
                          uint64_t cap, const float bg[3], float* rgb, float* T, int32_t* last,
-                         unsigned long long* counters, const uint32_t* keys, float* depth) {
+                         unsigned long long* counters, const uint32_t* keys, float* depth, const uint32_t* order) {
     const dim3 grid = wave_grid<TILE>(Lv);
 #define LP_K(C_, D_)                                                                                              \
     hipLaunchKernelGGL((k_render_fwd<TILE, KIND, C_, EXACT, D_>), grid, dim3(64), 0, s, views, nv, n, payload, vals, \
-                       ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters, keys, depth)
+                       ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters, keys, depth, order)
     if (depth) {
         if (count) LP_K(true, true); else LP_K(false, true);
     } else {
@@ -717,10 +721,11 @@ hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const Pair
     const uint2* ranges = reinterpret_cast<const uint2*>(vws + L.ranges);
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
     const uint32_t* keys = reinterpret_cast<const uint32_t*>(vws + L.depth_keys);
+    const uint32_t* order = reinterpret_cast<const uint32_t*>(vws + L.order);
     const uint64_t cap = (uint64_t)P.capacity;
     const bool count = counters != nullptr;
 #define LP_FWD(T_, K_, E_) fwd_dispatch<T_, K_, E_>(count, L, stream, views, n_views, L.n, payload, vals, ranges, st, \
-                                                    cap, bg, out_rgb, out_T, out_last, counters, keys, out_depth)
+                                                    cap, bg, out_rgb, out_T, out_last, counters, keys, out_depth, order)
 #define LP_FWD_T(K_, E_)                                                       \
     do {                                                                       \
         if (tile == 8) LP_FWD(8, K_, E_);                                      \
@@ -748,9 +753,9 @@ template <int TILE, int KIND, bool EXACT>
 static void bwd_dispatch(const ViewLayout& Lv, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
                          const float* payload, const uint32_t* vals, const uint2* ranges, const uint32_t* offsets,
                          const Status* st, uint64_t cap, const float bg[3], const float* T, const int32_t* last,
-                         const float* grad, float* grads) {
+                         const float* grad, float* grads, const uint32_t* order) {
     hipLaunchKernelGGL((k_render_bwd<TILE, KIND, EXACT>), wave_grid<TILE>(Lv), dim3(64), 0, s, views, nv, n, payload,
-                       vals, ranges, offsets, st, cap, bg[0], bg[1], bg[2], T, last, grad, grads);
+                       vals, ranges, offsets, st, cap, bg[0], bg[1], bg[2], T, last, grad, grads, order);
 }
 
 hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLayout& P, char* pws, int result_in_b,
@@ -764,9 +769,10 @@ hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLay
     const uint32_t* offsets = reinterpret_cast<const uint32_t*>(vws + L.offsets);
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
     float* grads = reinterpret_cast<float*>(pws + P.grads);
+    const uint32_t* order = reinterpret_cast<const uint32_t*>(vws + L.order);
     const uint64_t cap = (uint64_t)P.capacity;
 #define LP_BWD(T_, K_, E_) bwd_dispatch<T_, K_, E_>(L, stream, views, n_views, L.n, payload, vals, ranges, offsets, \
-                                                    st, cap, bg, out_T, out_last, grad_rgb, grads)
+                                                    st, cap, bg, out_T, out_last, grad_rgb, grads, order)
 #define LP_BWD_T(K_, E_)                                                       \
     do {                                                                       \
         if (tile == 8) LP_BWD(8, K_, E_);                                      \

@@ -452,6 +452,83 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
     if (i == (int64_t)np - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[tile].y = (uint32_t)(i + 1);
 }
 
+// Render order (heavy tiles first).  k_order_count: heavy tiles per block of
+// kScanItems tiles.  k_order_write: tile g goes to position (heavy tiles
+// before g) if heavy, else H + (light tiles before g), H the heavy total.
+__device__ inline bool heavy_tile(const uint2* __restrict__ ranges, int64_t g, int64_t n_tiles) {
+    if (g >= n_tiles) return false;
+    const uint2 rg = ranges[g];
+    return rg.y - rg.x > (uint32_t)kHeavyList;
+}
+
+__global__ __launch_bounds__(256) void k_order_count(const uint2* __restrict__ ranges, int64_t n_tiles,
+                                                     const Status* __restrict__ status, uint64_t capacity,
+                                                     uint32_t* __restrict__ sums) {
+    __shared__ uint32_t part[4];
+    if (status->n_pairs > capacity) return;
+    const int64_t base = (int64_t)blockIdx.x * kScanItems;
+    uint32_t c = 0;
+    for (int k = 0; k < kScanItems / 256; ++k) c += heavy_tile(ranges, base + k * 256 + threadIdx.x, n_tiles) ? 1u : 0u;
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) sums[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+__global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ ranges, int64_t n_tiles,
+                                                     const Status* __restrict__ status, uint64_t capacity,
+                                                     const uint32_t* __restrict__ sums, int64_t nblocks,
+                                                     uint32_t* __restrict__ order) {
+    __shared__ uint32_t red[2][4];
+    __shared__ uint32_t wsum[4];
+    if (status->n_pairs > capacity) return;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    // heavy tiles before this block, and in all
+    uint32_t before = 0, total = 0;
+    for (int64_t b = t; b < nblocks; b += 256) {
+        const uint32_t x = sums[b];
+        total += x;
+        if (b < (int64_t)blockIdx.x) before += x;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        before += __shfl_xor(before, off, 64);
+        total += __shfl_xor(total, off, 64);
+    }
+    if (lane == 0) {
+        red[0][wave] = before;
+        red[1][wave] = total;
+    }
+    // thread t handles the 16 consecutive tiles base + 16 t .. 16 t + 15
+    const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)t * 16;
+    uint32_t flags = 0, c = 0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        if (heavy_tile(ranges, base + k, n_tiles)) {
+            flags |= 1u << k;
+            ++c;
+        }
+    uint32_t incl = c;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    const uint32_t H = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    uint32_t hrun = red[0][0] + red[0][1] + red[0][2] + red[0][3] + incl - c;
+    for (int w = 0; w < wave; ++w) hrun += wsum[w];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int64_t g = base + k;
+        if (g >= n_tiles) break;
+        if (flags & (1u << k)) {
+            order[hrun++] = (uint32_t)g;
+        } else {
+            order[(int64_t)H + g - hrun] = (uint32_t)g;
+        }
+    }
+}
+
 // Passes over the tile bits alone (per-tile sort): at most 8 bits each,
 // spread evenly.
 inline void tile_passes(int tile_bits, int* passes, int* digit) {
@@ -525,6 +602,14 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
     if (P.capacity > 0)
         hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((P.capacity + 255) / 256)), dim3(256), 0, stream, kin, status,
                            cap, ranges);
+    {
+        uint32_t* order = reinterpret_cast<uint32_t*>(vws + L.order);
+        uint32_t* osums = reinterpret_cast<uint32_t*>(vws + L.order_sums);
+        const int64_t ob = (nt + kScanItems - 1) / kScanItems;
+        hipLaunchKernelGGL(k_order_count, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums);
+        hipLaunchKernelGGL(k_order_write, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums, ob,
+                           order);
+    }
     if (!radix) {
         // per-list sort from (kin, vin) into (kout, vout)
         hipLaunchKernelGGL(k_sort_short_lists, dim3((unsigned)nt), dim3(64), 0, stream, ranges, nt, status, cap, kin,

@@ -85,7 +85,8 @@ struct Status {
 
 // Offsets into the view workspace (all 256-byte aligned).
 struct ViewLayout {
-    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, vis, stats, total;
+    size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, vis, stats, order,
+        order_sums, total;
     int64_t n, n_views, n_tiles_total, scan_blocks;
 };
 
@@ -119,6 +120,11 @@ hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stre
 // is listed by the scan; its records are summed by kBigChunks waves, each
 // writing its partial sum over the chunk into the chunk's first record.
 constexpr int kBigRun = 64;
+
+// The render kernels take the tiles in the order written by bin_sort: the
+// tiles whose list holds more than kHeavyList pairs first, so that the
+// longest walks do not start last, then the others; each part in tile order.
+constexpr int kHeavyList = 48;
 constexpr int kBigChunks = 16;
 __host__ __device__ inline int big_chunk_start(int c, int nrec) {
     return (int)(((int64_t)c * nrec) / kBigChunks);

@@ -93,9 +93,10 @@ def test_sort_digit_widths(oracle_mod, digit):
 
 @pytest.mark.parametrize("n", [300, 3000, 9500])
 def test_sort_long_lists(oracle_mod, n):
-    """Tile lists of a few hundred (sorted in LDS) and of more than 4096
-    pairs (LDS-sorted chunks, then merged): large primitives seen at close
-    range on a small image with 32-pixel tiles, two views of uneven size."""
+    """Tile lists of a few hundred (ranked by one wave), of a few thousand
+    (sorted in LDS) and of more than 4096 pairs (LDS-sorted chunks, then
+    merged): large primitives seen at close range on a small image with
+    32-pixel tiles, two views of uneven size."""
     _say(f"sort long lists n={n}")
     sc = scenes.uniform_octahedra(n, seed=n, box=0.6, dmin=0.3, dmax=0.6)
     cams = [scenes.look_at((0.1, 0.2, -3.0), (0, 0, 0), 70, 50), scenes.look_at((2.5, 0.3, 1.5), (0, 0, 0), 40, 33)]
@@ -231,6 +232,40 @@ def test_backward_tile_sizes_agree(oracle_mod):
         scale = np.abs(res[0][k]).max() + 1e-12
         assert np.abs(res[0][k] - res[1][k]).max() <= 1e-4 * scale
         assert np.abs(res[0][k] - res[2][k]).max() <= 1e-4 * scale
+
+
+@pytest.mark.parametrize("opaque,tile", [(1.0, 8), (0.3, 16)])
+def test_backward_long_lists(oracle_mod, opaque, tile):
+    """Dense scene whose tiles hold several hundred pairs (rendered first, as
+    heavy tiles).  With opaque primitives the walks stop mid-list and the
+    entries behind get zero records; with mostly faint ones they run through
+    whole lists."""
+    _say(f"backward long lists opaque={opaque} tile={tile}")
+    sc = scenes.uniform_octahedra(3000, seed=41, box=0.8, dmin=0.1, dmax=0.25)
+    rng = np.random.default_rng(5)
+    faint = rng.uniform(size=sc.n) > opaque
+    sc.opacity[faint] = (0.02 * (0.5 + rng.uniform(size=int(faint.sum())))).astype(sc.opacity.dtype)
+    cams = [scenes.look_at((0.1, 0.2, -3.0), (0, 0, 0), 72, 52)]
+    bg = (0.2, 0.3, 0.1)
+    grad = scenes.image_gradient(cams, seed=12)
+    g = GC.gpu_forward(sc, cams, tile=tile, bg=bg)
+    O, r = _oracle_render(oracle_mod, sc, cams, tile, bg)
+    good, _, _ = GC.compare_images(g, r, f"long lists opaque={opaque}")
+    assert good <= GC.IMG_TOL
+    lens = O.sort()["ranges"]
+    lens = lens[:, 1] - lens[:, 0]
+    _say(f"  longest list {lens.max()}, lists over 256: {(lens > 256).sum()}")
+    assert lens.max() > 256
+    gg = GC.gpu_backward(g, grad, bg)
+    rb = O.backward(grad.astype(np.float64), bg=np.asarray(bg))
+    ok = ~rb["ill"]
+    _say(f"  prims ill {rb['ill'].mean() * 100:.2f}%")
+    # a primitive seen by any ill-conditioned pixel is left out; in a dense
+    # scene that is most of them, still leaving hundreds
+    assert ok.sum() >= 300
+    w = GC.grad_errors(gg, rb, ok, f"long lists opaque={opaque}")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k
 
 
 # ------------------------------------------------------------ edge cases
