@@ -314,6 +314,7 @@ __global__ __launch_bounds__(256) void k_scan_totals(uint64_t* __restrict__ bloc
         status->n_pairs = carry;
         status->overflow = 0;
         status->n_big = 0;
+        status->n_huge = 0;
         status->n_vis = (uint32_t)vcarry;
     }
 }
@@ -333,13 +334,14 @@ __device__ inline void wave_append(bool take, uint32_t value, uint32_t* __restri
 
 // Also lists, in slot order, the slots that touch a tile (for the
 // preprocessing backward), and, in no particular order, those with more than
-// kBigRun gradient records (tile count x groups per tile).
+// kBigRun gradient records (tile count x groups per tile) and those with
+// more than kHugeRun tiles.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t count,
                                                     const uint64_t* __restrict__ block_sums,
                                                     const uint64_t* __restrict__ vis_sums,
                                                     uint32_t* __restrict__ out, int nq,
                                                     Status* __restrict__ status, uint32_t* __restrict__ big,
-                                                    uint32_t* __restrict__ vis) {
+                                                    uint32_t* __restrict__ vis, uint32_t* __restrict__ huge) {
     __shared__ uint64_t lds[256];
     // thread t handles the 16 consecutive elements base + 16 t .. 16 t + 15
     const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * 16;
@@ -362,6 +364,7 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
         run += v[k];
         if (v[k]) vis[vrun++] = (uint32_t)idx;
         wave_append((int64_t)v[k] * nq > kBigRun, (uint32_t)idx, &status->n_big, big, lane, lt_mask);
+        wave_append(v[k] > (uint32_t)kHugeRun, (uint32_t)idx, &status->n_huge, huge, lane, lt_mask);
     }
 }
 
@@ -380,7 +383,8 @@ hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stre
     hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(256), 0, stream, bsums, vsums, nb, status);
     if (nb > 0)
         hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums,
-                           offsets, nq, status, big, reinterpret_cast<uint32_t*>(ws + L.vis));
+                           offsets, nq, status, big, reinterpret_cast<uint32_t*>(ws + L.vis),
+                           reinterpret_cast<uint32_t*>(ws + L.huge));
     return hipGetLastError();
 }
 

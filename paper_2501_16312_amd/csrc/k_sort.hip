@@ -19,50 +19,76 @@ __device__ inline void emit_pair(uint64_t g, uint32_t depth, uint32_t prim, uint
 }
 
 // One thread per (view, primitive) slot that touches a tile (from the
-// scan's list, in slot order); one (key, value) pair per tile of the slot's
-// tile rectangle, row-major, at the slot's offset.
-__global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ depth_keys,
-                                                    const uint32_t* __restrict__ tiles,
-                                                    const uint32_t* __restrict__ offsets,
-                                                    const float* __restrict__ payload,
-                                                    const ViewInfo* __restrict__ views, const uint32_t* __restrict__ vis,
-                                                    int64_t n, int tile_shift, Status* __restrict__ status,
-                                                    uint64_t capacity, uint64_t* __restrict__ keys,
-                                                    uint32_t* __restrict__ vals) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// scan's list, in slot order): one (key, value) pair per tile of the slot's
+// tile rectangle, row-major, at the slot's offset.  The short runs (at most
+// kShortRun tiles) of a wave's 64 slots are written together, one pair per
+// lane and iteration: each lane finds the slot of its pair by a binary
+// search over the wave's prefix of short-run lengths and takes the slot's
+// rectangle from that lane; consecutive slots have consecutive offsets, so
+// the stores are mostly contiguous.  Long runs (near or large primitives)
+// are then written by the whole wave, one run at a time, and huge runs by
+// the whole grid.
+constexpr uint32_t kShortRun = 32;
+
+__device__ inline void emit_wave(int64_t t, int64_t n_vis, const uint32_t* __restrict__ depth_keys,
+                                 const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ offsets,
+                                 const float* __restrict__ payload, const ViewInfo* __restrict__ views,
+                                 const uint32_t* __restrict__ vis, int64_t n, int tile_shift,
+                                 uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const int lane = threadIdx.x & 63;
-    const uint64_t npairs = status->n_pairs;
-    if (npairs > capacity) {
-        if (t == 0) status->overflow = 1;
-        return;
-    }
-    const int64_t n_vis = status->n_vis;
-    if (t - lane >= n_vis) return;    // whole wave past the list
-    uint32_t cnt = 0, key = 0, off = 0, prim = 0;
-    int v = 0;
-    int4 r = make_int4(0, 0, 0, 0);
+    uint32_t cnt = 0, key = 0, off = 0, prim = 0, ntx = 1, tiles_x = 0;
+    uint64_t g0 = 0;                  // global tile of the rectangle's first tile
     if (t < n_vis) {
         const int64_t vs = vis[t];
-        v = (int)(vs / n);
+        const int v = (int)(vs / n);
         prim = (uint32_t)(vs - (int64_t)v * n);
         cnt = tiles[vs];
-        r = reinterpret_cast<const int4*>(payload + vs * kRecordWords)[0];
+        const int4 r = reinterpret_cast<const int4*>(payload + vs * kRecordWords)[0];
         key = depth_keys[vs];
         off = offsets[vs];
-    }
-    const int tx0 = r.x >> tile_shift, ty0 = r.y >> tile_shift;
-    const int ntx = (r.z >> tile_shift) - tx0 + 1;
-    // short runs: one lane writes them in row-major tile order
-    if (cnt > 0 && cnt <= 32) {
+        const int tx0 = r.x >> tile_shift, ty0 = r.y >> tile_shift;
+        ntx = (uint32_t)((r.z >> tile_shift) - tx0 + 1);
         const ViewInfo& V = views[v];
-        for (uint32_t q = 0; q < cnt; ++q) {
-            const int tx = tx0 + (int)(q % ntx), ty = ty0 + (int)(q / ntx);
-            const uint64_t g = (uint64_t)(V.tile_base + (int64_t)ty * V.tiles_x + tx);
-            emit_pair(g, key, prim, off + q, keys, vals);
+        tiles_x = (uint32_t)V.tiles_x;
+        g0 = (uint64_t)(V.tile_base + (int64_t)ty0 * V.tiles_x + tx0);
+    }
+    // short runs: inclusive prefix of their lengths over the wave
+    const uint32_t cs = cnt <= kShortRun ? cnt : 0u;
+    uint32_t incl = cs;
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += y;
+    }
+    const uint32_t excl = incl - cs;
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    for (uint32_t q = (uint32_t)lane; q - lane < total; q += 64) {
+        // owner: the last lane whose exclusive prefix is <= q; a lane with an
+        // empty or long run shares its prefix with the next lane, and lanes
+        // at the end have prefix = total > q
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const uint32_t e = (uint32_t)__shfl((int)excl, lo + step, 64);
+            if (e <= q) lo += step;
+        }
+        const uint32_t r = q - (uint32_t)__shfl((int)excl, lo, 64);
+        const uint32_t bo = (uint32_t)__shfl((int)off, lo, 64);
+        const uint32_t bn = (uint32_t)__shfl((int)ntx, lo, 64);
+        const uint32_t btx = (uint32_t)__shfl((int)tiles_x, lo, 64);
+        const uint32_t bk = (uint32_t)__shfl((int)key, lo, 64);
+        const uint32_t bp = (uint32_t)__shfl((int)prim, lo, 64);
+        const uint64_t bg = ((uint64_t)(uint32_t)__shfl((int)(g0 >> 32), lo, 64) << 32) |
+                            (uint32_t)__shfl((int)(uint32_t)g0, lo, 64);
+        if (q < total) {
+            const uint32_t row = r / bn, col = r - row * bn;
+            const uint64_t g = bg + (uint64_t)row * btx + col;
+            keys[bo + r] = (g << 32) | bk;
+            vals[bo + r] = bp;
         }
     }
-    // long runs (near or large primitives): the whole wavefront writes them
-    uint64_t big = __ballot(cnt > 32);
+    // long runs: the whole wavefront writes each (huge ones are left to
+    // the whole grid)
+    uint64_t big = __ballot(cnt > kShortRun && cnt <= (uint32_t)kHugeRun);
     while (big) {
         const int b = __builtin_ctzll(big);
         big &= big - 1;
@@ -70,15 +96,57 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
         const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, b);
         const uint32_t k = (uint32_t)__builtin_amdgcn_readlane((int)key, b);
         const uint32_t pb = (uint32_t)__builtin_amdgcn_readlane((int)prim, b);
-        const int vb = __builtin_amdgcn_readlane(v, b);
-        const int bx0 = __builtin_amdgcn_readlane(tx0, b), by0 = __builtin_amdgcn_readlane(ty0, b);
-        const int bn = __builtin_amdgcn_readlane(ntx, b);
-        const int64_t tile_base = views[vb].tile_base;
-        const int tiles_x = views[vb].tiles_x;
+        const uint32_t bn = (uint32_t)__builtin_amdgcn_readlane((int)ntx, b);
+        const uint32_t btx = (uint32_t)__builtin_amdgcn_readlane((int)tiles_x, b);
+        const uint64_t bg = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(g0 >> 32), b) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)g0, b);
         for (uint32_t q = (uint32_t)lane; q < c; q += 64) {
-            const int tx = bx0 + (int)(q % bn), ty = by0 + (int)(q / bn);
-            const uint64_t g = (uint64_t)(tile_base + (int64_t)ty * tiles_x + tx);
-            emit_pair(g, k, pb, o + q, keys, vals);
+            const uint32_t row = q / bn, col = q - row * bn;
+            keys[o + q] = ((bg + (uint64_t)row * btx + col) << 32) | k;
+            vals[o + q] = pb;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ depth_keys,
+                                                    const uint32_t* __restrict__ tiles,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    const float* __restrict__ payload,
+                                                    const ViewInfo* __restrict__ views, const uint32_t* __restrict__ vis,
+                                                    int64_t n, int tile_shift, Status* __restrict__ status,
+                                                    uint64_t capacity, const uint32_t* __restrict__ huge,
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int lane = threadIdx.x & 63;
+    const uint64_t npairs = status->n_pairs;
+    if (npairs > capacity) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) status->overflow = 1;
+        return;
+    }
+    const int64_t n_vis = status->n_vis;
+    // a grid of a few waves per CU strides over the list, 64 slots at a time
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    for (int64_t w0 = wave_id * 64; w0 < n_vis; w0 += n_waves * 64)
+        emit_wave(w0 + lane, n_vis, depth_keys, tiles, offsets, payload, views, vis, n, tile_shift, keys, vals);
+    // huge runs: 64-pair chunks dealt round-robin over all waves
+    const uint32_t n_huge = status->n_huge;
+    for (uint32_t i = 0; i < n_huge; ++i) {
+        const int64_t vs = huge[i];
+        const int v = (int)(vs / n);
+        const uint32_t prim = (uint32_t)(vs - (int64_t)v * n);
+        const uint32_t c = tiles[vs], o = offsets[vs], k = depth_keys[vs];
+        const int4 r = reinterpret_cast<const int4*>(payload + vs * kRecordWords)[0];
+        const int tx0 = r.x >> tile_shift, ty0 = r.y >> tile_shift;
+        const uint32_t bn = (uint32_t)((r.z >> tile_shift) - tx0 + 1);
+        const ViewInfo& V = views[v];
+        const uint64_t bg = (uint64_t)(V.tile_base + (int64_t)ty0 * V.tiles_x + tx0);
+        for (int64_t q0 = wave_id * 64; q0 < (int64_t)c; q0 += n_waves * 64) {
+            const uint32_t q = (uint32_t)q0 + (uint32_t)lane;
+            if (q < c) {
+                const uint32_t row = q / bn, col = q - row * bn;
+                keys[o + q] = ((bg + (uint64_t)row * (uint32_t)V.tiles_x + col) << 32) | k;
+                vals[o + q] = prim;
+            }
         }
     }
 }
@@ -563,12 +631,15 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
     const int64_t nt = L.n_tiles_total;
     if (L.n > 0) {
         const int64_t vn = L.n * (int64_t)n_views;
-        hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)((vn + 255) / 256)), dim3(256), 0, stream,
+        // enough 4-wave blocks for the list, at most 1024 (16 waves per CU)
+        const int64_t blocks = (vn + 255) / 256 < 1024 ? (vn + 255) / 256 : 1024;
+        hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(256), 0, stream,
                            reinterpret_cast<const uint32_t*>(vws + L.depth_keys),
                            reinterpret_cast<const uint32_t*>(vws + L.tiles),
                            reinterpret_cast<const uint32_t*>(vws + L.offsets),
                            reinterpret_cast<const float*>(vws + L.payload), views,
-                           reinterpret_cast<const uint32_t*>(vws + L.vis), L.n, shift, status, cap, ka, va);
+                           reinterpret_cast<const uint32_t*>(vws + L.vis), L.n, shift, status, cap,
+                           reinterpret_cast<const uint32_t*>(vws + L.huge), ka, va);
     }
     const int tb = key_tile_bits(nt);
     int passes, digit, key_lo, key_bits;

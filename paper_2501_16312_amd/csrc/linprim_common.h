@@ -80,13 +80,15 @@ struct Status {
     uint64_t capacity;
     uint32_t n_long;       // tiles whose list is sorted by the long-list kernel
     uint32_t n_vis;        // (view, primitive) slots that touch a tile (list in ViewLayout::vis)
-    uint64_t pad[4];
+    uint32_t n_huge;       // slots with more than kHugeRun tiles (list in ViewLayout::huge)
+    uint32_t pad32;
+    uint64_t pad[3];
 };
 
 // Offsets into the view workspace (all 256-byte aligned).
 struct ViewLayout {
     size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, vis, stats, order,
-        order_sums, total;
+        order_sums, huge, total;
     int64_t n, n_views, n_tiles_total, scan_blocks;
 };
 
@@ -120,6 +122,9 @@ hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stre
 // is listed by the scan; its records are summed by kBigChunks waves, each
 // writing its partial sum over the chunk into the chunk's first record.
 constexpr int kBigRun = 64;
+// Slots whose tile rectangle holds more than kHugeRun tiles have their pairs
+// emitted by every wave of the emission grid together.
+constexpr int kHugeRun = 1024;
 
 // The render kernels take the tiles in the order written by bin_sort: the
 // tiles whose list holds more than kHeavyList pairs first, so that the
