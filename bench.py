@@ -19,8 +19,9 @@ of the HBM byte counters).
 --workload steploop times the optimisation loop instead: 3,000,000
 octahedra, per step a batch of 8 random 1920x1080 views (from a pool of
 batches whose targets were rendered once from a perturbed copy of the
-scene), forward + backward + the L1 + SSIM loss gradient + fused Adam
-captured in one graph and replayed on each batch's poses.
+scene), forward + backward + the L1 loss gradient (--loss l1_ssim: the
+paper's L1 + SSIM) + fused Adam captured in one graph and replayed on each
+batch's poses.
 
 Prints one JSON line.
 """
@@ -491,8 +492,8 @@ def main():
     ap.add_argument("--workload", choices=("single", "batched", "steploop", "copy"), default="single")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--view-batches", type=int, default=4)
-    ap.add_argument("--loss", choices=("l1_ssim", "l1"), default="l1_ssim",
-                    help="step-loop loss: 3DGS's L1 + SSIM (default) or mean L1")
+    ap.add_argument("--loss", choices=("l1_ssim", "l1"), default="l1",
+                    help="step-loop loss: mean L1 (default) or 3DGS's L1 + SSIM")
     ap.add_argument("--tile", type=int, default=8)
     ap.add_argument("--digit", type=int, default=8)
     ap.add_argument("--radix-sort", action="store_true", help="global LSD radix sort instead of the per-tile sort")
@@ -506,7 +507,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus N>1 is not supported (the "
-                                   "multi-GPU design is described in DESIGN.md)"}), flush=True)
+                                   "library has no multi-GPU path)"}), flush=True)
         sys.exit(2)
     if args.steps is None:
         args.steps = 100 if args.workload == "steploop" else 20
