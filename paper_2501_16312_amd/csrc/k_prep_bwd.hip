@@ -300,24 +300,43 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     float4* rp = reinterpret_cast<float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
     const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
     const int nrec = (int)tiles[vs] * nq;
+    // the primitive's inputs, loaded while the records are summed
+    float mu[3], qv[4], dv[ND];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mu[c] = means[3 * i + c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) qv[c] = quats[4 * i + c];
+#pragma unroll
+    for (int c = 0; c < ND; ++c) dv[c] = dists[ND * i + c];
+    const float alpha = opacity[i];
     float r[kGradWords];
     if (nrec <= kBigRun) {
-        // sum the run in record order (skipping groups the rectangle misses)
+        // sum the run in record order (skipping groups the rectangle misses),
+        // loading four records before adding them
         const int qx = (nq == 1) ? 1 : (nq == 4) ? 2 : 4, tile = 8 * qx;
         const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
         const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
 #pragma unroll
         for (int k = 0; k < kGradWords; ++k) r[k] = 0.0f;
-        for (int q = 0; q < nrec; ++q) {
-            if (nq > 1 && !record_exists(q, nq, qx, tile, rc, tx0, ty0, ntx)) continue;
+        for (int q0 = 0; q0 < nrec; q0 += 4) {
+            float4 x[4][kGradWords / 4];
 #pragma unroll
-            for (int k = 0; k < kGradWords / 4; ++k) {
-                const float4 x = rp[q * (kGradWords / 4) + k];
-                r[4 * k] += x.x;
-                r[4 * k + 1] += x.y;
-                r[4 * k + 2] += x.z;
-                r[4 * k + 3] += x.w;
+            for (int h = 0; h < 4; ++h) {
+                const int q = q0 + h;
+                const bool use = q < nrec && (nq == 1 || record_exists(q, nq, qx, tile, rc, tx0, ty0, ntx));
+#pragma unroll
+                for (int k = 0; k < kGradWords / 4; ++k)
+                    x[h][k] = use ? rp[q * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+#pragma unroll
+                for (int k = 0; k < kGradWords / 4; ++k) {
+                    r[4 * k] += x[h][k].x;
+                    r[4 * k + 1] += x[h][k].y;
+                    r[4 * k + 2] += x[h][k].z;
+                    r[4 * k + 3] += x[h][k].w;
+                }
         }
     } else {
         // the chunk sums k_sum_big left in each chunk's first record
@@ -337,17 +356,16 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     }
     const ViewInfo& V = views[v];
     Geom G;
-    if (!build_geometry(KIND, EXACT, aa != 0, means + 3 * i, quats + 4 * i, dists + ND * i, opacity[i], V, G))
-        return;
+    if (!build_geometry(KIND, EXACT, aa != 0, mu, qv, dv, alpha, V, G)) return;
     const double ox = (double)rc.x + 0.5 - G.c[0];
     const double oy = (double)rc.y + 0.5 - G.c[1];
     if (EXACT) {
         // the view-space positional gradient is a ray-space quantity: none here
         stats[vs] = make_float2(0.0f, (float)G.radius);
-        double dmin = (double)dists[ND * i];
-        for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dists[ND * i + k]);
-        const double sigma = -log(1.0 - kAlphaScaleD * (double)opacity[i]) / (2.0 * dmin);
-        exact_slot_bwd<KIND>(G, V, dists + ND * i, sigma, ox, oy, r, rp);
+        double dmin = (double)dv[0];
+        for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dv[k]);
+        const double sigma = -log(1.0 - kAlphaScaleD * (double)alpha) / (2.0 * dmin);
+        exact_slot_bwd<KIND>(G, V, dv, sigma, ox, oy, r, rp);
         return;
     }
 
@@ -457,13 +475,13 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
         double go[3];
         for (int c = 0; c < 3; ++c) go[c] = V.Rw[c] * goc[0] + V.Rw[3 + c] * goc[1] + V.Rw[6 + c] * goc[2];
         if (KIND == LINPRIM_OCTAHEDRON) {
-            const double dk = (double)dists[ND * i + k];
+            const double dk = (double)dv[k];
             for (int rr = 0; rr < 3; ++rr) {
                 gR[3 * rr + k] += go[rr] * dk;
                 gd[k] += go[rr] * G.R[3 * rr + k];
             }
         } else {
-            const double gk = (double)dists[ND * i + k] * kInvSqrt3;
+            const double gk = (double)dv[k] * kInvSqrt3;
             for (int rr = 0; rr < 3; ++rr) {
                 const double rb = kTetDir[k][0] * G.R[3 * rr] + kTetDir[k][1] * G.R[3 * rr + 1] +
                                   kTetDir[k][2] * G.R[3 * rr + 2];

@@ -294,6 +294,18 @@ __global__ __launch_bounds__(256) void k_sort_long_lists(const uint2* __restrict
         const uint2 rg = ranges[g];
         const int64_t len = (int64_t)rg.y - rg.x;
         uint64_t* seg = in_keys + rg.x;
+        if (len <= kLdsList) {
+            // one chunk: sorted in LDS and written out from there
+            int P = 128;
+            while (P < len) P <<= 1;
+            for (int i = threadIdx.x; i < P; i += blockDim.x)
+                s[i] = (i < len) ? depth_index(in_keys, in_vals, (int64_t)rg.x + i) : ~0ull;
+            __syncthreads();
+            lds_bitonic(s, P);
+            for (int i = threadIdx.x; i < len; i += blockDim.x) put_sorted(g, s[i], rg.x + (uint32_t)i, keys, vals);
+            __syncthreads();
+            continue;
+        }
         // sort chunks of kLdsList in LDS, written back in place
         for (int64_t c0 = 0; c0 < len; c0 += kLdsList) {
             const int cl = (int)min((int64_t)kLdsList, len - c0);
