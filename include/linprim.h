@@ -451,8 +451,9 @@ const char *linprim_strerror(int code);
 
 /* Device pointers into the workspaces, for tests and diagnostics:
  * payload [n_views*n][32] (float; words 0..3 are the int pixel rectangle
- * i0, j0, i1, j1 with i0 = -1 when culled), depth_keys [n_views*n] u32,
- * tiles_touched [n_views*n] u32, offsets [n_views*n] u32, sorted keys
+ * i0, j0, i1, j1; a culled slot, tiles_touched = 0, has no valid record),
+ * depth_keys [n_views*n] u32, tiles_touched [n_views*n] u32, offsets
+ * [n_views*n] u32, sorted keys
  * [max_pairs] u64 and values [max_pairs] u32 (first n_pairs valid),
  * ranges [total tiles] (u32 start, u32 end). */
 int linprim_debug_pointers(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,

@@ -48,58 +48,25 @@ hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int t
     return hipGetLastError();
 }
 
-// One thread per (primitive, view).  Writes the 32-dword payload record,
-// the depth key and the tile count.
-template <int KIND, int DEG, bool EXACT>
-__global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ means, const float* __restrict__ quats,
-                                                    const float* __restrict__ dists, const float* __restrict__ opacity,
-                                                    const float* __restrict__ sh, int64_t n,
-                                                    const ViewInfo* __restrict__ views, int tile_shift, int aa,
-                                                    float* __restrict__ payload, uint32_t* __restrict__ depth_keys,
-                                                    uint32_t* __restrict__ tiles) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int v = blockIdx.y;
-    if (i >= n) return;
-    const int nd = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
-    const ViewInfo& V = views[v];
-    const int64_t slot = (int64_t)v * n + i;
+// The geometric part of k_preprocess for slot `slot` (view V): the record
+// except its colour, the depth key and the tile count.  Returns whether the
+// primitive is visible in the view.
+template <int KIND, bool EXACT>
+__device__ inline bool preprocess_view(bool ok, Geom& G, const float* mu, double sigma, const ViewInfo& V,
+                                       int64_t slot, int tile_shift, int aa, float* __restrict__ payload,
+                                       uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tiles) {
     float* rec = payload + slot * kRecordWords;
-    Geom G;
-    const float alpha = opacity[i];
-    if (!build_geometry(KIND, EXACT, aa != 0, means + 3 * i, quats + 4 * i, dists + nd * i, alpha, V, G)) {
-        reinterpret_cast<int4*>(rec)[0] = make_int4(-1, -1, -1, -1);
+    if (!ok || !build_view(KIND, EXACT, aa != 0, mu, V, G)) {
+        // culled: no tiles; the record is left as it was (nothing reads it)
         depth_keys[slot] = 0u;
         tiles[slot] = 0u;
-        return;
+        return false;
     }
     const int i0 = G.rect[0], j0 = G.rect[1], i1 = G.rect[2], j1 = G.rect[3];
     const uint32_t ntile = (uint32_t)((i1 >> tile_shift) - (i0 >> tile_shift) + 1) *
                            (uint32_t)((j1 >> tile_shift) - (j0 >> tile_shift) + 1);
     depth_keys[slot] = G.key;
     tiles[slot] = ntile;
-
-    // Eq. 1 density; colour from the SH along the viewing direction.
-    double dmin = (double)dists[nd * i];
-    for (int k = 1; k < nd; ++k) dmin = fmin(dmin, (double)dists[nd * i + k]);
-    const double sigma = -log(1.0 - kAlphaScaleD * (double)alpha) / (2.0 * dmin);
-    double dx = (double)means[3 * i + 0] - V.cam_pos[0];
-    double dy = (double)means[3 * i + 1] - V.cam_pos[1];
-    double dz = (double)means[3 * i + 2] - V.cam_pos[2];
-    const double idn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
-    dx *= idn; dy *= idn; dz *= idn;
-    constexpr int K = (DEG + 1) * (DEG + 1);
-    float shv[48];
-    load_sh<DEG>(sh + (int64_t)i * K * 3, shv);
-    float Y[16];
-    sh_eval_f<DEG>((float)dx, (float)dy, (float)dz, Y);
-    float rgb[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc = __builtin_fmaf(shv[3 * k + c], Y[k], acc);
-        rgb[c] = fmaxf(acc + 0.5f, 0.0f);
-    }
 
     float out[kRecordWords];
     for (int k = 0; k < kRecordWords; ++k) out[k] = 0.0f;
@@ -108,9 +75,6 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
     out[R_I1] = __int_as_float(i1);
     out[R_J1] = __int_as_float(j1);
     out[R_S2] = (float)(sigma * kLog2e);
-    out[R_RGB + 0] = rgb[0];
-    out[R_RGB + 1] = rgb[1];
-    out[R_RGB + 2] = rgb[2];
     out[R_FI0] = (float)i0;
     out[R_FJ0] = (float)j0;
     out[R_FWI] = (float)(i1 - i0);
@@ -204,13 +168,88 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
     float4* dst = reinterpret_cast<float4*>(rec);
     for (int k = 0; k < kRecordWords / 4; ++k)
         dst[k] = make_float4(out[4 * k], out[4 * k + 1], out[4 * k + 2], out[4 * k + 3]);
+    return true;
 }
 
+// The colour of a visible slot: SH along the viewing direction (degree
+// DEG), written into the record's colour words.
+template <int DEG>
+__device__ inline void preprocess_colour(const float* shv, const float* mu, const ViewInfo& V,
+                                         float* __restrict__ rec) {
+    double dx = (double)mu[0] - V.cam_pos[0];
+    double dy = (double)mu[1] - V.cam_pos[1];
+    double dz = (double)mu[2] - V.cam_pos[2];
+    const double idn = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+    dx *= idn; dy *= idn; dz *= idn;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    float Y[16];
+    sh_eval_f<DEG>((float)dx, (float)dy, (float)dz, Y);
+    float rgb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc = __builtin_fmaf(shv[3 * k + c], Y[k], acc);
+        rgb[c] = fmaxf(acc + 0.5f, 0.0f);
+    }
+    static_assert(R_RGB % 2 == 1, "g, b share an aligned float2");
+    rec[R_RGB] = rgb[0];
+    *reinterpret_cast<float2*>(rec + R_RGB + 1) = make_float2(rgb[1], rgb[2]);
+}
+
+// One thread per primitive, looping over the views: the inputs, the
+// rotation, the world-space offsets, sigma and the SH coefficients are
+// taken once; per view the thread writes the 32-dword payload record, the
+// depth key and the tile count of slot v * n + i.
+template <int KIND, int DEG, bool EXACT>
+__global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ means, const float* __restrict__ quats,
+                                                    const float* __restrict__ dists, const float* __restrict__ opacity,
+                                                    const float* __restrict__ sh, int64_t n,
+                                                    const ViewInfo* __restrict__ views, int n_views, int tile_shift,
+                                                    int aa, float* __restrict__ payload,
+                                                    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tiles) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    constexpr int nd = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
+    float mu[3], qv[4], dv[nd];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mu[c] = means[3 * i + c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) qv[c] = quats[4 * i + c];
+#pragma unroll
+    for (int c = 0; c < nd; ++c) dv[c] = dists[nd * i + c];
+    const float alpha = opacity[i];
+    Geom G;
+    const bool ok = build_world(KIND, mu, qv, dv, alpha, G);
+    // Eq. 1 density
+    double dmin = (double)dv[0];
+    for (int k = 1; k < nd; ++k) dmin = fmin(dmin, (double)dv[k]);
+    const double sigma = -log(1.0 - kAlphaScaleD * (double)alpha) / (2.0 * dmin);
+    // views in chunks of 64: the geometry of every view, then, if the
+    // primitive is visible in any, its SH loaded once and the colours
+    for (int v0 = 0; v0 < n_views; v0 += 64) {
+        const int v1 = min(n_views, v0 + 64);
+        uint64_t seen = 0;
+        for (int v = v0; v < v1; ++v)
+            if (preprocess_view<KIND, EXACT>(ok, G, mu, sigma, views[v], (int64_t)v * n + i, tile_shift, aa, payload,
+                                             depth_keys, tiles))
+                seen |= 1ull << (v - v0);
+        if (seen) {
+            float shv[48];
+            load_sh<DEG>(sh + i * (DEG + 1) * (DEG + 1) * 3, shv);
+            while (seen) {
+                const int v = v0 + __builtin_ctzll(seen);
+                seen &= seen - 1;
+                preprocess_colour<DEG>(shv, mu, views[v], payload + ((int64_t)v * n + i) * kRecordWords);
+            }
+        }
+    }
+}
 hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, bool aa,
                              const ViewLayout& L, char* ws, hipStream_t stream) {
     if (p.n == 0) return hipSuccess;
     const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
-    dim3 grid((unsigned)((p.n + 255) / 256), (unsigned)n_views);
+    dim3 grid((unsigned)((p.n + 255) / 256));
     const ViewInfo* views = reinterpret_cast<const ViewInfo*>(ws + L.views);
     float* payload = reinterpret_cast<float*>(ws + L.payload);
     uint32_t* keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
@@ -219,10 +258,12 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
     do {                                                                                                     \
         if (exact)                                                                                           \
             hipLaunchKernelGGL((k_preprocess<K_, D_, true>), grid, dim3(256), 0, stream, p.means, p.quats,    \
-                               p.dists, p.opacity, p.sh, p.n, views, shift, aa ? 1 : 0, payload, keys, tiles); \
+                               p.dists, p.opacity, p.sh, p.n, views, n_views, shift, aa ? 1 : 0, payload, keys, \
+                               tiles);                                                                           \
         else                                                                                                 \
             hipLaunchKernelGGL((k_preprocess<K_, D_, false>), grid, dim3(256), 0, stream, p.means, p.quats,   \
-                               p.dists, p.opacity, p.sh, p.n, views, shift, aa ? 1 : 0, payload, keys, tiles); \
+                               p.dists, p.opacity, p.sh, p.n, views, n_views, shift, aa ? 1 : 0, payload, keys, \
+                               tiles);                                                                           \
     } while (0)
 #define LP_PRE_DEG(K_)                      \
     switch (p.sh_degree) {                  \

@@ -349,8 +349,12 @@ __device__ inline void antialias_shift(int type, double a[4][3]) {
     }
 }
 
-__device__ inline bool build_geometry(int type, bool exact, bool aa, const float* mu_f, const float* q_f,
-                                      const float* d_f, float alpha, const ViewInfo& V, Geom& G) {
+// The view-independent part of build_geometry: rotation, world-space
+// offsets, validity of the inputs.  Returns false for a primitive no view
+// can see (degenerate rotation, non-positive or non-finite distances,
+// non-finite centre, opacity outside [0, 1]).
+__device__ inline bool build_world(int type, const float* mu_f, const float* q_f, const float* d_f, float alpha,
+                                   Geom& G) {
     const int na = (type == LINPRIM_OCTAHEDRON) ? 3 : 4;
     if (!quat_rotation_d((double)q_f[0], (double)q_f[1], (double)q_f[2], (double)q_f[3], G.R)) return false;
     double d[4];
@@ -362,11 +366,6 @@ __device__ inline bool build_geometry(int type, bool exact, bool aa, const float
     if (!isfinite(mu[0]) || !isfinite(mu[1]) || !isfinite(mu[2])) return false;
     const double al = (double)alpha;
     if (!(al >= 0.0 && al <= 1.0)) return false;
-
-    for (int r = 0; r < 3; ++r)
-        G.tc[r] = V.Rw[3 * r + 0] * mu[0] + V.Rw[3 * r + 1] * mu[1] + V.Rw[3 * r + 2] * mu[2] + V.tw[r];
-    if (!(G.tc[2] > V.near_z)) return false;
-
     if (type == LINPRIM_OCTAHEDRON) {
         for (int k = 0; k < 3; ++k)
             for (int r = 0; r < 3; ++r) G.o[k][r] = G.R[3 * r + k] * d[k];
@@ -378,6 +377,17 @@ __device__ inline bool build_geometry(int type, bool exact, bool aa, const float
                              kTetDir[i][2] * G.R[3 * r + 2]) * g;
         }
     }
+    return true;
+}
+
+// The per-view part: G.R and G.o from build_world; the rest of G from the
+// camera.  Returns false if the primitive is culled in this view.
+__device__ inline bool build_view(int type, bool exact, bool aa, const float* mu_f, const ViewInfo& V, Geom& G) {
+    const int na = (type == LINPRIM_OCTAHEDRON) ? 3 : 4;
+    const double mu[3] = {(double)mu_f[0], (double)mu_f[1], (double)mu_f[2]};
+    for (int r = 0; r < 3; ++r)
+        G.tc[r] = V.Rw[3 * r + 0] * mu[0] + V.Rw[3 * r + 1] * mu[1] + V.Rw[3 * r + 2] * mu[2] + V.tw[r];
+    if (!(G.tc[2] > V.near_z)) return false;
     for (int k = 0; k < na; ++k)
         for (int r = 0; r < 3; ++r)
             G.oc[k][r] = V.Rw[3 * r + 0] * G.o[k][0] + V.Rw[3 * r + 1] * G.o[k][1] + V.Rw[3 * r + 2] * G.o[k][2];
@@ -456,6 +466,11 @@ __device__ inline bool build_geometry(int type, bool exact, bool aa, const float
     const float zf = (float)G.tc[2];
     G.key = __float_as_uint(zf);
     return true;
+}
+
+__device__ inline bool build_geometry(int type, bool exact, bool aa, const float* mu_f, const float* q_f,
+                                      const float* d_f, float alpha, const ViewInfo& V, Geom& G) {
+    return build_world(type, mu_f, q_f, d_f, alpha, G) && build_view(type, exact, aa, mu_f, V, G);
 }
 #pragma clang fp contract(on)
 

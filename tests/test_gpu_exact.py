@@ -55,7 +55,7 @@ def test_exact_binning_bit_exact(oracle_mod, kind, tile):
         pay = dbg["payload"][v * sc.n:(v + 1) * sc.n].numpy()
         rect = pay[:, :4].view(np.int32)
         assert np.array_equal(rect[p["valid"]], p["rect"][p["valid"]])
-        assert np.all(rect[~p["valid"], 0] == -1)
+        assert np.all(dbg["tiles"][v * sc.n:(v + 1) * sc.n].numpy()[~p["valid"]] == 0)   # culled
         keys = dbg["depth_keys"][v * sc.n:(v + 1) * sc.n].numpy().view(np.uint32)
         assert np.array_equal(keys[p["valid"]], p["key"][p["valid"]])
         assert np.array_equal(dbg["tiles"][v * sc.n:(v + 1) * sc.n].numpy(), p["tiles"])

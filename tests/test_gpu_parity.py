@@ -70,7 +70,7 @@ def test_preprocess_and_sort_bit_exact(oracle_mod, kind, tile, radix):
         rect = pay[:, :4].view(np.int32)
         ref = p["rect"].copy()
         assert np.array_equal(rect[p["valid"]], ref[p["valid"]])
-        assert np.all(rect[~p["valid"], 0] == -1)
+        assert np.all(dbg["tiles"][v * sc.n:(v + 1) * sc.n].numpy()[~p["valid"]] == 0)   # culled
         keys = dbg["depth_keys"][v * sc.n:(v + 1) * sc.n].numpy().view(np.uint32)
         assert np.array_equal(keys[p["valid"]], p["key"][p["valid"]])
         tiles = dbg["tiles"][v * sc.n:(v + 1) * sc.n].numpy()
