@@ -283,8 +283,8 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
 }
 
 // ---------------------------------------------------------------------------
-// Exclusive prefix sum of the tile counts (three passes: block totals, a
-// single-block scan of the totals, block-local scans).
+// Exclusive prefix sum of the tile counts (two passes: block totals, then
+// block-local scans, each block adding the totals of the blocks before it).
 // ---------------------------------------------------------------------------
 __device__ inline uint64_t block_exclusive_scan_u64(uint64_t x, uint64_t* lds, uint64_t* total) {
     // 256 threads: Hillis-Steele in shared memory
@@ -305,9 +305,26 @@ __device__ inline uint64_t block_exclusive_scan_u64(uint64_t x, uint64_t* lds, u
 
 // Per block of kScanItems slots: the sum of the tile counts and the number
 // of slots that touch a tile (block_sums[b] and vis_sums[b]).
+// The status of an empty slot range (no primitives).
+__global__ void k_status_empty(Status* __restrict__ status) {
+    if (threadIdx.x == 0) {
+        status->n_pairs = 0;
+        status->n_vis = 0;
+        status->overflow = 0;
+        status->n_big = 0;
+        status->n_huge = 0;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ in, int64_t count,
                                                      uint64_t* __restrict__ block_sums,
-                                                     uint64_t* __restrict__ vis_sums) {
+                                                     uint64_t* __restrict__ vis_sums, Status* __restrict__ status) {
+    // the lists k_scan_apply appends to start empty
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        status->overflow = 0;
+        status->n_big = 0;
+        status->n_huge = 0;
+    }
     __shared__ uint64_t part[2][4];
     const int64_t base = (int64_t)blockIdx.x * kScanItems;
     uint64_t s = 0, c = 0;
@@ -332,32 +349,15 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
     }
 }
 
-__global__ __launch_bounds__(256) void k_scan_totals(uint64_t* __restrict__ block_sums,
-                                                     uint64_t* __restrict__ vis_sums, int64_t nblocks,
-                                                     Status* __restrict__ status) {
-    __shared__ uint64_t lds[256];
-    uint64_t carry = 0, vcarry = 0;
-    for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
-        const int64_t idx = b0 + threadIdx.x;
-        const uint64_t x = (idx < nblocks) ? block_sums[idx] : 0;
-        const uint64_t y = (idx < nblocks) ? vis_sums[idx] : 0;
-        uint64_t total, vtotal;
-        const uint64_t ex = block_exclusive_scan_u64(x, lds, &total);
-        const uint64_t vex = block_exclusive_scan_u64(y, lds, &vtotal);
-        if (idx < nblocks) {
-            block_sums[idx] = carry + ex;
-            vis_sums[idx] = vcarry + vex;
-        }
-        carry += total;
-        vcarry += vtotal;
-    }
-    if (threadIdx.x == 0) {
-        status->n_pairs = carry;
-        status->overflow = 0;
-        status->n_big = 0;
-        status->n_huge = 0;
-        status->n_vis = (uint32_t)vcarry;
-    }
+// Sum of x[0, count) over the block (every thread gets it).
+__device__ inline uint64_t block_sum_u64(const uint64_t* __restrict__ x, int64_t count, uint64_t* part4) {
+    uint64_t s = 0;
+    for (int64_t b = threadIdx.x; b < count; b += blockDim.x) s += x[b];
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) part4[threadIdx.x >> 6] = s;
+    __syncthreads();
+    return part4[0] + part4[1] + part4[2] + part4[3];
 }
 
 // Appends a slot to a list (in no particular order) with one atomic per
@@ -379,11 +379,20 @@ __device__ inline void wave_append(bool take, uint32_t value, uint32_t* __restri
 // more than kHugeRun tiles.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t count,
                                                     const uint64_t* __restrict__ block_sums,
-                                                    const uint64_t* __restrict__ vis_sums,
+                                                    const uint64_t* __restrict__ vis_sums, int64_t nblocks,
                                                     uint32_t* __restrict__ out, int nq,
                                                     Status* __restrict__ status, uint32_t* __restrict__ big,
                                                     uint32_t* __restrict__ vis, uint32_t* __restrict__ huge) {
     __shared__ uint64_t lds[256];
+    __shared__ uint64_t part4[4];
+    // this block's start: the sums of the blocks before it (a few hundred
+    // values for a million slots)
+    const uint64_t pre = block_sum_u64(block_sums, blockIdx.x, part4);
+    const uint64_t vpre = block_sum_u64(vis_sums, blockIdx.x, part4);
+    if (blockIdx.x == nblocks - 1 && threadIdx.x == 0) {
+        status->n_pairs = pre + block_sums[blockIdx.x];
+        status->n_vis = (uint32_t)(vpre + vis_sums[blockIdx.x]);
+    }
     // thread t handles the 16 consecutive elements base + 16 t .. 16 t + 15
     const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * 16;
     uint32_t v[16];
@@ -395,8 +404,8 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
         c += v[k] ? 1u : 0u;
     }
     uint64_t total;
-    uint64_t run = block_sums[blockIdx.x] + block_exclusive_scan_u64(s, lds, &total);
-    uint64_t vrun = vis_sums[blockIdx.x] + block_exclusive_scan_u64(c, lds, &total);
+    uint64_t run = pre + block_exclusive_scan_u64(s, lds, &total);
+    uint64_t vrun = vpre + block_exclusive_scan_u64(c, lds, &total);
     const int lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     for (int k = 0; k < 16; ++k) {
@@ -419,13 +428,14 @@ hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stre
     const int nq = (tile / 8) * (tile / 8);
     const int64_t nb = L.scan_blocks;
     uint64_t* vsums = bsums + (nb + 1);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums);
-    hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(256), 0, stream, bsums, vsums, nb, status);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums,
+    if (nb > 0) {
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums, status);
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums, nb,
                            offsets, nq, status, big, reinterpret_cast<uint32_t*>(ws + L.vis),
                            reinterpret_cast<uint32_t*>(ws + L.huge));
+    } else {
+        hipLaunchKernelGGL(k_status_empty, dim3(1), dim3(64), 0, stream, status);
+    }
     return hipGetLastError();
 }
 

@@ -115,8 +115,13 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
                                                     const ViewInfo* __restrict__ views, const uint32_t* __restrict__ vis,
                                                     int64_t n, int tile_shift, Status* __restrict__ status,
                                                     uint64_t capacity, const uint32_t* __restrict__ huge,
-                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+                                                    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                    uint2* __restrict__ ranges, int64_t n_tiles) {
     const int lane = threadIdx.x & 63;
+    // the tile ranges start empty (k_tile_ranges fills them after the sort)
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += (int64_t)gridDim.x * blockDim.x)
+        ranges[t] = make_uint2(0u, 0u);
+    if (blockIdx.x == 0 && threadIdx.x == 0) status->n_long = 0u;
     const uint64_t npairs = status->n_pairs;
     if (npairs > capacity) {
         if (blockIdx.x == 0 && threadIdx.x == 0) status->overflow = 1;
@@ -651,7 +656,10 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
                            reinterpret_cast<const uint32_t*>(vws + L.offsets),
                            reinterpret_cast<const float*>(vws + L.payload), views,
                            reinterpret_cast<const uint32_t*>(vws + L.vis), L.n, shift, status, cap,
-                           reinterpret_cast<const uint32_t*>(vws + L.huge), ka, va);
+                           reinterpret_cast<const uint32_t*>(vws + L.huge), ka, va, ranges, nt);
+    } else {
+        hipLaunchKernelGGL(k_clear_ranges, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, ranges, nt,
+                           status);
     }
     const int tb = key_tile_bits(nt);
     int passes, digit, key_lo, key_bits;
@@ -681,7 +689,6 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
         uint64_t* tk = kin; kin = kout; kout = tk;
         uint32_t* tv = vin; vin = vout; vout = tv;
     }
-    hipLaunchKernelGGL(k_clear_ranges, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, ranges, nt, status);
     if (P.capacity > 0)
         hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((P.capacity + 255) / 256)), dim3(256), 0, stream, kin, status,
                            cap, ranges);
