@@ -161,10 +161,10 @@ int linprim_pair_count(const void *view_ws, int64_t *n_pairs, void *stream);
 /* Sec. 3.2 "Global Sorting and Tiling".  Orders the (tile, primitive)
  * pairs of every touched tile by key = (global tile << 32) | float32 bits of
  * the centre's camera depth, ties by primitive index, and writes every
- * tile's [start, end) range into view_ws.  By default the pairs are counted
- * per tile, scattered into their tile's segment and each segment is sorted
- * by (depth, primitive); with LINPRIM_FLAG_RADIX_SORT a stable LSD radix
- * sort of the emitted keys gives the same order.  If the pair count exceeds
+ * tile's [start, end) range into view_ws.  By default the pairs are grouped
+ * by tile with a stable LSD radix sort of the tile bits and each tile's
+ * segment is sorted by (depth, primitive); with LINPRIM_FLAG_RADIX_SORT a
+ * stable LSD radix sort of the full keys gives the same order.  If the pair count exceeds
  * max_pairs nothing is sorted, the overflow flag in view_ws is set and the
  * render calls leave their outputs untouched; linprim_read_status reports
  * it.  The sorted keys/values stay in pair_ws. */
