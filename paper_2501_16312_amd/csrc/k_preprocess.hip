@@ -54,7 +54,8 @@ hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int t
 template <int KIND, bool EXACT>
 __device__ inline bool preprocess_view(bool ok, Geom& G, const float* mu, double sigma, const ViewInfo& V,
                                        int64_t slot, int tile_shift, int aa, float* __restrict__ payload,
-                                       uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tiles) {
+                                       uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tiles,
+                                       uint2* __restrict__ trect) {
     float* rec = payload + slot * kRecordWords;
     if (!ok || !build_view(KIND, EXACT, aa != 0, mu, V, G)) {
         // culled: no tiles; the record is left as it was (nothing reads it)
@@ -67,6 +68,7 @@ __device__ inline bool preprocess_view(bool ok, Geom& G, const float* mu, double
                            (uint32_t)((j1 >> tile_shift) - (j0 >> tile_shift) + 1);
     depth_keys[slot] = G.key;
     tiles[slot] = ntile;
+    trect[slot] = pack_tile_rect(i0, j0, i1, j1, tile_shift);
 
     float out[kRecordWords];
     for (int k = 0; k < kRecordWords; ++k) out[k] = 0.0f;
@@ -207,7 +209,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
                                                     const float* __restrict__ sh, int64_t n,
                                                     const ViewInfo* __restrict__ views, int n_views, int tile_shift,
                                                     int aa, float* __restrict__ payload,
-                                                    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tiles) {
+                                                    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tiles,
+                                                    uint2* __restrict__ trect) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     constexpr int nd = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
         uint64_t seen = 0;
         for (int v = v0; v < v1; ++v)
             if (preprocess_view<KIND, EXACT>(ok, G, mu, sigma, views[v], (int64_t)v * n + i, tile_shift, aa, payload,
-                                             depth_keys, tiles))
+                                             depth_keys, tiles, trect))
                 seen |= 1ull << (v - v0);
         if (seen) {
             float shv[48];
@@ -254,16 +257,17 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
     float* payload = reinterpret_cast<float*>(ws + L.payload);
     uint32_t* keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
     uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
+    uint2* trect = reinterpret_cast<uint2*>(ws + L.trect);
 #define LP_PRE(K_, D_)                                                                                     \
     do {                                                                                                     \
         if (exact)                                                                                           \
             hipLaunchKernelGGL((k_preprocess<K_, D_, true>), grid, dim3(256), 0, stream, p.means, p.quats,    \
                                p.dists, p.opacity, p.sh, p.n, views, n_views, shift, aa ? 1 : 0, payload, keys, \
-                               tiles);                                                                           \
+                               tiles, trect);                                                                    \
         else                                                                                                 \
             hipLaunchKernelGGL((k_preprocess<K_, D_, false>), grid, dim3(256), 0, stream, p.means, p.quats,   \
                                p.dists, p.opacity, p.sh, p.n, views, n_views, shift, aa ? 1 : 0, payload, keys, \
-                               tiles);                                                                           \
+                               tiles, trect);                                                                    \
     } while (0)
 #define LP_PRE_DEG(K_)                      \
     switch (p.sh_degree) {                  \

@@ -32,8 +32,8 @@ constexpr uint32_t kShortRun = 32;
 
 __device__ inline void emit_wave(int64_t t, int64_t n_vis, const uint32_t* __restrict__ depth_keys,
                                  const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ offsets,
-                                 const float* __restrict__ payload, const ViewInfo* __restrict__ views,
-                                 const uint32_t* __restrict__ vis, int64_t n, int tile_shift,
+                                 const uint2* __restrict__ trect, const ViewInfo* __restrict__ views,
+                                 const uint32_t* __restrict__ vis, int64_t n,
                                  uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     const int lane = threadIdx.x & 63;
     uint32_t cnt = 0, key = 0, off = 0, prim = 0, ntx = 1, tiles_x = 0;
@@ -43,11 +43,11 @@ __device__ inline void emit_wave(int64_t t, int64_t n_vis, const uint32_t* __res
         const int v = (int)(vs / n);
         prim = (uint32_t)(vs - (int64_t)v * n);
         cnt = tiles[vs];
-        const int4 r = reinterpret_cast<const int4*>(payload + vs * kRecordWords)[0];
+        const uint2 tr = trect[vs];
         key = depth_keys[vs];
         off = offsets[vs];
-        const int tx0 = r.x >> tile_shift, ty0 = r.y >> tile_shift;
-        ntx = (uint32_t)((r.z >> tile_shift) - tx0 + 1);
+        const int tx0 = (int)(tr.x & 0xffffu), ty0 = (int)(tr.x >> 16);
+        ntx = tr.y & 0xffffu;
         const ViewInfo& V = views[v];
         tiles_x = (uint32_t)V.tiles_x;
         g0 = (uint64_t)(V.tile_base + (int64_t)ty0 * V.tiles_x + tx0);
@@ -111,9 +111,9 @@ __device__ inline void emit_wave(int64_t t, int64_t n_vis, const uint32_t* __res
 __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__ depth_keys,
                                                     const uint32_t* __restrict__ tiles,
                                                     const uint32_t* __restrict__ offsets,
-                                                    const float* __restrict__ payload,
+                                                    const uint2* __restrict__ trect,
                                                     const ViewInfo* __restrict__ views, const uint32_t* __restrict__ vis,
-                                                    int64_t n, int tile_shift, Status* __restrict__ status,
+                                                    int64_t n, Status* __restrict__ status,
                                                     uint64_t capacity, const uint32_t* __restrict__ huge,
                                                     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
                                                     uint2* __restrict__ ranges, int64_t n_tiles) {
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     const int64_t wave_id = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     for (int64_t w0 = wave_id * 64; w0 < n_vis; w0 += n_waves * 64)
-        emit_wave(w0 + lane, n_vis, depth_keys, tiles, offsets, payload, views, vis, n, tile_shift, keys, vals);
+        emit_wave(w0 + lane, n_vis, depth_keys, tiles, offsets, trect, views, vis, n, keys, vals);
     // huge runs: 64-pair chunks dealt round-robin over all waves
     const uint32_t n_huge = status->n_huge;
     for (uint32_t i = 0; i < n_huge; ++i) {
@@ -140,9 +140,9 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
         const int v = (int)(vs / n);
         const uint32_t prim = (uint32_t)(vs - (int64_t)v * n);
         const uint32_t c = tiles[vs], o = offsets[vs], k = depth_keys[vs];
-        const int4 r = reinterpret_cast<const int4*>(payload + vs * kRecordWords)[0];
-        const int tx0 = r.x >> tile_shift, ty0 = r.y >> tile_shift;
-        const uint32_t bn = (uint32_t)((r.z >> tile_shift) - tx0 + 1);
+        const uint2 tr = trect[vs];
+        const int tx0 = (int)(tr.x & 0xffffu), ty0 = (int)(tr.x >> 16);
+        const uint32_t bn = tr.y & 0xffffu;
         const ViewInfo& V = views[v];
         const uint64_t bg = (uint64_t)(V.tile_base + (int64_t)ty0 * V.tiles_x + tx0);
         for (int64_t q0 = wave_id * 64; q0 < (int64_t)c; q0 += n_waves * 64) {
@@ -654,8 +654,8 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
                            reinterpret_cast<const uint32_t*>(vws + L.depth_keys),
                            reinterpret_cast<const uint32_t*>(vws + L.tiles),
                            reinterpret_cast<const uint32_t*>(vws + L.offsets),
-                           reinterpret_cast<const float*>(vws + L.payload), views,
-                           reinterpret_cast<const uint32_t*>(vws + L.vis), L.n, shift, status, cap,
+                           reinterpret_cast<const uint2*>(vws + L.trect), views,
+                           reinterpret_cast<const uint32_t*>(vws + L.vis), L.n, status, cap,
                            reinterpret_cast<const uint32_t*>(vws + L.huge), ka, va, ranges, nt);
     } else {
         hipLaunchKernelGGL(k_clear_ranges, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, stream, ranges, nt,

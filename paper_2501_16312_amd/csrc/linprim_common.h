@@ -88,7 +88,7 @@ struct Status {
 // Offsets into the view workspace (all 256-byte aligned).
 struct ViewLayout {
     size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, vis, stats, order,
-        order_sums, huge, total;
+        order_sums, huge, trect, total;
     int64_t n, n_views, n_tiles_total, scan_blocks;
 };
 
@@ -125,6 +125,14 @@ constexpr int kBigRun = 64;
 // Slots whose tile rectangle holds more than kHugeRun tiles have their pairs
 // emitted by every wave of the emission grid together.
 constexpr int kHugeRun = 1024;
+
+// Tile rectangle of a visible slot, packed for the emission kernel (tile
+// coordinates are below 2^16): x = tx0 | ty0 << 16, y = ntx | nty << 16.
+__host__ __device__ inline uint2 pack_tile_rect(int i0, int j0, int i1, int j1, int tile_shift) {
+    const int tx0 = i0 >> tile_shift, ty0 = j0 >> tile_shift;
+    const int ntx = (i1 >> tile_shift) - tx0 + 1, nty = (j1 >> tile_shift) - ty0 + 1;
+    return make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)ntx | ((uint32_t)nty << 16));
+}
 
 // The render kernels take the tiles in the order written by bin_sort: the
 // tiles whose list holds more than kHeavyList pairs first, so that the

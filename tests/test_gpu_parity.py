@@ -81,6 +81,43 @@ def test_preprocess_and_sort_bit_exact(oracle_mod, kind, tile, radix):
     _check_sorted(dbg, O.sort(), g["n_pairs"])
 
 
+@pytest.mark.parametrize("radix", [False, True])
+def test_sort_huge_runs(oracle_mod, radix):
+    """Primitives close to the camera whose rectangles cover more than 1024
+    tiles (their pairs are emitted by the whole grid), one just under (one
+    wave), and many small ones (lanes of a wave together)."""
+    _say(f"sort huge runs radix={radix}")
+    sc = scenes.uniform_octahedra(300, seed=77, box=1.0, dmin=0.02, dmax=0.08)
+    sc.means[:3] = np.array([[0.0, 0.0, -2.0], [0.3, -0.2, -1.6], [-0.4, 0.3, -1.8]], sc.means.dtype)
+    sc.dists[:3] = np.array([[0.5, 0.4, 0.3], [0.6, 0.2, 0.5], [0.3, 0.7, 0.4]], sc.dists.dtype)
+    cams = [scenes.look_at((0.1, 0.2, -3.0), (0, 0, 0), 640, 480)]
+    O = oracle_mod.OracleScene(sc, cams, tile=8)
+    runs = np.sort(O.prep(0)["tiles"])
+    _say(f"  largest runs {runs[-4:]}")
+    assert (runs > 1024).sum() >= 2 and ((runs > 32) & (runs <= 1024)).sum() >= 1
+    g = GC.gpu_forward(sc, cams, tile=8, radix=radix)
+    _check_sorted(g["rast"].debug_arrays(g["prims"]), O.sort(), g["n_pairs"])
+
+
+def test_many_views(oracle_mod):
+    """70 small views in one call: the preprocessing takes the views in
+    chunks of 64 per primitive."""
+    _say("many views")
+    sc = _scene_small(OCTA, 300, seed=19)
+    rng = np.random.default_rng(3)
+    cams = []
+    for k in range(70):
+        a = 2 * np.pi * k / 70
+        cams.append(scenes.look_at((3 * np.cos(a), 0.5 * rng.uniform(-1, 1), 3 * np.sin(a)), (0, 0, 0),
+                                   int(rng.integers(16, 33)), int(rng.integers(12, 29))))
+    g = GC.gpu_forward(sc, cams, tile=8)
+    dbg = g["rast"].debug_arrays(g["prims"])
+    O, r = _oracle_render(oracle_mod, sc, cams, 8, (0, 0, 0))
+    _check_sorted(dbg, O.sort(), g["n_pairs"])
+    good, _, _ = GC.compare_images(g, r, "many views")
+    assert good <= GC.IMG_TOL
+
+
 @pytest.mark.parametrize("digit", [4, 5, 7, 8])
 def test_sort_digit_widths(oracle_mod, digit):
     _say(f"sort digit={digit}")
