@@ -373,28 +373,37 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_hist(const uint64_t* __r
     for (int d = threadIdx.x; d < radix; d += kSortThreads) hist[(int64_t)d * nblocks + blockIdx.x] = h[d];
 }
 
-__global__ __launch_bounds__(256) void k_radix_scan(uint32_t* __restrict__ hist, const Status* __restrict__ status,
-                                                    uint64_t capacity, int64_t nblocks,
-                                                    uint32_t* __restrict__ digit_totals) {
-    __shared__ uint32_t lds[256];
+// One block per digit: exclusive prefix of the digit's per-block counts over
+// the blocks (in place), 1024 at a time (wave scans by shuffles, then the
+// wave totals), and the digit's total.
+__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist, const Status* __restrict__ status,
+                                                     uint64_t capacity, int64_t nblocks,
+                                                     uint32_t* __restrict__ digit_totals) {
+    __shared__ uint32_t wsum[16];
     if (status->n_pairs > capacity) return;
     const int d = blockIdx.x;
     uint32_t* row = hist + (int64_t)d * nblocks;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     uint32_t carry = 0;
-    const int t = threadIdx.x;
-    for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
+    for (int64_t b0 = 0; b0 < nblocks; b0 += 1024) {
         const int64_t idx = b0 + t;
         const uint32_t x = (idx < nblocks) ? row[idx] : 0u;
-        lds[t] = x;
-        __syncthreads();
-        for (int off = 1; off < 256; off <<= 1) {
-            const uint32_t y = (t >= off) ? lds[t - off] : 0u;
-            __syncthreads();
-            lds[t] += y;
-            __syncthreads();
+        uint32_t incl = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
         }
-        if (idx < nblocks) row[idx] = carry + lds[t] - x;
-        carry += lds[255];
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            const uint32_t v = wsum[w];
+            before += (w < wave) ? v : 0u;
+            total += v;
+        }
+        if (idx < nblocks) row[idx] = carry + before + incl - x;
+        carry += total;
         __syncthreads();
     }
     if (t == 0) digit_totals[d] = carry;
@@ -682,7 +691,7 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
         if (nb > 0) {
             hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, status, cap,
                                key_lo + sh, bits, nb, hist);
-            hipLaunchKernelGGL(k_radix_scan, dim3(1u << bits), dim3(256), 0, stream, hist, status, cap, nb, totals);
+            hipLaunchKernelGGL(k_radix_scan, dim3(1u << bits), dim3(1024), 0, stream, hist, status, cap, nb, totals);
             hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kSortThreads), 0, stream, kin, vin, status,
                                cap, key_lo + sh, bits, nb, hist, totals, kout, vout);
         }
