@@ -242,11 +242,23 @@ __global__ __launch_bounds__(64) void k_sort_short_lists(const uint2* __restrict
         if (q * 64 + lane < len) put_sorted((uint64_t)g, k[q], rg.x + rank[q], keys, vals);
 }
 
-// Bitonic sort of s[0, P) ascending, P a power of two <= kLdsList.
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of s[0, P) ascending, P a power of two in [128, kLdsList],
+// by the whole block.  Compare-exchange steps whose partners are 64 or more
+// apart go through LDS, one barrier each; the steps below 64 of every merge
+// run in registers with shuffles (thread t holds elements t + blockDim m,
+// whose partners then belong to lanes of the same wave).
 __device__ inline void lds_bitonic(uint64_t* s, int P) {
+    const int t = threadIdx.x, T = blockDim.x;
     for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < (P >> 1); i += blockDim.x) {
+        int j = k >> 1;
+        for (; j >= 64; j >>= 1) {
+            for (int i = t; i < (P >> 1); i += T) {
                 const int lo = 2 * j * (i / j) + (i % j), hi = lo + j;
                 const uint64_t a = s[lo], b = s[hi];
                 const bool up = (lo & k) == 0;
@@ -257,6 +269,18 @@ __device__ inline void lds_bitonic(uint64_t* s, int P) {
             }
             __syncthreads();
         }
+        // steps j < 64 (wave-uniform: P and T are multiples of 64)
+        for (int e = t; e < P; e += T) {
+            uint64_t v = s[e];
+            const bool up = (e & k) == 0;
+            for (int jj = j; jj > 0; jj >>= 1) {
+                const uint64_t o = shfl_xor_u64(v, jj);
+                const bool keep_min = ((e & jj) == 0) == up;
+                v = keep_min ? (o < v ? o : v) : (o > v ? o : v);
+            }
+            s[e] = v;
+        }
+        __syncthreads();
     }
 }
 
