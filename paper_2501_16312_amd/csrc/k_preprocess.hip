@@ -288,7 +288,9 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
 
 // ---------------------------------------------------------------------------
 // Exclusive prefix sum of the tile counts (two passes: block totals, then
-// block-local scans, each block adding the totals of the blocks before it).
+// block-local scans, each block adding the totals of the blocks before it;
+// beyond kScanDirectBlocks blocks a single-block prefix of the totals runs
+// in between).
 // ---------------------------------------------------------------------------
 __device__ inline uint64_t block_exclusive_scan_u64(uint64_t x, uint64_t* lds, uint64_t* total) {
     // 256 threads: Hillis-Steele in shared memory
@@ -353,6 +355,33 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
     }
 }
 
+// Many blocks (k_scan_apply would re-add too many block totals): one block
+// turns the block totals into exclusive prefixes first, in place.
+__global__ __launch_bounds__(256) void k_scan_prefix(uint64_t* __restrict__ block_sums,
+                                                     uint64_t* __restrict__ vis_sums, int64_t nblocks,
+                                                     Status* __restrict__ status) {
+    __shared__ uint64_t lds[256];
+    uint64_t carry = 0, vcarry = 0;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += 256) {
+        const int64_t idx = b0 + threadIdx.x;
+        const uint64_t x = (idx < nblocks) ? block_sums[idx] : 0;
+        const uint64_t y = (idx < nblocks) ? vis_sums[idx] : 0;
+        uint64_t total, vtotal;
+        const uint64_t ex = block_exclusive_scan_u64(x, lds, &total);
+        const uint64_t vex = block_exclusive_scan_u64(y, lds, &vtotal);
+        if (idx < nblocks) {
+            block_sums[idx] = carry + ex;
+            vis_sums[idx] = vcarry + vex;
+        }
+        carry += total;
+        vcarry += vtotal;
+    }
+    if (threadIdx.x == 0) {
+        status->n_pairs = carry;
+        status->n_vis = (uint32_t)vcarry;
+    }
+}
+
 // Sum of x[0, count) over the block (every thread gets it).
 __device__ inline uint64_t block_sum_u64(const uint64_t* __restrict__ x, int64_t count, uint64_t* part4) {
     uint64_t s = 0;
@@ -384,18 +413,24 @@ __device__ inline void wave_append(bool take, uint32_t value, uint32_t* __restri
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t count,
                                                     const uint64_t* __restrict__ block_sums,
                                                     const uint64_t* __restrict__ vis_sums, int64_t nblocks,
-                                                    uint32_t* __restrict__ out, int nq,
+                                                    bool prefixed, uint32_t* __restrict__ out, int nq,
                                                     Status* __restrict__ status, uint32_t* __restrict__ big,
                                                     uint32_t* __restrict__ vis, uint32_t* __restrict__ huge) {
     __shared__ uint64_t lds[256];
     __shared__ uint64_t part4[4];
     // this block's start: the sums of the blocks before it (a few hundred
-    // values for a million slots)
-    const uint64_t pre = block_sum_u64(block_sums, blockIdx.x, part4);
-    const uint64_t vpre = block_sum_u64(vis_sums, blockIdx.x, part4);
-    if (blockIdx.x == nblocks - 1 && threadIdx.x == 0) {
-        status->n_pairs = pre + block_sums[blockIdx.x];
-        status->n_vis = (uint32_t)(vpre + vis_sums[blockIdx.x]);
+    // values for a million slots), or the prefix k_scan_prefix wrote
+    uint64_t pre, vpre;
+    if (prefixed) {
+        pre = block_sums[blockIdx.x];
+        vpre = vis_sums[blockIdx.x];
+    } else {
+        pre = block_sum_u64(block_sums, blockIdx.x, part4);
+        vpre = block_sum_u64(vis_sums, blockIdx.x, part4);
+        if (blockIdx.x == nblocks - 1 && threadIdx.x == 0) {
+            status->n_pairs = pre + block_sums[blockIdx.x];
+            status->n_vis = (uint32_t)(vpre + vis_sums[blockIdx.x]);
+        }
     }
     // thread t handles the 16 consecutive elements base + 16 t .. 16 t + 15
     const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * 16;
@@ -434,8 +469,10 @@ hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stre
     uint64_t* vsums = bsums + (nb + 1);
     if (nb > 0) {
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums, status);
+        const bool prefixed = nb > kScanDirectBlocks;
+        if (prefixed) hipLaunchKernelGGL(k_scan_prefix, dim3(1), dim3(256), 0, stream, bsums, vsums, nb, status);
         hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, stream, tiles, count, bsums, vsums, nb,
-                           offsets, nq, status, big, reinterpret_cast<uint32_t*>(ws + L.vis),
+                           prefixed, offsets, nq, status, big, reinterpret_cast<uint32_t*>(ws + L.vis),
                            reinterpret_cast<uint32_t*>(ws + L.huge));
     } else {
         hipLaunchKernelGGL(k_status_empty, dim3(1), dim3(64), 0, stream, status);

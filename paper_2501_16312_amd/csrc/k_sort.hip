@@ -593,20 +593,58 @@ __global__ __launch_bounds__(256) void k_order_count(const uint2* __restrict__ r
     if (threadIdx.x == 0) sums[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
+// Many blocks: one block turns the per-block counts into exclusive
+// prefixes in place, the total after them.
+__global__ __launch_bounds__(1024) void k_order_prefix(uint32_t* __restrict__ sums, int64_t nblocks,
+                                                       const Status* __restrict__ status, uint64_t capacity) {
+    __shared__ uint32_t wsum[16];
+    if (status->n_pairs > capacity) return;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += 1024) {
+        const int64_t idx = b0 + t;
+        const uint32_t x = (idx < nblocks) ? sums[idx] : 0u;
+        uint32_t incl = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t wb = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            wb += (w < wave) ? wsum[w] : 0u;
+            tot += wsum[w];
+        }
+        if (idx < nblocks) sums[idx] = carry + wb + incl - x;
+        carry += tot;
+        __syncthreads();
+    }
+    if (t == 0) sums[nblocks] = carry;
+}
+
 __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ ranges, int64_t n_tiles,
                                                      const Status* __restrict__ status, uint64_t capacity,
                                                      const uint32_t* __restrict__ sums, int64_t nblocks,
-                                                     uint32_t* __restrict__ order) {
+                                                     bool prefixed, uint32_t* __restrict__ order) {
     __shared__ uint32_t red[2][4];
     __shared__ uint32_t wsum[4];
     if (status->n_pairs > capacity) return;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     // heavy tiles before this block, and in all
     uint32_t before = 0, total = 0;
-    for (int64_t b = t; b < nblocks; b += 256) {
-        const uint32_t x = sums[b];
-        total += x;
-        if (b < (int64_t)blockIdx.x) before += x;
+    if (prefixed) {
+        if (t == 0) {
+            before = sums[blockIdx.x];
+            total = sums[nblocks];
+        }
+    } else {
+        for (int64_t b = t; b < nblocks; b += 256) {
+            const uint32_t x = sums[b];
+            total += x;
+            if (b < (int64_t)blockIdx.x) before += x;
+        }
     }
     for (int off = 32; off >= 1; off >>= 1) {
         before += __shfl_xor(before, off, 64);
@@ -730,8 +768,10 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
         uint32_t* osums = reinterpret_cast<uint32_t*>(vws + L.order_sums);
         const int64_t ob = (nt + kScanItems - 1) / kScanItems;
         hipLaunchKernelGGL(k_order_count, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums);
+        const bool prefixed = ob > kOrderDirectBlocks;
+        if (prefixed) hipLaunchKernelGGL(k_order_prefix, dim3(1), dim3(1024), 0, stream, osums, ob, status, cap);
         hipLaunchKernelGGL(k_order_write, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums, ob,
-                           order);
+                           prefixed, order);
     }
     if (!radix) {
         // per-list sort from (kin, vin) into (kout, vout)

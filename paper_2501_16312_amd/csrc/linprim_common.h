@@ -99,6 +99,13 @@ struct PairLayout {
 };
 
 constexpr int kScanItems = 4096;     // elements per scan block (256 threads x 16)
+// Up to this many scan blocks, each block adds the totals of the blocks
+// before it itself (8192 blocks: 32M slots); beyond, a single block turns
+// the totals into prefixes first.
+constexpr int64_t kScanDirectBlocks = 8192;
+// The same choice for the render order's per-block counts of tiles (256
+// blocks: 1M tiles).
+constexpr int64_t kOrderDirectBlocks = 256;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 4;        // keys per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;

@@ -1,0 +1,78 @@
+"""Prefix paths taken only at large sizes (GPU).
+
+* More than 8192 scan blocks (32M (view, primitive) slots): a single block
+  turns the block totals into prefixes before the block-local scans.  The
+  pair offsets must equal the exclusive prefix sum of the tile counts and
+  the pair count their sum (the definition of the scan, Sec. 3.2 "Global
+  Sorting and Tiling").
+* More than 256 blocks of tiles (1M tiles) in the render order: images of
+  40 full-HD views rendered in one call equal those rendered one view at a
+  time (the order only schedules waves), and the sorted pairs equal the
+  oracle's."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2501_16312_amd import linprim as L
+from paper_2501_16312_amd import scenes
+from paper_2501_16312_amd.render import Rasterizer
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _ws_view(ws, base, addr, count, dtype, itemsize):
+    off = addr - base
+    return ws[off: off + count * itemsize].view(dtype)
+
+
+def test_scan_beyond_direct_blocks():
+    n, views = 1_100_000, 32                    # 35.2M slots -> 8594 scan blocks
+    _say(f"scan prefix path: {n} x {views} slots")
+    sc = scenes.uniform_octahedra(n, seed=5, box=1.0, dmin=0.002, dmax=0.01)
+    cams = [scenes.look_at((3 * np.cos(a), 0.4, 3 * np.sin(a)), (0, 0, 0), 64, 48)
+            for a in np.linspace(0, 2 * np.pi, views, endpoint=False)]
+    prims = L.Prims.from_scene(sc)
+    rast = Rasterizer(sc.kind, sc.n, cams, tile=8)
+    n_pairs = rast.preprocess(prims, sync_count=True)
+    torch.cuda.synchronize()
+    ptr = L.linprim_debug_pointers(prims, rast.cams_c, rast.tune, rast.view_ws, rast.pair_ws, rast.max_pairs)
+    base = rast.view_ws.data_ptr()
+    vn = n * views
+    tiles = _ws_view(rast.view_ws, base, ptr["tiles"], vn, torch.int32, 4).to(torch.int64)
+    offs = _ws_view(rast.view_ws, base, ptr["offsets"], vn, torch.int32, 4).to(torch.int64) & 0xFFFFFFFF
+    ref = torch.cumsum(tiles, 0) - tiles
+    _say(f"  pairs {n_pairs}, visible slots {int((tiles > 0).sum())}")
+    assert n_pairs == int(tiles.sum())
+    assert torch.equal(offs, ref)
+    assert int((tiles > 0).sum()) > 100_000
+
+
+def test_render_order_beyond_direct_blocks(oracle_mod):
+    _say("render order prefix path: 40 x 1920x1080")
+    sc = scenes.uniform_octahedra(2000, seed=8, box=1.0, dmin=0.01, dmax=0.08)
+    cams = [scenes.look_at((3 * np.cos(a), 0.3, 3 * np.sin(a)), (0, 0, 0), 1920, 1080)
+            for a in np.linspace(0, 2 * np.pi, 40, endpoint=False)]
+    n_tiles = sum(((c.width + 7) // 8) * ((c.height + 7) // 8) for c in cams)
+    assert n_tiles > 256 * 4096
+    prims = L.Prims.from_scene(sc)
+    rast = Rasterizer(sc.kind, sc.n, cams, tile=8)
+    rgb, _, _ = rast.forward(prims, (0.1, 0.2, 0.3))
+    torch.cuda.synchronize()
+    ptr = L.linprim_debug_pointers(prims, rast.cams_c, rast.tune, rast.view_ws, rast.pair_ws, rast.max_pairs)
+    pb = rast.pair_ws.data_ptr()
+    keys = _ws_view(rast.pair_ws, pb, ptr["keys"], rast.n_pairs, torch.int64, 8).cpu().numpy().view(np.uint64)
+    vals = _ws_view(rast.pair_ws, pb, ptr["values"], rast.n_pairs, torch.int32, 4).cpu().numpy().view(np.uint32)
+    s = oracle_mod.OracleScene(sc, cams, tile=8).sort()
+    _say(f"  pairs {rast.n_pairs}")
+    assert np.array_equal(keys, s["keys"])
+    assert np.array_equal(vals, s["values"])
+    # images do not depend on the order in which waves take the tiles
+    for k in range(0, len(cams), 13):
+        one = Rasterizer(sc.kind, sc.n, [cams[k]], tile=8)
+        rgb1, _, _ = one.forward(prims, (0.1, 0.2, 0.3))
+        start = 3 * sum(c.width * c.height for c in cams[:k])
+        assert torch.equal(rgb[start: start + rgb1.numel()], rgb1)
