@@ -133,6 +133,16 @@ class Staged:
         L.linprim_preprocess_bwd(p, r.cams_c, r.tune, r.view_ws, r.pair_ws, r.max_pairs, self.grads)
         mark(5)
 
+    def time_plain(self, steps):
+        """Wall time of `steps` steps with no events between the stages."""
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.run()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
     def time_stages(self, steps):
         import numpy as np
         import torch
@@ -260,7 +270,10 @@ def single(args, log):
         log(f"{'exact rays: ' if exact else ''}pairs {rast.n_pairs}, capacity {rast.max_pairs}")
         for _ in range(args.warmup):
             st.run()
-        wall, stage_ms = st.time_stages(args.steps)
+        # the timed steps carry no instrumentation; a second pass with events
+        # around each stage gives the stage times
+        wall = st.time_plain(args.steps)
+        _, stage_ms = st.time_stages(args.steps)
         n_pairs, overflow = rast.status()
         if overflow:
             raise RuntimeError("pair capacity overflow in the timed region")
