@@ -74,56 +74,82 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ rgb,
         load_tiles<2>(srcs, W, H, x0, y0, dsts);
     }
     __syncthreads();
-    // row pass: 42 rows x 32 output columns, five statistics
-    for (int k = threadIdx.x; k < kSsimIn * kSsimTile; k += 256) {
-        const int r = k / kSsimTile, c = k % kSsimTile;
-        float a = 0.f, b = 0.f, xx = 0.f, yy = 0.f, xy = 0.f;
+    // row pass: 42 rows x 32 output columns, five statistics; a thread
+    // takes 4 neighbouring outputs of a row and slides over 14 inputs
+    constexpr int RUN = 4, NRUN = kSsimTile / RUN;     // 8 runs per row
+    for (int k = threadIdx.x; k < kSsimIn * NRUN; k += 256) {
+        const int r = k / NRUN, c0 = (k % NRUN) * RUN;
+        float acc[5][RUN];
 #pragma unroll
-        for (int t = 0; t < 11; ++t) {
-            const float xv = xs[r * kSsimIn + c + t], yv = ys[r * kSsimIn + c + t], wt = win.w[t];
-            a += wt * xv;
-            b += wt * yv;
-            xx += wt * xv * xv;
-            yy += wt * yv * yv;
-            xy += wt * xv * yv;
+        for (int q = 0; q < RUN; ++q)
+#pragma unroll
+            for (int m = 0; m < 5; ++m) acc[m][q] = 0.f;
+#pragma unroll
+        for (int i = 0; i < RUN + 10; ++i) {
+            const float xv = xs[r * kSsimIn + c0 + i], yv = ys[r * kSsimIn + c0 + i];
+            const float xx = xv * xv, yy = yv * yv, xy = xv * yv;
+#pragma unroll
+            for (int q = 0; q < RUN; ++q) {
+                const int u = i - q;     // tap of output c0 + q
+                if (u < 0 || u > 10) continue;
+                const float wt = win.w[u];
+                acc[0][q] += wt * xv;
+                acc[1][q] += wt * yv;
+                acc[2][q] += wt * xx;
+                acc[3][q] += wt * yy;
+                acc[4][q] += wt * xy;
+            }
         }
-        hs[0][k] = a;
-        hs[1][k] = b;
-        hs[2][k] = xx;
-        hs[3][k] = yy;
-        hs[4][k] = xy;
+#pragma unroll
+        for (int q = 0; q < RUN; ++q)
+#pragma unroll
+            for (int m = 0; m < 5; ++m) hs[m][r * kSsimTile + c0 + q] = acc[m][q];
     }
     __syncthreads();
+    // column pass: a thread takes 4 neighbouring rows of one column
+    // (lanes run along a row, so the map stores are coalesced)
     float ssum = 0.f, l1 = 0.f;
+    {
+        const int c = threadIdx.x % kSsimTile, r0 = (threadIdx.x / kSsimTile) * RUN;   // 8 x 4 rows
+        float acc[5][RUN];
 #pragma unroll
-    for (int k = threadIdx.x; k < kSsimTile * kSsimTile; k += 256) {
-        const int r = k / kSsimTile, c = k % kSsimTile;
-        const int x = x0 + c, y = y0 + r;
-        if (x >= W || y >= H) continue;
-        float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+        for (int q = 0; q < RUN; ++q)
 #pragma unroll
-        for (int t = 0; t < 11; ++t) {
-            const int q = (r + t) * kSsimTile + c;
-            const float wt = win.w[t];
-            mx += wt * hs[0][q];
-            my += wt * hs[1][q];
-            exx += wt * hs[2][q];
-            eyy += wt * hs[3][q];
-            exy += wt * hs[4][q];
+            for (int m = 0; m < 5; ++m) acc[m][q] = 0.f;
+#pragma unroll
+        for (int i = 0; i < RUN + 10; ++i) {
+            float v[5];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) v[m] = hs[m][(r0 + i) * kSsimTile + c];
+#pragma unroll
+            for (int q = 0; q < RUN; ++q) {
+                const int u = i - q;
+                if (u < 0 || u > 10) continue;
+                const float wt = win.w[u];
+#pragma unroll
+                for (int m = 0; m < 5; ++m) acc[m][q] += wt * v[m];
+            }
         }
-        const float A = 2.f * mx * my + kC1;
-        const float B = 2.f * (exy - mx * my) + kC2;
-        const float Cc = mx * mx + my * my + kC1;
-        const float D = (exx - mx * mx) + (eyy - my * my) + kC2;
-        const float icd = 1.0f / (Cc * D);
-        const float s = A * B * icd;
-        const int64_t p = (int64_t)y * W + x;
         float* dm = dmaps + (int64_t)ch * 3 * hw;
-        dm[p] = 2.f * my * (B - A) * icd - 2.f * mx * s / Cc + 2.f * mx * s / D;   // ds/dmx
-        dm[hw + p] = -s / D;                                                      // ds/dE[x^2]
-        dm[2 * hw + p] = 2.f * A * icd;                                           // ds/dE[xy]
-        ssum += s;
-        l1 += fabsf(xs[(r + kSsimHalo) * kSsimIn + c + kSsimHalo] - ys[(r + kSsimHalo) * kSsimIn + c + kSsimHalo]);
+#pragma unroll
+        for (int q = 0; q < RUN; ++q) {
+            const int r = r0 + q;
+            const int x = x0 + c, y = y0 + r;
+            if (x >= W || y >= H) continue;
+            const float mx = acc[0][q], my = acc[1][q], exx = acc[2][q], eyy = acc[3][q], exy = acc[4][q];
+            const float A = 2.f * mx * my + kC1;
+            const float B = 2.f * (exy - mx * my) + kC2;
+            const float Cc = mx * mx + my * my + kC1;
+            const float D = (exx - mx * mx) + (eyy - my * my) + kC2;
+            const float icd = 1.0f / (Cc * D);
+            const float sv = A * B * icd;
+            const int64_t p = (int64_t)y * W + x;
+            dm[p] = 2.f * my * (B - A) * icd - 2.f * mx * sv / Cc + 2.f * mx * sv / D;   // ds/dmx
+            dm[hw + p] = -sv / D;                                                       // ds/dE[x^2]
+            dm[2 * hw + p] = 2.f * A * icd;                                            // ds/dE[xy]
+            ssum += sv;
+            l1 += fabsf(xs[(r + kSsimHalo) * kSsimIn + c + kSsimHalo] - ys[(r + kSsimHalo) * kSsimIn + c + kSsimHalo]);
+        }
     }
     // block sums, fixed order
     red[0][threadIdx.x] = ssum;
@@ -158,44 +184,68 @@ __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ rgb,
         load_tiles<3>(srcs, W, H, x0, y0, dsts);
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < kSsimIn * kSsimTile; k += 256) {
-        const int r = k / kSsimTile, c = k % kSsimTile;
-        float a = 0.f, b = 0.f, d = 0.f;
+    // row pass over the three maps, 4 outputs per thread (sliding window)
+    constexpr int RUN = 4, NRUN = kSsimTile / RUN;
+    for (int k = threadIdx.x; k < kSsimIn * NRUN; k += 256) {
+        const int r = k / NRUN, c0 = (k % NRUN) * RUN;
+        float acc[3][RUN];
 #pragma unroll
-        for (int t = 0; t < 11; ++t) {
-            const int q = r * kSsimIn + c + t;
-            const float wt = win.w[t];
-            a += wt * ts[0][q];
-            b += wt * ts[1][q];
-            d += wt * ts[2][q];
+        for (int q = 0; q < RUN; ++q)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) acc[m][q] = 0.f;
+#pragma unroll
+        for (int i = 0; i < RUN + 10; ++i) {
+            float v[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) v[m] = ts[m][r * kSsimIn + c0 + i];
+#pragma unroll
+            for (int q = 0; q < RUN; ++q) {
+                const int u = i - q;
+                if (u < 0 || u > 10) continue;
+                const float wt = win.w[u];
+#pragma unroll
+                for (int m = 0; m < 3; ++m) acc[m][q] += wt * v[m];
+            }
         }
-        hs[0][k] = a;
-        hs[1][k] = b;
-        hs[2][k] = d;
+#pragma unroll
+        for (int q = 0; q < RUN; ++q)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) hs[m][r * kSsimTile + c0 + q] = acc[m][q];
     }
     __syncthreads();
     const float* X = rgb + ch * hw;
     const float* Y = target + ch * hw;
     float* G = grad + ch * hw;
+    // column pass: 4 neighbouring rows of one column per thread
+    const int c = threadIdx.x % kSsimTile, r0 = (threadIdx.x / kSsimTile) * RUN;
+    float acc[3][RUN];
 #pragma unroll
-    for (int k = threadIdx.x; k < kSsimTile * kSsimTile; k += 256) {
-        const int r = k / kSsimTile, c = k % kSsimTile;
-        const int x = x0 + c, y = y0 + r;
-        if (x >= W || y >= H) continue;
-        float ga = 0.f, gb = 0.f, gc = 0.f;
+    for (int q = 0; q < RUN; ++q)
 #pragma unroll
-        for (int t = 0; t < 11; ++t) {
-            const int q = (r + t) * kSsimTile + c;
-            const float wt = win.w[t];
-            ga += wt * hs[0][q];
-            gb += wt * hs[1][q];
-            gc += wt * hs[2][q];
+        for (int m = 0; m < 3; ++m) acc[m][q] = 0.f;
+#pragma unroll
+    for (int i = 0; i < RUN + 10; ++i) {
+        float v[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v[m] = hs[m][(r0 + i) * kSsimTile + c];
+#pragma unroll
+        for (int q = 0; q < RUN; ++q) {
+            const int u = i - q;
+            if (u < 0 || u > 10) continue;
+            const float wt = win.w[u];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) acc[m][q] += wt * v[m];
         }
+    }
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+        const int x = x0 + c, y = y0 + r0 + q;
+        if (x >= W || y >= H) continue;
         const int64_t p = (int64_t)y * W + x;
         const float xv = X[p], yv = Y[p];
         const float d = xv - yv;
         const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
-        G[p] = l1_scale * sg - ssim_scale * (ga + 2.f * xv * gb + yv * gc);
+        G[p] = l1_scale * sg - ssim_scale * (acc[0][q] + 2.f * xv * acc[1][q] + yv * acc[2][q]);
     }
 }
 
