@@ -406,18 +406,55 @@ __device__ inline void wave_append(bool take, uint32_t value, uint32_t* __restri
     if (take) list[first + __popcll(m & lt_mask)] = value;
 }
 
+// Exclusive scan of two counters over the 256 threads of a block (wave
+// shuffles, then the four wave totals); a and b become the sums over the
+// threads before this one, ta and tb the block totals.
+__device__ inline void block_scan2_u64(uint64_t& a, uint64_t& b, uint64_t* part8, uint64_t& ta, uint64_t& tb) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t ia = a, ib = b;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t ya = __shfl_up(ia, off, 64), yb = __shfl_up(ib, off, 64);
+        if (lane >= off) {
+            ia += ya;
+            ib += yb;
+        }
+    }
+    if (lane == 63) {
+        part8[w] = ia;
+        part8[4 + w] = ib;
+    }
+    __syncthreads();
+    uint64_t pa = 0, pb = 0;
+    for (int k = 0; k < 4; ++k)
+        if (k < w) {
+            pa += part8[k];
+            pb += part8[4 + k];
+        }
+    ta = part8[0] + part8[1] + part8[2] + part8[3];
+    tb = part8[4] + part8[5] + part8[6] + part8[7];
+    a = pa + ia - a;
+    b = pb + ib - b;
+}
+
 // Also lists, in slot order, the slots that touch a tile (for the
 // preprocessing backward), and, in no particular order, those with more than
 // kBigRun gradient records (tile count x groups per tile) and those with
-// more than kHugeRun tiles.
+// more than kHugeRun tiles.  The block's counts are loaded and its offsets
+// and list entries stored coalesced, through LDS; each thread scans 16
+// consecutive slots in between.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t count,
                                                     const uint64_t* __restrict__ block_sums,
                                                     const uint64_t* __restrict__ vis_sums, int64_t nblocks,
                                                     bool prefixed, uint32_t* __restrict__ out, int nq,
                                                     Status* __restrict__ status, uint32_t* __restrict__ big,
                                                     uint32_t* __restrict__ vis, uint32_t* __restrict__ huge) {
-    __shared__ uint64_t lds[256];
+    constexpr int PER = kScanItems / 256;
+    // slot e of the block at e + e / PER: a thread's PER consecutive slots
+    // then fall in distinct banks across the wave
+    __shared__ uint32_t stage[kScanItems + kScanItems / PER];
+    __shared__ uint32_t vstage[kScanItems];
     __shared__ uint64_t part4[4];
+    __shared__ uint64_t part8[8];
     // this block's start: the sums of the blocks before it (a few hundred
     // values for a million slots), or the prefix k_scan_prefix wrote
     uint64_t pre, vpre;
@@ -432,29 +469,46 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
             status->n_vis = (uint32_t)(vpre + vis_sums[blockIdx.x]);
         }
     }
-    // thread t handles the 16 consecutive elements base + 16 t .. 16 t + 15
-    const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)threadIdx.x * 16;
-    uint32_t v[16];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanItems;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = k * 256 + t;
+        const int64_t idx = base + e;
+        stage[e + e / PER] = (idx < count) ? in[idx] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[PER];
     uint64_t s = 0, c = 0;
-    for (int k = 0; k < 16; ++k) {
-        const int64_t idx = base + k;
-        v[k] = (idx < count) ? in[idx] : 0u;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = stage[t * (PER + 1) + k];
         s += v[k];
         c += v[k] ? 1u : 0u;
     }
-    uint64_t total;
-    uint64_t run = pre + block_exclusive_scan_u64(s, lds, &total);
-    uint64_t vrun = vpre + block_exclusive_scan_u64(c, lds, &total);
-    const int lane = threadIdx.x & 63;
+    uint64_t ts, tc;
+    block_scan2_u64(s, c, part8, ts, tc);
+    uint64_t run = pre + s;
+    uint32_t lv = (uint32_t)c;
+    const int lane = t & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int k = 0; k < 16; ++k) {
-        const int64_t idx = base + k;
-        if (idx < count) out[idx] = (uint32_t)run;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const uint32_t idx = (uint32_t)(base + (int64_t)t * PER + k);
+        stage[t * (PER + 1) + k] = (uint32_t)run;
         run += v[k];
-        if (v[k]) vis[vrun++] = (uint32_t)idx;
-        wave_append((int64_t)v[k] * nq > kBigRun, (uint32_t)idx, &status->n_big, big, lane, lt_mask);
-        wave_append(v[k] > (uint32_t)kHugeRun, (uint32_t)idx, &status->n_huge, huge, lane, lt_mask);
+        if (v[k]) vstage[lv++] = idx;
+        wave_append((int64_t)v[k] * nq > kBigRun, idx, &status->n_big, big, lane, lt_mask);
+        wave_append(v[k] > (uint32_t)kHugeRun, idx, &status->n_huge, huge, lane, lt_mask);
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = k * 256 + t;
+        const int64_t idx = base + e;
+        if (idx < count) out[idx] = stage[e + e / PER];
+    }
+    for (int j = t; j < (int)tc; j += 256) vis[vpre + j] = vstage[j];
 }
 
 hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stream) {

@@ -571,7 +571,7 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
 }
 
 // Render order (heavy tiles first).  k_order_count: heavy tiles per block of
-// kScanItems tiles.  k_order_write: tile g goes to position (heavy tiles
+// kOrderItems tiles.  k_order_write: tile g goes to position (heavy tiles
 // before g) if heavy, else H + (light tiles before g), H the heavy total.
 __device__ inline bool heavy_tile(const uint2* __restrict__ ranges, int64_t g, int64_t n_tiles) {
     if (g >= n_tiles) return false;
@@ -584,9 +584,10 @@ __global__ __launch_bounds__(256) void k_order_count(const uint2* __restrict__ r
                                                      uint32_t* __restrict__ sums) {
     __shared__ uint32_t part[4];
     if (status->n_pairs > capacity) return;
-    const int64_t base = (int64_t)blockIdx.x * kScanItems;
+    const int64_t base = (int64_t)blockIdx.x * kOrderItems;
     uint32_t c = 0;
-    for (int k = 0; k < kScanItems / 256; ++k) c += heavy_tile(ranges, base + k * 256 + threadIdx.x, n_tiles) ? 1u : 0u;
+#pragma unroll
+    for (int k = 0; k < kOrderItems / 256; ++k) c += heavy_tile(ranges, base + k * 256 + threadIdx.x, n_tiles) ? 1u : 0u;
     for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
     __syncthreads();
@@ -654,11 +655,12 @@ __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ r
         red[0][wave] = before;
         red[1][wave] = total;
     }
-    // thread t handles the 16 consecutive tiles base + 16 t .. 16 t + 15
-    const int64_t base = (int64_t)blockIdx.x * kScanItems + (int64_t)t * 16;
+    // thread t handles the PER consecutive tiles base + PER t .. PER t + PER - 1
+    constexpr int PER = kOrderItems / 256;
+    const int64_t base = (int64_t)blockIdx.x * kOrderItems + (int64_t)t * PER;
     uint32_t flags = 0, c = 0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
+    for (int k = 0; k < PER; ++k)
         if (heavy_tile(ranges, base + k, n_tiles)) {
             flags |= 1u << k;
             ++c;
@@ -674,7 +676,7 @@ __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ r
     uint32_t hrun = red[0][0] + red[0][1] + red[0][2] + red[0][3] + incl - c;
     for (int w = 0; w < wave; ++w) hrun += wsum[w];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
+    for (int k = 0; k < PER; ++k) {
         const int64_t g = base + k;
         if (g >= n_tiles) break;
         if (flags & (1u << k)) {
@@ -766,7 +768,7 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
     {
         uint32_t* order = reinterpret_cast<uint32_t*>(vws + L.order);
         uint32_t* osums = reinterpret_cast<uint32_t*>(vws + L.order_sums);
-        const int64_t ob = (nt + kScanItems - 1) / kScanItems;
+        const int64_t ob = (nt + kOrderItems - 1) / kOrderItems;
         hipLaunchKernelGGL(k_order_count, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums);
         const bool prefixed = ob > kOrderDirectBlocks;
         if (prefixed) hipLaunchKernelGGL(k_order_prefix, dim3(1), dim3(1024), 0, stream, osums, ob, status, cap);

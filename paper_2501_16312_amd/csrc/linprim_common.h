@@ -103,8 +103,9 @@ constexpr int kScanItems = 4096;     // elements per scan block (256 threads x 1
 // before it itself (8192 blocks: 32M slots); beyond, a single block turns
 // the totals into prefixes first.
 constexpr int64_t kScanDirectBlocks = 8192;
-// The same choice for the render order's per-block counts of tiles (256
-// blocks: 1M tiles).
+// Tiles per block of the render order kernels (256 threads x 4), and the
+// same choice for their per-block counts (256 blocks: 256K tiles).
+constexpr int kOrderItems = 1024;
 constexpr int64_t kOrderDirectBlocks = 256;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 4;        // keys per thread per sort block
