@@ -55,12 +55,13 @@ __global__ __launch_bounds__(256) void k_sum_big(const float* __restrict__ paylo
 #pragma unroll
         for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
         const float4* g = reinterpret_cast<const float4*>(grads + (int64_t)o * NQ * kGradWords);
-        for (int rb = r0 + lane; rb < r1; rb += 128) {
-            // two records per lane per iteration, all ten loads in flight together
-            float4 x[2][kGradWords / 4];
-            bool use[2];
+        for (int rb = r0 + lane; rb < r1; rb += 256) {
+            // four records per lane per iteration, all twenty loads in flight
+            // together (the longest chunk bounds the kernel's time)
+            float4 x[4][kGradWords / 4];
+            bool use[4];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < 4; ++h) {
                 const int r = rb + 64 * h;
                 use[h] = r < r1 && (NQ == 1 || record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx));
 #pragma unroll
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(256) void k_sum_big(const float* __restrict__ paylo
                     x[h][k] = use[h] ? g[(int64_t)r * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 4; ++h)
 #pragma unroll
                 for (int k = 0; k < kGradWords / 4; ++k) {
                     acc[4 * k] += x[h][k].x;
