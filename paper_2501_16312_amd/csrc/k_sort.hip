@@ -721,8 +721,8 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
     const int64_t nt = L.n_tiles_total;
     if (L.n > 0) {
         const int64_t vn = L.n * (int64_t)n_views;
-        // enough 4-wave blocks for the list, at most 1024 (16 waves per CU)
-        const int64_t blocks = (vn + 255) / 256 < 1024 ? (vn + 255) / 256 : 1024;
+        // enough 4-wave blocks for the list, at most 2048 (32 waves per CU)
+        const int64_t blocks = (vn + 255) / 256 < 2048 ? (vn + 255) / 256 : 2048;
         hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(256), 0, stream,
                            reinterpret_cast<const uint32_t*>(vws + L.depth_keys),
                            reinterpret_cast<const uint32_t*>(vws + L.tiles),
