@@ -41,7 +41,7 @@ def _cams():
 
 
 @pytest.mark.parametrize("kind", [OCTA, TETRA])
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 def test_exact_binning_bit_exact(oracle_mod, kind, tile):
     _say(f"exact binning kind={kind} tile={tile}")
     sc = _scene(kind, 700, seed=41)

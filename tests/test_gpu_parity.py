@@ -55,7 +55,7 @@ def _check_sorted(dbg, s, n_pairs):
 
 @pytest.mark.parametrize("radix", [False, True])
 @pytest.mark.parametrize("kind", [OCTA, TETRA])
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 def test_preprocess_and_sort_bit_exact(oracle_mod, kind, tile, radix):
     _say(f"binning kind={kind} tile={tile} radix={radix}")
     sc = _scene_small(kind, 800, seed=5)
