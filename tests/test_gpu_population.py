@@ -36,20 +36,22 @@ def oracle_mod():
     return oracle
 
 
-@pytest.mark.parametrize("kind", [OCTA, TETRA])
-def test_stats_parity(oracle_mod, kind):
-    _say(f"stats kind={kind}")
+@pytest.mark.parametrize("kind,tile", [(OCTA, 8), (TETRA, 8), (OCTA, 16), (TETRA, 32)])
+def test_stats_parity(oracle_mod, kind, tile):
+    """Densification statistics; with 16- and 32-pixel tiles each tile holds
+    several 8x8 groups, whose gradient records the slot backward sums."""
+    _say(f"stats kind={kind} tile={tile}")
     gen = scenes.uniform_octahedra if kind == OCTA else scenes.uniform_tetrahedra
     sc = gen(600, seed=111 + kind, dmin=0.02, dmax=0.15)
     cams = [scenes.look_at((0.2, 0.1, -3.0), (0, 0, 0), 88, 61), scenes.look_at((2.8, 0.5, 0.6), (0, 0, 0), 45, 37)]
     grad = scenes.image_gradient(cams, seed=12)
-    g = GC.gpu_forward(sc, cams, tile=8)
+    g = GC.gpu_forward(sc, cams, tile=tile)
     GC.gpu_backward(g, grad)
     pc = PopulationControl(kind, sc.sh_degree, sc.n)
     pc.accumulate(g["rast"], g["prims"])
     pc.accumulate(g["rast"], g["prims"])             # a second step adds again
     torch.cuda.synchronize()
-    O = oracle_mod.OracleScene(sc, cams, tile=8)
+    O = oracle_mod.OracleScene(sc, cams, tile=tile)
     rb = O.backward(grad.astype(np.float64))
     acc, cnt, rad = np.zeros(sc.n), np.zeros(sc.n), np.zeros(sc.n)
     POP.accumulate_stats(O, acc, cnt, rad)
