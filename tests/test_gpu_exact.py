@@ -116,7 +116,7 @@ def test_exact_tile_size_invariance():
 
 
 @pytest.mark.parametrize("kind", [OCTA, TETRA])
-@pytest.mark.parametrize("tile", [8, 16])
+@pytest.mark.parametrize("tile", [8, 16, 32])
 def test_exact_backward_parity(oracle_mod, kind, tile):
     _say(f"exact backward kind={kind} tile={tile}")
     gen = scenes.uniform_octahedra if kind == OCTA else scenes.uniform_tetrahedra
