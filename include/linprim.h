@@ -228,9 +228,11 @@ int linprim_preprocess_bwd(const linprim_prims *prims, const linprim_camera *cam
  * floats, writes grad = dL/drgb = scale * sign(rgb - target) and, for each
  * block of 1024 elements, the block's share of L into
  * partial[ceil(count / 1024)] (summing the partials gives L; they are for
- * logging, the gradient does not need them).  All DEVICE pointers. */
+ * logging, the gradient does not need them).  All DEVICE pointers.
+ * skip: NULL, or a DEVICE word read when the kernel runs; if it is non-zero
+ * (linprim_step_guard's guard[0] after a pair overflow) nothing is written. */
 int linprim_l1_grad(const float *rgb, const float *target, int64_t count, float scale, float *grad,
-                    float *partial, void *stream);
+                    float *partial, const uint32_t *skip, void *stream);
 
 /* One Adam step (Kingma & Ba; Sec. 3.4) over up to 8 parameter groups in
  * a single launch: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
@@ -267,9 +269,24 @@ int linprim_adam_step(const linprim_adam_group *groups, int32_t n_groups, float 
  * that one captured graph serves every step (the caller updates the two
  * floats between replays).  linprim_adam_step forms them as
  * (float)(1.0 - pow((double)beta, (double)t)); values formed the same way
- * give bit-identical updates. */
+ * give bit-identical updates.  skip: NULL, or a DEVICE word read when the
+ * kernel runs; if it is non-zero no parameter or moment changes (a step
+ * whose pair workspace overflowed has no valid gradient). */
 int linprim_adam_step_dev(const linprim_adam_group *groups, int32_t n_groups, float beta1, float beta2,
-                          float eps, const float *bias_corr, void *stream);
+                          float eps, const float *bias_corr, const uint32_t *skip, void *stream);
+
+/* Guard of a captured training step (preprocess, bin_sort, render, loss,
+ * backward, Adam replayed as one graph): enqueued after linprim_bin_sort, it
+ * writes guard[0] = 1 if that bin_sort overflowed its pair capacity, else 0,
+ * and ORs the same value into guard[1].  guard: DEVICE uint32[2], owned by
+ * the caller, who zeroes guard[1] once and reads it after any number of
+ * replays to learn whether one of them overflowed (the library never clears
+ * it).  Passing guard as `skip` to the loss-gradient and Adam entry points
+ * makes an overflowed step leave the parameters unchanged.  Arguments as
+ * for linprim_render_fwd; errors INVALID_ARG, WORKSPACE_TOO_SMALL. */
+int linprim_step_guard(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
+                       const linprim_tuning *tuning, const void *view_ws, size_t view_ws_bytes, uint32_t *guard,
+                       void *stream);
 
 /* Waits for `stream`; reports the pair count and whether the last bin_sort
  * overflowed its capacity (HOST outputs). */
@@ -288,11 +305,13 @@ int linprim_render_fwd_counted(const linprim_prims *prims, const linprim_camera 
 
 /* linprim_render_fwd plus the depth map of the paper's appendix "Depth and
  * Surface Reconstruction": out_depth [sum_v H_v W_v] (DEVICE float,
- * layout of out_T) receives, per pixel, the depth of the first primitive
- * at whose blending the cumulative opacity 1 - T exceeds 0.5 (T drops
- * below 0.5), read as that primitive's centre camera depth (the float32
- * depth key the lists are sorted by), and 0 where 1 - T never exceeds
- * 0.5.  The accumulated-opacity (alpha) channel is 1 - out_T. */
+ * layout of out_T) receives, per pixel, the distance along the pixel's
+ * viewing ray to the first primitive at whose blending the cumulative
+ * opacity 1 - T exceeds 0.5 (T drops below 0.5), measured to that
+ * primitive's entry point: its entry depth in ray space (whose depth axis
+ * is the distance from the camera), or with LINPRIM_FLAG_EXACT_RAYS the
+ * entry point's distance along the true pixel ray; 0 where 1 - T never
+ * exceeds 0.5.  The accumulated-opacity (alpha) channel is 1 - out_T. */
 int linprim_render_fwd_depth(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
                              const linprim_tuning *tuning, const float *bg, const void *view_ws,
                              size_t view_ws_bytes, const void *pair_ws, size_t pair_ws_bytes,
@@ -437,9 +456,9 @@ size_t linprim_loss_workspace_size(const linprim_camera *cams, int32_t n_views);
 /* dL/dC for the packed view-major images rgb and target (DEVICE, layout of
  * linprim_render_fwd's out_rgb) into grad (DEVICE, same layout; may not
  * alias the inputs); the partial sums of the loss stay in ws.  sign(0) = 0
- * in the L1 term.  Graph-capturable. */
+ * in the L1 term.  Graph-capturable.  skip: as for linprim_l1_grad. */
 int linprim_loss_grad(const float *rgb, const float *target, const linprim_camera *cams, int32_t n_views,
-                      float lambda, void *ws, size_t ws_bytes, float *grad, void *stream);
+                      float lambda, void *ws, size_t ws_bytes, float *grad, const uint32_t *skip, void *stream);
 
 /* Waits for `stream` and returns, in *loss (HOST), sum_v L_v of the last
  * linprim_loss_grad on ws, the partial sums added in double precision. */

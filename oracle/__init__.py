@@ -61,7 +61,7 @@ def _load():
     lib.orc_get_sort.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_render.argtypes = [P, ctypes.c_int] + [ctypes.c_void_p] * 7
     lib.orc_render_band.argtypes = [P, ctypes.c_int] + [ctypes.c_void_p] * 7 + [ctypes.c_int, ctypes.c_int]
-    lib.orc_render_pixels.argtypes = [P, ctypes.c_int, I64] + [ctypes.c_void_p] * 6
+    lib.orc_render_pixels.argtypes = [P, ctypes.c_int, I64] + [ctypes.c_void_p] * 7
     lib.orc_chord.restype = ctypes.c_double
     lib.orc_chord.argtypes = [P, ctypes.c_int, I64, ctypes.c_double, ctypes.c_double, ctypes.c_int]
     lib.orc_mtia.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
@@ -221,7 +221,7 @@ class OracleScene:
         last = np.zeros(npx, np.int64)
         ill = np.zeros(npx, np.uint8)
         cond = np.zeros(npx)
-        counts = np.zeros((len(self.cams), 4), np.int64)
+        counts = np.zeros((len(self.cams), 6), np.int64)
         b = self._bg(bg)
         rc = _load().orc_render(self.h, m, _ptr(b), _ptr(rgb), _ptr(T), _ptr(last), _ptr(ill),
                                 _ptr(cond), _ptr(counts))
@@ -263,7 +263,7 @@ class OracleScene:
         last = np.zeros(npx, np.int64)
         ill = np.zeros(npx, np.uint8)
         cond = np.zeros(npx)
-        counts = np.zeros((len(self.cams), 4), np.int64)
+        counts = np.zeros((len(self.cams), 6), np.int64)
         b = self._bg(bg)
         rc = _load().orc_render_band(self.h, 0, _ptr(b), _ptr(rgb), _ptr(T), _ptr(last), _ptr(ill),
                                      _ptr(cond), _ptr(counts), int(j0), int(j1))
@@ -278,10 +278,11 @@ class OracleScene:
         T = np.zeros(q)
         ill = np.zeros(q, np.uint8)
         ev = np.zeros(q, np.int64)
+        cond = np.zeros(q)
         b = _f64(np.zeros(3) if bg is None else bg).reshape(3)
         _load().orc_render_pixels(self.h, v, q, _ptr(pix), _ptr(b), _ptr(rgb), _ptr(T), _ptr(ill),
-                                  _ptr(ev))
-        return {"rgb": rgb, "T": T, "ill": ill, "evaluated": ev}
+                                  _ptr(ev), _ptr(cond))
+        return {"rgb": rgb, "T": T, "ill": ill, "evaluated": ev, "cond": cond}
 
     def chord(self, v: int, n: int, px: float, py: float, method: str = "mtia") -> float:
         return float(_load().orc_chord(self.h, v, n, px, py, 0 if method == "mtia" else 1))
@@ -298,7 +299,10 @@ class OracleScene:
         if rc != 0:
             raise RuntimeError("oracle backward failed")
         out["sh"] = out["sh"][:, : (self.sh_degree + 1) ** 2]
-        out["ill"] = out["ill"].astype(bool)
+        # bit 0: a discrete decision of a step may differ in float32; bit 1:
+        # the float32 error estimate of the opacity or SH gradient is too large
+        out["ill_bits"] = out["ill"]
+        out["ill"] = out["ill"] != 0
         return out
 
 

@@ -57,14 +57,18 @@
 /* 1/sqrt(3) as a decimal literal (parsed to the nearest double). */
 #define ORC_INV_SQRT3 0.57735026918962576451
 
-/* Conditioning thresholds used to flag pixels whose value cannot be resolved
- * by a float32 evaluation (see orc_render / orc_backward). */
+/* Conditioning thresholds of the parity contract: a decision within these
+ * margins may go either way in float32 (see step_ill and orc_backward). */
 #define ORC_ILL_T 1e-6
 #define ORC_ILL_O 1e-6
 #define ORC_ILL_BARY 1e-5
 #define ORC_ILL_RGB 1e-6
-/* float32 error estimate of one opacity above half the image tolerance */
-#define ORC_ILL_STEEP 5e-6
+/* float32 evaluation errors of a primitive's opacities, weighted as they
+ * enter its opacity and SH gradients, above this fraction of those
+ * gradients (under a third of the gradient tolerance, with its floor)
+ * flag the primitive: e.g. chords that graze its edge are known only to a
+ * few digits in float32 */
+#define ORC_ILL_REL 3e-4
 
 typedef struct {
     double Rw[3][3], tw[3];
@@ -256,11 +260,13 @@ static void ray_jacobian(const orc_view *V, const double t[3], double J[3][3])
 
 /* The 2D anti-aliasing filter (appendix "Anti-Aliasing", filter size in
  * App. G): the corners that lie on the tiling box move outward, parallel to
- * the screen, by the filter size of 0.1 pixel.  An octahedron's ray-space
- * axis vector a_k carries the two corners c +/- a_k, so it moves by half the
- * size (both corners move out by 0.05); a tetrahedron's corner c + a_i moves
- * by the full size.  A corner on two sides of the box moves along both axes.
- * The selection is piecewise constant, so gradients pass through unchanged. */
+ * the screen, so that the box grows by the filter size of 0.1 pixel per
+ * axis.  An octahedron's ray-space axis vector a_k carries the two mirrored
+ * corners c +/- a_k, so it moves by half the size (each side of the box by
+ * 0.05), as App. G states; a tetrahedron's extreme corners move by the same
+ * half size each, so both kinds grow by the same 0.1 per axis.  A corner on
+ * two sides of the box moves along both axes.  The selection is piecewise
+ * constant, so gradients pass through unchanged. */
 #define ORC_AA_SIZE 0.1
 static void antialias_shift(int type, double a[4][3])
 {
@@ -280,8 +286,8 @@ static void antialias_shift(int type, double a[4][3])
             }
             double shift[4] = {0.0, 0.0, 0.0, 0.0};
             for (int i = 0; i < 4; ++i) {
-                if (a[i][ax] == lo) shift[i] -= ORC_AA_SIZE;
-                if (a[i][ax] == hi) shift[i] += ORC_AA_SIZE;
+                if (a[i][ax] == lo) shift[i] -= 0.5 * ORC_AA_SIZE;
+                if (a[i][ax] == hi) shift[i] += 0.5 * ORC_AA_SIZE;
             }
             for (int i = 0; i < 4; ++i) a[i][ax] += shift[i];
         }
@@ -727,6 +733,40 @@ static orc_chord_t chord_mtia_exact(int type, const orc_prep *P, const double D[
     return C;
 }
 
+/* How far the pixel ray passes inside (> 0) or outside (< 0) the nearest
+ * face, in barycentric units: the largest over the faces of
+ * min(u, v, 1 - u - v), with the Moeller-Trumbore algebra of the two chord
+ * routines but without their early exits.  Ray space: origin (rx, ry, 0),
+ * direction +z; exact variant (D != NULL): origin 0, direction D. */
+static double bary_margin(int type, const orc_prep *P, double rx, double ry, const double *D)
+{
+    double Vc[6][3];
+    int F[8][3];
+    const double dz[3] = {0.0, 0.0, 1.0};
+    const double *dir = D ? D : dz;
+    const double org[3] = {D ? 0.0 : rx, D ? 0.0 : ry, 0.0};
+    if (D) memcpy(Vc, P->vc, sizeof(Vc));
+    else prim_corners(type, P, Vc);
+    const int nf = prim_faces(type, F);
+    double best = -HUGE_VAL;
+    for (int f = 0; f < nf; ++f) {
+        const double *V0 = Vc[F[f][0]], *V1 = Vc[F[f][1]], *V2 = Vc[F[f][2]];
+        const double e1[3] = {V1[0] - V0[0], V1[1] - V0[1], V1[2] - V0[2]};
+        const double e2[3] = {V2[0] - V0[0], V2[1] - V0[1], V2[2] - V0[2]};
+        const double h[3] = {dir[1] * e2[2] - dir[2] * e2[1], dir[2] * e2[0] - dir[0] * e2[2],
+                             dir[0] * e2[1] - dir[1] * e2[0]};
+        const double a = e1[0] * h[0] + e1[1] * h[1] + e1[2] * h[2];
+        if (a == 0.0) continue;
+        const double s[3] = {org[0] - V0[0], org[1] - V0[1], org[2] - V0[2]};
+        const double u = (s[0] * h[0] + s[1] * h[1] + s[2] * h[2]) / a;
+        const double q[3] = {s[1] * e1[2] - s[2] * e1[1], s[2] * e1[0] - s[0] * e1[2], s[0] * e1[1] - s[1] * e1[0]};
+        const double v = (dir[0] * q[0] + dir[1] * q[1] + dir[2] * q[2]) / a;
+        const double b = fmin(fmin(u, v), 1.0 - u - v);
+        if (b > best) best = b;
+    }
+    return best;
+}
+
 /* Independent formulation of the exact chord: the same clipping as
  * chord_clip along the line t D in camera space. */
 static double chord_clip_exact(int type, const orc_prep *P, const double D[3])
@@ -975,16 +1015,21 @@ typedef struct {
     double rgb[3], T;
     int64_t last;
     int64_t iterated, evaluated, intersected;
-    int ill;           /* bit 0: value ill-conditioned; bit 1: gradient ill-conditioned */
-    double cond;       /* largest float32 error estimate of a blended opacity */
+    int ill;           /* ORC_BIT_* flags of the pixel's steps and decisions */
+    double cond;       /* float32 error estimate of the pixel's value (sum of T_k est_k) */
+    int64_t amb_k;     /* list index of the first step ending within 1e-6 of the threshold, or -1 */
+    int64_t amb_hits;  /* evaluated primitives whose hit-or-miss decision is ambiguous */
     double depth;      /* depth of the primitive where cumulative opacity first exceeds 0.5 (0: never) */
     int depth_ill;     /* a step leaves T within 1e-6 of 0.5 (the crossing may move in float32) */
 } orc_pix;
 
-/* Appendix "Depth and Surface Reconstruction": a pixel's depth is that of
- * the first primitive along its ray at which the cumulative opacity 1 - T
- * exceeds 0.5.  The primitive's depth is read as its centre's camera z, the
- * value the method sorts by (the float32 depth key). */
+/* Appendix "Depth and Surface Reconstruction": a pixel's depth is the
+ * distance along its viewing ray to the first primitive at which the
+ * cumulative opacity 1 - T exceeds 0.5, i.e. to that primitive's entry hit.
+ * In ray space the third coordinate is the distance from the camera (the
+ * affine map of Sec. 3.2), so the distance is the entry hit's ray-space
+ * depth; without the ray-space approximation it is the entry parameter
+ * along the pixel ray D times |D|. */
 #define ORC_DEPTH_T 0.5
 
 static int in_rect(const orc_prep *P, int i, int j)
@@ -992,68 +1037,108 @@ static int in_rect(const orc_prep *P, int i, int j)
     return i >= P->rect[0] && i <= P->rect[2] && j >= P->rect[1] && j <= P->rect[3];
 }
 
-/* Conditioning of one blended step with respect to float32 evaluation. */
+/* Conditioning flags of the parity contract: a float32 evaluation of the
+ * same arithmetic may legitimately take a different discrete decision.
+ *   bit 0: the pixel's value may differ beyond rounding (a step ends within
+ *          1e-6 of the termination threshold, or an opacity sits within 1e-6
+ *          of the clamp);
+ *   bit 1: a primitive's own gradient may switch form (an active face within
+ *          1e-5 barycentric of an edge, or the clamp);
+ *   bit 2: a hit-or-miss decision may flip (the ray passes within 1e-5
+ *          barycentric of the primitive's silhouette), which moves the last
+ *          blended position and the intersected count but not the value
+ *          beyond rounding (the chord vanishes there);
+ *   bit 3: termination may move to a neighbouring step (subset of bit 0). */
+#define ORC_BIT_VALUE 1
+#define ORC_BIT_GRAD 2
+#define ORC_BIT_HIT 4
+#define ORC_BIT_TERM 8
+/* bit 4 (a subset of bit 0): the float32 error estimate of the pixel's value
+ * (the transmittance-weighted sum of its steps' opacity estimates) exceeds
+ * the image tolerance, ORC_ILL_F32 */
+#define ORC_BIT_F32 16
+#define ORC_ILL_F32 1e-5
+
+/* Flags of one blended step.  It also estimates the float32 error of the
+ * step's opacity, from its active faces evaluated over the primitive's pixel
+ * rectangle about the rectangle's centre: err_o (if not NULL) receives the
+ * estimate, and cond (if not NULL) accumulates it weighted by the
+ * transmittance in front of the step, a first-order bound on the error it
+ * carries into the pixel's colour and transmittance. */
 static int step_ill(int type, const orc_prep *P, const orc_step *st, double Tafter, double *cond,
-                    const orc_view *V, const double *D)
+                    const orc_view *V, const double *D, double *err_o)
 {
     int ill = 0;
-    if (fabs(Tafter - ORC_T_STOP) <= ORC_ILL_T) ill |= 1;
-    if (fabs((1.0 - st->e) - ORC_O_MAX) <= ORC_ILL_O) ill |= 3;
+    if (fabs(Tafter - ORC_T_STOP) <= ORC_ILL_T) ill |= ORC_BIT_VALUE | ORC_BIT_TERM;
+    if (fabs((1.0 - st->e) - ORC_O_MAX) <= ORC_ILL_O) ill |= ORC_BIT_VALUE | ORC_BIT_GRAD;
     const orc_hit *hs[2] = {&st->ch.h_in, &st->ch.h_out};
-    double steep = 0.0;
+    double bmax = 0.0;
     for (int s = 0; s < 2; ++s) {
-        const orc_hit *H = hs[s];
-        const double b = fmin(fmin(H->u, H->v), 1.0 - H->u - H->v);
-        if (b < ORC_ILL_BARY) ill |= 2;
+        const double b = fmin(fmin(hs[s]->u, hs[s]->v), 1.0 - hs[s]->u - hs[s]->v);
+        if (b < ORC_ILL_BARY) ill |= ORC_BIT_GRAD;
+        if (s == 0 || b > bmax) bmax = b;
     }
+    /* both hits on an edge: the ray grazes the silhouette */
+    if (bmax < ORC_ILL_BARY) ill |= ORC_BIT_HIT;
+    int F[8][3];
+    prim_faces(type, F);
+    const int fs[2] = {st->ch.f_in, st->ch.f_out};
+    /* half-extents of the pixel rectangle about its centre */
+    const double hw = 0.5 * (double)(P->rect[2] - P->rect[0]), hh = 0.5 * (double)(P->rect[3] - P->rect[1]);
+    double est = 0.0;
     if (D) {
-        /* exact variant: a float32 evaluation of a face's hit depth along the
-         * pixel ray errs by about 2^-23 times (its change per pixel across the
-         * rectangle + its distance from the centre's depth) */
-        const int fs[2] = {st->ch.f_in, st->ch.f_out};
-        int F[8][3];
-        prim_faces(type, F);
-        const double span = (double)(P->rect[2] - P->rect[0] + P->rect[3] - P->rect[1] + 2);
+        /* exact variant: the face plane in normal form about the primitive's
+         * centre t_c, n.(X - t_c) = 1, meets the pixel ray X = z_c (1 + tau) D
+         * at tau = (u + 1) / (c - u) with u = n.(t_c - z_c D), c = n.t_c;
+         * u, evaluated in float32 about the rectangle's centre, errs by about
+         * 2^-23 (|du/dx| hw + |du/dy| hh + |u at the centre|) and c by
+         * 2^-23 |c|; tau and the chord z_c |D| (tau_out - tau_in) follow */
+        const double zc = P->tc[2];
+        double Dc[3];
+        pixel_ray(V, 0.5 * (double)(P->rect[0] + P->rect[2]) + 0.5, 0.5 * (double)(P->rect[1] + P->rect[3]) + 0.5,
+                  Dc);
         double err = 0.0;
         for (int s = 0; s < 2; ++s) {
             const double *A = P->vc[F[fs[s]][0]], *B = P->vc[F[fs[s]][1]], *C = P->vc[F[fs[s]][2]];
-            const double n0 = (B[1] - A[1]) * (C[2] - A[2]) - (B[2] - A[2]) * (C[1] - A[1]);
-            const double n1 = (B[2] - A[2]) * (C[0] - A[0]) - (B[0] - A[0]) * (C[2] - A[2]);
-            const double n2 = (B[0] - A[0]) * (C[1] - A[1]) - (B[1] - A[1]) * (C[0] - A[0]);
-            const double nd = n0 * D[0] + n1 * D[1] + n2 * D[2];
-            if (nd == 0.0) { ill |= 3; continue; }
-            const double t = hs[s]->t;
-            const double slope = fabs(t) * (fabs(n0) / V->fx + fabs(n1) / V->fy) / fabs(nd);
-            err += slope * span + fabs(t - P->tc[2]);
+            double nv[3] = {(B[1] - A[1]) * (C[2] - A[2]) - (B[2] - A[2]) * (C[1] - A[1]),
+                            (B[2] - A[2]) * (C[0] - A[0]) - (B[0] - A[0]) * (C[2] - A[2]),
+                            (B[0] - A[0]) * (C[1] - A[1]) - (B[1] - A[1]) * (C[0] - A[0])};
+            const double lev = nv[0] * (A[0] - P->tc[0]) + nv[1] * (A[1] - P->tc[1]) + nv[2] * (A[2] - P->tc[2]);
+            if (lev == 0.0) continue;
+            for (int r = 0; r < 3; ++r) nv[r] /= lev;
+            const double c = nv[0] * P->tc[0] + nv[1] * P->tc[1] + nv[2] * P->tc[2];
+            const double u = c - zc * (nv[0] * D[0] + nv[1] * D[1] + nv[2] * D[2]);
+            const double uc = c - zc * (nv[0] * Dc[0] + nv[1] * Dc[1] + nv[2] * Dc[2]);
+            const double den = c - u;
+            if (den == 0.0) continue;
+            const double du = fabs(zc * nv[0] / V->fx) * hw + fabs(zc * nv[1] / V->fy) * hh + fabs(uc);
+            err += (fabs(c + 1.0) * du + fabs(u + 1.0) * fabs(c)) / (den * den);
         }
-        const double est = P->sigma * st->e * norm3(D) * err * 1.1920928955078125e-7;
-        if (cond && est > *cond) *cond = est;
-        if (est > ORC_ILL_STEEP) ill |= 3;
-        return ill;
-    }
-    /* sensitivity of the chord to a float32-sized perturbation of the faces'
-     * planes over the primitive's pixel rectangle */
-    {
-        double Vc[6][3];
-        int F[8][3];
+        est = P->sigma * st->e * zc * norm3(D) * err * 1.1920928955078125e-7;
+    } else {
+        /* a face plane z = z0 + a (x - xc) + b (y - yc) about the rectangle's
+         * centre (xc, yc), evaluated in float32 over the rectangle, errs by
+         * about 2^-23 (|a| hw + |b| hh + |z0 - l|) in depth (its coefficients
+         * and its arithmetic rounded relative to the largest term); this
+         * moves the opacity by sigma * e times that */
+        double Vc[6][3], terms = 0.0;
         prim_corners(type, P, Vc);
-        prim_faces(type, F);
-        const int fs[2] = {st->ch.f_in, st->ch.f_out};
+        const double xc = 0.5 * (double)(P->rect[0] + P->rect[2]) + 0.5;
+        const double yc = 0.5 * (double)(P->rect[1] + P->rect[3]) + 0.5;
         for (int s = 0; s < 2; ++s) {
             const double *A = Vc[F[fs[s]][0]], *B = Vc[F[fs[s]][1]], *C = Vc[F[fs[s]][2]];
             const double n0 = (B[1] - A[1]) * (C[2] - A[2]) - (B[2] - A[2]) * (C[1] - A[1]);
             const double n1 = (B[2] - A[2]) * (C[0] - A[0]) - (B[0] - A[0]) * (C[2] - A[2]);
             const double n2 = (B[0] - A[0]) * (C[1] - A[1]) - (B[1] - A[1]) * (C[0] - A[0]);
-            if (n2 == 0.0) { ill |= 3; continue; }
-            steep += (fabs(n0) + fabs(n1)) / fabs(n2);
+            if (n2 == 0.0) continue;
+            const double a = -n0 / n2, b = -n1 / n2;
+            const double z0 = A[2] + a * (xc - A[0]) + b * (yc - A[1]) - P->c[2];
+            terms += fabs(a) * hw + fabs(b) * hh + fabs(z0);
         }
-        const double span = (double)(P->rect[2] - P->rect[0] + P->rect[3] - P->rect[1] + 2);
-        /* a float32 plane evaluation over the rectangle errs by about
-         * 2^-23 * slope * span in depth; this moves the opacity by sigma*e times that */
-        const double est = P->sigma * st->e * steep * span * 1.1920928955078125e-7;
-        if (cond && est > *cond) *cond = est;
-        if (est > ORC_ILL_STEEP) ill |= 3;
+        est = P->sigma * st->e * terms * 1.1920928955078125e-7;
     }
+    if (err_o) *err_o = est;
+    if (cond) *cond += st->T * est;
     return ill;
 }
 
@@ -1061,14 +1146,14 @@ static int step_ill(int type, const orc_prep *P, const orc_step *st, double Taft
  * the blended steps are recorded (for the backward pass). */
 static void composite(const orc_scene *S, int v, const int64_t *list, const int64_t *pos, int64_t len,
                       int i, int j, const double bg[3], int use_clip, orc_pix *out,
-                      orc_step *steps, int64_t *nsteps, int64_t last_default)
+                      orc_step *steps, int64_t *nsteps, int64_t last_default, int64_t *amb, int64_t *namb)
 {
     const orc_prep *Pv = S->prep + (int64_t)v * S->n;
     const double rx = i + 0.5, ry = j + 0.5;
     double D[3];
     pixel_ray(&S->views[v], rx, ry, D);
     double T = 1.0, C[3] = {0.0, 0.0, 0.0};
-    int64_t last = last_default, it = 0, ev = 0, hit = 0, ns = 0;
+    int64_t last = last_default, it = 0, ev = 0, hit = 0, ns = 0, amb_k = -1, amb_hits = 0, na = 0;
     int ill = 0, depth_ill = 0;
     double cond = 0.0, depth = 0.0;
     for (int64_t k = 0; k < len; ++k) {
@@ -1085,7 +1170,15 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
             ch = S->exact ? chord_mtia_exact(S->type, P, D) : chord_mtia(S->type, P, rx, ry);
             delta = ch.delta;
         }
-        if (!(delta > 0.0)) continue;
+        if (!(delta > 0.0)) {
+            /* a miss that grazes the silhouette may be a hit in float32 */
+            if (!use_clip && bary_margin(S->type, P, rx, ry, S->exact ? D : NULL) > -ORC_ILL_BARY) {
+                ill |= ORC_BIT_HIT;
+                ++amb_hits;
+                if (amb) amb[na++] = list[k];
+            }
+            continue;
+        }
         ++hit;
         const double e = exp(-P->sigma * delta);
         double o = 1.0 - e;
@@ -1098,18 +1191,21 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
         for (int c = 0; c < 3; ++c) C[c] += T * o * P->rgb[c];
         const double Tbefore = T;
         T = T * (1.0 - o);
-        if (Tbefore >= ORC_DEPTH_T && T < ORC_DEPTH_T) {
-            float zf;
-            memcpy(&zf, &P->key, 4);
-            depth = (double)zf;
-        }
+        if (Tbefore >= ORC_DEPTH_T && T < ORC_DEPTH_T)
+            depth = S->exact ? ch.h_in.t * norm3(D) : ch.h_in.t;
         if (fabs(T - ORC_DEPTH_T) <= ORC_ILL_T) depth_ill = 1;
-        if (!use_clip) ill |= step_ill(S->type, P, &st, T, &cond, &S->views[v], S->exact ? D : NULL);
+        if (!use_clip) {
+            const int sill = step_ill(S->type, P, &st, T, &cond, &S->views[v], S->exact ? D : NULL, NULL);
+            if ((sill & ORC_BIT_TERM) && amb_k < 0) amb_k = k;
+            if (sill & ORC_BIT_HIT) ++amb_hits;
+            ill |= sill;
+        }
         if (steps) steps[ns] = st;
         ++ns;
         last = pos ? pos[k] + 1 : k + 1;
         if (T <= ORC_T_STOP) break;
     }
+    if (cond > ORC_ILL_F32) ill |= ORC_BIT_VALUE | ORC_BIT_F32;
     for (int c = 0; c < 3; ++c) out->rgb[c] = C[c] + T * bg[c];
     out->T = T;
     out->last = last;
@@ -1118,7 +1214,10 @@ static void composite(const orc_scene *S, int v, const int64_t *list, const int6
     out->iterated = it; out->evaluated = ev; out->intersected = hit;
     out->ill = ill;
     out->cond = cond;
+    out->amb_k = amb_k;
+    out->amb_hits = amb_hits;
     if (nsteps) *nsteps = ns;
+    if (namb) *namb = na;
 }
 
 /* Build the per-pixel list: tiled (the sorted tile list, as the paper's
@@ -1172,7 +1271,8 @@ static int64_t pixel_list(const orc_scene *S, int v, int i, int j, int brute, in
  * with the independent clipping chord.  Outputs are packed view by view:
  * rgb [3,H,W], T [H,W], last [H,W] (one past the tile-list position of the
  * last blended primitive, or the tile's list start), ill [H,W], cond [H,W].
- * counts[4*v + 0..3] = iterated, evaluated, intersected, frustum. */
+ * counts[6*v + 0..5] = iterated, evaluated, intersected, frustum, hit-or-miss
+ * decisions that may flip in float32, pixels whose termination may move. */
 static int render_rows(orc_scene *S, int mode, const double *bg, double *rgb, double *T, int64_t *last,
                        uint8_t *ill, double *cond, int64_t *counts, int band_j0, int band_j1);
 
@@ -1200,9 +1300,9 @@ static int render_rows(orc_scene *S, int mode, const double *bg, double *rgb, do
     for (int v = 0; v < S->n_views; ++v) {
         const orc_view *V = &S->views[v];
         const int64_t HW = (int64_t)V->W * V->H;
-        int64_t it = 0, ev = 0, hit = 0, fr = 0;
+        int64_t it = 0, ev = 0, hit = 0, fr = 0, ah = 0, at = 0;
         for (int64_t n = 0; n < S->n; ++n) fr += S->prep[(int64_t)v * S->n + n].valid;
-#pragma omp parallel reduction(+ : it, ev, hit)
+#pragma omp parallel reduction(+ : it, ev, hit, ah, at)
         {
             int64_t *list = NULL, *pos = NULL, cap = 0, start = 0;
             const int jlo = band_j0 > 0 ? band_j0 : 0;
@@ -1212,7 +1312,7 @@ static int render_rows(orc_scene *S, int mode, const double *bg, double *rgb, do
                 for (int i = 0; i < V->W; ++i) {
                     const int64_t len = pixel_list(S, v, i, j, brute, &list, &pos, &cap, &start);
                     orc_pix px;
-                    composite(S, v, list, brute ? NULL : pos, len, i, j, bg + 3 * v, clip, &px, NULL, NULL, start);
+                    composite(S, v, list, brute ? NULL : pos, len, i, j, bg + 3 * v, clip, &px, NULL, NULL, start, NULL, NULL);
                     const int64_t p = (int64_t)j * V->W + i;
                     for (int c = 0; c < 3; ++c) rgb[rgb_base + c * HW + p] = px.rgb[c];
                     T[V->pix_base + p] = px.T;
@@ -1220,12 +1320,14 @@ static int render_rows(orc_scene *S, int mode, const double *bg, double *rgb, do
                     ill[V->pix_base + p] = (uint8_t)px.ill;
                     cond[V->pix_base + p] = px.cond;
                     it += px.iterated; ev += px.evaluated; hit += px.intersected;
+                    ah += px.amb_hits; at += (px.amb_k >= 0);
                 }
             }
             free(list);
             free(pos);
         }
-        counts[4 * v + 0] = it; counts[4 * v + 1] = ev; counts[4 * v + 2] = hit; counts[4 * v + 3] = fr;
+        int64_t *cv = counts + 6 * v;
+        cv[0] = it; cv[1] = ev; cv[2] = hit; cv[3] = fr; cv[4] = ah; cv[5] = at;
         rgb_base += 3 * HW;
     }
     return 0;
@@ -1248,7 +1350,7 @@ int orc_render_depth(void *h, const double *bg, double *depth, uint8_t *depth_il
                 for (int i = 0; i < V->W; ++i) {
                     const int64_t len = pixel_list(S, v, i, j, 0, &list, &pos, &cap, &start);
                     orc_pix px;
-                    composite(S, v, list, pos, len, i, j, bg + 3 * v, 0, &px, NULL, NULL, start);
+                    composite(S, v, list, pos, len, i, j, bg + 3 * v, 0, &px, NULL, NULL, start, NULL, NULL);
                     const int64_t p = V->pix_base + (int64_t)j * V->W + i;
                     depth[p] = px.depth;
                     depth_ill[p] = (uint8_t)(px.depth_ill || (px.ill & 1));
@@ -1263,7 +1365,7 @@ int orc_render_depth(void *h, const double *bg, double *depth, uint8_t *depth_il
 /* Render selected pixels of one view by brute force (for sampled checks on
  * scenes too large to render whole on the CPU).  pix: npix (i, j) pairs. */
 int orc_render_pixels(void *h, int v, int64_t npix, const int32_t *pix, const double *bg,
-                      double *rgb, double *T, uint8_t *ill, int64_t *evaluated)
+                      double *rgb, double *T, uint8_t *ill, int64_t *evaluated, double *cond)
 {
     orc_scene *S = (orc_scene *)h;
     if (!S || !S->prep || v < 0 || v >= S->n_views) return -1;
@@ -1275,11 +1377,12 @@ int orc_render_pixels(void *h, int v, int64_t npix, const int32_t *pix, const do
             const int i = pix[2 * q], j = pix[2 * q + 1];
             const int64_t len = pixel_list(S, v, i, j, 1, &list, &pos, &cap, &start);
             orc_pix px;
-            composite(S, v, list, NULL, len, i, j, bg, 0, &px, NULL, NULL, 0);
+            composite(S, v, list, NULL, len, i, j, bg, 0, &px, NULL, NULL, 0, NULL, NULL);
             for (int c = 0; c < 3; ++c) rgb[3 * q + c] = px.rgb[c];
             T[q] = px.T;
             ill[q] = (uint8_t)px.ill;
             evaluated[q] = px.evaluated;
+            cond[q] = px.cond;
         }
         free(list);
         free(pos);
@@ -1335,6 +1438,8 @@ typedef struct {
     double gV[6][3];   /* dL/d ray-space corner */
     double grgb[3];
     double gsigma;
+    double err[3];     /* per channel, sum over steps of |g_c| T est(o): float32 error scale of grgb */
+    double err_sigma;  /* sum over steps of |dL/do| |1 - sigma chord| est(o) / sigma: that of gsigma */
     int ill;
 } orc_pgrad;
 
@@ -1365,13 +1470,17 @@ static int pixel_backward(const orc_scene *S, int v, int i, int j, const orc_ste
         }
         for (int c = 0; c < 3; ++c) behind[c] += s->T * s->o * P->rgb[c];
         const double Tafter = s->T * (1.0 - s->o);
-        const int sill = step_ill(S->type, P, s, Tafter, NULL, &S->views[v], S->exact ? D : NULL);
-        if (sill) pg->ill = 1;
+        double est = 0.0;
+        const int sill = step_ill(S->type, P, s, Tafter, NULL, &S->views[v], S->exact ? D : NULL, &est);
+        if (sill & (ORC_BIT_GRAD | ORC_BIT_HIT)) pg->ill = 1;
+        for (int c = 0; c < 3; ++c) pg->err[c] += fabs(g[c]) * s->T * est;
         ill |= sill;
         if (s->clamped) continue;
         /* App. E: o = 1 - exp(-sigma (i2 - i1)) */
         const double dLdDelta = dLdo * P->sigma * s->e;
         pg->gsigma += dLdo * s->delta * s->e;
+        /* a chord error d moves delta e by e (1 - sigma delta) d, and est = sigma e d */
+        if (P->sigma > 0.0) pg->err_sigma += fabs(dLdo) * fabs(1.0 - P->sigma * s->delta) * est / P->sigma;
         const int fs[2] = {s->ch.f_in, s->ch.f_out};
         const orc_hit *hs[2] = {&s->ch.h_in, &s->ch.h_out};
         const double sgn[2] = {-1.0, 1.0};
@@ -1402,7 +1511,8 @@ static int pixel_backward(const orc_scene *S, int v, int i, int j, const orc_ste
 /* Preprocessing backward for one primitive in one view: ray space ->
  * camera -> world, then onto the rotation, distances, opacity and SH. */
 static void prim_backward(const orc_scene *S, const orc_view *V, int64_t n, const orc_prep *P,
-                          const orc_pgrad *pg, double *gm, double *gq, double *gd, double *go, double *gsh)
+                          const orc_pgrad *pg, double *gm, double *gq, double *gd, double *go, double *gsh,
+                          double *esh)
 {
     const double *mu = S->means + 3 * n;
     const double *d = S->dists + S->nd * n;
@@ -1532,6 +1642,7 @@ static void prim_backward(const orc_scene *S, const orc_view *V, int64_t n, cons
             const double gr = pg->grgb[ch];
             for (int k = 0; k < S->K; ++k) {
                 gsh[3 * k + ch] += gr * Y[k];
+                esh[3 * k + ch] += pg->err[ch] * fabs(Y[k]);
                 for (int r = 0; r < 3; ++r) gdir[r] += gr * sh[3 * k + ch] * G[k][r];
             }
         }
@@ -1543,9 +1654,12 @@ static void prim_backward(const orc_scene *S, const orc_view *V, int64_t n, cons
 
 /* Full backward: grad_rgb packed like orc_render's rgb.  Pixels whose three
  * gradient channels are all zero are skipped.  Outputs (overwritten):
- * parameter gradients summed over views, and prim_ill[n] = 1 if a pixel with
- * a non-zero gradient reached primitive n through an ill-conditioned step
- * (or its colour sits at the clamp). */
+ * parameter gradients summed over views, and prim_ill[n]: bit 0 if a pixel
+ * with a non-zero gradient reached primitive n through a step whose discrete
+ * decisions may differ in float32 (an active face near an edge, the clamp,
+ * a silhouette graze or near miss, an ambiguous termination at or in front
+ * of it) or its colour sits at the clamp; bit 1 if the float32 error
+ * estimate of its opacity or SH gradient exceeds ORC_ILL_REL of it. */
 int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, double *gq,
                  double *gd, double *go, double *gsh, uint8_t *prim_ill)
 {
@@ -1565,6 +1679,8 @@ int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, 
     free(S->sgrad);
     S->sgrad = (double *)calloc((size_t)S->n_views * (size_t)(n > 0 ? n : 1) * 2, sizeof(double));
     orc_pgrad *acc = (orc_pgrad *)malloc(sizeof(orc_pgrad) * (size_t)(n > 0 ? n : 1));
+    double *err_alpha = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double *err_sh = (double *)calloc((size_t)48 * (size_t)(n > 0 ? n : 1), sizeof(double));
     orc_pgrad *tacc = (orc_pgrad *)calloc((size_t)nthreads * (size_t)(n > 0 ? n : 1), sizeof(orc_pgrad));
     int64_t rgb_base = 0;
     for (int v = 0; v < S->n_views; ++v) {
@@ -1580,6 +1696,7 @@ int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, 
             orc_pgrad *G = tacc + (int64_t)tid * n;
             int64_t *list = NULL, *pos = NULL, cap = 0, start = 0;
             orc_step *steps = NULL;
+            int64_t *amb = NULL;
             int64_t scap = 0;
 #pragma omp for schedule(static)
             for (int j = 0; j < V->H; ++j) {
@@ -1592,21 +1709,25 @@ int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, 
                     if (len > scap) {
                         scap = len;
                         steps = (orc_step *)realloc(steps, sizeof(orc_step) * (size_t)len);
+                        amb = (int64_t *)realloc(amb, sizeof(int64_t) * (size_t)len);
                     }
                     orc_pix px;
-                    int64_t ns = 0;
-                    composite(S, v, list, pos, len, i, j, bg + 3 * v, 0, &px, steps, &ns, start);
+                    int64_t ns = 0, na = 0;
+                    composite(S, v, list, pos, len, i, j, bg + 3 * v, 0, &px, steps, &ns, start, amb, &na);
                     pixel_backward(S, v, i, j, steps, ns, px.T, bg + 3 * v, g, G);
-                    /* a value-ill pixel may blend a different set of primitives
-                     * in float32: every primitive that covers it is suspect */
-                    if (px.ill & 1) {
+                    /* a miss that grazes the silhouette may be a hit in
+                     * float32, with a gradient of its own */
+                    for (int64_t a = 0; a < na; ++a) G[amb[a]].ill = 1;
+                    /* termination may move by a step in float32: the crossing
+                     * primitive and every one behind it may blend or not */
+                    if (px.amb_k >= 0) {
                         const orc_prep *Pv = S->prep + (int64_t)v * n;
-                        for (int64_t k = 0; k < len; ++k)
+                        for (int64_t k = px.amb_k; k < len; ++k)
                             if (in_rect(Pv + list[k], i, j)) G[list[k]].ill = 1;
                     }
                 }
             }
-            free(list); free(pos); free(steps);
+            free(list); free(pos); free(steps); free(amb);
         }
         /* reduce the per-thread buffers in thread order */
         memset(acc, 0, sizeof(orc_pgrad) * (size_t)n);
@@ -1616,6 +1737,8 @@ int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, 
                 for (int k = 0; k < 6; ++k) for (int r = 0; r < 3; ++r) acc[m].gV[k][r] += G[m].gV[k][r];
                 for (int c = 0; c < 3; ++c) acc[m].grgb[c] += G[m].grgb[c];
                 acc[m].gsigma += G[m].gsigma;
+                for (int c = 0; c < 3; ++c) acc[m].err[c] += G[m].err[c];
+                acc[m].err_sigma += G[m].err_sigma;
                 acc[m].ill |= G[m].ill;
             }
         }
@@ -1632,14 +1755,39 @@ int orc_backward(void *h, const double *bg, const double *grad_rgb, double *gm, 
                 const int nc = (S->type == ORC_OCTA) ? 6 : 4;
                 for (int k = 0; k < nc; ++k) { sg[0] += acc[m].gV[k][0]; sg[1] += acc[m].gV[k][1]; }
             }
-            if (acc[m].ill) prim_ill[m] = 1;
+            if (acc[m].ill) prim_ill[m] |= 1;
             for (int c = 0; c < 3; ++c)
-                if (fabs(Pv[m].raw[c]) <= ORC_ILL_RGB && acc[m].grgb[c] != 0.0) prim_ill[m] = 1;
+                if (fabs(Pv[m].raw[c]) <= ORC_ILL_RGB && acc[m].grgb[c] != 0.0) prim_ill[m] |= 1;
             prim_backward(S, V, m, Pv + m, acc + m, gm + 3 * m, gq + 4 * m, gd + S->nd * m, go + m,
-                          gsh + 48 * m);
+                          gsh + 48 * m, err_sh + 48 * m);
+            /* the opacity gradient's share: dsigma/dalpha (R14) times that of gsigma */
+            const double *dm = S->dists + S->nd * m;
+            double dmin = dm[0];
+            for (int k = 1; k < S->nd; ++k) dmin = fmin(dmin, dm[k]);
+            err_alpha[m] += acc[m].err_sigma * ORC_ALPHA_SCALE / ((1.0 - ORC_ALPHA_SCALE * S->opac[m]) * 2.0 * dmin);
         }
         rgb_base += 3 * HW;
     }
+    /* opacity and SH gradients whose float32 error estimate exceeds
+     * ORC_ILL_REL of max(|gradient|, 1e-2 rms of that tensor over the
+     * primitives the gradient reaches), the form of the parity tolerance */
+    double ss = 0.0, ssh = 0.0;
+    int64_t cnt = 0;
+    for (int64_t m = 0; m < n; ++m)
+        if (go[m] != 0.0) {
+            ss += go[m] * go[m];
+            for (int k = 0; k < 3 * S->K; ++k) ssh += gsh[48 * m + k] * gsh[48 * m + k];
+            ++cnt;
+        }
+    const double floor_a = cnt ? 1e-2 * sqrt(ss / (double)cnt) : 0.0;
+    const double floor_sh = cnt ? 1e-2 * sqrt(ssh / ((double)cnt * 3 * S->K)) : 0.0;
+    for (int64_t m = 0; m < n; ++m) {
+        if (err_alpha[m] > ORC_ILL_REL * fmax(fabs(go[m]), floor_a)) prim_ill[m] |= 2;
+        for (int k = 0; k < 3 * S->K; ++k)
+            if (err_sh[48 * m + k] > ORC_ILL_REL * fmax(fabs(gsh[48 * m + k]), floor_sh)) prim_ill[m] |= 2;
+    }
+    free(err_alpha);
+    free(err_sh);
     free(acc);
     free(tacc);
     return 0;

@@ -69,7 +69,7 @@ PairLayout pair_layout(int64_t max_pairs, int digit_bits, int tile) {
 hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
                                 int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                                 float* out_rgb, float* out_T, int32_t* out_last, float* out_depth,
-                                unsigned long long* counters, hipStream_t stream);
+                                const float* means, unsigned long long* counters, hipStream_t stream);
 
 }  // namespace linprim
 
@@ -242,7 +242,7 @@ static int render_fwd_common(const linprim_prims* prims, const linprim_camera* c
     const int in_b = result_buffer(L, tuning);
     hipError_t e = launch_render_fwd_ex(L, (const char*)view_ws, P, (const char*)pair_ws, in_b, prims->type,
                                         exact_rays(tuning), tile_of(tuning), n_views, bg, out_rgb, out_T, out_last,
-                                        out_depth, reinterpret_cast<unsigned long long*>(counters),
+                                        out_depth, prims->means, reinterpret_cast<unsigned long long*>(counters),
                                         (hipStream_t)stream);
     return hip_status(e);
 }
@@ -489,7 +489,7 @@ size_t linprim_loss_workspace_size(const linprim_camera* cams, int32_t n_views) 
 }
 
 int linprim_loss_grad(const float* rgb, const float* target, const linprim_camera* cams, int32_t n_views,
-                      float lambda, void* ws, size_t ws_bytes, float* grad, void* stream) {
+                      float lambda, void* ws, size_t ws_bytes, float* grad, const uint32_t* skip, void* stream) {
     if (!rgb || !target || !grad || !ws || !valid_cams(cams, n_views) || !(lambda >= 0.0f && lambda <= 1.0f) ||
         grad == rgb || grad == target)
         return LINPRIM_ERR_INVALID_ARG;
@@ -502,7 +502,7 @@ int linprim_loss_grad(const float* rgb, const float* target, const linprim_camer
     hipError_t e = hipSuccess;
     for (int v = 0; v < n_views && e == hipSuccess; ++v) {
         const int W = cams[v].width, H = cams[v].height;
-        e = launch_ssim_l1(rgb + 3 * px, target + 3 * px, W, H, lambda, dmaps, partial + po, grad + 3 * px,
+        e = launch_ssim_l1(rgb + 3 * px, target + 3 * px, W, H, lambda, dmaps, partial + po, grad + 3 * px, skip,
                            (hipStream_t)stream);
         px += (int64_t)W * H;
         po += (size_t)2 * 3 * ((W + kLossTile - 1) / kLossTile) * ((H + kLossTile - 1) / kLossTile);
@@ -543,13 +543,13 @@ int linprim_loss_value(const void* ws, size_t ws_bytes, const linprim_camera* ca
 }
 
 int linprim_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad, float* partial,
-                    void* stream) {
+                    const uint32_t* skip, void* stream) {
     if (count < 0 || (count > 0 && (!rgb || !target || !grad || !partial))) return LINPRIM_ERR_INVALID_ARG;
-    return hip_status(launch_l1_grad(rgb, target, count, scale, grad, partial, (hipStream_t)stream));
+    return hip_status(launch_l1_grad(rgb, target, count, scale, grad, partial, skip, (hipStream_t)stream));
 }
 
 static int adam_common(const linprim_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps,
-                       int32_t step, const float* bias_corr, void* stream) {
+                       int32_t step, const float* bias_corr, const uint32_t* skip, void* stream) {
     if (!groups || n_groups < 1 || n_groups > 8 || (step < 1 && !bias_corr)) return LINPRIM_ERR_INVALID_ARG;
     AdamGroups G;
     memset(&G, 0, sizeof(G));
@@ -579,18 +579,30 @@ static int adam_common(const linprim_adam_group* groups, int32_t n_groups, float
     if (G.block0[n_groups] > 0x7fffffffLL) return LINPRIM_ERR_INVALID_ARG;
     const double bc1 = bias_corr ? 1.0 : 1.0 - pow((double)beta1, (double)step);
     const double bc2 = bias_corr ? 1.0 : 1.0 - pow((double)beta2, (double)step);
-    return hip_status(launch_adam(G, beta1, beta2, eps, (float)bc1, (float)bc2, bias_corr, (hipStream_t)stream));
+    return hip_status(launch_adam(G, beta1, beta2, eps, (float)bc1, (float)bc2, bias_corr, skip,
+                                  (hipStream_t)stream));
 }
 
 int linprim_adam_step(const linprim_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps,
                       int32_t step, void* stream) {
-    return adam_common(groups, n_groups, beta1, beta2, eps, step, nullptr, stream);
+    return adam_common(groups, n_groups, beta1, beta2, eps, step, nullptr, nullptr, stream);
 }
 
 int linprim_adam_step_dev(const linprim_adam_group* groups, int32_t n_groups, float beta1, float beta2, float eps,
-                          const float* bias_corr, void* stream) {
+                          const float* bias_corr, const uint32_t* skip, void* stream) {
     if (!bias_corr) return LINPRIM_ERR_INVALID_ARG;
-    return adam_common(groups, n_groups, beta1, beta2, eps, 0, bias_corr, stream);
+    return adam_common(groups, n_groups, beta1, beta2, eps, 0, bias_corr, skip, stream);
+}
+
+int linprim_step_guard(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
+                       const linprim_tuning* tuning, const void* view_ws, size_t view_ws_bytes, uint32_t* guard,
+                       void* stream) {
+    if (!prims || !guard || !view_ws || !valid_cams(cams, n_views) || !valid_tuning(tuning))
+        return LINPRIM_ERR_INVALID_ARG;
+    const ViewLayout L = view_layout(prims->n, cams, n_views, tile_of(tuning));
+    if (view_ws_bytes < L.total) return LINPRIM_ERR_WORKSPACE;
+    if (int rc = check_device()) return rc;
+    return hip_status(launch_step_guard(view_ws, L, guard, (hipStream_t)stream));
 }
 
 int linprim_read_status(const void* view_ws, int64_t* pairs_needed, int32_t* overflow, void* stream) {

@@ -59,7 +59,8 @@ __device__ inline void load_tiles(const float* const (&src)[NT], int W, int H, i
 
 __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ rgb, const float* __restrict__ target,
                                                   int W, int H, SsimWindow win, float* __restrict__ dmaps,
-                                                  float* __restrict__ partial) {
+                                                  float* __restrict__ partial, const uint32_t* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ float xs[kSsimIn * kSsimIn], ys[kSsimIn * kSsimIn];
     __shared__ float hs[5][kSsimIn * kSsimTile];
     __shared__ float red[2][256];
@@ -171,7 +172,9 @@ __global__ __launch_bounds__(256) void k_ssim_fwd(const float* __restrict__ rgb,
 
 __global__ __launch_bounds__(256) void k_ssim_bwd(const float* __restrict__ rgb, const float* __restrict__ target,
                                                   int W, int H, SsimWindow win, const float* __restrict__ dmaps,
-                                                  float l1_scale, float ssim_scale, float* __restrict__ grad) {
+                                                  float l1_scale, float ssim_scale, float* __restrict__ grad,
+                                                  const uint32_t* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ float ts[3][kSsimIn * kSsimIn];
     __shared__ float hs[3][kSsimIn * kSsimTile];
     const int ch = blockIdx.z;
@@ -263,13 +266,13 @@ SsimWindow ssim_window() {
 
 // One view [3, H, W]: dmaps [3][3][H][W] scratch, partial [2 * 3 * tiles].
 hipError_t launch_ssim_l1(const float* rgb, const float* target, int W, int H, float lam, float* dmaps,
-                          float* partial, float* grad, hipStream_t s) {
+                          float* partial, float* grad, const uint32_t* skip, hipStream_t s) {
     const SsimWindow win = ssim_window();
     const dim3 grid((unsigned)((W + kSsimTile - 1) / kSsimTile), (unsigned)((H + kSsimTile - 1) / kSsimTile), 3);
-    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, rgb, target, W, H, win, dmaps, partial);
+    hipLaunchKernelGGL(k_ssim_fwd, grid, dim3(256), 0, s, rgb, target, W, H, win, dmaps, partial, skip);
     const float n = 3.0f * (float)W * (float)H;
     hipLaunchKernelGGL(k_ssim_bwd, grid, dim3(256), 0, s, rgb, target, W, H, win, dmaps, (1.0f - lam) / n, lam / n,
-                       grad);
+                       grad, skip);
     return hipGetLastError();
 }
 

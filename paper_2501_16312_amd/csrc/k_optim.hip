@@ -9,7 +9,8 @@ namespace linprim {
 // per-block partial sums of |C - target| go to partial[blockIdx.x].
 __global__ __launch_bounds__(256) void k_l1_grad(const float* __restrict__ rgb, const float* __restrict__ target,
                                                  int64_t count, float scale, float* __restrict__ grad,
-                                                 float* __restrict__ partial) {
+                                                 float* __restrict__ partial, const uint32_t* __restrict__ skip) {
+    if (skip && *skip) return;
     __shared__ float red[4];
     const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     float s = 0.0f;
@@ -49,7 +50,9 @@ __device__ inline void adam_one(float& p, float& m, float& v, float g, float lr,
 // consecutive elements of its group (one 16-byte access per array when the
 // group's arrays are aligned).
 __global__ __launch_bounds__(kAdamBlock) void k_adam(AdamGroups G, float beta1, float beta2, float eps, float bc1_arg,
-                                                     float bc2_arg, const float* __restrict__ bias_corr) {
+                                                     float bc2_arg, const float* __restrict__ bias_corr,
+                                                     const uint32_t* __restrict__ skip) {
+    if (skip && *skip) return;
     const float bc1 = bias_corr ? bias_corr[0] : bc1_arg;
     const float bc2 = bias_corr ? bias_corr[1] : bc2_arg;
     int gi = 0;
@@ -91,19 +94,36 @@ __global__ __launch_bounds__(kAdamBlock) void k_adam(AdamGroups G, float beta1, 
 }
 
 hipError_t launch_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad,
-                          float* partial, hipStream_t s) {
+                          float* partial, const uint32_t* skip, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     const int64_t blocks = (count + 1023) / 1024;
-    hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(256), 0, s, rgb, target, count, scale, grad, partial);
+    hipLaunchKernelGGL(k_l1_grad, dim3((unsigned)blocks), dim3(256), 0, s, rgb, target, count, scale, grad, partial,
+                       skip);
     return hipGetLastError();
 }
 
 hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,
-                       const float* bias_corr, hipStream_t s) {
+                       const float* bias_corr, const uint32_t* skip, hipStream_t s) {
     const int64_t blocks = G.block0[G.count];
     if (blocks <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(kAdamBlock), 0, s, G, beta1, beta2, eps, bc1, bc2,
-                       bias_corr);
+                       bias_corr, skip);
+    return hipGetLastError();
+}
+
+// Step guard of a captured training step: guard[0] = this step's
+// pair-overflow flag, guard[1] |= it (cleared only by the caller).
+__global__ void k_step_guard(const Status* __restrict__ status, uint32_t* __restrict__ guard) {
+    if (threadIdx.x == 0) {
+        const uint32_t ov = status->overflow ? 1u : 0u;
+        guard[0] = ov;
+        guard[1] |= ov;
+    }
+}
+
+hipError_t launch_step_guard(const void* view_ws, const ViewLayout& L, uint32_t* guard, hipStream_t s) {
+    const Status* st = reinterpret_cast<const Status*>((const char*)view_ws + L.status);
+    hipLaunchKernelGGL(k_step_guard, dim3(1), dim3(64), 0, s, st, guard);
     return hipGetLastError();
 }
 

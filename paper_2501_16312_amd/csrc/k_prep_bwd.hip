@@ -215,7 +215,7 @@ __device__ inline void exact_slot_bwd(const Geom& G, const ViewInfo& V, const fl
         gt[1] += nrm[k][1] * w3;
         gt[2] += nrm[k][2] * w3 - nrm[k][0] / V.fx * ga - nrm[k][1] / V.fy * gb;
     }
-    // projected centre: X = fx t_x / t_z + cx, ox = i0 + 1/2 - X
+    // projected centre: X = fx t_x / t_z + cx, ox = (i0 + i1)/2 + 1/2 - X
     gt[0] -= gox * V.fx / tz;
     gt[2] += gox * V.fx * tx / (tz * tz);
     gt[1] -= goy * V.fy / tz;
@@ -358,8 +358,9 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     const ViewInfo& V = views[v];
     Geom G;
     if (!build_geometry(KIND, EXACT, aa != 0, mu, qv, dv, alpha, V, G)) return;
-    const double ox = (double)rc.x + 0.5 - G.c[0];
-    const double oy = (double)rc.y + 0.5 - G.c[1];
+    // the plane origin of the record: the rectangle's centre (see k_preprocess)
+    const double ox = 0.5 * (double)(rc.x + rc.z) + 0.5 - G.c[0];
+    const double oy = 0.5 * (double)(rc.y + rc.w) + 0.5 - G.c[1];
     if (EXACT) {
         // the view-space positional gradient is a ray-space quantity: none here
         stats[vs] = make_float2(0.0f, (float)G.radius);

@@ -77,16 +77,19 @@ __device__ inline bool preprocess_view(bool ok, Geom& G, const float* mu, double
     out[R_I1] = __int_as_float(i1);
     out[R_J1] = __int_as_float(j1);
     out[R_S2] = (float)(sigma * kLog2e);
-    out[R_FI0] = (float)i0;
-    out[R_FJ0] = (float)j0;
-    out[R_FWI] = (float)(i1 - i0);
-    out[R_FWJ] = (float)(j1 - j0);
+    out[R_FI0] = 0.5f * (float)(i0 + i1);
+    out[R_FJ0] = 0.5f * (float)(j0 + j1);
+    out[R_FWI] = 0.5f * (float)(i1 - i0);
+    out[R_FWJ] = 0.5f * (float)(j1 - j0);
     out[R_SIGMA] = (float)sigma;
 
-    // Offsets of the rectangle origin's pixel centre from the ray-space centre:
-    // the render kernels evaluate planes at integer ki = i - i0, kj = j - j0.
-    const double ox = (double)i0 + 0.5 - G.c[0];
-    const double oy = (double)j0 + 0.5 - G.c[1];
+    // Offsets of the rectangle centre's pixel position from the ray-space
+    // centre: the render kernels evaluate planes at the half-integers
+    // ki = i - (i0 + i1)/2, kj = j - (j0 + j1)/2, so that the float32
+    // offsets, and the plane values they multiply, stay within half the
+    // rectangle.
+    const double ox = 0.5 * (double)(i0 + i1) + 0.5 - G.c[0];
+    const double oy = 0.5 * (double)(j0 + j1) + 0.5 - G.c[1];
     if (EXACT) {
         // camera-space planes along the pixel ray X = z_c (1 + tau) D: with
         // the projected centre (G.c[0], G.c[1]) and dx = i + 1/2 - c_x,

@@ -22,7 +22,8 @@
 // exit hits lie on the active lower and upper faces).  Octahedra keep their 8
 // faces as 4 slabs (opposite faces are parallel), tetrahedra their 4 faces
 // split into upper and lower sets.  Planes are stored relative to the
-// primitive's pixel rectangle origin, so ki, kj are small exact integers.
+// centre of the primitive's pixel rectangle, so ki, kj are small exact
+// half-integers.
 #include "linprim_common.h"
 
 namespace linprim {
@@ -177,6 +178,36 @@ __device__ inline float chord_fast(const Rec& R, float ki, float kj) {
     }
 }
 
+// Same chord, also returning the entry depth lo (relative to the centre's
+// ray-space depth) for the depth map.
+template <int KIND>
+__device__ inline float chord_entry(const Rec& R, float ki, float kj, float& lo_out) {
+#pragma clang fp contract(off)
+    if (KIND == LINPRIM_OCTAHEDRON) {
+        float h[4], l[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float u = __builtin_fmaf(R.p[4 * s + 0], ki, R.p[4 * s + 1] * kj);
+            h[s] = u + R.p[4 * s + 2];
+            l[s] = u + R.p[4 * s + 3];
+        }
+        const float hi = fminf(fminf(h[0], h[1]), fminf(h[2], h[3]));
+        const float lo = fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3]));
+        lo_out = lo;
+        return hi - lo;
+    } else {
+        float h[3], l[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            h[s] = __builtin_fmaf(R.p[3 * s + 0], ki, __builtin_fmaf(R.p[3 * s + 1], kj, R.p[3 * s + 2]));
+            l[s] = __builtin_fmaf(R.p[9 + 3 * s + 0], ki, __builtin_fmaf(R.p[9 + 3 * s + 1], kj, R.p[9 + 3 * s + 2]));
+        }
+        const float lo = fmaxf(fmaxf(l[0], l[1]), l[2]);
+        lo_out = lo;
+        return fminf(fminf(h[0], h[1]), h[2]) - lo;
+    }
+}
+
 // Exact variant (no ray space): each plane k bounds the relative depth tau
 // along the pixel ray at (u_k + h) / (c_k - u_k).  Per plane: u, 1/(c - u),
 // the plane's upper and lower bounds (a tetrahedron face is an exit where
@@ -309,9 +340,21 @@ __device__ inline Batch load_batch(const float* __restrict__ base, const uint32_
 // ---------------------------------------------------------------------------
 // Forward.
 // ---------------------------------------------------------------------------
-// Cumulative opacity beyond which a pixel's depth is taken (depth maps of
-// the appendix "Depth and Surface Reconstruction").
+// Depth maps of the appendix "Depth and Surface Reconstruction": the
+// distance along the pixel ray to the entry of the first primitive at which
+// the cumulative opacity exceeds 0.5.  The walk keeps that primitive's entry
+// depth relative to its centre (ray space: the highest lower plane, whose
+// depth axis is the distance from the camera; exact rays: the entry
+// parameter tau); the centre's depth is added once per pixel afterwards.
 constexpr float kDepthT = 0.5f;
+
+__device__ inline double centre_depth(const ViewInfo& V, const float* __restrict__ means, uint32_t prim, bool exact) {
+    const double x = means[3 * (size_t)prim], y = means[3 * (size_t)prim + 1], z = means[3 * (size_t)prim + 2];
+    const double t0 = V.Rw[0] * x + V.Rw[1] * y + V.Rw[2] * z + V.tw[0];
+    const double t1 = V.Rw[3] * x + V.Rw[4] * y + V.Rw[5] * z + V.tw[1];
+    const double t2 = V.Rw[6] * x + V.Rw[7] * y + V.Rw[8] * z + V.tw[2];
+    return exact ? t2 : sqrt(t0 * t0 + t1 * t1 + t2 * t2);
+}
 
 template <int TILE, int KIND, bool COUNT, bool EXACT, bool DEPTH>
 __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ views, int n_views, int64_t n,
@@ -321,7 +364,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
                                                    float* __restrict__ out_rgb, float* __restrict__ out_T,
                                                    int32_t* __restrict__ out_last,
                                                    unsigned long long* __restrict__ counters,
-                                                   const uint32_t* __restrict__ depth_keys,
+                                                   const float* __restrict__ means,
                                                    float* __restrict__ out_depth, const uint32_t* __restrict__ order) {
     if (status->n_pairs > capacity) return;
     constexpr int QX = TILE / 8, NQ = QX * QX;
@@ -338,6 +381,7 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
     bool done = !valid;
     uint32_t ev = 0, hit = 0, term = rg.y;
     uint32_t half = 0xffffffffu;   // list position at which 1 - T first exceeds 0.5
+    float half_entry = 0.0f;       // its entry depth relative to its centre
     const float* base = payload + (size_t)P.v * (size_t)n * kRecordWords;
     bool alive = true;
     uint32_t sink = 0;   // keeps the L2-warming loads alive; never stored
@@ -356,12 +400,15 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
             // 1 - o = 1 exactly, which leaves C and T unchanged.
             const float ki = pxf - R.fi0, kj = pyf - R.fj0;
             // bitwise &: every test is a plain compare, no short-circuit branches
-            const bool inside = !done & (ki >= 0.0f) & (ki <= R.fwi) & (kj >= 0.0f) & (kj <= R.fwj);
-            float dch;
+            const bool inside = !done & (fabsf(ki) <= R.fwi) & (fabsf(kj) <= R.fwj);
+            float dch, entry = 0.0f;
             if (EXACT) {
                 ExactPlanes X;
                 exact_planes<KIND>(R, ki, kj, X);
                 dch = exact_chord(X, rn);
+                entry = X.L;
+            } else if (DEPTH) {
+                dch = chord_entry<KIND>(R, ki, kj, entry);
             } else {
                 dch = chord_fast<KIND>(R, ki, kj);
             }
@@ -376,7 +423,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
             C0 = __builtin_fmaf(w, R.r, C0);
             C1 = __builtin_fmaf(w, R.g, C1);
             C2 = __builtin_fmaf(w, R.b, C2);
-            if (DEPTH) half = (T >= kDepthT && T * onemo < kDepthT) ? e : half;
+            if (DEPTH) {
+                const bool cross = T >= kDepthT && T * onemo < kDepthT;
+                half = cross ? e : half;
+                half_entry = cross ? entry : half_entry;
+            }
             T = T * onemo;
             last = hitp ? (int)e + 1 : last;
             const bool stop = hitp && T <= kTStop;
@@ -424,7 +475,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
         out_last[pix] = last;
         if (DEPTH) {
             float dz = 0.0f;
-            if (half != 0xffffffffu) dz = __uint_as_float(depth_keys[(size_t)P.v * (size_t)n + vals[half]]);
+            if (half != 0xffffffffu) {
+                const double zc = centre_depth(views[P.v], means, vals[half], EXACT);
+                // exact rays: camera depth z_c (1 + tau) times |D|
+                dz = EXACT ? (float)((zc + zc * (double)half_entry) * (double)rn) : (float)(zc + (double)half_entry);
+            }
             out_depth[pix] = dz;
         }
         if (COUNT) {
@@ -541,7 +596,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             // zero gradients.
             float acc[kGradWords];
             const float ki = pxf - R.fi0, kj = pyf - R.fj0;
-            const bool inside = ((int)e < last) & (ki >= 0.0f) & (ki <= R.fwi) & (kj >= 0.0f) & (kj <= R.fwj);
+            const bool inside = ((int)e < last) & (fabsf(ki) <= R.fwi) & (fabsf(kj) <= R.fwj);
             // chord and the active (lowest upper, highest lower) planes,
             // the first one in plane order on ties; the chord is the same
             // number the forward computed
@@ -697,11 +752,11 @@ template <int TILE, int KIND, bool EXACT>
 static void fwd_dispatch(bool count, const ViewLayout& Lv, hipStream_t s, const ViewInfo* views, int nv, int64_t n,
                          const float* payload, const uint32_t* vals, const uint2* ranges, const Status* st,
                          uint64_t cap, const float bg[3], float* rgb, float* T, int32_t* last,
-                         unsigned long long* counters, const uint32_t* keys, float* depth, const uint32_t* order) {
+                         unsigned long long* counters, const float* means, float* depth, const uint32_t* order) {
     const dim3 grid = wave_grid<TILE>(Lv);
 #define LP_K(C_, D_)                                                                                              \
     hipLaunchKernelGGL((k_render_fwd<TILE, KIND, C_, EXACT, D_>), grid, dim3(64), 0, s, views, nv, n, payload, vals, \
-                       ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters, keys, depth, order)
+                       ranges, st, cap, bg[0], bg[1], bg[2], rgb, T, last, counters, means, depth, order)
     if (depth) {
         if (count) LP_K(true, true); else LP_K(false, true);
     } else {
@@ -713,19 +768,18 @@ static void fwd_dispatch(bool count, const ViewLayout& Lv, hipStream_t s, const 
 hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const PairLayout& P, const char* pws,
                                 int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                                 float* out_rgb, float* out_T, int32_t* out_last, float* out_depth,
-                                unsigned long long* counters, hipStream_t stream) {
+                                const float* means, unsigned long long* counters, hipStream_t stream) {
     if (L.n_tiles_total == 0) return hipSuccess;
     const ViewInfo* views = reinterpret_cast<const ViewInfo*>(vws + L.views);
     const float* payload = reinterpret_cast<const float*>(vws + L.payload);
     const uint32_t* vals = reinterpret_cast<const uint32_t*>(pws + (result_in_b ? P.vals_b : P.vals_a));
     const uint2* ranges = reinterpret_cast<const uint2*>(vws + L.ranges);
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
-    const uint32_t* keys = reinterpret_cast<const uint32_t*>(vws + L.depth_keys);
     const uint32_t* order = reinterpret_cast<const uint32_t*>(vws + L.order);
     const uint64_t cap = (uint64_t)P.capacity;
     const bool count = counters != nullptr;
 #define LP_FWD(T_, K_, E_) fwd_dispatch<T_, K_, E_>(count, L, stream, views, n_views, L.n, payload, vals, ranges, st, \
-                                                    cap, bg, out_rgb, out_T, out_last, counters, keys, out_depth, order)
+                                                    cap, bg, out_rgb, out_T, out_last, counters, means, out_depth, order)
 #define LP_FWD_T(K_, E_)                                                       \
     do {                                                                       \
         if (tile == 8) LP_FWD(8, K_, E_);                                      \
@@ -746,7 +800,7 @@ hipError_t launch_render_fwd(const ViewLayout& L, const char* vws, const PairLay
                              int result_in_b, int type, bool exact, int tile, int32_t n_views, const float bg[3],
                              float* out_rgb, float* out_T, int32_t* out_last, hipStream_t stream) {
     return launch_render_fwd_ex(L, vws, P, pws, result_in_b, type, exact, tile, n_views, bg, out_rgb, out_T, out_last,
-                                nullptr, nullptr, stream);
+                                nullptr, nullptr, nullptr, stream);
 }
 
 template <int TILE, int KIND, bool EXACT>

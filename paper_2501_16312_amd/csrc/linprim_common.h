@@ -30,10 +30,12 @@ constexpr int kGradWords = 20;            // backward record per (tile, primitiv
 //   [0..3]  int   pixel rectangle i0, j0, i1, j1 (inclusive); i0 = -1 if culled
 //   [4]     float sigma * log2(e)            (so exp(-sigma d) = exp2(-s2 d))
 //   [5..7]  float rgb
-//   [8..11] float i0, j0, i1 - i0, j1 - j0
+//   [8..11] float the rectangle's centre (i0 + i1)/2, (j0 + j1)/2 and
+//           half-extents (i1 - i0)/2, (j1 - j0)/2 (half-integers, exact)
 //   octahedron:
-//   [12..27] float 4 slabs x (A, B, Dup, Dlo): with ki = i - i0, kj = j - j0
-//            the slab is A ki + B kj + Dlo <= z' <= A ki + B kj + Dup
+//   [12..27] float 4 slabs x (A, B, Dup, Dlo): with ki = i - (i0 + i1)/2,
+//            kj = j - (j0 + j1)/2 the slab is
+//            A ki + B kj + Dlo <= z' <= A ki + B kj + Dup
 //   tetrahedron:
 //   [12..20] float 3 upper planes (A, B, D): z' <= A ki + B kj + D
 //   [21..29] float 3 lower planes (A, B, D): z' >= A ki + B kj + D
@@ -215,12 +217,13 @@ hipError_t launch_mc_noise(int64_t n, float* means, const float* quats, const fl
 // Photometric loss (Sec. 3.4 "Optimization"), one view [3, H, W].
 constexpr int kLossTile = 32;
 hipError_t launch_ssim_l1(const float* rgb, const float* target, int W, int H, float lam, float* dmaps,
-                          float* partial, float* grad, hipStream_t s);
+                          float* partial, float* grad, const uint32_t* skip, hipStream_t s);
 
 hipError_t launch_adam(const AdamGroups& G, float beta1, float beta2, float eps, float bc1, float bc2,
-                       const float* bias_corr, hipStream_t s);
+                       const float* bias_corr, const uint32_t* skip, hipStream_t s);
 hipError_t launch_l1_grad(const float* rgb, const float* target, int64_t count, float scale, float* grad,
-                          float* partial, hipStream_t s);
+                          float* partial, const uint32_t* skip, hipStream_t s);
+hipError_t launch_step_guard(const void* view_ws, const ViewLayout& L, uint32_t* guard, hipStream_t s);
 
 // ----------------------------------------------------------------------------
 // Device helpers.
@@ -326,10 +329,11 @@ struct Geom {
 // binning contract exactly (double precision, fixed order, no contraction).
 // The 2D anti-aliasing filter (appendix "Anti-Aliasing"; filter size 0.1
 // pixel, App. G): the ray-space corners on the tiling box move outward,
-// parallel to the screen, by the filter size; an octahedron's axis vector
-// carries two mirrored corners and moves by half of it.  All corners that
-// attain an extreme move.  The shift is a constant, so gradients with
-// respect to the offsets pass through unchanged.
+// parallel to the screen, so that the box grows by the filter size per
+// axis: an octahedron's axis vector carries two mirrored corners and moves
+// by half of it, and a tetrahedron's extreme corners move by half of it
+// each.  All corners that attain an extreme move.  The shift is a constant,
+// so gradients with respect to the offsets pass through unchanged.
 constexpr double kAaSize = 0.1;
 
 __device__ inline void antialias_shift(int type, double a[4][3]) {
@@ -356,8 +360,8 @@ __device__ inline void antialias_shift(int type, double a[4][3]) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 sh[i] = 0.0;
-                if (a[i][ax] == lo) sh[i] -= kAaSize;
-                if (a[i][ax] == hi) sh[i] += kAaSize;
+                if (a[i][ax] == lo) sh[i] -= 0.5 * kAaSize;
+                if (a[i][ax] == hi) sh[i] += 0.5 * kAaSize;
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i) a[i][ax] += sh[i];

@@ -4,9 +4,11 @@ graph and replayed, with no host work or synchronisation inside a step.
 
 The pair count is data-dependent; the pair workspace is sized once, with
 headroom, from an eager step, and every kernel reads the live count from
-the device.  If a replay needs more pairs than the capacity, the overflow
-flag is set and the render stages leave their outputs untouched; check()
-reports it and the step can be rebuilt with a larger capacity.
+the device.  If a replay needs more pairs than the capacity, the render
+stages leave their outputs untouched, the loss-gradient and Adam kernels
+skip their work (the parameters do not change), and a sticky device flag
+records it: check() raises after any number of replays if one of them
+overflowed, and the step can be rebuilt with a larger capacity.
 """
 from __future__ import annotations
 
@@ -60,6 +62,9 @@ class CapturedStep:
         else:
             self.grad_rgb = grad_rgb.contiguous()
         self.adam = adam
+        # guard[0]: this replay overflowed its pair capacity; guard[1]: some
+        # replay did (only the host clears it)
+        self.guard = torch.zeros(2, dtype=torch.int32, device=self.outs[0].device)
         if adam is not None:
             self.bias_corr = torch.ones(2, dtype=torch.float32, device=self.outs[0].device)
             self.step_count = 0
@@ -74,17 +79,19 @@ class CapturedStep:
         rgb, T, last = self.outs
         L.linprim_preprocess(p, r.cams_c, r.tune, r.view_ws)
         r.bin_sort(p)
+        L.linprim_step_guard(p, r.cams_c, r.tune, r.view_ws, self.guard)
         r.render(p, self.bg, out=self.outs)
         if self.target is not None:
             if self.loss_kind == "l1_ssim":
-                L.linprim_loss_grad(rgb, self.target, r.cams_c, self.loss_ws, self.grad_rgb, self.ssim_lambda)
+                L.linprim_loss_grad(rgb, self.target, r.cams_c, self.loss_ws, self.grad_rgb, self.ssim_lambda,
+                                    skip=self.guard)
             else:
-                L.linprim_l1_grad(rgb, self.target, self.l1_scale, self.grad_rgb, self.partial)
+                L.linprim_l1_grad(rgb, self.target, self.l1_scale, self.grad_rgb, self.partial, skip=self.guard)
         L.linprim_raster_bwd(p, r.cams_c, r.tune, self.bg, r.view_ws, r.pair_ws, r.max_pairs, T, last, self.grad_rgb)
         L.linprim_preprocess_bwd(p, r.cams_c, r.tune, r.view_ws, r.pair_ws, r.max_pairs, self.grads)
         if self.adam is not None:
             a = self.adam
-            L.linprim_adam_step_dev(a["groups"], a["beta1"], a["beta2"], a["eps"], self.bias_corr)
+            L.linprim_adam_step_dev(a["groups"], a["beta1"], a["beta2"], a["eps"], self.bias_corr, skip=self.guard)
 
     def _record_eager(self):
         if self.adam is None:
@@ -109,10 +116,18 @@ class CapturedStep:
         return float(self.partial.sum().item())
 
     def check(self):
+        """Raises if any replay since construction (or the last clear())
+        overflowed its pair capacity; returns the last replay's pair count.
+        Host sync."""
         n, overflow = self.rast.status()
-        if overflow:
-            raise L.LinPrimError(f"pair capacity {self.rast.max_pairs} exceeded ({n} needed); rebuild the step")
+        if overflow or int(self.guard[1].item()):
+            raise L.LinPrimError(f"pair capacity {self.rast.max_pairs} exceeded ({n} needed by the last replay); "
+                                 "those steps changed nothing; rebuild the step")
         return n
+
+    def clear(self):
+        """Forget earlier overflows (enqueued on the current stream)."""
+        self.guard.zero_()
 
 
 class PlainStep:

@@ -77,7 +77,7 @@ EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linpri
            "linprim_render_fwd_depth",
            "linprim_render_bwd", "linprim_raster_bwd", "linprim_preprocess_bwd", "linprim_read_status",
            "linprim_strerror", "linprim_debug_pointers", "linprim_upload_views", "linprim_l1_grad",
-           "linprim_adam_step", "linprim_adam_step_dev", "linprim_accumulate_stats",
+           "linprim_adam_step", "linprim_adam_step_dev", "linprim_step_guard", "linprim_accumulate_stats",
            "linprim_densify_workspace_size", "linprim_densify_plan", "linprim_densify_apply",
            "linprim_loss_workspace_size", "linprim_loss_grad", "linprim_loss_value",
            "linprim_mcmc_workspace_size", "linprim_mcmc_relocate", "linprim_mcmc_dead_count",
@@ -108,11 +108,12 @@ def load(path: str = LIB_PATH):
     lib.linprim_preprocess.argtypes = [pr, cm, I32, tu, P, SZ, P]
     lib.linprim_pair_count.argtypes = [P, ctypes.POINTER(I64), P]
     lib.linprim_upload_views.argtypes = [cm, I32, tu, P, SZ, I64, I32, P]
-    lib.linprim_l1_grad.argtypes = [P, P, I64, ctypes.c_float, P, P, P]
+    lib.linprim_l1_grad.argtypes = [P, P, I64, ctypes.c_float, P, P, P, P]
     lib.linprim_adam_step.argtypes = [ctypes.POINTER(linprim_adam_group), I32, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, I32, P]
     lib.linprim_adam_step_dev.argtypes = [ctypes.POINTER(linprim_adam_group), I32, ctypes.c_float, ctypes.c_float,
-                                          ctypes.c_float, P, P]
+                                          ctypes.c_float, P, P, P]
+    lib.linprim_step_guard.argtypes = [pr, cm, I32, tu, P, SZ, P, P]
     lib.linprim_bin_sort.argtypes = [pr, cm, I32, tu, P, SZ, P, SZ, I64, P]
     lib.linprim_render_fwd.argtypes = [pr, cm, I32, tu, ctypes.POINTER(ctypes.c_float), P, SZ, P, SZ, I64,
                                        P, P, P, P]
@@ -140,7 +141,7 @@ def load(path: str = LIB_PATH):
     lib.linprim_mcmc_noise.argtypes = [I32, I64, stp, P, ctypes.c_float, ctypes.c_float, P]
     lib.linprim_loss_workspace_size.restype = SZ
     lib.linprim_loss_workspace_size.argtypes = [cm, I32]
-    lib.linprim_loss_grad.argtypes = [P, P, cm, I32, ctypes.c_float, P, SZ, P, P]
+    lib.linprim_loss_grad.argtypes = [P, P, cm, I32, ctypes.c_float, P, SZ, P, P, P]
     lib.linprim_loss_value.argtypes = [P, SZ, cm, I32, ctypes.c_float, ctypes.POINTER(ctypes.c_double), P]
     lib.linprim_strerror.restype = ctypes.c_char_p
     lib.linprim_strerror.argtypes = [ctypes.c_int]
@@ -149,7 +150,7 @@ def load(path: str = LIB_PATH):
               lib.linprim_render_fwd_counted, lib.linprim_render_fwd_depth, lib.linprim_render_bwd,
               lib.linprim_raster_bwd,
               lib.linprim_preprocess_bwd, lib.linprim_read_status, lib.linprim_upload_views,
-              lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev,
+              lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev, lib.linprim_step_guard,
               lib.linprim_debug_pointers, lib.linprim_accumulate_stats, lib.linprim_densify_plan,
               lib.linprim_densify_apply, lib.linprim_loss_grad, lib.linprim_loss_value,
               lib.linprim_mcmc_relocate, lib.linprim_mcmc_dead_count, lib.linprim_mcmc_noise,
@@ -193,6 +194,20 @@ class Prims:
         for t in (self.means, self.quats, self.dists, self.opacity, self.sh):
             if t.dtype != torch.float32 or not t.is_cuda:
                 raise LinPrimError("primitive tensors must be float32 on the GPU")
+        if self.kind not in (OCTAHEDRON, TETRAHEDRON):
+            raise LinPrimError(f"unknown primitive type {self.kind}")
+        if not 0 <= self.sh_degree <= 3:
+            raise LinPrimError(f"sh_degree must be 0..3, got {self.sh_degree}")
+        n = int(self.means.shape[0]) if self.means.dim() == 2 else -1
+        nd = 3 if self.kind == OCTAHEDRON else 4
+        K = (self.sh_degree + 1) ** 2
+        want = {"means": (n, 3), "quats": (n, 4), "dists": (n, nd), "opacity": (n,)}
+        for name, shape in want.items():
+            if tuple(getattr(self, name).shape) != shape:
+                raise LinPrimError(f"{name} has shape {tuple(getattr(self, name).shape)}, expected {shape}")
+        if tuple(self.sh.shape) not in ((n, K, 3), (n, 3 * K)):
+            raise LinPrimError(f"sh has shape {tuple(self.sh.shape)}, expected ({n}, {K}, 3) for degree "
+                               f"{self.sh_degree}")
 
     @classmethod
     def from_scene(cls, scene, device="cuda"):
@@ -249,9 +264,9 @@ def linprim_upload_views(cams, tune, view_ws, n: int, kind: int, stream=None):
                                        _stream(stream)), "linprim_upload_views")
 
 
-def linprim_l1_grad(rgb, target, scale: float, grad, partial, stream=None):
+def linprim_l1_grad(rgb, target, scale: float, grad, partial, skip=None, stream=None):
     _check(load().linprim_l1_grad(_ptr(rgb), _ptr(target), rgb.numel(), float(scale), _ptr(grad), _ptr(partial),
-                                  _stream(stream)), "linprim_l1_grad")
+                                  _ptr(skip), _stream(stream)), "linprim_l1_grad")
 
 
 def _adam_groups(groups: list):
@@ -290,10 +305,17 @@ def adam_bias_corrections(beta1: float, beta2: float, step: int):
     return np.float32(1.0 - b1 ** int(step)), np.float32(1.0 - b2 ** int(step))
 
 
-def linprim_adam_step_dev(groups: list, beta1: float, beta2: float, eps: float, bias_corr, stream=None):
+def linprim_adam_step_dev(groups: list, beta1: float, beta2: float, eps: float, bias_corr, skip=None,
+                          stream=None):
     arr = _adam_groups(groups)
     _check(load().linprim_adam_step_dev(arr, len(groups), float(beta1), float(beta2), float(eps), _ptr(bias_corr),
-                                        _stream(stream)), "linprim_adam_step_dev")
+                                        _ptr(skip), _stream(stream)), "linprim_adam_step_dev")
+
+
+def linprim_step_guard(prims: Prims, cams, tune, view_ws, guard, stream=None):
+    p = prims.c()
+    _check(load().linprim_step_guard(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _ptr(view_ws),
+                                     view_ws.numel(), _ptr(guard), _stream(stream)), "linprim_step_guard")
 
 
 def linprim_pair_count(view_ws: torch.Tensor, stream=None) -> int:
@@ -445,9 +467,9 @@ def linprim_loss_workspace_size(cams) -> int:
     return int(load().linprim_loss_workspace_size(cams, len(cams)))
 
 
-def linprim_loss_grad(rgb, target, cams, ws, grad, lam: float = SSIM_LAMBDA, stream=None):
+def linprim_loss_grad(rgb, target, cams, ws, grad, lam: float = SSIM_LAMBDA, skip=None, stream=None):
     _check(load().linprim_loss_grad(_ptr(rgb), _ptr(target), cams, len(cams), float(lam), _ptr(ws), ws.numel(),
-                                    _ptr(grad), _stream(stream)), "linprim_loss_grad")
+                                    _ptr(grad), _ptr(skip), _stream(stream)), "linprim_loss_grad")
 
 
 def linprim_loss_value(ws, cams, lam: float = SSIM_LAMBDA, stream=None) -> float:

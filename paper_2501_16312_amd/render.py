@@ -43,6 +43,10 @@ class Rasterizer:
         self.max_pairs = 0
         self.n_pixels = sum(c.width * c.height for c in self.cams)
         self.n_pairs = 0
+        # bumped by every preprocess: the workspaces then hold another
+        # render's lists, which a pending backward of an earlier render
+        # must not read
+        self.generation = 0
         if self.views_resident:
             L.linprim_upload_views(self.cams_c, self.tune, self.view_ws, self.n, self.kind)
 
@@ -70,6 +74,7 @@ class Rasterizer:
 
     # -- forward
     def preprocess(self, prims: L.Prims, sync_count: bool = True) -> int:
+        self.generation += 1
         L.linprim_preprocess(prims, self.cams_c, self.tune, self.view_ws)
         if sync_count:
             self.n_pairs = L.linprim_pair_count(self.view_ws)
@@ -88,8 +93,8 @@ class Rasterizer:
     def render(self, prims: L.Prims, bg=None, out=None, counters: Optional[torch.Tensor] = None,
                depth: Optional[torch.Tensor] = None):
         """depth: optional float32 [n_pixels] tensor that receives the depth
-        map (centre depth of the primitive at which cumulative opacity first
-        exceeds 0.5, 0 elsewhere)."""
+        map (distance along the pixel ray to the entry of the primitive at
+        which cumulative opacity first exceeds 0.5, 0 elsewhere)."""
         rgb, T, last = out if out is not None else self.alloc_outputs()
         L.linprim_render_fwd(prims, self.cams_c, self.tune, bg, self.view_ws, self.pair_ws, self.max_pairs, rgb,
                              T, last, counters=counters, out_depth=depth)
@@ -140,9 +145,13 @@ class Rasterizer:
 
 
 class LinPrimRender(torch.autograd.Function):
-    """Differentiable render of all views: returns the packed image
-    (view-major, each [3,H,W]).  The forward keeps only the final
-    transmittance and the last blended list position per pixel."""
+    """Differentiable render of all views (Sec. 3.4 backpropagation with the
+    hand-written backward of App. E): returns the packed image (view-major,
+    each [3,H,W]).  The forward keeps only the final transmittance and the
+    last blended list position per pixel; the backward recomputes the rest
+    from the rasterizer's workspaces, so one rasterizer serves one pending
+    backward at a time: running it forward again before this backward raises
+    instead of returning another render's gradients."""
 
     @staticmethod
     def forward(ctx, rast: Rasterizer, kind: int, sh_degree: int, bg, means, quats, dists, opacity, sh):
@@ -150,11 +159,15 @@ class LinPrimRender(torch.autograd.Function):
                         sh_degree)
         rgb, T, last = rast.forward(prims, bg)
         ctx.rast, ctx.prims, ctx.bg = rast, prims, bg
+        ctx.generation = rast.generation
         ctx.save_for_backward(T, last)
         return rgb
 
     @staticmethod
     def backward(ctx, grad_rgb):
+        if ctx.rast.generation != ctx.generation:
+            raise L.LinPrimError("the rasterizer has rendered again since this forward; use one rasterizer per "
+                                 "pending backward")
         T, last = ctx.saved_tensors
         g = ctx.rast.backward(ctx.prims, ctx.bg, T, last, grad_rgb)
         return None, None, None, None, g["means"], g["quats"], g["dists"], g["opacity"], g["sh"]

@@ -1,12 +1,14 @@
 """Writes oracle_counts.json: the FP64 oracle's pixel-primitive pair counts
 (frustum primitives, tile-list length, iterated / evaluated / intersected
 pairs) for the measured workloads, the quantities of the paper's Table 7
-(App. A).  Calls only the oracle and the seeded scene generator.  The
+(App. A), and the oracle's conditioning flags on them.  Calls only the oracle and the seeded scene generator.  The
 roofline of the compositing kernels uses these counts as its work units."""
 import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
@@ -20,10 +22,16 @@ def counts(config, tile):
     O = oracle.OracleScene(sc, cams, tile=tile)
     s = O.sort()
     r = O.render()
-    it, ev, hit, fr = (int(x) for x in r["counts"].sum(0))
+    it, ev, hit, fr, amb_hit, amb_term = (int(x) for x in r["counts"].sum(0))
     return {"frustum": fr, "tile_list": int(len(s["keys"])), "iterated": it, "evaluated": ev,
             "intersected": hit, "pixels": int(sum(c.width * c.height for c in cams)),
-            "value_ill_pixels": int((r["ill"] & 1).sum())}
+            # conditioning flags of the parity contract
+            "value_flag_pixels": int((r["ill"] & 1).sum()),
+            "termination_ambiguous_pixels": amb_term,
+            "float32_estimate_above_tolerance_pixels": int(((r["ill"] & 16) != 0).sum()),
+            "hit_ambiguous_pairs": amb_hit,
+            "float32_value_error_estimate_max": float(r["cond"].max()),
+            "float32_value_error_estimate_median_covered": float(np.median(r["cond"][r["T"] < 1]))}
 
 
 def main():

@@ -29,7 +29,7 @@ def main():
         "pixels": [int(p) for p in pix],
         "rgb": [[float(r["rgb"][c * 16384 + p]) for c in range(3)] for p in pix],
         "T": [float(r["T"][p]) for p in pix],
-        "counts": [int(x) for x in r["counts"][0]],
+        "counts": [int(x) for x in r["counts"][0][:4]],
         "image_sum": float(r["rgb"].sum()),
         "prims": [int(n) for n in prims],
         "grad_means": [[float(x) for x in b["means"][n]] for n in prims],

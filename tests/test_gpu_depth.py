@@ -1,10 +1,11 @@
 """Depth map of the forward pass (appendix "Depth and Surface
 Reconstruction") vs the FP64 oracle, through the C ABI (MI355X only).
 
-The depth is the float32 depth key of the primitive at which cumulative
-opacity first exceeds 0.5, so it is compared bit for bit on every pixel
-the oracle does not flag (a step ending within 1e-6 of 0.5, or a value-ill
-pixel)."""
+The depth is the distance along the pixel ray to the entry of the first
+primitive at which cumulative opacity exceeds 0.5.  Which pixels have a
+depth is compared exactly, and the distance within 1e-5 relative (a float32
+plane evaluation), on every pixel the oracle does not flag (a step ending
+within 1e-6 of 0.5, or a value-ill pixel)."""
 import sys
 
 import numpy as np
@@ -29,6 +30,17 @@ def oracle_mod():
     import oracle
     oracle._load()
     return oracle
+
+
+DEPTH_TOL = 1e-5   # relative, floor 1 world unit
+
+
+def _check_depth(depth, ref, ok, label):
+    got = depth.astype(np.float64)
+    assert np.array_equal(got[ok] > 0, ref[ok] > 0)
+    err = np.abs(got - ref) / np.maximum(ref, 1.0)
+    _say(f"  [{label}] depth max rel err {err[ok].max(initial=0.0):.3e} (all pixels {err.max(initial=0.0):.3e})")
+    assert err[ok].max(initial=0.0) <= DEPTH_TOL
 
 
 def _gpu_depth(sc, cams, tile, bg, exact=False):
@@ -56,8 +68,8 @@ def test_depth_parity(oracle_mod, kind, tile, exact):
     ok = ~d["ill"]
     has = d["depth"] > 0
     _say(f"  covered {has.mean() * 100:.1f}%, flagged {(~ok).mean() * 100:.3f}%")
-    assert has.mean() > 0.2 and ok.mean() > 0.95      # flagged: about 3% of the pixels here
-    assert np.array_equal(depth[ok].astype(np.float64), d["depth"][ok])
+    assert has.mean() > 0.2 and ok.mean() > 0.999
+    _check_depth(depth, d["depth"], ok, f"kind={kind} tile={tile} exact={exact}")
     assert np.all(depth >= 0)
 
 
@@ -67,5 +79,5 @@ def test_depth_config0(oracle_mod):
     g, depth, _, _ = _gpu_depth(sc, cams, 16, (0.0, 0.0, 0.0))
     d = oracle_mod.OracleScene(sc, cams, tile=16).render_depth()
     ok = ~d["ill"]
-    assert np.array_equal(depth[ok].astype(np.float64), d["depth"][ok])
+    _check_depth(depth, d["depth"], ok, "config0")
     assert (d["depth"] > 0).mean() > 0.04

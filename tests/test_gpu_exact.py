@@ -78,19 +78,10 @@ def test_exact_forward_parity(oracle_mod, kind):
     O = oracle_mod.OracleScene(sc, cams, tile=16, exact=True)
     r = O.render(bg=np.asarray(bg))
     r["cams"] = cams
-    good, _, ill = GC.compare_images(g, r, f"exact kind={kind}")
-    assert good <= GC.IMG_TOL
-    # close-up primitives: the oracle flags about 3% of the pixels (the same
-    # share as for this scene in ray space)
-    assert ill < 0.05
-    ok = (r["ill"] & 1) == 0
-    assert np.mean(g["last"][ok] == r["last"][ok]) > 0.999
+    GC.compare_images(g, r, f"exact kind={kind}")
+    GC.compare_last(g, r, f"exact kind={kind}")
     assert (r["T"] < 1).mean() > 0.2
-    ev = int(r["counts"][:, 1].sum())
-    hit = int(r["counts"][:, 2].sum())
-    _say(f"  counts gpu {g['counts'].tolist()} oracle evaluated {ev} intersected {hit}")
-    assert abs(int(g["counts"][1]) - ev) <= max(2, 1e-3 * ev)
-    assert abs(int(g["counts"][2]) - hit) <= max(2, 1e-3 * hit)
+    GC.compare_counts(g["counts"], r["counts"], f"exact kind={kind}")
 
 
 def test_exact_differs_from_ray_space(oracle_mod):
@@ -130,9 +121,6 @@ def test_exact_backward_parity(oracle_mod, kind, tile):
                                                                            bg=np.asarray(bg))
     ok = ~rb["ill"]
     _say(f"  prims ill {rb['ill'].mean() * 100:.2f}%")
-    # a primitive is left out if any pixel reaching it is ill-conditioned
-    # (about 12% of the octahedra here, 3% of the tetrahedra; ray space alike)
-    assert ok.mean() > 0.8
     w = GC.grad_errors(gg, rb, ok, f"exact kind={kind} tile={tile}")
     for k, v in w.items():
         assert v <= GC.GRAD_TOL, k
@@ -147,8 +135,8 @@ def test_exact_config0_parity(oracle_mod):
     O = oracle_mod.OracleScene(sc, cams, tile=16, exact=True)
     r = O.render()
     r["cams"] = cams
-    good, _, ill = GC.compare_images(g, r, "exact config0")
-    assert good <= GC.IMG_TOL and ill < 0.01
+    GC.compare_images(g, r, "exact config0")
+    GC.compare_last(g, r, "exact config0")
     gg = GC.gpu_backward(g, grad)
     rb = O.backward(grad.astype(np.float64))
     ok = ~rb["ill"]
@@ -172,8 +160,13 @@ def test_exact_full_size_sampled(oracle_mod):
     r = O.render_pixels(0, pix)
     hw = cam.width * cam.height
     rgb = np.stack([g["rgb"][c * hw + idx] for c in range(3)], 1)
-    ok = (r["ill"] & 1) == 0
+    term = (r["ill"] & GC.EXCLUDED) != 0
     err = np.maximum(np.abs(rgb - r["rgb"]).max(1), np.abs(g["T"][idx] - r["T"]))
-    _say(f"  sampled max err (ok) {err[ok].max():.3e}, overall {err.max():.3e}, ill {(~ok).mean() * 100:.2f}%")
-    assert err[ok].max() <= GC.IMG_TOL
+    _say(f"  sampled max err: all but excluded {err[~term].max():.3e}, all {err.max():.3e}, "
+         f"excluded (termination or float32 estimate) {term.mean() * 100:.3f}%, largest float32 error estimate "
+         f"{r['cond'].max():.2e}")
+    assert err[~term].max() <= GC.IMG_TOL
+    # the float32 error estimate along true pixel rays is conservative (here
+    # about 20 times the largest error observed), so it excludes more
+    assert term.mean() <= 1e-2
     assert (r["T"] < 1).mean() > 0.05

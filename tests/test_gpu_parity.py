@@ -1,9 +1,13 @@
 """HIP path vs the FP64 oracle through the C ABI (MI355X only).
 
 Bit-exact: pixel rectangles, depth keys, tile counts, offsets, sorted keys
-and values, tile ranges.  Images within 1e-5 absolute and gradients within
-1e-3 relative on well-conditioned pixels / primitives, as flagged by the
-oracle."""
+and values, tile ranges.  Images within 1e-5 absolute on every pixel whose
+termination cannot move in float32 (at most 0.1% of the pixels are
+excluded); the last blended position exactly wherever no termination or
+hit-or-miss decision is ambiguous; gradients within 1e-3 relative on every
+primitive whose own steps are well conditioned and which no ambiguous
+termination can add or drop (at least 95% of the primitives the gradient
+reaches are checked)."""
 import math
 import sys
 
@@ -30,9 +34,14 @@ def oracle_mod():
     return oracle
 
 
-def _scene_small(kind, n=600, seed=3):
+def _scene_small(kind, n=600, seed=3, sh_degree=3):
     gen = scenes.uniform_octahedra if kind == OCTA else scenes.uniform_tetrahedra
-    return gen(n, seed=seed, dmin=0.03, dmax=0.2)
+    sc = gen(n, seed=seed, dmin=0.03, dmax=0.2)
+    if sh_degree != 3:
+        K = (sh_degree + 1) ** 2
+        sc = scenes.Scene(sc.kind, sc.means, sc.quats, sc.dists, sc.opacity, np.ascontiguousarray(sc.sh[:, :K]),
+                          sh_degree)
+    return sc
 
 
 def _oracle_render(oracle_mod, sc, cams, tile, bg):
@@ -114,8 +123,8 @@ def test_many_views(oracle_mod):
     dbg = g["rast"].debug_arrays(g["prims"])
     O, r = _oracle_render(oracle_mod, sc, cams, 8, (0, 0, 0))
     _check_sorted(dbg, O.sort(), g["n_pairs"])
-    good, _, _ = GC.compare_images(g, r, "many views")
-    assert good <= GC.IMG_TOL
+    GC.compare_images(g, r, "many views")
+    GC.compare_last(g, r, "many views")
 
 
 @pytest.mark.parametrize("digit", [4, 5, 7, 8])
@@ -147,19 +156,18 @@ def test_sort_long_lists(oracle_mod, n):
 
 
 # ------------------------------------------------------------ forward
+@pytest.mark.parametrize("sh_degree", [0, 1, 2, 3])
 @pytest.mark.parametrize("kind", [OCTA, TETRA])
-def test_forward_parity_small(oracle_mod, kind):
-    _say(f"forward small kind={kind}")
-    sc = _scene_small(kind, 900, seed=11)
+def test_forward_parity_small(oracle_mod, kind, sh_degree):
+    _say(f"forward small kind={kind} sh_degree={sh_degree}")
+    sc = _scene_small(kind, 900, seed=11, sh_degree=sh_degree)
     cams = [scenes.look_at((0.2, 0.1, -3.0), (0, 0, 0), 88, 61)]   # ragged: not a multiple of the tile
     bg = (0.1, 0.2, 0.3)
-    g = GC.gpu_forward(sc, cams, tile=16, bg=bg)
+    g = GC.gpu_forward(sc, cams, tile=16, bg=bg, counters=True)
     O, r = _oracle_render(oracle_mod, sc, cams, 16, bg)
-    good, _, ill = GC.compare_images(g, r, f"small kind={kind}")
-    assert good <= GC.IMG_TOL
-    assert ill < 0.01
-    ok = (r["ill"] & 1) == 0
-    assert np.mean(g["last"][ok] == r["last"][ok]) > 0.999
+    GC.compare_images(g, r, f"small kind={kind} deg={sh_degree}")
+    GC.compare_last(g, r, f"small kind={kind} deg={sh_degree}")
+    GC.compare_counts(g["counts"], r["counts"], f"small kind={kind} deg={sh_degree}")
     assert (r["T"] < 1).mean() > 0.2
 
 
@@ -168,13 +176,9 @@ def test_forward_parity_config0(oracle_mod):
     sc, cams = scenes.config0()
     g = GC.gpu_forward(sc, cams, tile=16, counters=True)
     O, r = _oracle_render(oracle_mod, sc, cams, 16, (0, 0, 0))
-    good, _, ill = GC.compare_images(g, r, "config0")
-    assert good <= GC.IMG_TOL
-    assert ill < 0.01
-    it, ev, hit, fr = r["counts"][0]
-    _say(f"counts gpu {g['counts'].tolist()} oracle {[it, ev, hit]}")
-    assert abs(int(g["counts"][1]) - ev) <= max(2, 1e-3 * ev)
-    assert abs(int(g["counts"][2]) - hit) <= max(2, 1e-3 * hit)
+    GC.compare_images(g, r, "config0")
+    GC.compare_last(g, r, "config0")
+    GC.compare_counts(g["counts"], r["counts"], "config0")
 
 
 def test_tile_size_invariance(oracle_mod):
@@ -199,15 +203,16 @@ def test_multiview_equals_single_views(oracle_mod):
         assert np.array_equal(multi["rgb"][off:off + n], single["rgb"])
         off += n
     O, r = _oracle_render(oracle_mod, sc, cams, 16, (0, 0, 0))
-    good, _, _ = GC.compare_images(multi, r, "multiview")
-    assert good <= GC.IMG_TOL
+    GC.compare_images(multi, r, "multiview")
+    GC.compare_last(multi, r, "multiview")
 
 
 # ------------------------------------------------------------ backward
+@pytest.mark.parametrize("sh_degree", [0, 1, 2, 3])
 @pytest.mark.parametrize("kind", [OCTA, TETRA])
-def test_backward_parity_small(oracle_mod, kind):
-    _say(f"backward small kind={kind}")
-    sc = _scene_small(kind, 500, seed=23)
+def test_backward_parity_small(oracle_mod, kind, sh_degree):
+    _say(f"backward small kind={kind} sh_degree={sh_degree}")
+    sc = _scene_small(kind, 500, seed=23, sh_degree=sh_degree)
     cams = [scenes.look_at((0.2, 0.1, -3.0), (0, 0, 0), 72, 56)]
     bg = (0.3, 0.1, 0.2)
     grad = scenes.image_gradient(cams, seed=4)
@@ -217,7 +222,7 @@ def test_backward_parity_small(oracle_mod, kind):
     rb = O.backward(grad.astype(np.float64), bg=np.asarray(bg))
     ok = ~rb["ill"]
     _say(f"prims ill {rb['ill'].mean() * 100:.2f}%")
-    w = GC.grad_errors(gg, rb, ok, f"small kind={kind}")
+    w = GC.grad_errors(gg, rb, ok, f"small kind={kind} deg={sh_degree}")
     for k, v in w.items():
         assert v <= GC.GRAD_TOL, k
 
@@ -256,19 +261,23 @@ def test_backward_multiview_parity(oracle_mod, kind):
         assert v <= GC.GRAD_TOL, k
 
 
-def test_backward_tile_sizes_agree(oracle_mod):
-    _say("backward tile sizes")
-    sc = _scene_small(OCTA, 400, seed=29)
-    cams = [scenes.look_at((0, 0.2, -3.0), (0, 0, 0), 64, 40)]
+@pytest.mark.parametrize("kind", [OCTA, TETRA])
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_backward_tile_sizes(oracle_mod, kind, tile):
+    """Ray-space backward against the oracle at every tile size (several
+    8x8 groups per tile at 16 and 32), on an image that is not a multiple
+    of the tile."""
+    _say(f"backward tile={tile} kind={kind}")
+    sc = _scene_small(kind, 400, seed=29)
+    cams = [scenes.look_at((0, 0.2, -3.0), (0, 0, 0), 70, 45)]
+    bg = (0.05, 0.1, 0.2)
     grad = scenes.image_gradient(cams, seed=6)
-    res = []
-    for t in (8, 16, 32):
-        g = GC.gpu_forward(sc, cams, tile=t)
-        res.append(GC.gpu_backward(g, grad))
-    for k in ("means", "opacity", "sh"):
-        scale = np.abs(res[0][k]).max() + 1e-12
-        assert np.abs(res[0][k] - res[1][k]).max() <= 1e-4 * scale
-        assert np.abs(res[0][k] - res[2][k]).max() <= 1e-4 * scale
+    g = GC.gpu_forward(sc, cams, tile=tile, bg=bg)
+    gg = GC.gpu_backward(g, grad, bg)
+    rb = oracle_mod.OracleScene(sc, cams, tile=tile).backward(grad.astype(np.float64), bg=np.asarray(bg))
+    w = GC.grad_errors(gg, rb, ~rb["ill"], f"tile={tile} kind={kind}")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k
 
 
 @pytest.mark.parametrize("opaque,tile", [(1.0, 8), (0.3, 16)])
@@ -287,8 +296,8 @@ def test_backward_long_lists(oracle_mod, opaque, tile):
     grad = scenes.image_gradient(cams, seed=12)
     g = GC.gpu_forward(sc, cams, tile=tile, bg=bg)
     O, r = _oracle_render(oracle_mod, sc, cams, tile, bg)
-    good, _, _ = GC.compare_images(g, r, f"long lists opaque={opaque}")
-    assert good <= GC.IMG_TOL
+    GC.compare_images(g, r, f"long lists opaque={opaque}", max_excluded=5e-3)
+    GC.compare_last(g, r, f"long lists opaque={opaque}")
     lens = O.sort()["ranges"]
     lens = lens[:, 1] - lens[:, 0]
     _say(f"  longest list {lens.max()}, lists over 256: {(lens > 256).sum()}")
@@ -297,9 +306,6 @@ def test_backward_long_lists(oracle_mod, opaque, tile):
     rb = O.backward(grad.astype(np.float64), bg=np.asarray(bg))
     ok = ~rb["ill"]
     _say(f"  prims ill {rb['ill'].mean() * 100:.2f}%")
-    # a primitive seen by any ill-conditioned pixel is left out; in a dense
-    # scene that is most of them, still leaving hundreds
-    assert ok.sum() >= 300
     w = GC.grad_errors(gg, rb, ok, f"long lists opaque={opaque}")
     for k, v in w.items():
         assert v <= GC.GRAD_TOL, k
@@ -361,11 +367,13 @@ def test_full_size_sampled_forward(oracle_mod, config):
     r = O.render_pixels(0, pix)
     hw = cam.width * cam.height
     rgb = np.stack([g["rgb"][c * hw + idx] for c in range(3)], 1)
-    ok = (r["ill"] & 1) == 0
+    term = (r["ill"] & GC.EXCLUDED) != 0
     err = np.maximum(np.abs(rgb - r["rgb"]).max(1), np.abs(g["T"][idx] - r["T"]))
-    _say(f"sampled max err (ok) {err[ok].max():.3e}, overall {err.max():.3e}, ill {(~ok).mean() * 100:.2f}%, "
-         f"covered {(r['T'] < 1).mean() * 100:.1f}%")
-    assert err[ok].max() <= GC.IMG_TOL
+    _say(f"sampled max err: all but excluded {err[~term].max():.3e}, all {err.max():.3e}, "
+         f"excluded (termination or float32 estimate) {term.mean() * 100:.3f}%, value flag {((r['ill'] & 1) != 0).mean() * 100:.3f}%, "
+         f"covered {(r['T'] < 1).mean() * 100:.1f}%, largest float32 error estimate {r['cond'].max():.2e}")
+    assert err[~term].max() <= GC.IMG_TOL
+    assert term.mean() <= 5e-3
     assert (r["T"] < 1).mean() > 0.05
 
 
@@ -386,6 +394,15 @@ def test_full_size_sparse_backward(oracle_mod, config):
     w = GC.grad_errors(gg, rb, ok, f"config{config} sparse")
     for k, v in w.items():
         assert v <= GC.GRAD_TOL, k
+    # primitives whose gradient records (one per 8x8 group of each tile they
+    # touch) are summed in chunks by several waves are checked too
+    records = O.prep()["tiles"] * (16 // 8) ** 2
+    for floor in (64, 256):
+        big = touched & (records > floor)
+        _say(f"  touched primitives with more than {floor} gradient records: {big.sum()}, checked {(big & ok).sum()}")
+        assert (big & ok).sum() >= 0.8 * big.sum()
+        if config == 2:
+            assert (big & ok).sum() >= 5
     # primitives no gradient pixel reaches get exactly zero
     untouched = ~touched & (np.abs(rb["sh"]).sum((1, 2)) == 0)
     assert np.abs(gg["means"][untouched]).max(initial=0.0) == 0.0
@@ -409,6 +426,7 @@ def test_config1_finite_differences(oracle_mod):
     base64 = {k: getattr(sc, k).astype(np.float64) for k in ("means", "quats", "dists", "opacity", "sh")}
     plan = [("means", 16), ("quats", 8), ("dists", 16), ("opacity", 8), ("sh", 16)]
     results = []
+    literal = []
     for field, count in plan:
         for _ in range(count):
             n = int(rng.choice(vis))
@@ -420,17 +438,20 @@ def test_config1_finite_differences(oracle_mod):
             pix = np.stack([ii.ravel(), jj.ravel()], 1).astype(np.int32)
             pidx = jj.ravel() * cam.width + ii.ravel()
             gsel = np.stack([grad[c * hw + pidx] for c in range(3)], 1)
-            if field in ("means", "dists"):
-                h = 1e-3 * float(base64["dists"][n].min())
-            else:
-                h = 1e-3
-            vals = []
-            for sgn in (1, -1):
-                pp = {k: v.copy() for k, v in base64.items()}
-                pp[field][(n,) + comp] += sgn * h
-                Op = oracle_mod.OracleScene(sc, cams, tile=16, inputs64=pp)
-                vals.append(float((Op.render_pixels(0, pix)["rgb"] * gsel).sum()))
-            fd = (vals[0] - vals[1]) / (2 * h)
+            def central(h):
+                vals = []
+                for sgn in (1, -1):
+                    pp = {k: v.copy() for k, v in base64.items()}
+                    pp[field][(n,) + comp] += sgn * h
+                    Op = oracle_mod.OracleScene(sc, cams, tile=16, inputs64=pp)
+                    vals.append(float((Op.render_pixels(0, pix)["rgb"] * gsel).sum()))
+                return (vals[0] - vals[1]) / (2 * h)
+
+            # the step of the workload's definition, 1e-3, is 2-20% of these
+            # distances; positions and distances are also stepped by
+            # 1e-3 min d, the step the comparison is judged on
+            fd_lit = central(1e-3)
+            fd = central(1e-3 * float(base64["dists"][n].min())) if field in ("means", "dists") else fd_lit
             an = float(gg[field][(n,) + comp])
             dn = base64["dists"][n]
             if field == "dists" and dn[comp[0]] == dn.min():
@@ -444,9 +465,41 @@ def test_config1_finite_differences(oracle_mod):
                 w = 1.0 if np.sum(dn == dmin) == 1 else 0.5
                 an += w * float(gg["opacity"][n]) / (0.99 / ((1 - 0.99 * al) * 2 * dmin)) * (-sig / dmin)
             results.append((field, n, comp, an, fd))
+            literal.append((field, n, comp, an, fd_lit))
     scale = {f: max(abs(fd) for ff, _, _, _, fd in results if ff == f) for f, _ in plan}
-    bad = [(f, n, c, a, d) for f, n, c, a, d in results if abs(a - d) > 2e-2 * max(abs(d), 0.05 * scale[f])]
+
+    def mismatches(res):
+        return [(f, n, c, a, d) for f, n, c, a, d in res if abs(a - d) > 2e-2 * max(abs(d), 0.05 * scale[f])]
+
+    bad, bad_lit = mismatches(results), mismatches(literal)
     for r in results[:8]:
         _say(f"fd sample {r}")
-    _say(f"fd mismatches {len(bad)} of {len(results)}: {bad[:5]}")
-    assert len(bad) <= 2
+    _say(f"fd mismatches, scaled step: {len(bad)} of {len(results)}: {bad[:5]}")
+    by_field = {f: sum(1 for r in bad_lit if r[0] == f) for f, _ in plan}
+    _say(f"fd mismatches, literal step 1e-3: {len(bad_lit)} of {len(literal)} (per field {by_field})")
+    assert not bad
+    # with the literal step only positions and distances, whose step is then
+    # a sizeable part of the primitive, may leave the linear range
+    assert by_field["quats"] + by_field["opacity"] + by_field["sh"] <= 2
+
+
+def test_headline_full_frame(oracle_mod):
+    """The headline workload in the launch configuration the benchmark times
+    (1M octahedra, 1920x1080, 8-pixel tiles, per-tile sort): every pixel of
+    the image, the last blended positions and the pair counters against the
+    oracle's tiled render, and the gradients of a dense per-pixel loss
+    gradient against the oracle's backward."""
+    _say("headline full frame config2 tile 8")
+    sc, cams = scenes.CONFIGS[2]()
+    g = GC.gpu_forward(sc, cams, tile=8, counters=True)
+    O, r = _oracle_render(oracle_mod, sc, cams, 8, (0, 0, 0))
+    _check_sorted(g["rast"].debug_arrays(g["prims"]), O.sort(), g["n_pairs"])
+    GC.compare_images(g, r, "headline")
+    GC.compare_last(g, r, "headline")
+    GC.compare_counts(g["counts"], r["counts"], "headline")
+    grad = scenes.image_gradient(cams, seed=3)
+    gg = GC.gpu_backward(g, grad)
+    rb = O.backward(grad.astype(np.float64))
+    w = GC.grad_errors(gg, rb, ~rb["ill"], "headline")
+    for k, v in w.items():
+        assert v <= GC.GRAD_TOL, k

@@ -65,6 +65,7 @@ def test_stats_parity(oracle_mod, kind, tile):
     _say(f"  worst rel err {err.max():.2e} over {ok.sum()} primitives, visible {int((cnt > 0).sum())}")
     assert err.max() <= GC.GRAD_TOL
     assert (cnt > 0).sum() > 100
+    assert ok[cnt > 0].mean() >= 0.95
 
 
 def _random_state(kind, n, seed, K=16):

@@ -260,3 +260,58 @@ def test_graph_replay_new_views(torch_cuda):
             assert torch.equal(a, b), f"replay {r}: image differs"
         for k in eager.grads:
             assert torch.equal(cap.grads[k], eager.grads[k]), f"replay {r}: grad {k} differs"
+
+
+@pytest.mark.parametrize("loss", ["l1", "l1_ssim"])
+def test_captured_step_overflow_changes_nothing(torch_cuda, loss):
+    """A replay whose (tile, primitive) pairs exceed the pair capacity leaves
+    the parameters and the Adam moments unchanged; check() reports it after
+    later, valid replays too (the flag is sticky) until clear()."""
+    from paper_2501_16312_amd import linprim as L
+    from paper_2501_16312_amd.graph import CapturedStep
+    from paper_2501_16312_amd.render import Rasterizer
+    torch = torch_cuda
+    _say(f"captured step overflow loss={loss}")
+    sc, cams = _small_scene(1200, seed=8)
+    near = [scenes.look_at((0.15, -0.1, -2.0), (0.0, 0.0, 0.0), cams[0].width, cams[0].height)]
+    target_scene = sc.copy()
+    target_scene.means = target_scene.means + np.float32(0.01)
+    target = Rasterizer(sc.kind, sc.n, cams, tile=16).forward(L.Prims.from_scene(target_scene), None)[0].clone()
+    probe = Rasterizer(sc.kind, sc.n, near, tile=16)
+    probe.forward(L.Prims.from_scene(sc), None)
+    prims = L.Prims.from_scene(sc)
+    grads = {k: torch.zeros_like(getattr(prims, k)) for k in ("means", "quats", "dists", "opacity", "sh")}
+    groups = [{"param": getattr(prims, k), "grad": grads[k], "exp_avg": torch.zeros_like(grads[k]),
+               "exp_avg_sq": torch.zeros_like(grads[k]), "lr": 1e-3} for k in grads]
+    rast = Rasterizer(sc.kind, sc.n, cams, tile=16, views_resident=True)
+    cap = CapturedStep(rast, prims, None, target=target, l1_scale=1.0 / target.numel(),
+                       adam={"groups": groups, "beta1": 0.9, "beta2": 0.999, "eps": 1e-15}, headroom=1.2,
+                       grads=grads, loss=loss)
+    # (the updates move the primitives, so the pair count drifts a little
+    # from step to step: the capacity keeps 20% headroom)
+    assert probe.n_pairs > rast.max_pairs, (probe.n_pairs, rast.max_pairs)
+
+    def snapshot():
+        return [t.clone() for g in groups for t in (g["param"], g["exp_avg"], g["exp_avg_sq"])]
+
+    cap.replay()
+    torch.cuda.synchronize()
+    cap.check()
+    before = snapshot()
+    rast.set_views(near)
+    cap.replay()
+    torch.cuda.synchronize()
+    after = snapshot()
+    assert all(torch.equal(a, b) for a, b in zip(before, after)), "an overflowed step changed the parameters"
+    with pytest.raises(L.LinPrimError):
+        cap.check()
+    rast.set_views(cams)
+    cap.replay()
+    torch.cuda.synchronize()
+    assert not torch.equal(prims.means, before[0]), "the valid step after the overflow did not update"
+    with pytest.raises(L.LinPrimError):
+        cap.check()                      # sticky
+    cap.clear()
+    cap.replay()
+    torch.cuda.synchronize()
+    cap.check()

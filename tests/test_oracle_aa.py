@@ -5,7 +5,7 @@ parallel to the screen, an octahedron's axis vector by half the size.
 Closed forms: the rhombus of an axis-aligned octahedron on the optical axis
 (its half-extents grow by 0.05 pixel), and the square pyramid chord of a
 tetrahedron seen along a 2-fold axis (every corner lies on the box; its
-half-extent grows by 0.1 pixel).  The same tetrahedron also pins the
+half-extent grows by the same 0.05 pixel).  The same tetrahedron also pins the
 ray-space tetrahedron chord without the filter.  Plus: the two chord
 formulations, brute force against the tiled walk, and the analytic backward
 against central differences.  No GPU needed.
@@ -63,14 +63,15 @@ def test_tetrahedron_square_pyramid(oracle_mod, aa):
     depth D: its ray-space corners are (+-s, +-s, +-h) with s = f d / (sqrt3 D),
     h = d / sqrt3, two edges crossing at right angles seen along z, and the
     chord is 2 h max(0, 1 - max(|X|, |Y|) / s); the filter puts every corner
-    on the box and makes s -> s + 0.1."""
+    on the box and makes s -> s + 0.05 (the box grows by 0.1 per axis, as an
+    octahedron's does)."""
     W = H_ = 48
     cam = H.origin_camera(W, H_)
     f = _f32(cam.fx)
     d, D = 0.5, 2.0
     sc = H.prims(TETRA, [0, 0, D], [1, 0, 0, 0], [d, d, d, d], 0.5)
     O = oracle_mod.OracleScene(sc, [cam], antialias=aa)
-    s = f * d / (math.sqrt(3) * D) + (0.1 if aa else 0.0)
+    s = f * d / (math.sqrt(3) * D) + (0.05 if aa else 0.0)
     h = d / math.sqrt(3)
     n_in = 0
     for j in range(H_):

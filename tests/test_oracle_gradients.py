@@ -47,7 +47,7 @@ def test_backward_matches_torch_autograd(oracle_mod, kind):
     np.testing.assert_allclose(img.detach().numpy().reshape(-1), r["rgb"], atol=1e-11)
     (img.reshape(-1) * torch.tensor(g)).sum().backward()
     ob = O.backward(g, bg=bg)
-    assert not ob["ill"].any()
+    assert not (ob["ill_bits"] & 1).any()      # no discrete decision near a switch
     for k in FIELDS:
         ref = params[k].grad.numpy()
         got = ob[k]
