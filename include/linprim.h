@@ -395,6 +395,26 @@ int linprim_densify_apply(int32_t type, int32_t sh_degree, int64_t n, const linp
                           const float *max_radius, const linprim_densify_params *params, const void *ws,
                           size_t ws_bytes, const linprim_state *dst, int64_t n_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): linprim_densify_plan
+ * and linprim_densify_apply in one call, with the plan's block sums in a
+ * scratch array the library holds in device memory (8 bytes per 1,024
+ * primitives of up to LINPRIM_NOALLOC_MAX_PRIMS, about 64 KiB per device,
+ * kept until the process ends) instead of a caller workspace.  It calls no
+ * allocating routine.  dst: DEVICE arrays of dst_rows rows (3 n rows always
+ * suffice); *n_out (HOST) receives the number of primitives after the pass;
+ * if it exceeds dst_rows, dst is left untouched and WORKSPACE_TOO_SMALL is
+ * returned.  Waits for `stream` once, between plan and apply.  Errors:
+ * WORKSPACE_TOO_SMALL for n > LINPRIM_NOALLOC_MAX_PRIMS (checked first) or
+ * dst_rows < *n_out; INVALID_ARG as for the two calls it combines.  Every
+ * call on one device shares that device's scratch: calls that overlap on
+ * one device (other streams, other host threads) race. */
+#define LINPRIM_NOALLOC_MAX_PRIMS 8388608
+int linprim_densify_noalloc(int32_t type, int32_t sh_degree, int64_t n, const linprim_state *src,
+                            const float *normals, const float *grad_accum, const int32_t *count,
+                            const float *max_radius, const linprim_densify_params *params,
+                            const linprim_state *dst, int64_t dst_rows, int64_t *n_out, void *stream);
+
 /* ------------------------------------------------------------------------
  * LinPrim-MCMC (Sec. 3.4 "LinPrim-MCMC"): GS-MCMC's relocation and noise
  * steps for octahedra treated as Gaussians with standard deviations d / 2.6.

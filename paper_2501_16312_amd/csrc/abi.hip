@@ -416,6 +416,35 @@ int linprim_densify_apply(int32_t type, int32_t sh_degree, int64_t n, const linp
                                            (const int64_t*)ws, state_set(dst), (hipStream_t)stream));
 }
 
+int linprim_densify_noalloc(int32_t type, int32_t sh_degree, int64_t n, const linprim_state* src,
+                            const float* normals, const float* grad_accum, const int32_t* count,
+                            const float* max_radius, const linprim_densify_params* params, const linprim_state* dst,
+                            int64_t dst_rows, int64_t* n_out, void* stream) {
+    if (n > kNoAllocMaxPrims) return LINPRIM_ERR_WORKSPACE;
+    if ((type != LINPRIM_OCTAHEDRON && type != LINPRIM_TETRAHEDRON) || sh_degree < 0 || sh_degree > 3 || n < 0 ||
+        dst_rows < 0 || !n_out || !valid_densify(params) || !state_ok(src, n) || !state_ok(dst, dst_rows))
+        return LINPRIM_ERR_INVALID_ARG;
+    if (n > 0 && (!normals || !grad_accum || !count || !max_radius)) return LINPRIM_ERR_INVALID_ARG;
+    if (int rc = check_device()) return rc;
+    int64_t* bs = nullptr;
+    if (densify_scratch(&bs) != hipSuccess) return LINPRIM_ERR_HIP;
+    hipStream_t s = (hipStream_t)stream;
+    // the plan writes every block sum and the total it uses: nothing to clear
+    if (launch_densify_plan(type, n, src->dists, src->opacity, grad_accum, count, max_radius,
+                            densify_params(params), params->extent, bs, s) != hipSuccess)
+        return LINPRIM_ERR_HIP;
+    const int64_t nb = (n + kDensifyItems - 1) / kDensifyItems;
+    int64_t total = 0;
+    if (hipMemcpyAsync(&total, bs + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return LINPRIM_ERR_HIP;
+    *n_out = total;
+    if (total > dst_rows) return LINPRIM_ERR_WORKSPACE;
+    return hip_status(launch_densify_apply(type, sh_degree, n, state_set(src), normals, grad_accum, count,
+                                           max_radius, densify_params(params), params->extent, bs, state_set(dst),
+                                           s));
+}
+
 size_t linprim_mcmc_workspace_size(int64_t n) {
     if (n < 0 || n >= (int64_t(1) << 31)) return 0;
     return mc_workspace_bytes(n);

@@ -11,6 +11,8 @@
 //   k_dens_scan     exclusive scan of the block sums (one block).
 //   k_dens_apply    per primitive: its rows' offset (block scan) and the rows:
 //                   the original or its two split children, then its clone.
+#include <mutex>
+
 #include "linprim_common.h"
 
 namespace linprim {
@@ -258,6 +260,35 @@ hipError_t launch_densify_apply(int type, int sh_degree, int64_t n, const StateS
         hipLaunchKernelGGL(k_dens_apply<4>, dim3((unsigned)nb), dim3(256), 0, s, type, n, src, dst, shf, normals,
                            grad_accum, count, max_radius, dp, extent, block_sums);
     return hipGetLastError();
+}
+
+// Scratch of the allocation-free densify entry point: the plan's block sums
+// and total, (n / kDensifyItems + 1) values, held by each device the
+// library runs on until the process ends.  Host code reaches it only through
+// the address hipGetSymbolAddress returns for the current device.
+constexpr int64_t kDensifyScratchItems = kNoAllocMaxPrims / kDensifyItems + 8;
+static __device__ __align__(256) int64_t scratch[kDensifyScratchItems];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices];
+}  // namespace
+
+hipError_t densify_scratch(int64_t** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<int64_t*>(g_scratch_ptr[dev]);
+    return hipSuccess;
 }
 
 }  // namespace linprim

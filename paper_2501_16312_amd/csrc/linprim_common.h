@@ -196,6 +196,10 @@ struct StateSet {
     float* v[5];     // Adam second moments
 };
 constexpr int kDensifyItems = 1024;   // primitives per scan block
+constexpr int64_t kNoAllocMaxPrims = LINPRIM_NOALLOC_MAX_PRIMS;
+static_assert(kNoAllocMaxPrims % kDensifyItems == 0, "whole scan blocks");
+// Per-device address of the static scratch of linprim_densify_noalloc.
+hipError_t densify_scratch(int64_t** out);
 hipError_t launch_accumulate_stats(int64_t n, int32_t n_views, const ViewLayout& L, const char* vws,
                                    float* grad_accum, int32_t* count, float* max_radius, hipStream_t s);
 hipError_t launch_densify_plan(int type, int64_t n, const float* dists, const float* opacity,

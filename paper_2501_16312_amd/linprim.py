@@ -27,6 +27,8 @@ ERR_WORKSPACE = -2
 ERR_PAIR_OVERFLOW = -3
 ERR_HIP = -4
 ERR_DEVICE = -5
+# largest primitive count of linprim_densify_noalloc (its scratch is static)
+NOALLOC_MAX_PRIMS = 8388608
 
 FLAG_COUNTERS = 1
 FLAG_VIEWS_RESIDENT = 2
@@ -79,6 +81,7 @@ EXPORTS = ("linprim_view_workspace_size", "linprim_pair_workspace_size", "linpri
            "linprim_strerror", "linprim_debug_pointers", "linprim_upload_views", "linprim_l1_grad",
            "linprim_adam_step", "linprim_adam_step_dev", "linprim_step_guard", "linprim_accumulate_stats",
            "linprim_densify_workspace_size", "linprim_densify_plan", "linprim_densify_apply",
+           "linprim_densify_noalloc",
            "linprim_loss_workspace_size", "linprim_loss_grad", "linprim_loss_value",
            "linprim_mcmc_workspace_size", "linprim_mcmc_relocate", "linprim_mcmc_dead_count",
            "linprim_mcmc_noise", "linprim_mcmc_add")
@@ -142,6 +145,9 @@ def load(path: str = LIB_PATH):
     lib.linprim_loss_workspace_size.restype = SZ
     lib.linprim_loss_workspace_size.argtypes = [cm, I32]
     lib.linprim_loss_grad.argtypes = [P, P, cm, I32, ctypes.c_float, P, SZ, P, P, P]
+    lib.linprim_densify_noalloc.argtypes = [I32, I32, I64, ctypes.POINTER(linprim_state), P, P, P, P,
+                                            ctypes.POINTER(linprim_densify_params), ctypes.POINTER(linprim_state),
+                                            I64, ctypes.POINTER(I64), P]
     lib.linprim_loss_value.argtypes = [P, SZ, cm, I32, ctypes.c_float, ctypes.POINTER(ctypes.c_double), P]
     lib.linprim_strerror.restype = ctypes.c_char_p
     lib.linprim_strerror.argtypes = [ctypes.c_int]
@@ -152,7 +158,7 @@ def load(path: str = LIB_PATH):
               lib.linprim_preprocess_bwd, lib.linprim_read_status, lib.linprim_upload_views,
               lib.linprim_l1_grad, lib.linprim_adam_step, lib.linprim_adam_step_dev, lib.linprim_step_guard,
               lib.linprim_debug_pointers, lib.linprim_accumulate_stats, lib.linprim_densify_plan,
-              lib.linprim_densify_apply, lib.linprim_loss_grad, lib.linprim_loss_value,
+              lib.linprim_densify_apply, lib.linprim_densify_noalloc, lib.linprim_loss_grad, lib.linprim_loss_value,
               lib.linprim_mcmc_relocate, lib.linprim_mcmc_dead_count, lib.linprim_mcmc_noise,
               lib.linprim_mcmc_add):
         f.restype = ctypes.c_int
@@ -455,6 +461,19 @@ def linprim_densify_apply(kind: int, sh_degree: int, n: int, src: linprim_state,
                                         _ptr(grad_accum), _ptr(count), _ptr(max_radius), ctypes.byref(dp), _ptr(ws),
                                         ws.numel(), ctypes.byref(dst), int(n_out), _stream(stream)),
            "linprim_densify_apply")
+
+
+def linprim_densify_noalloc(kind: int, sh_degree: int, n: int, src: linprim_state, normals, grad_accum, count,
+                            max_radius, dp: linprim_densify_params, dst: linprim_state, dst_rows: int,
+                            stream=None) -> int:
+    """Plan and apply in one call with the library's own scratch (no
+    workspace); returns the number of primitives written to dst."""
+    out = ctypes.c_int64(0)
+    _check(load().linprim_densify_noalloc(int(kind), int(sh_degree), int(n), ctypes.byref(src), _ptr(normals),
+                                          _ptr(grad_accum), _ptr(count), _ptr(max_radius), ctypes.byref(dp),
+                                          ctypes.byref(dst), int(dst_rows), ctypes.byref(out), _stream(stream)),
+           "linprim_densify_noalloc")
+    return int(out.value)
 
 
 # ---------------------------------------------------------------------------
