@@ -9,7 +9,8 @@ preprocessing backward.  Inputs and the loss gradient dL/dC are resident in
 HBM before the timed region.  The line also carries the batched-views
 comparison (500,000 octahedra, 16 views of mixed resolution: one
 graph-captured multi-view step against 16 per-view plain launches) unless
---no-batched is given.
+--no-batched is given, and a short run of the optimisation step loop (20
+replays, see below) unless --no-steploop is given.
 
 --workload batched runs only the batched-views comparison.
 
@@ -51,57 +52,95 @@ def _src_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def _traffic(kernel_key, src_file):
-    """HBM bytes per launch measured by rocprofv3 counters, if the record on
-    file was taken on the current kernel source."""
+def _traffic(workload_key, kernel_key, src_file):
+    """HBM bytes per launch measured by rocprofv3 counters for this workload
+    and kernel, if the record on file was taken on the current kernel
+    source."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
     with open(p) as f:
-        rec = json.load(f).get(kernel_key)
+        rec = json.load(f).get(f"{workload_key}/{kernel_key}")
     if not rec or rec.get("source_sha256_16") != _src_hash(src_file):
         return None
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(scene, cams, grad, band_rows, threads, min_seconds=10.0, max_repeats=10):
-    """FP64 oracle on a bounded sample: every primitive preprocessed and
-    sorted, then a band of image rows (the whole frame by default)
-    composited and back-propagated, repeated until about min_seconds of CPU
-    work; the frame time is extrapolated by the row fraction."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(scene, cams, grad, band_rows, threads):
+    """The FP64 oracle (as it stands) on the headline workload, wall time:
+    on all host threads the whole frame, forward (preprocess, sort,
+    compositing) and forward + backward; on one thread the preprocess and
+    sort of every primitive, then a band of rows composited and
+    back-propagated, the band's times scaled by the frame's rows (which also
+    scales the backward's fixed per-call cost: conservative for the CPU)."""
     import numpy as np
 
     import oracle
-    os.environ.setdefault("OMP_NUM_THREADS", str(threads))
     cam = cams[0]
-    band_rows = cam.height if band_rows <= 0 else min(band_rows, cam.height)
+    hw = cam.width * cam.height
+    mp = hw / 1e6
+    band_rows = max(1, min(band_rows if band_rows > 0 else 216, cam.height))
     j0 = cam.height // 2 - band_rows // 2
     j1 = j0 + band_rows
-    hw = cam.width * cam.height
-    g = np.zeros_like(grad, dtype=np.float64)
+    g_band = np.zeros_like(grad, dtype=np.float64)
     for c in range(3):
-        sl = grad[c * hw: (c + 1) * hw].reshape(cam.height, cam.width)
-        g[c * hw: (c + 1) * hw].reshape(cam.height, cam.width)[j0:j1] = sl[j0:j1]
-    frames, t_setup, t_band = 0, 0.0, 0.0
-    while frames < max_repeats and (frames == 0 or t_setup + t_band < min_seconds):
+        g_band[c * hw: (c + 1) * hw].reshape(cam.height, cam.width)[j0:j1] = \
+            grad[c * hw: (c + 1) * hw].reshape(cam.height, cam.width)[j0:j1]
+
+    def setup():
         t0 = time.perf_counter()
         O = oracle.OracleScene(scene, cams, tile=16)
         O.sort()
-        t1 = time.perf_counter()
-        O.render_band(j0, j1)
-        O.backward(g)
-        t2 = time.perf_counter()
-        del O
-        t_setup += t1 - t0
-        t_band += t2 - t1
-        frames += 1
-    frac = band_rows / cam.height
-    t_full = (t_setup + t_band / frac) / frames
-    mp = cam.width * cam.height / 1e6
-    what = "the whole frame" if band_rows == cam.height else f"rows {j0}-{j1 - 1} ({band_rows} of {cam.height})"
-    return {"value": mp / t_full, "unit": "megapixels/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{frames} x (all {scene.n} primitives preprocessed and sorted, {what} composited and "
-                      f"back-propagated): {t_setup + t_band:.1f} s of CPU time"}
+        return O, time.perf_counter() - t0
+
+    # all threads, whole frame
+    oracle.set_threads(threads)
+    O, t_setup = setup()
+    t0 = time.perf_counter()
+    O.render()
+    t_render = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.backward(grad.astype(np.float64))
+    t_bwd = time.perf_counter() - t0
+    cores = oracle.num_threads()
+    del O
+    all_fwd = mp / (t_setup + t_render)
+    all_fb = mp / (t_setup + t_render + t_bwd)
+    # one thread, a band of rows
+    oracle.set_threads(1)
+    O, t1_setup = setup()
+    t0 = time.perf_counter()
+    O.render_band(j0, j1)
+    t1_render = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.backward(g_band)
+    t1_bwd = time.perf_counter() - t0
+    del O
+    oracle.set_threads(threads)
+    scale = cam.height / band_rows
+    one_fwd_t = t1_setup + t1_render * scale
+    one_fb_t = one_fwd_t + t1_bwd * scale
+    wall = t_setup + t_render + t_bwd + t1_setup + t1_render + t1_bwd
+    return {"value": round(all_fb, 4), "unit": "megapixels/s", "cores": cores, "kind": "oracle",
+            "timing": "wall time", "cpu_model": _cpu_model(),
+            "fwd_megapixels_per_s": {"all_cores": round(all_fwd, 4), "one_core": round(mp / one_fwd_t, 4)},
+            "fwd_bwd_megapixels_per_s": {"all_cores": round(all_fb, 4), "one_core": round(mp / one_fb_t, 4)},
+            "sample": f"{cores} threads: the whole frame once (all {scene.n} primitives preprocessed and sorted "
+                      f"{t_setup:.1f} s, composited {t_render:.1f} s, back-propagated {t_bwd:.1f} s); 1 thread: "
+                      f"preprocess and sort {t1_setup:.1f} s, rows {j0}-{j1 - 1} ({band_rows} of {cam.height}) "
+                      f"composited {t1_render:.1f} s and back-propagated {t1_bwd:.1f} s, both scaled to the frame; "
+                      f"{wall:.1f} s wall"}
 
 
 class Staged:
@@ -165,7 +204,7 @@ class Staged:
         return tuple(int(x) for x in cnt.cpu())
 
 
-def roofline_of(kind, stage_ms, counts):
+def roofline_of(kind, stage_ms, counts, workload_key):
     iterated, evaluated, intersected = counts
     fwd_flop = evaluated * F_FWD[kind]
     bwd_flop = evaluated * F_FWD[kind] + intersected * F_BWD_EXTRA[kind]
@@ -174,7 +213,7 @@ def roofline_of(kind, stage_ms, counts):
     achieved = flop / (stage_ms[dominant] * 1e-3) / 1e12
     src = os.path.join(ROOT, "paper_2501_16312_amd", "csrc", "k_render.hip")
     return {"bound": "alu", "kernel": dominant, "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(dominant, src)}
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": _traffic(workload_key, dominant, src)}
 
 
 def batched_comparison(args, log):
@@ -287,7 +326,7 @@ def single(args, log):
 
     ms_per_step, stage_ms, counts, n_pairs = measure(args.exact)
     value = cam.width * cam.height / 1e6 / (ms_per_step / 1e3)
-    roofline = roofline_of(scene.kind, stage_ms, counts) if not args.exact else None
+    roofline = roofline_of(scene.kind, stage_ms, counts, f"octa1M_1080p_tile{args.tile}") if not args.exact else None
 
     exact = None
     if not args.exact and not args.no_exact:
@@ -308,10 +347,25 @@ def single(args, log):
         log(f"batched: {batched['graph_ms']} ms vs per-view {batched['per_view_ms']} ms, "
             f"speedup {batched['speedup']}")
         torch.cuda.empty_cache()
+    steploop_leg = None
+    if not args.no_steploop:
+        # the optimisation step loop, short: 20 replays on 2 batches of views
+        log("step loop ...")
+        import copy
+        a2 = copy.copy(args)
+        a2.steps, a2.warmup, a2.view_batches = args.steploop_steps, 3, 2
+        sl = steploop(a2, log)
+        steploop_leg = {"workload": sl["config"]["workload"], "steps": a2.steps, "warmup": a2.warmup,
+                        "steps_per_s": sl["value"], "ms_per_step": sl["ms_per_step"],
+                        "megapixels_per_s": sl["megapixels_per_s"], "peak_hbm_gb": sl["peak_hbm_gb"],
+                        "device_memory_in_use_gb": sl["device_memory_in_use_gb"],
+                        "loss": sl["loss"], "pairs_last": sl["config"]["pairs_last"], "params": sl["config"]["params"]}
+        log(f"step loop: {sl['value']} steps/s, peak HBM {sl['peak_hbm_gb']} GB")
+        torch.cuda.empty_cache()
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the oracle on a bounded sample ...")
-        cpu = cpu_baseline(scene, cams, grad_np, args.band_rows, threads=os.cpu_count() or 1)
+        cpu = cpu_baseline(scene, cams, grad_np, args.band_rows, threads=min(os.cpu_count() or 1, 16))
     return {
         "metric": "fwd+bwd megapixels/s at 1M octahedra 1080p" + (", exact rays" if args.exact else ""),
         "value": round(value, 3), "unit": "megapixels/s", "n_gpus": 1, "steps": args.steps,
@@ -325,6 +379,7 @@ def single(args, log):
         "roofline": roofline,
         "batched": batched,
         "exact_rays": exact,
+        "steploop": steploop_leg,
         "cpu_baseline": cpu,
     }
 
@@ -410,6 +465,7 @@ def steploop(args, log):
     n_pairs = cap.check()
     loss1 = cap.loss()
     peak = torch.cuda.max_memory_allocated()
+    free, total = torch.cuda.mem_get_info()          # hipMemGetInfo: everything on the device
 
     # one instrumented eager step on the final parameters for the roofline,
     # and the Adam kernel timed alone
@@ -455,11 +511,12 @@ def steploop(args, log):
                    "params": n_params},
         "megapixels_per_s": round(mp / (ms * 1e-3), 1),
         "peak_hbm_gb": round(peak / 1e9, 3),
+        "device_memory_in_use_gb": round((total - free) / 1e9, 3),
         "loss": {"before": loss0, "after": loss1, "kernel_ms": loss_ms},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "adam": {"ms": round(adam_ms, 4), "achieved_gbs": round(adam_gbs, 1), "peak_gbs": PEAK_HBM_GBS,
                  "frac": round(adam_gbs / PEAK_HBM_GBS, 4), "bytes_per_param": ADAM_BYTES_PER_PARAM},
-        "roofline": roofline_of(scene.kind, stage_ms, counts),
+        "roofline": roofline_of(scene.kind, stage_ms, counts, "steploop_3M_8views"),
         "cpu_baseline": None,
     }
 
@@ -515,7 +572,9 @@ def main():
     ap.add_argument("--exact", action="store_true", help="time the variant without the ray-space approximation")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-rays comparison of the default run")
     ap.add_argument("--batched-steps", type=int, default=10)
-    ap.add_argument("--band-rows", type=int, default=0, help="rows of the oracle sample (0: whole frame)")
+    ap.add_argument("--no-steploop", action="store_true", help="skip the short step-loop leg of the default run")
+    ap.add_argument("--steploop-steps", type=int, default=20)
+    ap.add_argument("--band-rows", type=int, default=216, help="rows of the one-thread oracle sample")
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -73,6 +73,7 @@ def _load():
     lib.orc_sh_basis.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
     lib.orc_backward.argtypes = [P] + [ctypes.c_void_p] * 8
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
 
@@ -87,6 +88,11 @@ def _f64(a) -> np.ndarray:
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's parallel regions from now on."""
+    _load().orc_set_threads(int(n))
 
 
 def sh_basis(deg: int, direction) -> np.ndarray:

@@ -1810,6 +1810,17 @@ int orc_get_stats(void *h, double *sgrad, double *radius, uint8_t *visible)
     return 0;
 }
 
+/* Threads of the OpenMP regions that follow (used to time the oracle on
+ * one core and on all cores). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
