@@ -95,12 +95,16 @@ struct Rec {
     int fmap;
 };
 
-template <int KIND, bool EXACT = false>
+template <int KIND, bool EXACT = false, bool RECT = true>
 __device__ inline void load_rec(const float* __restrict__ rec, Rec& R) {
-    R.i0 = __float_as_int(rec[R_I0]);
-    R.j0 = __float_as_int(rec[R_J0]);
-    R.i1 = __float_as_int(rec[R_I1]);
-    R.j1 = __float_as_int(rec[R_J1]);
+    if (RECT) {
+        R.i0 = __float_as_int(rec[R_I0]);
+        R.j0 = __float_as_int(rec[R_J0]);
+        R.i1 = __float_as_int(rec[R_I1]);
+        R.j1 = __float_as_int(rec[R_J1]);
+    } else {
+        R.i0 = R.j0 = R.i1 = R.j1 = 0;
+    }
     R.s2 = rec[R_S2];
     R.r = rec[R_RGB];
     R.g = rec[R_RGB + 1];
@@ -302,17 +306,26 @@ __device__ inline bool rect_meets_group(int4 r, int gx0, int gy0) {
 }
 
 // One batch of up to 64 list entries starting at e0: lane l holds entry
-// e0 + l's primitive index (and, if needed, its rectangle / record offset).
+// e0 + l's primitive index (and, for the backward, the index of the
+// gradient record of that (tile, primitive) pair and this group).
 struct Batch {
     uint32_t idx;
-    uint32_t off;
+    uint32_t off;      // gradient record index (backward only)
     uint64_t mask;     // entries whose pixel rectangle meets the group
     uint32_t touch;    // words of the entries' records read only to bring them into L2
 };
 
+// Gradient records of a slot are laid out by tile of its tile rectangle
+// (row-major), NQ groups per tile, from the slot's pair offset on.
+__device__ inline uint32_t record_index(int4 r, int tile_shift, int tx, int ty, uint32_t prim_offset, int NQ, int q) {
+    const int tx0 = r.x >> tile_shift, ty0 = r.y >> tile_shift, tx1 = r.z >> tile_shift;
+    return (prim_offset + (uint32_t)((ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0))) * (uint32_t)NQ + (uint32_t)q;
+}
+
 template <int NQ, bool WANT_OFF>
 __device__ inline Batch load_batch(const float* __restrict__ base, const uint32_t* __restrict__ vals,
-                                   const uint32_t* __restrict__ offs, uint32_t e0, uint32_t nb, int gx0, int gy0) {
+                                   const uint32_t* __restrict__ offs, uint32_t e0, uint32_t nb, int gx0, int gy0,
+                                   int tile_shift = 0, int tx = 0, int ty = 0, int q = 0) {
     const int lane = threadIdx.x;
     Batch B;
     B.idx = 0;
@@ -322,16 +335,16 @@ __device__ inline Batch load_batch(const float* __restrict__ base, const uint32_
     if ((uint32_t)lane < nb) {
         B.idx = vals[e0 + lane];
         const float* rp = base + (size_t)B.idx * kRecordWords;
-        if (NQ == 1) {
+        if (NQ == 1 && !WANT_OFF) {
             rel = true;   // every entry of a group-sized tile meets it
             B.touch = __float_as_uint(rp[0]);
         } else {
             const int4 r = *reinterpret_cast<const int4*>(rp);
-            rel = rect_meets_group(r, gx0, gy0);
+            rel = (NQ == 1) || rect_meets_group(r, gx0, gy0);
+            if (WANT_OFF) B.off = record_index(r, tile_shift, tx, ty, offs[B.idx], NQ, q);
         }
         // the record's second 64-byte line, for the scalar loads that follow
         if (rel) B.touch ^= __float_as_uint(rp[16]);
-        if (WANT_OFF) B.off = offs[B.idx];
     }
     B.mask = __ballot(rel);
     return B;
@@ -507,11 +520,6 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
 //   tetrahedron: [3 f + 0..2] dL/d(A_f, B_f, D_f) for face f
 //   [16..18] dL/d rgb, [19] dL/d sigma
 // ---------------------------------------------------------------------------
-__device__ inline int64_t record_slot(const Rec& R, int tile_shift, int tx, int ty, uint32_t prim_offset, int NQ,
-                                      int q) {
-    const int tx0 = R.i0 >> tile_shift, ty0 = R.j0 >> tile_shift, tx1 = R.i1 >> tile_shift;
-    return ((int64_t)prim_offset + (int64_t)(ty - ty0) * (tx1 - tx0 + 1) + (tx - tx0)) * NQ + q;
-}
 
 template <int TILE, int KIND, bool EXACT>
 __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ views, int n_views, int64_t n,
@@ -558,17 +566,14 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
 
     // zero records of the entries that meet the group but no pixel reached
     for (uint32_t e0 = walk_end; e0 < rg.y; e0 += 64) {
-        const Batch bt = load_batch<NQ, true>(base, vals, offs, e0, min(64u, rg.y - e0), P.gx0, P.gy0);
+        const Batch bt = load_batch<NQ, true>(base, vals, offs, e0, min(64u, rg.y - e0), P.gx0, P.gy0, SHIFT, P.tx,
+                                              P.ty, P.q);
         uint64_t mask = bt.mask;
         while (mask) {
             const int b = __builtin_ctzll(mask);
             mask &= mask - 1;
-            const uint32_t idx = (uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b);
-            const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, b);
-            const int4 r = *reinterpret_cast<const int4*>(base + (size_t)idx * kRecordWords);
-            const int tx0 = r.x >> SHIFT, ty0 = r.y >> SHIFT, tx1 = r.z >> SHIFT;
-            const int64_t slot = ((int64_t)off + (int64_t)(P.ty - ty0) * (tx1 - tx0 + 1) + (P.tx - tx0)) * NQ + P.q;
-            if (lane < kGradWords) grads[slot * kGradWords + lane] = 0.0f;
+            const uint32_t slot = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, b);
+            if (lane < kGradWords) grads[(size_t)slot * kGradWords + lane] = 0.0f;
         }
     }
 
@@ -576,7 +581,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
         const uint32_t nb = min(64u, e_hi - rg.x);
         const uint32_t e0 = e_hi - nb;
         e_hi = e0;
-        const Batch bt = load_batch<NQ, true>(base, vals, offs, e0, nb, P.gx0, P.gy0);
+        const Batch bt = load_batch<NQ, true>(base, vals, offs, e0, nb, P.gx0, P.gy0, SHIFT, P.tx, P.ty, P.q);
         uint64_t mask = bt.mask;
         if (!mask) continue;
         // Entries in reverse order, two record buffers used in turn (see the
@@ -584,7 +589,8 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
         auto next_rec = [&](Rec& R) {
             const int b = 63 - __builtin_clzll(mask);
             mask &= ~(1ull << b);
-            load_rec<KIND, EXACT>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) * kRecordWords, R);
+            load_rec<KIND, EXACT, false>(base + (size_t)(uint32_t)__builtin_amdgcn_readlane((int)bt.idx, b) *
+                                             kRecordWords, R);
             return b;
         };
         auto step = [&](const Rec& R, int bcur) {
@@ -711,8 +717,7 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
 #pragma unroll
                 for (int k = 12; k < 16; ++k) acc[k] = 0.0f;
             }
-            const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, bcur);
-            const int64_t slot = record_slot(R, SHIFT, P.tx, P.ty, off, NQ, P.q);
+            const size_t slot = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, bcur);
             float outv = 0.0f;
             if (__ballot(contributed) != 0) outv = wave_reduce20(acc, lane);
             const int ridx = reduce20_index(lane);
