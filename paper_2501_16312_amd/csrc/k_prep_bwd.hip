@@ -25,62 +25,106 @@ __device__ inline bool record_exists(int r, int NQ, int QX, int tile, int4 rect,
 }
 
 // Sums the gradient records of the slots on the big-slot list (more than
-// kBigRun records: primitives spanning many tiles).  Each slot's run is cut
-// into kBigChunks equal chunks; one wavefront per chunk strides over it,
-// sums across lanes in a fixed order and writes the chunk's sum into the
-// chunk's first record, so no wave holds up the kernel with a long run and
-// the result does not depend on scheduling.  k_slot_bwd adds the chunk sums
-// in chunk order; shorter runs it sums itself.
+// kBigRun records: primitives spanning many tiles) and on the mid list.  A
+// big slot's run is cut into kBigChunks equal chunks; one wavefront per chunk
+// strides over it, sums across lanes in a fixed order and writes the chunk's
+// sum into the chunk's first record, so no wave holds up the kernel with a
+// long run and the result does not depend on scheduling.  k_slot_bwd adds the
+// chunk sums in chunk order; shorter runs it sums itself.
+__device__ inline void sum_big_chunk(const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
+                                     const uint32_t* __restrict__ offsets, int64_t slot, int c, int tile,
+                                     float* __restrict__ grads, int lane) {
+    const int QX = tile / 8, NQ = QX * QX;
+    const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
+    const int nr = (int)tiles[slot] * NQ;
+    const int r0 = big_chunk_start(c, nr), r1 = big_chunk_start(c + 1, nr);
+    const uint32_t o = offsets[slot];
+    const int4 rc = *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
+    const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
+    float acc[kGradWords];
+#pragma unroll
+    for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
+    const float4* g = reinterpret_cast<const float4*>(grads + (int64_t)o * NQ * kGradWords);
+    for (int rb = r0 + lane; rb < r1; rb += 256) {
+        // four records per lane per iteration, all twenty loads in flight
+        // together (the longest chunk bounds the kernel's time)
+        float4 x[4][kGradWords / 4];
+        bool use[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int r = rb + 64 * h;
+            use[h] = r < r1 && (NQ == 1 || record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx));
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k)
+                x[h][k] = use[h] ? g[(int64_t)r * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k) {
+                acc[4 * k] += x[h][k].x;
+                acc[4 * k + 1] += x[h][k].y;
+                acc[4 * k + 2] += x[h][k].z;
+                acc[4 * k + 3] += x[h][k].w;
+            }
+    }
+    const float outv = wave_reduce20(acc, lane);
+    const int ridx = reduce20_index(lane);
+    if (ridx >= 0) grads[((int64_t)o * NQ + r0) * kGradWords + ridx] = outv;
+}
+
+// A mid slot's run (kMidRun < records <= kBigRun) summed by twenty lanes, one
+// word each, in record order: the same additions, in the same order, as the
+// slot's own thread in k_slot_bwd makes for a short run.  The sum goes into
+// the slot's first record, once every lane of the slot has read it.
+__device__ inline void sum_mid_slot(const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
+                                    const uint32_t* __restrict__ offsets, int64_t slot, int w, int tile,
+                                    float* __restrict__ grads) {
+    const int QX = tile / 8, NQ = QX * QX;
+    const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
+    const int nr = (int)tiles[slot] * NQ;
+    const uint32_t o = offsets[slot];
+    const int4 rc = *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
+    const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
+    float* g = grads + (int64_t)o * NQ * kGradWords + w;
+    float acc = 0.0f;
+    constexpr int B = 16;
+    for (int q0 = 0; q0 < nr; q0 += B) {
+        float x[B];
+#pragma unroll
+        for (int h = 0; h < B; ++h) {
+            const int q = q0 + h;
+            const bool use = q < nr && (NQ == 1 || record_exists(q, NQ, QX, tile, rc, tx0, ty0, ntx));
+            x[h] = use ? g[(int64_t)q * kGradWords] : 0.0f;
+        }
+#pragma unroll
+        for (int h = 0; h < B; ++h) acc += x[h];
+    }
+    g[0] = acc;
+}
+
+constexpr int kMidPerWave = 64 / kGradWords;   // mid slots per wavefront (three)
+
 __global__ __launch_bounds__(256) void k_sum_big(const float* __restrict__ payload,
                                                  const uint32_t* __restrict__ tiles,
                                                  const uint32_t* __restrict__ offsets,
-                                                 const uint32_t* __restrict__ big, int tile,
+                                                 const uint32_t* __restrict__ big, int64_t n_slots, int tile,
                                                  const Status* __restrict__ status, uint64_t capacity,
                                                  float* __restrict__ grads) {
     if (status->n_pairs > capacity) return;
-    const int QX = tile / 8, NQ = QX * QX;
-    const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
     const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const int64_t items = (int64_t)status->n_big * kBigChunks;
+    const int64_t n_chunked = (int64_t)status->n_big * kBigChunks;
+    const int64_t n_mid = status->n_mid;
+    const int64_t items = n_chunked + (n_mid + kMidPerWave - 1) / kMidPerWave;
     for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); it < items; it += waves) {
-        const int64_t slot = big[it / kBigChunks];
-        const int c = (int)(it % kBigChunks);
-        const int nr = (int)tiles[slot] * NQ;
-        const int r0 = big_chunk_start(c, nr), r1 = big_chunk_start(c + 1, nr);
-        const uint32_t o = offsets[slot];
-        const int4 rc = *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
-        const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
-        float acc[kGradWords];
-#pragma unroll
-        for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
-        const float4* g = reinterpret_cast<const float4*>(grads + (int64_t)o * NQ * kGradWords);
-        for (int rb = r0 + lane; rb < r1; rb += 256) {
-            // four records per lane per iteration, all twenty loads in flight
-            // together (the longest chunk bounds the kernel's time)
-            float4 x[4][kGradWords / 4];
-            bool use[4];
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int r = rb + 64 * h;
-                use[h] = r < r1 && (NQ == 1 || record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx));
-#pragma unroll
-                for (int k = 0; k < kGradWords / 4; ++k)
-                    x[h][k] = use[h] ? g[(int64_t)r * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-#pragma unroll
-            for (int h = 0; h < 4; ++h)
-#pragma unroll
-                for (int k = 0; k < kGradWords / 4; ++k) {
-                    acc[4 * k] += x[h][k].x;
-                    acc[4 * k + 1] += x[h][k].y;
-                    acc[4 * k + 2] += x[h][k].z;
-                    acc[4 * k + 3] += x[h][k].w;
-                }
+        if (it < n_chunked) {
+            sum_big_chunk(payload, tiles, offsets, big[it / kBigChunks], (int)(it % kBigChunks), tile, grads, lane);
+        } else {
+            const int64_t m = (it - n_chunked) * kMidPerWave + lane / kGradWords;
+            if (lane < kMidPerWave * kGradWords && m < n_mid)
+                sum_mid_slot(payload, tiles, offsets, big[n_slots - 1 - m], lane % kGradWords, tile, grads);
         }
-        const float outv = wave_reduce20(acc, lane);
-        const int ridx = reduce20_index(lane);
-        if (ridx >= 0) grads[((int64_t)o * NQ + r0) * kGradWords + ridx] = outv;
     }
 }
 
@@ -98,6 +142,27 @@ struct ShBack {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             gsh[3 * k + ch] += gr[ch] * Y;
+            const float w = gr[ch] * sh[3 * k + ch];
+            gdir[0] += w * gx;
+            gdir[1] += w * gy;
+            gdir[2] += w * gz;
+        }
+    }
+};
+
+// The same terms with the coefficient gradients stored as they are made
+// (one view: no accumulation over views), so that they need no registers.
+struct ShStore {
+    int K;
+    const float* sh;     // [48] coefficients (registers)
+    float* gs;           // the primitive's row of dL/dSH (global)
+    float gr[3];
+    float gdir[3];
+    __device__ inline void term(int k, float Y, float gx, float gy, float gz) {
+        if (k >= K) return;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            gs[3 * k + ch] = gr[ch] * Y;
             const float w = gr[ch] * sh[3 * k + ch];
             gdir[0] += w * gx;
             gdir[1] += w * gy;
@@ -135,7 +200,8 @@ __device__ inline void sh_raw_f(int K, const float* sh, float x, float y, float 
             for (int ch = 0; ch < 3; ++ch) raw[ch] += sh[3 * k + ch] * Y[k];
 }
 
-__device__ inline void sh_backward(ShBack& S, float x, float y, float z) {
+template <class S_>
+__device__ inline void sh_backward(S_& S, float x, float y, float z) {
     const ShConstF K = sh_constants_f();
     S.term(0, K.c0, 0, 0, 0);
     S.term(1, -K.c1 * y, 0, -K.c1, 0);
@@ -186,6 +252,20 @@ __device__ inline void offsets_to_rotation(const Geom& G, const ViewInfo& V, con
     }
 }
 
+// The slot result, in the layout the record summation leaves it in:
+//   [0..2] dL/d mu (geometric part), [3..11] dL/dR (row-major),
+//   [12..15] dL/d distances, [16..18] dL/d rgb, [19] dL/d sigma.
+__device__ inline void pack_slot_result(const double gm[3], const double gR[9], const double gd[4], float gr, float gg,
+                                        float gb, float gsig, float res[kGradWords]) {
+    for (int c = 0; c < 3; ++c) res[c] = (float)gm[c];
+    for (int c = 0; c < 9; ++c) res[3 + c] = (float)gR[c];
+    for (int c = 0; c < 4; ++c) res[12 + c] = (float)gd[c];
+    res[16] = gr;
+    res[17] = gg;
+    res[18] = gb;
+    res[19] = gsig;
+}
+
 // Exact variant (no ray space): the summed record holds, per plane k,
 // dL/d(a_k, b_k) at the rectangle origin (words 0, 1), dL/du_k (word 2, the
 // plane's offset g_k = a_k ox + b_k oy) and dL/dc_k (word 3), plus
@@ -195,7 +275,7 @@ __device__ inline void offsets_to_rotation(const Geom& G, const ViewInfo& V, con
 // then n_k -> camera offsets oc (and, for octahedra, the 1/d^2 weights).
 template <int KIND>
 __device__ inline void exact_slot_bwd(const Geom& G, const ViewInfo& V, const float* __restrict__ dists, double sigma,
-                                      double ox, double oy, const float r[kGradWords], float4* rp) {
+                                      double ox, double oy, const float r[kGradWords], float res[kGradWords]) {
     double nrm[4][3];
     exact_normals(KIND, G, nrm);
     const double tx = G.tc[0], ty = G.tc[1], tz = G.tc[2];
@@ -266,111 +346,17 @@ __device__ inline void exact_slot_bwd(const Geom& G, const ViewInfo& V, const fl
     offsets_to_rotation<KIND>(G, V, dists, goc, gR, gd);
     double gm[3];
     for (int c = 0; c < 3; ++c) gm[c] = V.Rw[c] * gt[0] + V.Rw[3 + c] * gt[1] + V.Rw[6 + c] * gt[2];
-    rp[0] = make_float4((float)gm[0], (float)gm[1], (float)gm[2], (float)gR[0]);
-    rp[1] = make_float4((float)gR[1], (float)gR[2], (float)gR[3], (float)gR[4]);
-    rp[2] = make_float4((float)gR[5], (float)gR[6], (float)gR[7], (float)gR[8]);
-    rp[3] = make_float4((float)gd[0], (float)gd[1], (float)gd[2], (float)gd[3]);
-    rp[4] = make_float4(r[16], r[17], r[18], (float)gsig);
+    pack_slot_result(gm, gR, gd, r[16], r[17], r[18], (float)gsig, res);
 }
 
-// ---------------------------------------------------------------------------
-// Stage 1, one thread per (view, primitive): the summed record (dL/d plane
-// coefficients, dL/d rgb, dL/d sigma) -> dL/d(ray-space centre, offsets) ->
-// camera -> world.  Writes back in place, into the same record:
-//   [0..2] dL/d mu (geometric part), [3..11] dL/dR (row-major),
-//   [12..15] dL/d distances, [16..19] unchanged (rgb, sigma).
-// ---------------------------------------------------------------------------
-template <int KIND, bool EXACT>
-__global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ means, const float* __restrict__ quats,
-                                                  const float* __restrict__ dists, const float* __restrict__ opacity,
-                                                  int64_t n, const ViewInfo* __restrict__ views,
-                                                  const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
-                                                  const uint32_t* __restrict__ offsets, float* __restrict__ grads,
-                                                  int nq, const Status* __restrict__ status, uint64_t capacity,
-                                                  const uint32_t* __restrict__ vis, int aa,
-                                                  float2* __restrict__ stats) {
-    // one thread per (view, primitive) slot that touches a tile, taken from
-    // the list the scan built, so that no lane idles on a culled slot
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (status->n_pairs > capacity) return;
-    if (t >= (int64_t)status->n_vis) return;
-    const int64_t vs = vis[t];
-    const int v = (int)(vs / n);
-    const int64_t i = vs - (int64_t)v * n;
+// Ray-space variant: the summed record r (dL/d plane coefficients, dL/d rgb,
+// dL/d sigma) -> dL/d(ray-space centre, offsets) -> camera -> world, into the
+// slot result.  `stat` receives the view-space positional gradient and the
+// screen radius used by population control.
+template <int KIND>
+__device__ inline void ray_slot_bwd(const Geom& G, const ViewInfo& V, const float dv[4], double ox, double oy,
+                                    const float r[kGradWords], float res[kGradWords], float2& stat) {
     constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
-    float4* rp = reinterpret_cast<float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
-    const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
-    const int nrec = (int)tiles[vs] * nq;
-    // the primitive's inputs, loaded while the records are summed
-    float mu[3], qv[4], dv[ND];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) mu[c] = means[3 * i + c];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) qv[c] = quats[4 * i + c];
-#pragma unroll
-    for (int c = 0; c < ND; ++c) dv[c] = dists[ND * i + c];
-    const float alpha = opacity[i];
-    float r[kGradWords];
-    if (nrec <= kBigRun) {
-        // sum the run in record order (skipping groups the rectangle misses),
-        // loading four records before adding them
-        const int qx = (nq == 1) ? 1 : (nq == 4) ? 2 : 4, tile = 8 * qx;
-        const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
-        const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
-#pragma unroll
-        for (int k = 0; k < kGradWords; ++k) r[k] = 0.0f;
-        for (int q0 = 0; q0 < nrec; q0 += 4) {
-            float4 x[4][kGradWords / 4];
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int q = q0 + h;
-                const bool use = q < nrec && (nq == 1 || record_exists(q, nq, qx, tile, rc, tx0, ty0, ntx));
-#pragma unroll
-                for (int k = 0; k < kGradWords / 4; ++k)
-                    x[h][k] = use ? rp[q * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-#pragma unroll
-            for (int h = 0; h < 4; ++h)
-#pragma unroll
-                for (int k = 0; k < kGradWords / 4; ++k) {
-                    r[4 * k] += x[h][k].x;
-                    r[4 * k + 1] += x[h][k].y;
-                    r[4 * k + 2] += x[h][k].z;
-                    r[4 * k + 3] += x[h][k].w;
-                }
-        }
-    } else {
-        // the chunk sums k_sum_big left in each chunk's first record
-#pragma unroll
-        for (int k = 0; k < kGradWords; ++k) r[k] = 0.0f;
-        for (int c = 0; c < kBigChunks; ++c) {
-            const int q = big_chunk_start(c, nrec);
-#pragma unroll
-            for (int k = 0; k < kGradWords / 4; ++k) {
-                const float4 x = rp[q * (kGradWords / 4) + k];
-                r[4 * k] += x.x;
-                r[4 * k + 1] += x.y;
-                r[4 * k + 2] += x.z;
-                r[4 * k + 3] += x.w;
-            }
-        }
-    }
-    const ViewInfo& V = views[v];
-    Geom G;
-    if (!build_geometry(KIND, EXACT, aa != 0, mu, qv, dv, alpha, V, G)) return;
-    // the plane origin of the record: the rectangle's centre (see k_preprocess)
-    const double ox = 0.5 * (double)(rc.x + rc.z) + 0.5 - G.c[0];
-    const double oy = 0.5 * (double)(rc.y + rc.w) + 0.5 - G.c[1];
-    if (EXACT) {
-        // the view-space positional gradient is a ray-space quantity: none here
-        stats[vs] = make_float2(0.0f, (float)G.radius);
-        double dmin = (double)dv[0];
-        for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dv[k]);
-        const double sigma = -log(1.0 - kAlphaScaleD * (double)alpha) / (2.0 * dmin);
-        exact_slot_bwd<KIND>(G, V, dv, sigma, ox, oy, r, rp);
-        return;
-    }
-
     // ---- planes -> ray-space centre (xy) and offsets a_k
     double gox = 0.0, goy = 0.0;
     double ga[4][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
@@ -448,7 +434,7 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     // normalised device coordinates, and the screen radius
     {
         const double ex = gc0 * 0.5 * (double)V.width, ey = gc1 * 0.5 * (double)V.height;
-        stats[vs] = make_float2((float)sqrt(ex * ex + ey * ey), (float)G.radius);
+        stat = make_float2((float)sqrt(ex * ex + ey * ey), (float)G.radius);
     }
 
     // ---- ray space -> camera: c = phi(t) with d phi/dt = J; a_k = J(t) oc_k
@@ -494,17 +480,302 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
     }
     double gm[3];
     for (int c = 0; c < 3; ++c) gm[c] = V.Rw[c] * gt[0] + V.Rw[3 + c] * gt[1] + V.Rw[6 + c] * gt[2];
-    rp[0] = make_float4((float)gm[0], (float)gm[1], (float)gm[2], (float)gR[0]);
-    rp[1] = make_float4((float)gR[1], (float)gR[2], (float)gR[3], (float)gR[4]);
-    rp[2] = make_float4((float)gR[5], (float)gR[6], (float)gR[7], (float)gR[8]);
-    rp[3] = make_float4((float)gd[0], (float)gd[1], (float)gd[2], (float)gd[3]);
-    rp[4] = make_float4(r[16], r[17], r[18], r[19]);
+    pack_slot_result(gm, gR, gd, r[16], r[17], r[18], r[19], res);
+}
+
+// Colour backward of one view (single precision): the colour gradient
+// (zero where the raw colour was clamped) onto the SH coefficients (added to
+// gsh, or stored to a row of dL/dSH by ShStore) and, through the viewing
+// direction, onto the mean (added to gm).
+template <int K, class S_>
+__device__ inline void view_colour_bwd_t(S_& S, const float shp[48], const float mu[3], const ViewInfo& V, float er,
+                                         float eg, float eb, double gm[3]) {
+    float dir[3] = {(float)((double)mu[0] - V.cam_pos[0]), (float)((double)mu[1] - V.cam_pos[1]),
+                    (float)((double)mu[2] - V.cam_pos[2])};
+    const float dn = sqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    const float idn = 1.0f / dn;
+    for (int q = 0; q < 3; ++q) dir[q] *= idn;
+    float raw[3];
+    sh_raw_f(K, shp, dir[0], dir[1], dir[2], raw);
+    S.K = K;
+    S.sh = shp;
+    S.gr[0] = raw[0] > 0.0f ? er : 0.0f;
+    S.gr[1] = raw[1] > 0.0f ? eg : 0.0f;
+    S.gr[2] = raw[2] > 0.0f ? eb : 0.0f;
+    S.gdir[0] = S.gdir[1] = S.gdir[2] = 0.0f;
+    sh_backward(S, dir[0], dir[1], dir[2]);
+    const float dot = S.gdir[0] * dir[0] + S.gdir[1] * dir[1] + S.gdir[2] * dir[2];
+    for (int q = 0; q < 3; ++q) gm[q] += (double)((S.gdir[q] - dot * dir[q]) * idn);
+}
+
+template <int K>
+__device__ inline void view_colour_bwd(const float shp[48], const float mu[3], const ViewInfo& V, float er, float eg,
+                                       float eb, float gsh[48], double gm[3]) {
+    ShBack S;
+    S.gsh = gsh;
+    view_colour_bwd_t<K>(S, shp, mu, V, er, eg, eb, gm);
+}
+
+// Rotation -> quaternion through R = I + s K(q), s = 2/|q|^2, and Eq. 1 ->
+// opacity with min(d) held constant.
+template <int KIND>
+__device__ inline void rotation_opacity_bwd(const float qf[4], const float* dv, float alpha, const double gR[9],
+                                            double gsig, double gq[4], double& ga) {
+    constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
+    const double w = qf[0], qx = qf[1], qy = qf[2], qz = qf[3];
+    const double n2 = w * w + qx * qx + qy * qy + qz * qz;
+    for (int m = 0; m < 4; ++m) gq[m] = 0.0;
+    if (n2 > 0.0) {
+        const double s = 2.0 / n2;
+        const double Km[9] = {-(qy * qy + qz * qz), qx * qy - w * qz, qx * qz + w * qy,
+                              qx * qy + w * qz, -(qx * qx + qz * qz), qy * qz - w * qx,
+                              qx * qz - w * qy, qy * qz + w * qx, -(qx * qx + qy * qy)};
+        double gK = 0.0;
+        for (int k = 0; k < 9; ++k) gK += gR[k] * Km[k];
+        const double qv[4] = {w, qx, qy, qz};
+        const double dK[4][9] = {{0, -qz, qy, qz, 0, -qx, -qy, qx, 0},
+                                 {0, qy, qz, qy, -2 * qx, -w, qz, w, -2 * qx},
+                                 {-2 * qy, qx, w, qx, 0, qz, -w, qz, -2 * qy},
+                                 {-2 * qz, -w, qx, w, -2 * qz, qy, qx, qy, 0}};
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+            double acc = -s * s * qv[mm] * gK;
+            for (int k = 0; k < 9; ++k) acc += s * gR[k] * dK[mm][k];
+            gq[mm] = acc;
+        }
+    }
+    double dmin = (double)dv[0];
+    for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dv[k]);
+    const double al = (double)alpha;
+    ga = gsig * kAlphaScaleD / ((1.0 - kAlphaScaleD * al) * 2.0 * dmin);
 }
 
 // ---------------------------------------------------------------------------
-// Stage 2, one thread per primitive: sums the views, then rotation ->
-// quaternion, Eq. 1 -> opacity (min d held constant), colour -> SH and the
-// viewing direction.  Outputs are overwritten.
+// Stage 1, the work of visible slot t: sums the slot's records, then the slot
+// result (ray-space or exact variant).  With several views (DEG < 0) it is
+// written back in place, into the slot's first record, for k_prim_bwd.  With
+// one view (DEG >= 0) a primitive has at most one slot, so the thread
+// finishes the primitive itself: colour -> SH and viewing direction, rotation
+// -> quaternion, Eq. 1 -> opacity, and writes its gradients.
+// ---------------------------------------------------------------------------
+template <int KIND, bool EXACT, int DEG>
+__device__ inline void slot_work(int64_t t, const float* __restrict__ means, const float* __restrict__ quats,
+                                 const float* __restrict__ dists, const float* __restrict__ opacity,
+                                 const float* __restrict__ sh, int64_t n, const ViewInfo* __restrict__ views,
+                                 const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
+                                 const uint32_t* __restrict__ offsets, float* __restrict__ grads, int nq,
+                                 const uint32_t* __restrict__ vis, int aa, float2* __restrict__ stats,
+                                 float* __restrict__ g_means, float* __restrict__ g_quats, float* __restrict__ g_dists,
+                                 float* __restrict__ g_opacity, float* __restrict__ g_sh) {
+    const int64_t vs = vis[t];
+    const int v = (int)(vs / n);
+    const int64_t i = vs - (int64_t)v * n;
+    constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
+    float4* rp = reinterpret_cast<float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
+    const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
+    const int nrec = (int)tiles[vs] * nq;
+    // the primitive's inputs, loaded while the records are summed
+    float mu[3], qv[4], dv[ND];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mu[c] = means[3 * i + c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) qv[c] = quats[4 * i + c];
+#pragma unroll
+    for (int c = 0; c < ND; ++c) dv[c] = dists[ND * i + c];
+    const float alpha = opacity[i];
+    float r[kGradWords];
+#pragma unroll
+    for (int k = 0; k < kGradWords; ++k) r[k] = 0.0f;
+    if (nrec <= kMidRun) {
+        // sum the run in record order (skipping groups the rectangle misses),
+        // loading four records before adding them
+        const int qx = (nq == 1) ? 1 : (nq == 4) ? 2 : 4, tile = 8 * qx;
+        const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
+        const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
+        for (int q0 = 0; q0 < nrec; q0 += 4) {
+            float4 x[4][kGradWords / 4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int q = q0 + h;
+                const bool use = q < nrec && (nq == 1 || record_exists(q, nq, qx, tile, rc, tx0, ty0, ntx));
+#pragma unroll
+                for (int k = 0; k < kGradWords / 4; ++k)
+                    x[h][k] = use ? rp[q * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int h = 0; h < 4; ++h)
+#pragma unroll
+                for (int k = 0; k < kGradWords / 4; ++k) {
+                    r[4 * k] += x[h][k].x;
+                    r[4 * k + 1] += x[h][k].y;
+                    r[4 * k + 2] += x[h][k].z;
+                    r[4 * k + 3] += x[h][k].w;
+                }
+        }
+    } else {
+        // the chunk sums k_sum_big left in each chunk's first record (one
+        // chunk for a run of at most kBigRun records)
+        const int nch = (nrec <= kBigRun) ? 1 : kBigChunks;
+        for (int c = 0; c < nch; ++c) {
+            const int q = big_chunk_start(c, nrec);
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k) {
+                const float4 x = rp[q * (kGradWords / 4) + k];
+                r[4 * k] += x.x;
+                r[4 * k + 1] += x.y;
+                r[4 * k + 2] += x.z;
+                r[4 * k + 3] += x.w;
+            }
+        }
+    }
+    const ViewInfo& V = views[v];
+    Geom G;
+    float res[kGradWords];
+    if (build_geometry(KIND, EXACT, aa != 0, mu, qv, dv, alpha, V, G)) {
+        // the plane origin of the record: the rectangle's centre (see k_preprocess)
+        const double ox = 0.5 * (double)(rc.x + rc.z) + 0.5 - G.c[0];
+        const double oy = 0.5 * (double)(rc.y + rc.w) + 0.5 - G.c[1];
+        if (EXACT) {
+            // the view-space positional gradient is a ray-space quantity: none here
+            stats[vs] = make_float2(0.0f, (float)G.radius);
+            double dmin = (double)dv[0];
+            for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dv[k]);
+            const double sigma = -log(1.0 - kAlphaScaleD * (double)alpha) / (2.0 * dmin);
+            exact_slot_bwd<KIND>(G, V, dv, sigma, ox, oy, r, res);
+        } else {
+            float2 st;
+            ray_slot_bwd<KIND>(G, V, dv, ox, oy, r, res, st);
+            stats[vs] = st;
+        }
+    } else {
+        // not reached for a slot the forward pass binned (same geometry)
+        if (DEG < 0) return;
+#pragma unroll
+        for (int k = 0; k < kGradWords; ++k) res[k] = 0.0f;
+    }
+    if (DEG < 0) {
+#pragma unroll
+        for (int k = 0; k < kGradWords / 4; ++k)
+            rp[k] = make_float4(res[4 * k], res[4 * k + 1], res[4 * k + 2], res[4 * k + 3]);
+        return;
+    }
+    // one view: the primitive's gradients, summed as k_prim_bwd sums them;
+    // rotation and opacity first, so that only the mean's gradient is live
+    // through the colour backward
+    constexpr int DG = (DEG < 0) ? 0 : DEG;
+    constexpr int K = (DG + 1) * (DG + 1);
+    // the primitive's inputs again (cache hits), through an index the
+    // compiler cannot see through, so that the first copies are not held in
+    // registers across the geometry
+    int64_t ii = i;
+    asm volatile("" : "+v"(ii));
+    float m2[3], q2[4], d2[4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m2[c] = means[3 * ii + c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) q2[c] = quats[4 * ii + c];
+#pragma unroll
+    for (int c = 0; c < ND; ++c) d2[c] = dists[ND * ii + c];
+    const float al = opacity[ii];
+    float shp[48];
+    load_sh<DG>(sh + i * (int64_t)K * 3, shp);
+    {
+        double gR[9];
+        for (int c = 0; c < 9; ++c) gR[c] = res[3 + c];
+        double gq[4], ga;
+        rotation_opacity_bwd<KIND>(q2, d2, al, gR, (double)res[19], gq, ga);
+        for (int c = 0; c < 4; ++c) g_quats[4 * i + c] = (float)gq[c];
+        for (int c = 0; c < ND; ++c) g_dists[ND * i + c] = res[12 + c];
+        g_opacity[i] = (float)ga;
+    }
+    double gm[3];
+    for (int c = 0; c < 3; ++c) gm[c] = res[c];
+    ShStore S;
+    S.gs = g_sh + i * (int64_t)(3 * K);
+    view_colour_bwd_t<K>(S, shp, m2, V, res[16], res[17], res[18], gm);
+    for (int c = 0; c < 3; ++c) g_means[3 * i + c] = (float)gm[c];
+}
+
+// One view: zero gradients for the primitives without a slot (all of them
+// when the pairs overflowed the capacity).  Thread t takes primitive t; the
+// wave's SH rows, contiguous, are written together by all its lanes (four
+// words per lane and store where a row is a whole number of float4s).
+template <int KIND, int DEG>
+__device__ inline void zero_unseen(const uint32_t* __restrict__ tiles, int64_t n, bool all, int64_t t,
+                                   float* __restrict__ g_means, float* __restrict__ g_quats,
+                                   float* __restrict__ g_dists, float* __restrict__ g_opacity,
+                                   float* __restrict__ g_sh) {
+    constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
+    constexpr int W = 3 * (DEG + 1) * (DEG + 1);
+    constexpr int U = (W % 4 == 0) ? 4 : 1;   // words per store
+    constexpr int UPR = W / U;                 // stores per primitive
+    const int lane = threadIdx.x & 63;
+    const bool unseen = t < n && (all || tiles[t] == 0);
+    if (unseen) {
+        for (int c = 0; c < 3; ++c) g_means[3 * t + c] = 0.0f;
+        for (int c = 0; c < 4; ++c) g_quats[4 * t + c] = 0.0f;
+        for (int c = 0; c < ND; ++c) g_dists[ND * t + c] = 0.0f;
+        g_opacity[t] = 0.0f;
+    }
+    const uint64_t m = __ballot(unseen);
+    if (m == 0) return;
+    const int64_t u0 = (t - lane) * UPR;   // first store unit of the wave's rows
+#pragma unroll 4
+    for (int j = 0; j < UPR; ++j) {
+        const int u = lane + 64 * j;
+        if ((m >> (u / UPR)) & 1) {
+            if (U == 4)
+                reinterpret_cast<float4*>(g_sh)[u0 + u] = make_float4(0.f, 0.f, 0.f, 0.f);
+            else
+                g_sh[u0 + u] = 0.0f;
+        }
+    }
+}
+
+// Stage 1, one thread per (view, primitive) slot that touches a tile, taken
+// from the list the scan built, so that no lane idles on a culled slot.  With
+// one view the grid (one thread per primitive at least) also writes the zero
+// gradients of the primitives without a slot, after the slot work (memory
+// traffic that overlaps the arithmetic of the other waves).
+template <int KIND, bool EXACT, int DEG>
+__global__ __launch_bounds__(128, (KIND == LINPRIM_OCTAHEDRON ? 3 : 2)) void k_slot_bwd(const float* __restrict__ means, const float* __restrict__ quats,
+                                                  const float* __restrict__ dists, const float* __restrict__ opacity,
+                                                  const float* __restrict__ sh,
+                                                  int64_t n, const ViewInfo* __restrict__ views,
+                                                  const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
+                                                  const uint32_t* __restrict__ offsets, float* __restrict__ grads,
+                                                  int nq, const Status* __restrict__ status, uint64_t capacity,
+                                                  const uint32_t* __restrict__ vis, int aa,
+                                                  float2* __restrict__ stats, float* __restrict__ g_means,
+                                                  float* __restrict__ g_quats, float* __restrict__ g_dists,
+                                                  float* __restrict__ g_opacity, float* __restrict__ g_sh) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool overflow = status->n_pairs > capacity;
+    const int64_t n_vis = status->n_vis;
+    if (DEG < 0) {
+        if (!overflow && t < n_vis)
+            slot_work<KIND, EXACT, DEG>(t, means, quats, dists, opacity, sh, n, views, payload, tiles, offsets, grads,
+                                        nq, vis, aa, stats, g_means, g_quats, g_dists, g_opacity, g_sh);
+        return;
+    }
+    // one view: the S blocks of slot work are spread evenly over the grid
+    // (block b takes slot block b S / B when that is where the quotient steps),
+    // so that slot arithmetic and zero stores run side by side
+    const int64_t S = (n_vis + blockDim.x - 1) / blockDim.x, B = gridDim.x;
+    const int64_t bs = (int64_t)blockIdx.x * S;
+    if (!overflow && bs % B < S) {
+        const int64_t ts = (bs / B) * blockDim.x + threadIdx.x;
+        if (ts < n_vis)
+            slot_work<KIND, EXACT, DEG>(ts, means, quats, dists, opacity, sh, n, views, payload, tiles, offsets, grads,
+                                        nq, vis, aa, stats, g_means, g_quats, g_dists, g_opacity, g_sh);
+    }
+    zero_unseen<KIND, (DEG < 0 ? 0 : DEG)>(tiles, n, overflow, t, g_means, g_quats, g_dists, g_opacity, g_sh);
+}
+
+// ---------------------------------------------------------------------------
+// Stage 2 (several views), one thread per primitive: sums the views' slot
+// results, the colour backward of each view, then rotation -> quaternion and
+// Eq. 1 -> opacity.  Outputs are overwritten.
 // ---------------------------------------------------------------------------
 template <int KIND, int DEG>
 __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ means, const float* __restrict__ quats,
@@ -527,16 +798,15 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
     float gsh[48];
 #pragma unroll
     for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
-    float shp[48];
+    float shp[48], mu[3];
     bool seen = false;
-    bool sh_loaded = false;
     for (int v = 0; ok && v < n_views; ++v) {
         const int64_t vs = (int64_t)v * n + i;
         if (tiles[vs] == 0) continue;
-        seen = true;
-        if (!sh_loaded) {
+        if (!seen) {
             load_sh<DEG>(sh + i * (int64_t)K * 3, shp);
-            sh_loaded = true;
+            for (int c = 0; c < 3; ++c) mu[c] = means[3 * i + c];
+            seen = true;
         }
         const float4* rp = reinterpret_cast<const float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
         const float4 a = rp[0], b = rp[1], c = rp[2], d = rp[3], e = rp[4];
@@ -545,59 +815,14 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
         gR[5] += c.x; gR[6] += c.y; gR[7] += c.z; gR[8] += c.w;
         gd[0] += d.x; gd[1] += d.y; gd[2] += d.z; gd[3] += d.w;
         gsig += e.w;
-        // colour -> SH coefficients and viewing direction (single precision)
-        const ViewInfo& V = views[v];
-        float dir[3] = {(float)((double)means[3 * i] - V.cam_pos[0]), (float)((double)means[3 * i + 1] - V.cam_pos[1]),
-                        (float)((double)means[3 * i + 2] - V.cam_pos[2])};
-        const float dn = sqrtf(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
-        const float idn = 1.0f / dn;
-        for (int q = 0; q < 3; ++q) dir[q] *= idn;
-        float raw[3];
-        sh_raw_f(K, shp, dir[0], dir[1], dir[2], raw);
-        ShBack S;
-        S.K = K;
-        S.sh = shp;
-        S.gsh = gsh;
-        S.gr[0] = raw[0] > 0.0f ? e.x : 0.0f;
-        S.gr[1] = raw[1] > 0.0f ? e.y : 0.0f;
-        S.gr[2] = raw[2] > 0.0f ? e.z : 0.0f;
-        S.gdir[0] = S.gdir[1] = S.gdir[2] = 0.0f;
-        sh_backward(S, dir[0], dir[1], dir[2]);
-        const float dot = S.gdir[0] * dir[0] + S.gdir[1] * dir[1] + S.gdir[2] * dir[2];
-        for (int q = 0; q < 3; ++q) gm[q] += (double)((S.gdir[q] - dot * dir[q]) * idn);
+        view_colour_bwd<K>(shp, mu, views[v], e.x, e.y, e.z, gsh, gm);
     }
-    // rotation -> quaternion through R = I + s K(q), s = 2/|q|^2
-    double gq[4] = {0, 0, 0, 0};
+    double gq[4] = {0, 0, 0, 0}, ga = 0.0;
     if (seen) {
-        const double w = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
-        const double n2 = w * w + qx * qx + qy * qy + qz * qz;
-        if (n2 > 0.0) {
-            const double s = 2.0 / n2;
-            const double Km[9] = {-(qy * qy + qz * qz), qx * qy - w * qz, qx * qz + w * qy,
-                                  qx * qy + w * qz, -(qx * qx + qz * qz), qy * qz - w * qx,
-                                  qx * qz - w * qy, qy * qz + w * qx, -(qx * qx + qy * qy)};
-            double gK = 0.0;
-            for (int k = 0; k < 9; ++k) gK += gR[k] * Km[k];
-            const double qv[4] = {w, qx, qy, qz};
-            const double dK[4][9] = {{0, -qz, qy, qz, 0, -qx, -qy, qx, 0},
-                                     {0, qy, qz, qy, -2 * qx, -w, qz, w, -2 * qx},
-                                     {-2 * qy, qx, w, qx, 0, qz, -w, qz, -2 * qy},
-                                     {-2 * qz, -w, qx, w, -2 * qz, qy, qx, qy, 0}};
-#pragma unroll
-            for (int mm = 0; mm < 4; ++mm) {
-                double acc = -s * s * qv[mm] * gK;
-                for (int k = 0; k < 9; ++k) acc += s * gR[k] * dK[mm][k];
-                gq[mm] = acc;
-            }
-        }
-    }
-    // Eq. 1 with min(d) held constant
-    double ga = 0.0;
-    if (seen) {
-        double dmin = (double)dists[ND * i];
-        for (int k = 1; k < ND; ++k) dmin = fmin(dmin, (double)dists[ND * i + k]);
-        const double al = (double)opacity[i];
-        ga = gsig * kAlphaScaleD / ((1.0 - kAlphaScaleD * al) * 2.0 * dmin);
+        float qf[4], dv[4];
+        for (int c = 0; c < 4; ++c) qf[c] = quats[4 * i + c];
+        for (int c = 0; c < ND; ++c) dv[c] = dists[ND * i + c];
+        rotation_opacity_bwd<KIND>(qf, dv, opacity[i], gR, gsig, gq, ga);
     }
     if (i < n) {
         for (int c = 0; c < 3; ++c) g_means[3 * i + c] = (float)gm[c];
@@ -633,38 +858,43 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
     const uint32_t* big = reinterpret_cast<const uint32_t*>(vws + L.big);
     // a fixed grid of waves strides over the (big slot, chunk) items, whose
     // number is only known on the device
-    const int64_t max_waves = (vn * kBigChunks + 3) / 4;
+    const int64_t max_waves = (vn * kBigChunks + 3) / 4;   // bounds the grid only
     const unsigned big_blocks = (unsigned)(max_waves < 1024 ? (max_waves > 0 ? max_waves : 1) : 1024);
-    hipLaunchKernelGGL(k_sum_big, dim3(big_blocks), dim3(256), 0, stream, payload, tiles, offsets, big, tile, st, cap,
-                       grads);
+    hipLaunchKernelGGL(k_sum_big, dim3(big_blocks), dim3(256), 0, stream, payload, tiles, offsets, big, vn, tile, st,
+                       cap, grads);
     const dim3 g1((unsigned)((vn + 127) / 128));
     const uint32_t* vis = reinterpret_cast<const uint32_t*>(vws + L.vis);
     float2* stats = reinterpret_cast<float2*>(const_cast<char*>(vws) + L.stats);
     const dim3 g2((unsigned)((p.n + 127) / 128));
-#define LP_PRIM(K_, D_)                                                                                        \
-    hipLaunchKernelGGL((k_prim_bwd<K_, D_>), g2, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, p.sh, \
-                       p.n, n_views, views, tiles, offsets, grads, nq, st, cap, g_means, g_quats, g_dists, g_opacity, \
-                       g_sh)
-#define LP_PRIM_DEG(K_)                      \
-    switch (p.sh_degree) {                   \
-        case 0: LP_PRIM(K_, 0); break;       \
-        case 1: LP_PRIM(K_, 1); break;       \
-        case 2: LP_PRIM(K_, 2); break;       \
-        default: LP_PRIM(K_, 3); break;      \
+    const bool one = n_views == 1;
+#define LP_SLOT(K_, E_, D_)                                                                                     \
+    hipLaunchKernelGGL((k_slot_bwd<K_, E_, D_>), g1, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, \
+                       p.sh, p.n, views, payload, tiles, offsets, grads, nq, st, cap, vis, aa ? 1 : 0, stats,   \
+                       g_means, g_quats, g_dists, g_opacity, g_sh)
+#define LP_STAGES(K_, E_, D_)                                                                                     \
+    if (one) {                                                                                                     \
+        LP_SLOT(K_, E_, D_);                                                                                       \
+    } else {                                                                                                       \
+        LP_SLOT(K_, E_, -1);                                                                                       \
+        hipLaunchKernelGGL((k_prim_bwd<K_, D_>), g2, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity,  \
+                           p.sh, p.n, n_views, views, tiles, offsets, grads, nq, st, cap, g_means, g_quats,       \
+                           g_dists, g_opacity, g_sh);                                                              \
     }
-#define LP_SLOT(K_, E_)                                                                                         \
-    hipLaunchKernelGGL((k_slot_bwd<K_, E_>), g1, dim3(128), 0, stream, p.means, p.quats, p.dists, p.opacity, p.n, \
-                       views, payload, tiles, offsets, grads, nq, st, cap, vis, aa ? 1 : 0, stats)
+#define LP_DEG(K_, E_)                          \
+    switch (p.sh_degree) {                      \
+        case 0: LP_STAGES(K_, E_, 0) break;     \
+        case 1: LP_STAGES(K_, E_, 1) break;     \
+        case 2: LP_STAGES(K_, E_, 2) break;     \
+        default: LP_STAGES(K_, E_, 3) break;    \
+    }
     if (p.type == LINPRIM_OCTAHEDRON) {
-        if (exact) LP_SLOT(LINPRIM_OCTAHEDRON, true); else LP_SLOT(LINPRIM_OCTAHEDRON, false);
-        LP_PRIM_DEG(LINPRIM_OCTAHEDRON)
+        if (exact) LP_DEG(LINPRIM_OCTAHEDRON, true) else LP_DEG(LINPRIM_OCTAHEDRON, false)
     } else {
-        if (exact) LP_SLOT(LINPRIM_TETRAHEDRON, true); else LP_SLOT(LINPRIM_TETRAHEDRON, false);
-        LP_PRIM_DEG(LINPRIM_TETRAHEDRON)
+        if (exact) LP_DEG(LINPRIM_TETRAHEDRON, true) else LP_DEG(LINPRIM_TETRAHEDRON, false)
     }
+#undef LP_DEG
+#undef LP_STAGES
 #undef LP_SLOT
-#undef LP_PRIM_DEG
-#undef LP_PRIM
     return hipGetLastError();
 }
 

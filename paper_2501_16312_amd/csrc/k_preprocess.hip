@@ -321,6 +321,7 @@ __global__ void k_status_empty(Status* __restrict__ status) {
         status->n_vis = 0;
         status->overflow = 0;
         status->n_big = 0;
+        status->n_mid = 0;
         status->n_huge = 0;
     }
 }
@@ -332,6 +333,7 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict_
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         status->overflow = 0;
         status->n_big = 0;
+        status->n_mid = 0;
         status->n_huge = 0;
     }
     __shared__ uint64_t part[2][4];
@@ -442,7 +444,9 @@ __device__ inline void block_scan2_u64(uint64_t& a, uint64_t& b, uint64_t* part8
 // Also lists, in slot order, the slots that touch a tile (for the
 // preprocessing backward), and, in no particular order, those with more than
 // kBigRun gradient records (tile count x groups per tile) and those with
-// more than kHugeRun tiles.  The block's counts are loaded and its offsets
+// more than kHugeRun tiles; per block in slot order, the slots with more
+// than kMidRun up to kBigRun records (the mid list, from the end of the big
+// list's array).  The block's counts are loaded and its offsets
 // and list entries stored coalesced, through LDS; each thread scans 16
 // consecutive slots in between.
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__ in, int64_t count,
@@ -482,17 +486,26 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
     }
     __syncthreads();
     uint32_t v[PER];
+    // per thread: tile sum; slots that touch a tile (low word) and mid slots
+    // (high word), scanned together
     uint64_t s = 0, c = 0;
+    auto is_mid = [nq](uint32_t x) {
+        const int64_t nrec = (int64_t)x * nq;
+        return nrec > kMidRun && nrec <= kBigRun;
+    };
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         v[k] = stage[t * (PER + 1) + k];
         s += v[k];
-        c += v[k] ? 1u : 0u;
+        c += (v[k] ? 1u : 0u) + (is_mid(v[k]) ? (1ull << 32) : 0ull);
     }
     uint64_t ts, tc;
     block_scan2_u64(s, c, part8, ts, tc);
+    // the block's mid slots take one run of the mid list (a single atomic)
+    __shared__ uint32_t mid_base;
+    if (t == 0 && (tc >> 32)) mid_base = atomicAdd(&status->n_mid, (uint32_t)(tc >> 32));
     uint64_t run = pre + s;
-    uint32_t lv = (uint32_t)c;
+    uint32_t lv = (uint32_t)c, lm = (uint32_t)(c >> 32);
     const int lane = t & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -510,8 +523,10 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
         const int e = k * 256 + t;
         const int64_t idx = base + e;
         if (idx < count) out[idx] = stage[e + e / PER];
+        const int64_t own = base + (int64_t)t * PER + k;
+        if (is_mid(v[k])) big[count - 1 - (int64_t)(mid_base + lm++)] = (uint32_t)own;
     }
-    for (int j = t; j < (int)tc; j += 256) vis[vpre + j] = vstage[j];
+    for (int j = t; j < (int)(uint32_t)tc; j += 256) vis[vpre + j] = vstage[j];
 }
 
 hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stream) {

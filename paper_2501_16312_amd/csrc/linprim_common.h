@@ -83,7 +83,7 @@ struct Status {
     uint32_t n_long;       // tiles whose list is sorted by the long-list kernel
     uint32_t n_vis;        // (view, primitive) slots that touch a tile (list in ViewLayout::vis)
     uint32_t n_huge;       // slots with more than kHugeRun tiles (list in ViewLayout::huge)
-    uint32_t pad32;
+    uint32_t n_mid;        // slots with kMidRun < records <= kBigRun (listed from the end of ViewLayout::big)
     uint64_t pad[3];
 };
 
@@ -130,8 +130,14 @@ hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stre
 
 // A (view, primitive) slot whose gradient records number more than kBigRun
 // is listed by the scan; its records are summed by kBigChunks waves, each
-// writing its partial sum over the chunk into the chunk's first record.
+// writing its partial sum over the chunk into the chunk's first record.  A
+// slot with more than kMidRun records, up to kBigRun, is summed in record
+// order by twenty lanes, one word each, into its first record (the mid list,
+// stored from the end of the same array: each slot is on at most one of the
+// two lists).  The thread of a slot with at most kMidRun records sums them
+// itself.
 constexpr int kBigRun = 64;
+constexpr int kMidRun = 8;
 // Slots whose tile rectangle holds more than kHugeRun tiles have their pairs
 // emitted by every wave of the emission grid together.
 constexpr int kHugeRun = 1024;
