@@ -39,7 +39,9 @@ __device__ inline void sum_big_chunk(const float* __restrict__ payload, const ui
     const int nr = (int)tiles[slot] * NQ;
     const int r0 = big_chunk_start(c, nr), r1 = big_chunk_start(c + 1, nr);
     const uint32_t o = offsets[slot];
-    const int4 rc = *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
+    // the pixel rectangle decides which records exist only with several
+    // groups per tile
+    const int4 rc = (NQ == 1) ? make_int4(0, 0, 0, 0) : *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
     const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
     float acc[kGradWords];
 #pragma unroll
@@ -84,7 +86,9 @@ __device__ inline void sum_mid_slot(const float* __restrict__ payload, const uin
     const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
     const int nr = (int)tiles[slot] * NQ;
     const uint32_t o = offsets[slot];
-    const int4 rc = *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
+    // the pixel rectangle decides which records exist only with several
+    // groups per tile
+    const int4 rc = (NQ == 1) ? make_int4(0, 0, 0, 0) : *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
     const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
     float* g = grads + (int64_t)o * NQ * kGradWords + w;
     float acc = 0.0f;
@@ -572,7 +576,10 @@ __device__ inline void slot_work(int64_t t, const float* __restrict__ means, con
     const int64_t i = vs - (int64_t)v * n;
     constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
     float4* rp = reinterpret_cast<float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
-    const int4 rc = *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
+    // the pixel rectangle: read here only where it decides which records
+    // exist (several groups per tile); the plane origin below takes it from
+    // the recomputed geometry, which reproduces the preprocessing's exactly
+    const int4 rc = (nq == 1) ? make_int4(0, 0, 0, 0) : *reinterpret_cast<const int4*>(payload + vs * kRecordWords);
     const int nrec = (int)tiles[vs] * nq;
     // the primitive's inputs, loaded while the records are summed
     float mu[3], qv[4], dv[ND];
@@ -633,8 +640,8 @@ __device__ inline void slot_work(int64_t t, const float* __restrict__ means, con
     float res[kGradWords];
     if (build_geometry(KIND, EXACT, aa != 0, mu, qv, dv, alpha, V, G)) {
         // the plane origin of the record: the rectangle's centre (see k_preprocess)
-        const double ox = 0.5 * (double)(rc.x + rc.z) + 0.5 - G.c[0];
-        const double oy = 0.5 * (double)(rc.y + rc.w) + 0.5 - G.c[1];
+        const double ox = 0.5 * (double)(G.rect[0] + G.rect[2]) + 0.5 - G.c[0];
+        const double oy = 0.5 * (double)(G.rect[1] + G.rect[3]) + 0.5 - G.c[1];
         if (EXACT) {
             // the view-space positional gradient is a ray-space quantity: none here
             stats[vs] = make_float2(0.0f, (float)G.radius);
