@@ -745,7 +745,7 @@ __device__ inline void zero_unseen(const uint32_t* __restrict__ tiles, int64_t n
 // gradients of the primitives without a slot, after the slot work (memory
 // traffic that overlaps the arithmetic of the other waves).
 template <int KIND, bool EXACT, int DEG>
-__global__ __launch_bounds__(128, (KIND == LINPRIM_OCTAHEDRON ? 3 : 2)) void k_slot_bwd(const float* __restrict__ means, const float* __restrict__ quats,
+__global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ means, const float* __restrict__ quats,
                                                   const float* __restrict__ dists, const float* __restrict__ opacity,
                                                   const float* __restrict__ sh,
                                                   int64_t n, const ViewInfo* __restrict__ views,
