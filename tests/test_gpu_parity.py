@@ -346,6 +346,21 @@ def test_edge_cases(oracle_mod):
     n, ov = rast.status()
     assert n == need and ov
     assert torch.all(rgb == -7.0).item()
+    # ... and the backward overwrites every gradient with zeros (one view: the
+    # slot kernel's own zero pass; two views: the per-primitive stage)
+    for views in (cams, cams + [scenes.look_at((2.5, 0.3, 1.5), (0, 0, 0), 40, 33)]):
+        r2 = Rasterizer(sc.kind, sc.n, views, tile=16)
+        need2 = r2.preprocess(prims, sync_count=True)
+        r2.pair_ws = torch.empty(L.linprim_pair_workspace_size(need2 // 2, r2.cams_c, r2.tune), dtype=torch.uint8,
+                                 device="cuda")
+        r2.max_pairs = need2 // 2
+        r2.bin_sort(prims)
+        rgb2, T2, last2 = r2.alloc_outputs()
+        r2.render(prims, None, out=(rgb2, T2, last2))
+        grads = {k: v.fill_(float("nan")) for k, v in r2.alloc_grads(prims).items()}
+        r2.backward(prims, None, T2, last2, torch.ones_like(rgb2), grads=grads)
+        torch.cuda.synchronize()
+        assert all(torch.all(v == 0).item() for v in grads.values()), f"{len(views)} views: gradients not zeroed"
 
 
 # ------------------------------------------------------------ full-size workloads
