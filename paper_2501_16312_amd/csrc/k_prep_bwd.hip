@@ -24,13 +24,13 @@ __device__ inline bool record_exists(int r, int NQ, int QX, int tile, int4 rect,
     return !(rect.x > gx0 + 7 || rect.z < gx0 || rect.y > gy0 + 7 || rect.w < gy0);
 }
 
-// Sums the gradient records of the slots on the big-slot list (more than
-// kBigRun records: primitives spanning many tiles) and on the mid list.  A
-// big slot's run is cut into kBigChunks equal chunks; one wavefront per chunk
-// strides over it, sums across lanes in a fixed order and writes the chunk's
-// sum into the chunk's first record, so no wave holds up the kernel with a
-// long run and the result does not depend on scheduling.  k_slot_bwd adds the
-// chunk sums in chunk order; shorter runs it sums itself.
+// Sums the gradient records of the slots with more than kMidRun records.
+// The run of a slot with more than kBigRun records is cut into kBigChunks
+// equal chunks; for a huge slot (more than kHugeRun tiles) one wavefront per
+// chunk strides over it, sums across lanes in a fixed order and writes the
+// chunk's sum into the chunk's first record, so no wave holds up the kernel
+// with a long run and the result does not depend on scheduling.  k_slot_bwd
+// adds the chunk sums in chunk order; shorter runs it sums itself.
 __device__ inline void sum_big_chunk(const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
                                      const uint32_t* __restrict__ offsets, int64_t slot, int c, int tile,
                                      float* __restrict__ grads, int lane) {
@@ -107,25 +107,85 @@ __device__ inline void sum_mid_slot(const float* __restrict__ payload, const uin
     g[0] = acc;
 }
 
+// A big slot's run (more than kBigRun records, up to kHugeRun tiles) summed
+// by one wave: four lanes per chunk (lane l takes chunk l / 4), each lane the
+// chunk's records l % 4, l % 4 + 4, ... in order, four loads in flight, then
+// the four lanes' sums added across the quad; the quad's first lane writes
+// the chunk's sum into the chunk's first record.
+__device__ inline void sum_big_quads(const float* __restrict__ payload, const uint32_t* __restrict__ tiles,
+                                     const uint32_t* __restrict__ offsets, int64_t slot, int tile,
+                                     float* __restrict__ grads, int lane) {
+    const int QX = tile / 8, NQ = QX * QX;
+    const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
+    const int nr = (int)tiles[slot] * NQ;
+    const int c = lane >> 2, sub = lane & 3;
+    const int r0 = big_chunk_start(c, nr), r1 = big_chunk_start(c + 1, nr);
+    const uint32_t o = offsets[slot];
+    const int4 rc = (NQ == 1) ? make_int4(0, 0, 0, 0) : *reinterpret_cast<const int4*>(payload + slot * kRecordWords);
+    const int tx0 = rc.x >> shift, ty0 = rc.y >> shift, ntx = (rc.z >> shift) - tx0 + 1;
+    float acc[kGradWords];
+#pragma unroll
+    for (int k = 0; k < kGradWords; ++k) acc[k] = 0.0f;
+    const float4* g = reinterpret_cast<const float4*>(grads + (int64_t)o * NQ * kGradWords);
+    for (int rb = r0 + sub; rb < r1; rb += 16) {
+        float4 x[4][kGradWords / 4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int r = rb + 4 * h;
+            const bool use = r < r1 && (NQ == 1 || record_exists(r, NQ, QX, tile, rc, tx0, ty0, ntx));
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k)
+                x[h][k] = use ? g[(int64_t)r * (kGradWords / 4) + k] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k) {
+                acc[4 * k] += x[h][k].x;
+                acc[4 * k + 1] += x[h][k].y;
+                acc[4 * k + 2] += x[h][k].z;
+                acc[4 * k + 3] += x[h][k].w;
+            }
+    }
+    // quad sums: lanes i and i ^ 1, then i and i ^ 2
+#pragma unroll
+    for (int k = 0; k < kGradWords; ++k) {
+        acc[k] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc[k]), 0xB1, 0xF, 0xF, false));
+        acc[k] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc[k]), 0x4E, 0xF, 0xF, false));
+    }
+    if (sub == 0) {
+        float4* dst = reinterpret_cast<float4*>(grads + ((int64_t)o * NQ + r0) * kGradWords);
+#pragma unroll
+        for (int k = 0; k < kGradWords / 4; ++k)
+            dst[k] = make_float4(acc[4 * k], acc[4 * k + 1], acc[4 * k + 2], acc[4 * k + 3]);
+    }
+}
+
 constexpr int kMidPerWave = 64 / kGradWords;   // mid slots per wavefront (three)
 
+// Items: kBigChunks per huge slot (one wave per chunk), one per big slot
+// (sum_big_quads), one per kMidPerWave mid slots.
 __global__ __launch_bounds__(256) void k_sum_big(const float* __restrict__ payload,
                                                  const uint32_t* __restrict__ tiles,
                                                  const uint32_t* __restrict__ offsets,
-                                                 const uint32_t* __restrict__ big, int64_t n_slots, int tile,
+                                                 const uint32_t* __restrict__ big,
+                                                 const uint32_t* __restrict__ huge, int64_t n_slots, int tile,
                                                  const Status* __restrict__ status, uint64_t capacity,
                                                  float* __restrict__ grads) {
     if (status->n_pairs > capacity) return;
     const int lane = threadIdx.x & 63;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    const int64_t n_chunked = (int64_t)status->n_big * kBigChunks;
+    const int64_t n_chunked = (int64_t)status->n_huge * kBigChunks;
+    const int64_t n_quads = n_chunked + status->n_big;
     const int64_t n_mid = status->n_mid;
-    const int64_t items = n_chunked + (n_mid + kMidPerWave - 1) / kMidPerWave;
+    const int64_t items = n_quads + (n_mid + kMidPerWave - 1) / kMidPerWave;
     for (int64_t it = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); it < items; it += waves) {
         if (it < n_chunked) {
-            sum_big_chunk(payload, tiles, offsets, big[it / kBigChunks], (int)(it % kBigChunks), tile, grads, lane);
+            sum_big_chunk(payload, tiles, offsets, huge[it / kBigChunks], (int)(it % kBigChunks), tile, grads, lane);
+        } else if (it < n_quads) {
+            sum_big_quads(payload, tiles, offsets, big[it - n_chunked], tile, grads, lane);
         } else {
-            const int64_t m = (it - n_chunked) * kMidPerWave + lane / kGradWords;
+            const int64_t m = (it - n_quads) * kMidPerWave + lane / kGradWords;
             if (lane < kMidPerWave * kGradWords && m < n_mid)
                 sum_mid_slot(payload, tiles, offsets, big[n_slots - 1 - m], lane % kGradWords, tile, grads);
         }
@@ -867,8 +927,9 @@ hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int ti
     // number is only known on the device
     const int64_t max_waves = (vn * kBigChunks + 3) / 4;   // bounds the grid only
     const unsigned big_blocks = (unsigned)(max_waves < 1024 ? (max_waves > 0 ? max_waves : 1) : 1024);
-    hipLaunchKernelGGL(k_sum_big, dim3(big_blocks), dim3(256), 0, stream, payload, tiles, offsets, big, vn, tile, st,
-                       cap, grads);
+    const uint32_t* huge = reinterpret_cast<const uint32_t*>(vws + L.huge);
+    hipLaunchKernelGGL(k_sum_big, dim3(big_blocks), dim3(256), 0, stream, payload, tiles, offsets, big, huge, vn, tile,
+                       st, cap, grads);
     const dim3 g1((unsigned)((vn + 127) / 128));
     const uint32_t* vis = reinterpret_cast<const uint32_t*>(vws + L.vis);
     float2* stats = reinterpret_cast<float2*>(const_cast<char*>(vws) + L.stats);

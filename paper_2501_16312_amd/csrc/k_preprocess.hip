@@ -443,8 +443,8 @@ __device__ inline void block_scan2_u64(uint64_t& a, uint64_t& b, uint64_t* part8
 
 // Also lists, in slot order, the slots that touch a tile (for the
 // preprocessing backward), and, in no particular order, those with more than
-// kBigRun gradient records (tile count x groups per tile) and those with
-// more than kHugeRun tiles; per block in slot order, the slots with more
+// kBigRun gradient records (tile count x groups per tile) up to kHugeRun
+// tiles and those with more than kHugeRun tiles; per block in slot order, the slots with more
 // than kMidRun up to kBigRun records (the mid list, from the end of the big
 // list's array).  The block's counts are loaded and its offsets
 // and list entries stored coalesced, through LDS; each thread scans 16
@@ -514,7 +514,9 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* __restrict__
         stage[t * (PER + 1) + k] = (uint32_t)run;
         run += v[k];
         if (v[k]) vstage[lv++] = idx;
-        wave_append((int64_t)v[k] * nq > kBigRun, idx, &status->n_big, big, lane, lt_mask);
+        // (slots over kHugeRun tiles are on the huge list, which also serves
+        // their record sums)
+        wave_append((int64_t)v[k] * nq > kBigRun && v[k] <= (uint32_t)kHugeRun, idx, &status->n_big, big, lane, lt_mask);
         wave_append(v[k] > (uint32_t)kHugeRun, idx, &status->n_huge, huge, lane, lt_mask);
     }
     __syncthreads();

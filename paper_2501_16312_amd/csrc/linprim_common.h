@@ -78,7 +78,7 @@ struct ViewInfo {
 struct Status {
     uint64_t n_pairs;      // written by the scan
     uint32_t overflow;     // set by bin_sort when n_pairs > capacity
-    uint32_t n_big;        // slots with more than kBigRun gradient records (list in ViewLayout::big)
+    uint32_t n_big;        // slots with more than kBigRun records, up to kHugeRun tiles (list in ViewLayout::big)
     uint64_t capacity;
     uint32_t n_long;       // tiles whose list is sorted by the long-list kernel
     uint32_t n_vis;        // (view, primitive) slots that touch a tile (list in ViewLayout::vis)
@@ -129,13 +129,14 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
 hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stream);
 
 // A (view, primitive) slot whose gradient records number more than kBigRun
-// is listed by the scan; its records are summed by kBigChunks waves, each
-// writing its partial sum over the chunk into the chunk's first record.  A
-// slot with more than kMidRun records, up to kBigRun, is summed in record
-// order by twenty lanes, one word each, into its first record (the mid list,
-// stored from the end of the same array: each slot is on at most one of the
-// two lists).  The thread of a slot with at most kMidRun records sums them
-// itself.
+// has them summed in kBigChunks chunks, each chunk's sum written into the
+// chunk's first record: by one wave, four lanes per chunk, if the slot is on
+// the scan's big list (up to kHugeRun tiles), else (more than kHugeRun tiles:
+// the huge list) by kBigChunks waves, one per chunk.  A slot with more than
+// kMidRun records, up to kBigRun, is summed in record order by twenty lanes,
+// one word each, into its first record (the mid list, stored from the end of
+// the big list's array: each slot is on at most one of the two).  The thread
+// of a slot with at most kMidRun records sums them itself.
 constexpr int kBigRun = 64;
 constexpr int kMidRun = 8;
 // Slots whose tile rectangle holds more than kHugeRun tiles have their pairs
