@@ -720,41 +720,46 @@ __device__ inline void slot_work(int64_t t, const float* __restrict__ means, con
 #pragma unroll
         for (int k = 0; k < kGradWords; ++k) res[k] = 0.0f;
     }
-    if (DEG < 0) {
-#pragma unroll
-        for (int k = 0; k < kGradWords / 4; ++k)
-            rp[k] = make_float4(res[4 * k], res[4 * k + 1], res[4 * k + 2], res[4 * k + 3]);
-        return;
-    }
-    // one view: the primitive's gradients, summed as k_prim_bwd sums them;
-    // rotation and opacity first, so that only the mean's gradient is live
-    // through the colour backward
-    constexpr int DG = (DEG < 0) ? 0 : DEG;
-    constexpr int K = (DG + 1) * (DG + 1);
-    // the primitive's inputs again (cache hits), through an index the
-    // compiler cannot see through, so that the first copies are not held in
-    // registers across the geometry
+    // rotation -> quaternion and Eq. 1 -> opacity for this slot (linear in
+    // the slot's dL/dR and dL/dsigma, so the per-view values sum to the
+    // primitive's); the primitive's inputs are read again (cache hits) through
+    // an index the compiler cannot see through, so that the first copies are
+    // not held in registers across the geometry
     int64_t ii = i;
     asm volatile("" : "+v"(ii));
-    float m2[3], q2[4], d2[4];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) m2[c] = means[3 * ii + c];
+    float q2[4], d2[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) q2[c] = quats[4 * ii + c];
 #pragma unroll
     for (int c = 0; c < ND; ++c) d2[c] = dists[ND * ii + c];
     const float al = opacity[ii];
-    float shp[48];
-    load_sh<DG>(sh + i * (int64_t)K * 3, shp);
+    double gq[4], ga;
     {
         double gR[9];
         for (int c = 0; c < 9; ++c) gR[c] = res[3 + c];
-        double gq[4], ga;
         rotation_opacity_bwd<KIND>(q2, d2, al, gR, (double)res[19], gq, ga);
-        for (int c = 0; c < 4; ++c) g_quats[4 * i + c] = (float)gq[c];
-        for (int c = 0; c < ND; ++c) g_dists[ND * i + c] = res[12 + c];
-        g_opacity[i] = (float)ga;
     }
+    if (DEG < 0) {
+        // the slot result, written back into the slot's first record:
+        // [0..2] dL/d mu (geometric part), [3..6] dL/dq, [7..10] dL/d
+        // distances, [11..13] dL/d rgb, [14] dL/d alpha
+        rp[0] = make_float4(res[0], res[1], res[2], (float)gq[0]);
+        rp[1] = make_float4((float)gq[1], (float)gq[2], (float)gq[3], res[12]);
+        rp[2] = make_float4(res[13], res[14], res[15], res[16]);
+        rp[3] = make_float4(res[17], res[18], (float)ga, 0.0f);
+        return;
+    }
+    // one view: the primitive's gradients, written as they are formed
+    constexpr int DG = (DEG < 0) ? 0 : DEG;
+    constexpr int K = (DG + 1) * (DG + 1);
+    for (int c = 0; c < 4; ++c) g_quats[4 * i + c] = (float)gq[c];
+    for (int c = 0; c < ND; ++c) g_dists[ND * i + c] = res[12 + c];
+    g_opacity[i] = (float)ga;
+    float m2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m2[c] = means[3 * ii + c];
+    float shp[48];
+    load_sh<DG>(sh + i * (int64_t)K * 3, shp);
     double gm[3];
     for (int c = 0; c < 3; ++c) gm[c] = res[c];
     ShStore S;
@@ -805,7 +810,7 @@ __device__ inline void zero_unseen(const uint32_t* __restrict__ tiles, int64_t n
 // gradients of the primitives without a slot, after the slot work (memory
 // traffic that overlaps the arithmetic of the other waves).
 template <int KIND, bool EXACT, int DEG>
-__global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ means, const float* __restrict__ quats,
+__global__ __launch_bounds__(128, (DEG < 0 && KIND == LINPRIM_OCTAHEDRON) ? 3 : 1) void k_slot_bwd(const float* __restrict__ means, const float* __restrict__ quats,
                                                   const float* __restrict__ dists, const float* __restrict__ opacity,
                                                   const float* __restrict__ sh,
                                                   int64_t n, const ViewInfo* __restrict__ views,
@@ -841,8 +846,8 @@ __global__ __launch_bounds__(128) void k_slot_bwd(const float* __restrict__ mean
 
 // ---------------------------------------------------------------------------
 // Stage 2 (several views), one thread per primitive: sums the views' slot
-// results, the colour backward of each view, then rotation -> quaternion and
-// Eq. 1 -> opacity.  Outputs are overwritten.
+// results (quaternion and opacity gradients already formed per slot) and
+// runs the colour backward of each view.  Outputs are overwritten.
 // ---------------------------------------------------------------------------
 template <int KIND, int DEG>
 __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ means, const float* __restrict__ quats,
@@ -861,7 +866,7 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
     constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
     constexpr int K = (DEG + 1) * (DEG + 1);
     const bool ok = status->n_pairs <= capacity && i < n;
-    double gm[3] = {0, 0, 0}, gR[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, gd[4] = {0, 0, 0, 0}, gsig = 0.0;
+    double gm[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gd[4] = {0, 0, 0, 0}, ga = 0.0;
     float gsh[48];
 #pragma unroll
     for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
@@ -875,21 +880,14 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
             for (int c = 0; c < 3; ++c) mu[c] = means[3 * i + c];
             seen = true;
         }
+        // the slot result k_slot_bwd left in the slot's first record
         const float4* rp = reinterpret_cast<const float4*>(grads + (int64_t)offsets[vs] * nq * kGradWords);
-        const float4 a = rp[0], b = rp[1], c = rp[2], d = rp[3], e = rp[4];
+        const float4 a = rp[0], b = rp[1], c = rp[2], d = rp[3];
         gm[0] += a.x; gm[1] += a.y; gm[2] += a.z;
-        gR[0] += a.w; gR[1] += b.x; gR[2] += b.y; gR[3] += b.z; gR[4] += b.w;
-        gR[5] += c.x; gR[6] += c.y; gR[7] += c.z; gR[8] += c.w;
-        gd[0] += d.x; gd[1] += d.y; gd[2] += d.z; gd[3] += d.w;
-        gsig += e.w;
-        view_colour_bwd<K>(shp, mu, views[v], e.x, e.y, e.z, gsh, gm);
-    }
-    double gq[4] = {0, 0, 0, 0}, ga = 0.0;
-    if (seen) {
-        float qf[4], dv[4];
-        for (int c = 0; c < 4; ++c) qf[c] = quats[4 * i + c];
-        for (int c = 0; c < ND; ++c) dv[c] = dists[ND * i + c];
-        rotation_opacity_bwd<KIND>(qf, dv, opacity[i], gR, gsig, gq, ga);
+        gq[0] += a.w; gq[1] += b.x; gq[2] += b.y; gq[3] += b.z;
+        gd[0] += b.w; gd[1] += c.x; gd[2] += c.y; gd[3] += c.z;
+        ga += d.z;
+        view_colour_bwd<K>(shp, mu, views[v], c.w, d.x, d.y, gsh, gm);
     }
     if (i < n) {
         for (int c = 0; c < 3; ++c) g_means[3 * i + c] = (float)gm[c];
