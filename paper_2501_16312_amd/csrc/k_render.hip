@@ -521,6 +521,134 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
 //   [16..18] dL/d rgb, [19] dL/d sigma
 // ---------------------------------------------------------------------------
 
+// One step of the backward walk for this lane's pixel, branch-free: a lane
+// that does not see the primitive (not active, outside the rectangle, zero
+// chord) runs the same instructions with delta = 0, o = 0, 1 - o = 1, which
+// leaves T and the colour behind (GB = dL/dC . colour behind) unchanged
+// exactly and yields zero terms.  Writes the lane's gradient terms of the
+// entry's record into acc; returns whether the lane contributed.
+template <int KIND, bool EXACT>
+__device__ inline bool bwd_step(const Rec& R, bool active, float pxf, float pyf, float rn, float G0, float G1,
+                                float G2, float& T, float& GB, float (&acc)[kGradWords]) {
+    const float ki = pxf - R.fi0, kj = pyf - R.fj0;
+    const bool inside = active & (fabsf(ki) <= R.fwi) & (fabsf(kj) <= R.fwj);
+    // chord and the active (lowest upper, highest lower) planes,
+    // the first one in plane order on ties; the chord is the same
+    // number the forward computed
+    float dch;
+    bool eh[4], el[4];
+    int ih = 0, il = 0;
+    ExactPlanes X;
+    if (EXACT) {
+        exact_planes<KIND>(R, ki, kj, X);
+        dch = exact_chord(X, rn);
+        bool fh = false, fl = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            eh[k] = !fh && X.hi[k] == X.U;
+            el[k] = !fl && X.lo[k] == X.L;
+            fh = fh || eh[k];
+            fl = fl || el[k];
+        }
+    } else if (KIND == LINPRIM_OCTAHEDRON) {
+#pragma clang fp contract(off)
+        float h[4], l[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float u = __builtin_fmaf(R.p[4 * s + 0], ki, R.p[4 * s + 1] * kj);
+            h[s] = u + R.p[4 * s + 2];
+            l[s] = u + R.p[4 * s + 3];
+        }
+        const float hi = fminf(fminf(h[0], h[1]), fminf(h[2], h[3]));
+        const float lo = fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3]));
+        dch = hi - lo;
+        bool fh = false, fl = false;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            eh[s] = !fh && h[s] == hi;
+            el[s] = !fl && l[s] == lo;
+            fh = fh || eh[s];
+            fl = fl || el[s];
+        }
+        eh[3] = !fh;
+        el[3] = !fl;
+    } else {
+        dch = chord<KIND>(R, ki, kj, ih, il);
+    }
+    const bool contributed = inside && dch > 0.0f;
+    const float delta = contributed ? dch : 0.0f;
+    const float ex = contributed ? chord_exp(R.s2, delta) : 1.0f;
+    const float onemo = fmaxf(ex, kOneMinusOMax);
+    const float o = 1.0f - onemo;
+    const float ro = __builtin_amdgcn_rcpf(onemo);
+    const float Tk = T * ro;                     // transmittance in front of this primitive
+    // dL/do = G . (T_k rgb - behind / (1 - o))
+    const float Grgb = G0 * R.r + G1 * R.g + G2 * R.b;
+    const float dLdo = Tk * Grgb - ro * GB;
+    const float wk = Tk * o;
+    acc[16] = G0 * wk;
+    acc[17] = G1 * wk;
+    acc[18] = G2 * wk;
+    GB += wk * Grgb;
+    T = Tk;
+    // not clamped: o = 1 - exp(-sigma chord)
+    const bool open = contributed && ex >= kOneMinusOMax;
+    const float q = dLdo * ex;
+    const float gD = open ? q * R.sigma : 0.0f;    // dL/dchord
+    acc[19] = open ? q * delta : 0.0f;             // dL/dsigma
+    if (EXACT) {
+        // words 4 k + 0..3: dL/d(a_k, b_k, g_k, c_k); a plane bound
+        // tau = (u + h) / (c - u) has dtau/du = (c + h) / (c - u)^2
+        // and dtau/dc = -tau / (c - u)
+        const float g = gD * rn;                   // dL/d(U - L)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float c = R.p[4 * k + 3];
+            const float inv = X.inv[k];
+            const float ge = eh[k] ? g : 0.0f, gl = el[k] ? g : 0.0f;
+            float gu;
+            if (KIND == LINPRIM_OCTAHEDRON) {
+                // the upper bound has h = +1 where c - u >= 0, else h = -1
+                const float hh = (c - X.u[k] >= 0.0f) ? 1.0f : -1.0f;
+                gu = (ge * (c + hh) - gl * (c - hh)) * (inv * inv);
+            } else {
+                gu = (ge - gl) * (c + 1.0f) * (inv * inv);
+            }
+            const float gc = (gl * X.L - ge * X.U) * inv;
+            const bool act = eh[k] || el[k];
+            const float Gu = act ? gu : 0.0f, Gc = act ? gc : 0.0f;
+            acc[4 * k + 0] = Gu * ki;
+            acc[4 * k + 1] = Gu * kj;
+            acc[4 * k + 2] = Gu;
+            acc[4 * k + 3] = Gc;
+        }
+    } else if (KIND == LINPRIM_OCTAHEDRON) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float gh = eh[s] ? gD : 0.0f;
+            const float gl = el[s] ? gD : 0.0f;
+            const float d = gh - gl;
+            acc[4 * s + 0] = d * ki;
+            acc[4 * s + 1] = d * kj;
+            acc[4 * s + 2] = gh;
+            acc[4 * s + 3] = gl;                   // negated after the reduction
+        }
+    } else {
+        const int fh = (R.fmap >> (2 * ih)) & 3;
+        const int fl = (R.fmap >> (2 * (il + 3))) & 3;
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const float d = ((fh == f) ? gD : 0.0f) - ((fl == f) ? gD : 0.0f);
+            acc[3 * f + 0] = d * ki;
+            acc[3 * f + 1] = d * kj;
+            acc[3 * f + 2] = d;
+        }
+#pragma unroll
+        for (int k = 12; k < 16; ++k) acc[k] = 0.0f;
+    }
+    return contributed;
+}
+
 template <int TILE, int KIND, bool EXACT>
 __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ views, int n_views, int64_t n,
                                                    const float* __restrict__ payload, const uint32_t* __restrict__ vals,
@@ -595,128 +723,9 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
         };
         auto step = [&](const Rec& R, int bcur) {
             const uint32_t e = e0 + (uint32_t)bcur;
-            // Branch-free: a lane that does not see the primitive (outside
-            // the rectangle, past its last blended entry, zero chord) runs
-            // the same instructions with delta = 0, o = 0, 1 - o = 1, which
-            // leaves T and the colour behind unchanged exactly and yields
-            // zero gradients.
+            // a lane past its last blended entry takes no part
             float acc[kGradWords];
-            const float ki = pxf - R.fi0, kj = pyf - R.fj0;
-            const bool inside = ((int)e < last) & (fabsf(ki) <= R.fwi) & (fabsf(kj) <= R.fwj);
-            // chord and the active (lowest upper, highest lower) planes,
-            // the first one in plane order on ties; the chord is the same
-            // number the forward computed
-            float dch;
-            bool eh[4], el[4];
-            int ih = 0, il = 0;
-            ExactPlanes X;
-            if (EXACT) {
-                exact_planes<KIND>(R, ki, kj, X);
-                dch = exact_chord(X, rn);
-                bool fh = false, fl = false;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    eh[k] = !fh && X.hi[k] == X.U;
-                    el[k] = !fl && X.lo[k] == X.L;
-                    fh = fh || eh[k];
-                    fl = fl || el[k];
-                }
-            } else if (KIND == LINPRIM_OCTAHEDRON) {
-#pragma clang fp contract(off)
-                float h[4], l[4];
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float u = __builtin_fmaf(R.p[4 * s + 0], ki, R.p[4 * s + 1] * kj);
-                    h[s] = u + R.p[4 * s + 2];
-                    l[s] = u + R.p[4 * s + 3];
-                }
-                const float hi = fminf(fminf(h[0], h[1]), fminf(h[2], h[3]));
-                const float lo = fmaxf(fmaxf(l[0], l[1]), fmaxf(l[2], l[3]));
-                dch = hi - lo;
-                bool fh = false, fl = false;
-#pragma unroll
-                for (int s = 0; s < 3; ++s) {
-                    eh[s] = !fh && h[s] == hi;
-                    el[s] = !fl && l[s] == lo;
-                    fh = fh || eh[s];
-                    fl = fl || el[s];
-                }
-                eh[3] = !fh;
-                el[3] = !fl;
-            } else {
-                dch = chord<KIND>(R, ki, kj, ih, il);
-            }
-            const bool contributed = inside && dch > 0.0f;
-            const float delta = contributed ? dch : 0.0f;
-            const float ex = contributed ? chord_exp(R.s2, delta) : 1.0f;
-            const float onemo = fmaxf(ex, kOneMinusOMax);
-            const float o = 1.0f - onemo;
-            const float ro = __builtin_amdgcn_rcpf(onemo);
-            const float Tk = T * ro;                     // transmittance in front of this primitive
-            // dL/do = G . (T_k rgb - behind / (1 - o))
-            const float Grgb = G0 * R.r + G1 * R.g + G2 * R.b;
-            const float dLdo = Tk * Grgb - ro * GB;
-            const float wk = Tk * o;
-            acc[16] = G0 * wk;
-            acc[17] = G1 * wk;
-            acc[18] = G2 * wk;
-            GB += wk * Grgb;
-            T = Tk;
-            // not clamped: o = 1 - exp(-sigma chord)
-            const bool open = contributed && ex >= kOneMinusOMax;
-            const float q = dLdo * ex;
-            const float gD = open ? q * R.sigma : 0.0f;    // dL/dchord
-            acc[19] = open ? q * delta : 0.0f;             // dL/dsigma
-            if (EXACT) {
-                // words 4 k + 0..3: dL/d(a_k, b_k, g_k, c_k); a plane bound
-                // tau = (u + h) / (c - u) has dtau/du = (c + h) / (c - u)^2
-                // and dtau/dc = -tau / (c - u)
-                const float g = gD * rn;                   // dL/d(U - L)
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const float c = R.p[4 * k + 3];
-                    const float inv = X.inv[k];
-                    const float ge = eh[k] ? g : 0.0f, gl = el[k] ? g : 0.0f;
-                    float gu;
-                    if (KIND == LINPRIM_OCTAHEDRON) {
-                        // the upper bound has h = +1 where c - u >= 0, else h = -1
-                        const float hh = (c - X.u[k] >= 0.0f) ? 1.0f : -1.0f;
-                        gu = (ge * (c + hh) - gl * (c - hh)) * (inv * inv);
-                    } else {
-                        gu = (ge - gl) * (c + 1.0f) * (inv * inv);
-                    }
-                    const float gc = (gl * X.L - ge * X.U) * inv;
-                    const bool act = eh[k] || el[k];
-                    const float Gu = act ? gu : 0.0f, Gc = act ? gc : 0.0f;
-                    acc[4 * k + 0] = Gu * ki;
-                    acc[4 * k + 1] = Gu * kj;
-                    acc[4 * k + 2] = Gu;
-                    acc[4 * k + 3] = Gc;
-                }
-            } else if (KIND == LINPRIM_OCTAHEDRON) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const float gh = eh[s] ? gD : 0.0f;
-                    const float gl = el[s] ? gD : 0.0f;
-                    const float d = gh - gl;
-                    acc[4 * s + 0] = d * ki;
-                    acc[4 * s + 1] = d * kj;
-                    acc[4 * s + 2] = gh;
-                    acc[4 * s + 3] = gl;                   // negated after the reduction
-                }
-            } else {
-                const int fh = (R.fmap >> (2 * ih)) & 3;
-                const int fl = (R.fmap >> (2 * (il + 3))) & 3;
-#pragma unroll
-                for (int f = 0; f < 4; ++f) {
-                    const float d = ((fh == f) ? gD : 0.0f) - ((fl == f) ? gD : 0.0f);
-                    acc[3 * f + 0] = d * ki;
-                    acc[3 * f + 1] = d * kj;
-                    acc[3 * f + 2] = d;
-                }
-#pragma unroll
-                for (int k = 12; k < 16; ++k) acc[k] = 0.0f;
-            }
+            const bool contributed = bwd_step<KIND, EXACT>(R, (int)e < last, pxf, pyf, rn, G0, G1, G2, T, GB, acc);
             const size_t slot = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, bcur);
             float outv = 0.0f;
             if (__ballot(contributed) != 0) outv = wave_reduce20(acc, lane);
@@ -740,6 +749,232 @@ __global__ __launch_bounds__(64) void k_render_bwd(const ViewInfo* __restrict__ 
             sched_fence();
             step(RB, bB);
             if (!haveA) break;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Backward of the exact variant: each 16-lane row of the wave owns one 4 x 4
+// quad of the 8 x 8 group and walks, in reverse list order, only the entries
+// whose rectangle meets its quad and that lie before the last blended entry
+// of one of its pixels; the four rows walk independently, so a step
+// evaluates up to four entries.  The list is taken in batches of kBwdBatch
+// entries: the batch's records (words 4..31) are staged in LDS, a row reads
+// the record of its current entry from there, sums its 16 lanes' gradient
+// terms (transposed, inside the row) and adds them to the entry's LDS
+// accumulator, the rows one after the other (a fixed order); the batch's
+// records are then written out, one per lane.  Same records as
+// k_render_bwd.  The exact step is heavy enough that skipping the entries a
+// quad does not meet pays for the LDS round trips; the ray-space step is not.
+// ---------------------------------------------------------------------------
+constexpr int kBwdBatch = 32;
+static_assert(kBwdBatch <= 32, "entry masks are 32-bit");
+
+// Sums 20 values over the 16 lanes of each row, transposed: four DPP steps
+// each halve the values a lane keeps (row mirror: lane i with 15 - i, split
+// on bit 3; half-row mirror: i with 7 - i, bit 2; quad swaps i with i ^ 2,
+// bit 1, and i with i ^ 1, bit 0).  With base = 10 b3 + 5 b2 of the row lane
+// index, a lane ends with the totals of words
+//   b1 b0 = 00: base, base + 1;  01: base + 2;  10: base + 3, base + 4;
+//   11: none.
+__device__ inline void row_reduce20(const float (&v)[20], int li, float& t0, float& t1, int& w0, int& w1) {
+    const bool h3 = (li >> 3) & 1, h2 = (li >> 2) & 1, h1 = (li >> 1) & 1, h0 = li & 1;
+    float a[10];
+#pragma unroll
+    for (int j = 0; j < 10; ++j) {
+        const float keep = h3 ? v[j + 10] : v[j];
+        const float give = h3 ? v[j] : v[j + 10];
+        a[j] = keep + dpp_move<0x140>(give);
+    }
+    float b[6];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const float keep = h2 ? a[j + 5] : a[j];
+        const float give = h2 ? a[j] : a[j + 5];
+        b[j] = keep + dpp_move<0x141>(give);
+    }
+    b[5] = 0.0f;
+    float c[4];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float keep = h1 ? b[j + 3] : b[j];
+        const float give = h1 ? b[j] : b[j + 3];
+        c[j] = keep + dpp_move<0x4E>(give);
+    }
+    c[3] = 0.0f;
+    float d[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const float keep = h0 ? c[j + 2] : c[j];
+        const float give = h0 ? c[j] : c[j + 2];
+        d[j] = keep + dpp_move<0xB1>(give);
+    }
+    const int base = 10 * (int)h3 + 5 * (int)h2;
+    t0 = d[0];
+    t1 = d[1];
+    if (!h1 && !h0) { w0 = base; w1 = base + 1; }
+    else if (!h1) { w0 = base + 2; w1 = -1; }
+    else if (!h0) { w0 = base + 3; w1 = base + 4; }
+    else { w0 = -1; w1 = -1; }
+}
+
+template <int TILE, int KIND, bool EXACT>
+__global__ __launch_bounds__(64) void k_render_bwd_rows(const ViewInfo* __restrict__ views, int n_views, int64_t n,
+                                                   const float* __restrict__ payload, const uint32_t* __restrict__ vals,
+                                                   const uint2* __restrict__ ranges, const uint32_t* __restrict__ offsets,
+                                                   const Status* __restrict__ status, uint64_t capacity, float bg0,
+                                                   float bg1, float bg2, const float* __restrict__ out_T,
+                                                   const int32_t* __restrict__ out_last,
+                                                   const float* __restrict__ grad_rgb, float* __restrict__ grads,
+                                                   const uint32_t* __restrict__ order) {
+    __shared__ float4 srec[kBwdBatch][7];             // record words 4..31
+    __shared__ float sacc[kBwdBatch][kGradWords];     // gradient record accumulators
+    if (status->n_pairs > capacity) return;
+    constexpr int QX = TILE / 8, NQ = QX * QX;
+    constexpr int SHIFT = (TILE == 8) ? 3 : (TILE == 16) ? 4 : 5;
+    const Place P = place_wave<TILE>(views, n_views, order);
+    if (P.gx0 >= P.W || P.gy0 >= P.H) return;
+    const int lane = threadIdx.x, row = lane >> 4, li = lane & 15;
+    // row r owns the quad (r & 1, r >> 1) of the group
+    const int x = P.gx0 + 4 * (row & 1) + (li & 3), y = P.gy0 + 4 * (row >> 1) + (li >> 2);
+    const bool valid = x < P.W && y < P.H;
+    const float pxf = (float)x, pyf = (float)y;
+    const float rn = EXACT ? ray_norm(views[P.v], x, y) : 1.0f;
+    const uint2 rg = ranges[P.g];
+    const int64_t hw = (int64_t)P.W * P.H;
+    const float* base = payload + (size_t)P.v * (size_t)n * kRecordWords;
+    const uint32_t* offs = offsets + (size_t)P.v * (size_t)n;
+
+    // GB = dL/dC . (colour behind the current step), kept as one running
+    // dot product (the colour behind itself is not needed)
+    float T = 1.0f, GB = 0.0f, G0 = 0.0f, G1 = 0.0f, G2 = 0.0f;
+    int last = (int)rg.x;
+    if (valid) {
+        const int64_t p = (int64_t)y * P.W + x;
+        const int64_t pix = views[P.v].pix_base + p;
+        const float* gi = grad_rgb + 3 * views[P.v].pix_base;
+        T = out_T[pix];
+        // stay inside this tile's list whatever the caller passed
+        last = min(max(out_last[pix], (int)rg.x), (int)rg.y);
+        G0 = gi[p];
+        G1 = gi[hw + p];
+        G2 = gi[2 * hw + p];
+        // the colour behind starts as T_final bg
+        GB = T * (G0 * bg0 + G1 * bg1 + G2 * bg2);
+    }
+    const uint32_t walk_end = (uint32_t)wave_max_int(last);
+    // each row's end: the largest last blended position of its 16 pixels
+    int rlast = last;
+#pragma unroll
+    for (int m = 8; m >= 1; m >>= 1) rlast = max(rlast, __shfl_xor(rlast, m, 16));
+    const uint32_t rend[4] = {(uint32_t)__builtin_amdgcn_readlane(rlast, 0),
+                              (uint32_t)__builtin_amdgcn_readlane(rlast, 16),
+                              (uint32_t)__builtin_amdgcn_readlane(rlast, 32),
+                              (uint32_t)__builtin_amdgcn_readlane(rlast, 48)};
+
+    // zero records of the entries that meet the group but no pixel reached
+    for (uint32_t e0 = walk_end; e0 < rg.y; e0 += 64) {
+        const Batch bt = load_batch<NQ, true>(base, vals, offs, e0, min(64u, rg.y - e0), P.gx0, P.gy0, SHIFT, P.tx,
+                                              P.ty, P.q);
+        uint64_t mask = bt.mask;
+        while (mask) {
+            const int b = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            const uint32_t slot = (uint32_t)__builtin_amdgcn_readlane((int)bt.off, b);
+            if (lane < kGradWords) grads[(size_t)slot * kGradWords + lane] = 0.0f;
+        }
+    }
+
+    for (uint32_t e_hi = walk_end; e_hi > rg.x;) {
+        const uint32_t nb = min((uint32_t)kBwdBatch, e_hi - rg.x);
+        const uint32_t e0 = e_hi - nb;
+        e_hi = e0;
+        // lane l < nb stages entry e0 + l: its record, a zero accumulator, and
+        // the quads whose row walks it
+        bool meets = false;
+        uint32_t qm = 0, off = 0;
+        if ((uint32_t)lane < nb) {
+            const uint32_t idx = vals[e0 + lane];
+            const float* rp = base + (size_t)idx * kRecordWords;
+            const int4 r = *reinterpret_cast<const int4*>(rp);
+            meets = (NQ == 1) || rect_meets_group(r, P.gx0, P.gy0);
+            if (meets) {
+                off = record_index(r, SHIFT, P.tx, P.ty, offs[idx], NQ, P.q);
+                const float4* src = reinterpret_cast<const float4*>(rp + 4);
+#pragma unroll
+                for (int k = 0; k < 7; ++k) srec[lane][k] = src[k];
+                float4* acc4 = reinterpret_cast<float4*>(sacc[lane]);
+#pragma unroll
+                for (int k = 0; k < kGradWords / 4; ++k) acc4[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                const uint32_t e = e0 + (uint32_t)lane;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int qx0 = P.gx0 + 4 * (q & 1), qy0 = P.gy0 + 4 * (q >> 1);
+                    const bool mq = !(r.x > qx0 + 3 || r.z < qx0 || r.y > qy0 + 3 || r.w < qy0);
+                    qm |= (mq && e < rend[q]) ? (1u << q) : 0u;
+                }
+            }
+        }
+        const uint32_t staged = (uint32_t)__ballot(meets);   // kBwdBatch <= 32 entries
+        if (staged == 0) continue;
+        // a staged entry: the record a row without an entry reads (finite
+        // values, so that its lanes' state stays exactly unchanged)
+        const int bsafe = __builtin_ctz(staged);
+        const uint32_t m0 = (uint32_t)__ballot(qm & 1u), m1 = (uint32_t)__ballot(qm & 2u),
+                       m2 = (uint32_t)__ballot(qm & 4u), m3 = (uint32_t)__ballot(qm & 8u);
+        uint32_t mask = (row == 0) ? m0 : (row == 1) ? m1 : (row == 2) ? m2 : m3;
+        while (true) {
+            const bool act = mask != 0;
+            if (__ballot(act) == 0) break;
+            // the row's next entry, in reverse order (a row without one runs
+            // the step with every lane outside)
+            const int bcur = act ? 31 - __builtin_clz(mask) : bsafe;
+            mask &= act ? ~(1u << bcur) : ~0u;
+            Rec R;
+            {
+                const float4 w0 = srec[bcur][0], w1 = srec[bcur][1];
+                R.s2 = w0.x; R.r = w0.y; R.g = w0.z; R.b = w0.w;
+                R.fi0 = w1.x; R.fj0 = w1.y; R.fwi = w1.z; R.fwj = w1.w;
+                float pw[20];
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    const float4 w = srec[bcur][2 + k];
+                    pw[4 * k] = w.x; pw[4 * k + 1] = w.y; pw[4 * k + 2] = w.z; pw[4 * k + 3] = w.w;
+                }
+#pragma unroll
+                for (int k = 0; k < 18; ++k) R.p[k] = pw[k];
+                R.sigma = pw[R_SIGMA - R_PLANES];
+                R.fmap = (EXACT || KIND == LINPRIM_OCTAHEDRON) ? 0 : __float_as_int(pw[R_FACEMAP - R_PLANES]);
+                R.i0 = R.j0 = R.i1 = R.j1 = 0;
+            }
+            const uint32_t e = e0 + (uint32_t)bcur;
+            float acc[kGradWords];
+            const bool contributed = bwd_step<KIND, EXACT>(R, act && (int)e < last, pxf, pyf, rn, G0, G1, G2, T, GB, acc);
+            if (__ballot(contributed) != 0) {
+                float t0, t1;
+                int w0, w1;
+                row_reduce20(acc, li, t0, t1, w0, w1);
+                // the rows one after the other: a fixed order of the additions
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    if (row == rr && act) {
+                        if (w0 >= 0) atomicAdd(&sacc[bcur][w0], t0);
+                        if (w1 >= 0) atomicAdd(&sacc[bcur][w1], t1);
+                    }
+                }
+            }
+        }
+        // the batch's records, one per lane (octahedra: words 4 s + 3 are
+        // dL/dDlo = -sum of the lower-plane terms)
+        if (meets) {
+            const float4* acc4 = reinterpret_cast<const float4*>(sacc[lane]);
+            float4* dst = reinterpret_cast<float4*>(grads + (size_t)off * kGradWords);
+#pragma unroll
+            for (int k = 0; k < kGradWords / 4; ++k) {
+                float4 o = acc4[k];
+                if (!EXACT && KIND == LINPRIM_OCTAHEDRON && k < 4) o.w = -o.w;
+                dst[k] = o;
+            }
         }
     }
 }
@@ -813,8 +1048,12 @@ static void bwd_dispatch(const ViewLayout& Lv, hipStream_t s, const ViewInfo* vi
                          const float* payload, const uint32_t* vals, const uint2* ranges, const uint32_t* offsets,
                          const Status* st, uint64_t cap, const float bg[3], const float* T, const int32_t* last,
                          const float* grad, float* grads, const uint32_t* order) {
-    hipLaunchKernelGGL((k_render_bwd<TILE, KIND, EXACT>), wave_grid<TILE>(Lv), dim3(64), 0, s, views, nv, n, payload,
-                       vals, ranges, offsets, st, cap, bg[0], bg[1], bg[2], T, last, grad, grads, order);
+    if (EXACT)
+        hipLaunchKernelGGL((k_render_bwd_rows<TILE, KIND, true>), wave_grid<TILE>(Lv), dim3(64), 0, s, views, nv, n,
+                           payload, vals, ranges, offsets, st, cap, bg[0], bg[1], bg[2], T, last, grad, grads, order);
+    else
+        hipLaunchKernelGGL((k_render_bwd<TILE, KIND, false>), wave_grid<TILE>(Lv), dim3(64), 0, s, views, nv, n,
+                           payload, vals, ranges, offsets, st, cap, bg[0], bg[1], bg[2], T, last, grad, grads, order);
 }
 
 hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLayout& P, char* pws, int result_in_b,
