@@ -273,9 +273,11 @@ __device__ inline float ray_norm(const ViewInfo& V, int x, int y) {
 
 // ---------------------------------------------------------------------------
 // Wave placement: wave w (XCD-chunked) handles group q = w % NQ of the tile at
-// position w / NQ of the render order (heavy tiles first, then the others,
-// each part in tile order, so that consecutive positions are mostly
-// neighbouring tiles).
+// position w / NQ of a render order.  The forward's: heavy tiles first, then
+// the others, each part in tile order, so that consecutive positions are
+// mostly neighbouring tiles.  The backward's: longest lists first in classes
+// of list length (tile order inside a class), so that the waves that start
+// last are short and the kernel has no long tail.
 // ---------------------------------------------------------------------------
 struct Place {
     int v, tx, ty, gx0, gy0, W, H, q;
@@ -391,7 +393,9 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
     const uint2 rg = ranges[P.g];
     float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
     int last = (int)rg.x;
-    bool done = !valid;
+    // lanes still compositing, as a wave-uniform mask (kept in scalar
+    // registers; each lane's bit is read back with an inverse ballot)
+    uint64_t live = __builtin_amdgcn_ballot_w64(valid);
     uint32_t ev = 0, hit = 0, term = rg.y;
     uint32_t half = 0xffffffffu;   // list position at which 1 - T first exceeds 0.5
     float half_entry = 0.0f;       // its entry depth relative to its centre
@@ -413,7 +417,10 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
             // 1 - o = 1 exactly, which leaves C and T unchanged.
             const float ki = pxf - R.fi0, kj = pyf - R.fj0;
             // bitwise &: every test is a plain compare, no short-circuit branches
-            const bool inside = !done & (fabsf(ki) <= R.fwi) & (fabsf(kj) <= R.fwj);
+            // lane masks of single compares combine in scalar registers
+            const uint64_t m_in = __builtin_amdgcn_ballot_w64(fabsf(ki) <= R.fwi) &
+                                  __builtin_amdgcn_ballot_w64(fabsf(kj) <= R.fwj) & live;
+            const bool inside = __builtin_amdgcn_inverse_ballot_w64(m_in);
             float dch, entry = 0.0f;
             if (EXACT) {
                 ExactPlanes X;
@@ -425,7 +432,8 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
             } else {
                 dch = chord_fast<KIND>(R, ki, kj);
             }
-            const bool hitp = inside && dch > 0.0f;
+            const uint64_t m_hit = m_in & __builtin_amdgcn_ballot_w64(dch > 0.0f);
+            const bool hitp = __builtin_amdgcn_inverse_ballot_w64(m_hit);
             if (COUNT) {
                 ev += inside ? 1u : 0u;
                 hit += hitp ? 1u : 0u;
@@ -443,10 +451,11 @@ __global__ __launch_bounds__(64) void k_render_fwd(const ViewInfo* __restrict__ 
             }
             T = T * onemo;
             last = hitp ? (int)e + 1 : last;
-            const bool stop = hitp && T <= kTStop;
-            term = stop ? e + 1 : term;
-            done = done || stop;
-            return __ballot(!done) != 0;
+            // T only falls where the primitive was hit
+            const uint64_t stop = __builtin_amdgcn_ballot_w64(T <= kTStop) & m_hit;
+            if (COUNT) term = __builtin_amdgcn_inverse_ballot_w64(stop) ? e + 1 : term;
+            live &= ~stop;
+            return live != 0;
         };
         auto next_rec = [&](Rec& R) {
             const int b = __builtin_ctzll(mask);
@@ -1067,7 +1076,7 @@ hipError_t launch_render_bwd(const ViewLayout& L, const char* vws, const PairLay
     const uint32_t* offsets = reinterpret_cast<const uint32_t*>(vws + L.offsets);
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
     float* grads = reinterpret_cast<float*>(pws + P.grads);
-    const uint32_t* order = reinterpret_cast<const uint32_t*>(vws + L.order);
+    const uint32_t* order = reinterpret_cast<const uint32_t*>(vws + L.order_bwd);
     const uint64_t cap = (uint64_t)P.capacity;
 #define LP_BWD(T_, K_, E_) bwd_dispatch<T_, K_, E_>(L, stream, views, n_views, L.n, payload, vals, ranges, offsets, \
                                                     st, cap, bg, out_T, out_last, grad_rgb, grads, order)

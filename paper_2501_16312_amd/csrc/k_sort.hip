@@ -570,41 +570,52 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
     if (i == (int64_t)np - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[tile].y = (uint32_t)(i + 1);
 }
 
-// Render order (heavy tiles first).  k_order_count: heavy tiles per block of
-// kOrderItems tiles.  k_order_write: tile g goes to position (heavy tiles
-// before g) if heavy, else H + (light tiles before g), H the heavy total.
-__device__ inline bool heavy_tile(const uint2* __restrict__ ranges, int64_t g, int64_t n_tiles) {
-    if (g >= n_tiles) return false;
-    const uint2 rg = ranges[g];
-    return rg.y - rg.x > (uint32_t)kHeavyList;
+// Render orders.  The backward takes the tiles by list length, longest
+// first, in kOrderClasses classes (tile order inside a class), so that the
+// waves that start last are short.  The forward, whose walks are cheaper and
+// more sensitive to cache locality, takes the heavy tiles (classes up to
+// kOrderHeavyClass) first and then the others, each part in tile order.
+// Counts are kept class-major, sums[c * nblocks + b] for class c in block b
+// of kOrderItems tiles, so that one exclusive scan over them gives every
+// (class, block) its first position.
+__device__ inline int order_class(uint32_t len) {
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < kOrderClasses - 1; ++k) c += (len <= kOrderBounds[k]) ? 1 : 0;
+    return c;
 }
 
 __global__ __launch_bounds__(256) void k_order_count(const uint2* __restrict__ ranges, int64_t n_tiles,
                                                      const Status* __restrict__ status, uint64_t capacity,
                                                      uint32_t* __restrict__ sums) {
-    __shared__ uint32_t part[4];
+    __shared__ uint32_t cnt[kOrderClasses];
     if (status->n_pairs > capacity) return;
-    const int64_t base = (int64_t)blockIdx.x * kOrderItems;
-    uint32_t c = 0;
-#pragma unroll
-    for (int k = 0; k < kOrderItems / 256; ++k) c += heavy_tile(ranges, base + k * 256 + threadIdx.x, n_tiles) ? 1u : 0u;
-    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+    if (threadIdx.x < kOrderClasses) cnt[threadIdx.x] = 0u;
     __syncthreads();
-    if (threadIdx.x == 0) sums[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+    const int64_t base = (int64_t)blockIdx.x * kOrderItems;
+#pragma unroll
+    for (int k = 0; k < kOrderItems / 256; ++k) {
+        const int64_t g = base + k * 256 + threadIdx.x;
+        if (g < n_tiles) {
+            const uint2 rg = ranges[g];
+            atomicAdd(&cnt[order_class(rg.y - rg.x)], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kOrderClasses) sums[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// Many blocks: one block turns the per-block counts into exclusive
-// prefixes in place, the total after them.
-__global__ __launch_bounds__(1024) void k_order_prefix(uint32_t* __restrict__ sums, int64_t nblocks,
+// Many blocks: one block turns the count entries into exclusive prefixes in
+// place, the total after them.
+__global__ __launch_bounds__(1024) void k_order_prefix(uint32_t* __restrict__ sums, int64_t count,
                                                        const Status* __restrict__ status, uint64_t capacity) {
     __shared__ uint32_t wsum[16];
     if (status->n_pairs > capacity) return;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < nblocks; b0 += 1024) {
+    for (int64_t b0 = 0; b0 < count; b0 += 1024) {
         const int64_t idx = b0 + t;
-        const uint32_t x = (idx < nblocks) ? sums[idx] : 0u;
+        const uint32_t x = (idx < count) ? sums[idx] : 0u;
         uint32_t incl = x;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(incl, off, 64);
@@ -618,72 +629,123 @@ __global__ __launch_bounds__(1024) void k_order_prefix(uint32_t* __restrict__ su
             wb += (w < wave) ? wsum[w] : 0u;
             tot += wsum[w];
         }
-        if (idx < nblocks) sums[idx] = carry + wb + incl - x;
+        if (idx < count) sums[idx] = carry + wb + incl - x;
         carry += tot;
         __syncthreads();
     }
-    if (t == 0) sums[nblocks] = carry;
+    if (t == 0) sums[count] = carry;
 }
+
+// Backward order: tile g of class c goes to (first position of c in this
+// block) + (tiles of class c before g in this block).  Forward order: a heavy
+// tile goes to (heavy tiles before it), a light one to H + (light tiles
+// before it), H the heavy total.  The block takes its tiles in rounds of 256,
+// in tile order; a tile's rank among the tiles of its wave with the same
+// class (or the same heaviness) comes from ballots.  Counter slots: classes
+// 0..K-1, then heavy (K) and light (K + 1).
+static_assert(kOrderDirectBlocks <= 256, "direct mode: one block's counts per thread");
 
 __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ ranges, int64_t n_tiles,
                                                      const Status* __restrict__ status, uint64_t capacity,
                                                      const uint32_t* __restrict__ sums, int64_t nblocks,
-                                                     bool prefixed, uint32_t* __restrict__ order) {
-    __shared__ uint32_t red[2][4];
-    __shared__ uint32_t wsum[4];
+                                                     bool prefixed, uint32_t* __restrict__ order_fwd,
+                                                     uint32_t* __restrict__ order_bwd) {
+    constexpr int K = kOrderClasses, HC = kOrderHeavyClass, NS = K + 2;
+    __shared__ uint32_t first[NS + 1];   // [K + 2]: the heavy total
+    __shared__ uint32_t running[NS];
+    __shared__ uint32_t wave_cnt[4][NS];
     if (status->n_pairs > capacity) return;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    // heavy tiles before this block, and in all
-    uint32_t before = 0, total = 0;
+    const int64_t b = blockIdx.x;
     if (prefixed) {
-        if (t == 0) {
-            before = sums[blockIdx.x];
-            total = sums[nblocks];
+        // sums holds the exclusive scan: the class-c base is sums[c nblocks]
+        if (t < K) first[t] = sums[(int64_t)t * nblocks + b];
+        if (t == K || t == K + 1) {
+            uint32_t v = 0;
+            for (int c = (t == K) ? 0 : HC + 1; c <= ((t == K) ? HC : K - 1); ++c)
+                v += sums[(int64_t)c * nblocks + b] - sums[(int64_t)c * nblocks];
+            first[t] = v;
         }
+        if (t == K + 2) first[t] = sums[(int64_t)(HC + 1) * nblocks];
     } else {
-        for (int64_t b = t; b < nblocks; b += 256) {
-            const uint32_t x = sums[b];
-            total += x;
-            if (b < (int64_t)blockIdx.x) before += x;
-        }
-    }
-    for (int off = 32; off >= 1; off >>= 1) {
-        before += __shfl_xor(before, off, 64);
-        total += __shfl_xor(total, off, 64);
-    }
-    if (lane == 0) {
-        red[0][wave] = before;
-        red[1][wave] = total;
-    }
-    // thread t handles the PER consecutive tiles base + PER t .. PER t + PER - 1
-    constexpr int PER = kOrderItems / 256;
-    const int64_t base = (int64_t)blockIdx.x * kOrderItems + (int64_t)t * PER;
-    uint32_t flags = 0, c = 0;
+        // thread t < nblocks reads block t's counts: first[c] sums the counts
+        // of the classes before c in all blocks and of class c in the blocks
+        // before b; heavy and light tiles in the blocks before b; the heavy
+        // total
+        uint32_t part[NS + 1];
 #pragma unroll
-    for (int k = 0; k < PER; ++k)
-        if (heavy_tile(ranges, base + k, n_tiles)) {
-            flags |= 1u << k;
-            ++c;
-        }
-    uint32_t incl = c;
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
-    }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    const uint32_t H = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-    uint32_t hrun = red[0][0] + red[0][1] + red[0][2] + red[0][3] + incl - c;
-    for (int w = 0; w < wave; ++w) hrun += wsum[w];
+        for (int c = 0; c <= NS; ++c) part[c] = 0u;
+        if (t < nblocks) {
+            const bool before = t < b;
+            uint32_t acc = 0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int64_t g = base + k;
-        if (g >= n_tiles) break;
-        if (flags & (1u << k)) {
-            order[hrun++] = (uint32_t)g;
-        } else {
-            order[(int64_t)H + g - hrun] = (uint32_t)g;
+            for (int c = 0; c < K; ++c) {
+                const uint32_t x = sums[(int64_t)c * nblocks + t];
+                part[c] = acc + (before ? x : 0u);
+                acc += x;
+                if (c <= HC) {
+                    part[K] += before ? x : 0u;
+                    part[K + 2] += x;
+                } else {
+                    part[K + 1] += before ? x : 0u;
+                }
+            }
         }
+#pragma unroll
+        for (int c = 0; c <= NS; ++c) {
+            uint32_t v = part[c];
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) {
+                if (c < NS) wave_cnt[wave][c] = v;
+                else running[wave] = v;
+            }
+        }
+        __syncthreads();
+        if (t < NS) first[t] = wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
+        if (t == NS) first[t] = running[0] + running[1] + running[2] + running[3];
+        __syncthreads();
+    }
+    if (t < NS) running[t] = 0u;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int r = 0; r < kOrderItems / 256; ++r) {
+        const int64_t g = b * kOrderItems + r * 256 + t;
+        const bool valid = g < n_tiles;
+        int c = 0;
+        if (valid) {
+            const uint2 rg = ranges[g];
+            c = order_class(rg.y - rg.x);
+        }
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < 4; ++bit) {
+            const uint64_t m = __ballot(valid && ((c >> bit) & 1));
+            peers &= ((c >> bit) & 1) ? m : ~m;
+        }
+        const bool heavy = c <= HC;
+        const uint64_t hm = __ballot(valid && heavy), lm = __ballot(valid && !heavy);
+        if (lane < NS) wave_cnt[wave][lane] = 0u;
+        const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+        if (valid && rank == 0) wave_cnt[wave][c] = (uint32_t)__popcll(peers);
+        if (lane == 0) {
+            wave_cnt[wave][K] = (uint32_t)__popcll(hm);
+            wave_cnt[wave][K + 1] = (uint32_t)__popcll(lm);
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = first[c] + running[c] + rank;
+            const int s = heavy ? K : K + 1;
+            uint32_t pf = first[s] + running[s] + (uint32_t)__popcll((heavy ? hm : lm) & lt_mask) +
+                          (heavy ? 0u : first[K + 2]);
+            for (int w = 0; w < wave; ++w) {
+                pos += wave_cnt[w][c];
+                pf += wave_cnt[w][s];
+            }
+            order_bwd[pos] = (uint32_t)g;
+            order_fwd[pf] = (uint32_t)g;
+        }
+        __syncthreads();
+        if (t < NS) running[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
+        __syncthreads();
     }
 }
 
@@ -767,13 +829,15 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
                            cap, ranges);
     {
         uint32_t* order = reinterpret_cast<uint32_t*>(vws + L.order);
+        uint32_t* order_bwd = reinterpret_cast<uint32_t*>(vws + L.order_bwd);
         uint32_t* osums = reinterpret_cast<uint32_t*>(vws + L.order_sums);
         const int64_t ob = (nt + kOrderItems - 1) / kOrderItems;
         hipLaunchKernelGGL(k_order_count, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums);
         const bool prefixed = ob > kOrderDirectBlocks;
-        if (prefixed) hipLaunchKernelGGL(k_order_prefix, dim3(1), dim3(1024), 0, stream, osums, ob, status, cap);
+        if (prefixed)
+            hipLaunchKernelGGL(k_order_prefix, dim3(1), dim3(1024), 0, stream, osums, ob * kOrderClasses, status, cap);
         hipLaunchKernelGGL(k_order_write, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums, ob,
-                           prefixed, order);
+                           prefixed, order, order_bwd);
     }
     if (!radix) {
         // per-list sort from (kin, vin) into (kout, vout)

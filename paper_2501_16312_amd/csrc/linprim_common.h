@@ -90,7 +90,7 @@ struct Status {
 // Offsets into the view workspace (all 256-byte aligned).
 struct ViewLayout {
     size_t status, views, payload, depth_keys, tiles, offsets, block_sums, ranges, big, long_list, vis, stats, order,
-        order_sums, huge, trect, total;
+        order_bwd, order_sums, huge, trect, total;
     int64_t n, n_views, n_tiles_total, scan_blocks;
 };
 
@@ -107,7 +107,7 @@ constexpr int kScanItems = 4096;     // elements per scan block (256 threads x 1
 constexpr int64_t kScanDirectBlocks = 8192;
 // Tiles per block of the render order kernels (256 threads x 4), and the
 // same choice for their per-block counts (256 blocks: 256K tiles).
-constexpr int kOrderItems = 1024;
+constexpr int kOrderItems = 256;
 constexpr int64_t kOrderDirectBlocks = 256;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 4;        // keys per thread per sort block
@@ -151,10 +151,16 @@ __host__ __device__ inline uint2 pack_tile_rect(int i0, int j0, int i1, int j1, 
     return make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)ntx | ((uint32_t)nty << 16));
 }
 
-// The render kernels take the tiles in the order written by bin_sort: the
-// tiles whose list holds more than kHeavyList pairs first, so that the
-// longest walks do not start last, then the others; each part in tile order.
-constexpr int kHeavyList = 48;
+// The render kernels take the tiles in the orders written by bin_sort.  The
+// backward's: by list length, longest first, in classes of lengths (> 192,
+// > 128, ..., > 4, > 0, empty), each class in tile order, so that the longest
+// walks start first and the waves that start last are short.  The forward's:
+// the tiles of the first kOrderHeavyClass + 1 classes (lists of more than 48
+// pairs) first, then the others, each part in tile order.
+constexpr int kOrderClasses = 16;
+constexpr int kOrderHeavyClass = 5;
+__device__ constexpr uint32_t kOrderBounds[kOrderClasses - 1] = {192, 128, 96, 72, 56, 48, 40, 32,
+                                                                 26, 20, 16, 12, 8, 4, 0};
 constexpr int kBigChunks = 16;
 __host__ __device__ inline int big_chunk_start(int c, int nrec) {
     return (int)(((int64_t)c * nrec) / kBigChunks);
