@@ -494,11 +494,16 @@ const char *linprim_strerror(int code);
  * depth_keys [n_views*n] u32, tiles_touched [n_views*n] u32, offsets
  * [n_views*n] u32, sorted keys
  * [max_pairs] u64 and values [max_pairs] u32 (first n_pairs valid),
- * ranges [total tiles] (u32 start, u32 end). */
+ * ranges [total tiles] (u32 start, u32 end), and the two render orders
+ * [total tiles] u32 written by linprim_bin_sort (the tile taken by each wave
+ * position: forward, lists of more than 48 pairs first, then the others, each
+ * part in tile order; backward, by classes of list length, longest first,
+ * each class in tile order).  Any out-pointer may be NULL. */
 int linprim_debug_pointers(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
                            const linprim_tuning *tuning, const void *view_ws, const void *pair_ws,
                            int64_t max_pairs, void **payload, void **depth_keys, void **tiles_touched,
-                           void **offsets, void **keys, void **values, void **ranges);
+                           void **offsets, void **keys, void **values, void **ranges, void **order_fwd,
+                           void **order_bwd);
 
 #ifdef __cplusplus
 }

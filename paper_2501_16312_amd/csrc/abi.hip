@@ -662,7 +662,7 @@ const char* linprim_strerror(int code) {
 int linprim_debug_pointers(const linprim_prims* prims, const linprim_camera* cams, int32_t n_views,
                            const linprim_tuning* tuning, const void* view_ws, const void* pair_ws, int64_t max_pairs,
                            void** payload, void** depth_keys, void** tiles_touched, void** offsets, void** keys,
-                           void** values, void** ranges) {
+                           void** values, void** ranges, void** order_fwd, void** order_bwd) {
     if (!view_ws || !pair_ws) return LINPRIM_ERR_INVALID_ARG;
     ViewLayout L;
     PairLayout P;
@@ -677,6 +677,8 @@ int linprim_debug_pointers(const linprim_prims* prims, const linprim_camera* cam
     if (keys) *keys = (void*)(p + (in_b ? P.keys_b : P.keys_a));
     if (values) *values = (void*)(p + (in_b ? P.vals_b : P.vals_a));
     if (ranges) *ranges = (void*)(v + L.ranges);
+    if (order_fwd) *order_fwd = (void*)(v + L.order);
+    if (order_bwd) *order_bwd = (void*)(v + L.order_bwd);
     return LINPRIM_OK;
 }
 

@@ -573,8 +573,8 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
 // Render orders.  The backward takes the tiles by list length, longest
 // first, in kOrderClasses classes (tile order inside a class), so that the
 // waves that start last are short.  The forward, whose walks are cheaper and
-// more sensitive to cache locality, takes the heavy tiles (classes up to
-// kOrderHeavyClass) first and then the others, each part in tile order.
+// more sensitive to cache locality, takes them in kFwdGroups coarser groups
+// of consecutive classes (tile order inside a group).
 // Counts are kept class-major, sums[c * nblocks + b] for class c in block b
 // of kOrderItems tiles, so that one exclusive scan over them gives every
 // (class, block) its first position.
@@ -637,72 +637,78 @@ __global__ __launch_bounds__(1024) void k_order_prefix(uint32_t* __restrict__ su
 }
 
 // Backward order: tile g of class c goes to (first position of c in this
-// block) + (tiles of class c before g in this block).  Forward order: a heavy
-// tile goes to (heavy tiles before it), a light one to H + (light tiles
-// before it), H the heavy total.  The block takes its tiles in rounds of 256,
-// in tile order; a tile's rank among the tiles of its wave with the same
-// class (or the same heaviness) comes from ballots.  Counter slots: classes
-// 0..K-1, then heavy (K) and light (K + 1).
+// block) + (tiles of class c before g in this block).  Forward order: the
+// same with groups of consecutive classes in place of the classes.  The
+// block takes its tiles in rounds of 256, in tile order; a tile's rank among
+// the tiles of its wave with the same class (or group) comes from ballots.
+// Counter slots: classes 0..K-1, then groups K..K+G-1; first[K + G + g] is
+// the first position of group g in the whole forward order.
 static_assert(kOrderDirectBlocks <= 256, "direct mode: one block's counts per thread");
+
+__device__ inline int order_group(int c) {
+    int g = 0;
+#pragma unroll
+    for (int k = 0; k < kFwdGroups - 1; ++k) g += (c > kFwdGroupLast[k]) ? 1 : 0;
+    return g;
+}
 
 __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ ranges, int64_t n_tiles,
                                                      const Status* __restrict__ status, uint64_t capacity,
                                                      const uint32_t* __restrict__ sums, int64_t nblocks,
                                                      bool prefixed, uint32_t* __restrict__ order_fwd,
                                                      uint32_t* __restrict__ order_bwd) {
-    constexpr int K = kOrderClasses, HC = kOrderHeavyClass, NS = K + 2;
-    __shared__ uint32_t first[NS + 1];   // [K + 2]: the heavy total
+    constexpr int K = kOrderClasses, G = kFwdGroups, NS = K + G;
+    __shared__ uint32_t first[NS + G];
     __shared__ uint32_t running[NS];
-    __shared__ uint32_t wave_cnt[4][NS];
+    __shared__ uint32_t wave_cnt[4][NS + G];
     if (status->n_pairs > capacity) return;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t b = blockIdx.x;
     if (prefixed) {
-        // sums holds the exclusive scan: the class-c base is sums[c nblocks]
+        // sums holds the exclusive scan: the first position of class c is
+        // sums[c nblocks], its tiles in the blocks before b sums[c nblocks + b]
+        // - sums[c nblocks]
         if (t < K) first[t] = sums[(int64_t)t * nblocks + b];
-        if (t == K || t == K + 1) {
+        if (t >= K && t < NS) {
+            const int g = t - K;
             uint32_t v = 0;
-            for (int c = (t == K) ? 0 : HC + 1; c <= ((t == K) ? HC : K - 1); ++c)
+            for (int c = (g == 0) ? 0 : kFwdGroupLast[g - 1] + 1; c <= kFwdGroupLast[g]; ++c)
                 v += sums[(int64_t)c * nblocks + b] - sums[(int64_t)c * nblocks];
             first[t] = v;
         }
-        if (t == K + 2) first[t] = sums[(int64_t)(HC + 1) * nblocks];
+        if (t >= NS && t < NS + G) {
+            const int g = t - NS;
+            first[t] = sums[(int64_t)((g == 0) ? 0 : kFwdGroupLast[g - 1] + 1) * nblocks];
+        }
     } else {
         // thread t < nblocks reads block t's counts: first[c] sums the counts
         // of the classes before c in all blocks and of class c in the blocks
-        // before b; heavy and light tiles in the blocks before b; the heavy
-        // total
-        uint32_t part[NS + 1];
+        // before b; then the tiles of each group in the blocks before b; then
+        // the tiles of the classes before each group
+        uint32_t part[NS + G];
 #pragma unroll
-        for (int c = 0; c <= NS; ++c) part[c] = 0u;
+        for (int c = 0; c < NS + G; ++c) part[c] = 0u;
         if (t < nblocks) {
             const bool before = t < b;
             uint32_t acc = 0;
 #pragma unroll
             for (int c = 0; c < K; ++c) {
                 const uint32_t x = sums[(int64_t)c * nblocks + t];
+                const int g = order_group(c);
+                if (c == 0 || order_group(c - 1) != g) part[NS + g] = acc;
                 part[c] = acc + (before ? x : 0u);
+                part[K + g] += before ? x : 0u;
                 acc += x;
-                if (c <= HC) {
-                    part[K] += before ? x : 0u;
-                    part[K + 2] += x;
-                } else {
-                    part[K + 1] += before ? x : 0u;
-                }
             }
         }
 #pragma unroll
-        for (int c = 0; c <= NS; ++c) {
+        for (int c = 0; c < NS + G; ++c) {
             uint32_t v = part[c];
             for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (lane == 0) {
-                if (c < NS) wave_cnt[wave][c] = v;
-                else running[wave] = v;
-            }
+            if (lane == 0) wave_cnt[wave][c] = v;
         }
         __syncthreads();
-        if (t < NS) first[t] = wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
-        if (t == NS) first[t] = running[0] + running[1] + running[2] + running[3];
+        if (t < NS + G) first[t] = wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
         __syncthreads();
     }
     if (t < NS) running[t] = 0u;
@@ -721,21 +727,22 @@ __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ r
             const uint64_t m = __ballot(valid && ((c >> bit) & 1));
             peers &= ((c >> bit) & 1) ? m : ~m;
         }
-        const bool heavy = c <= HC;
-        const uint64_t hm = __ballot(valid && heavy), lm = __ballot(valid && !heavy);
-        if (lane < NS) wave_cnt[wave][lane] = 0u;
+        const int grp = order_group(c);
+        uint64_t gm = 0;   // lanes of this wave in the tile's group
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const uint64_t m = __ballot(valid && grp == k);
+            if (lane == 0) wave_cnt[wave][K + k] = (uint32_t)__popcll(m);
+            gm = (grp == k) ? m : gm;
+        }
+        if (lane < K) wave_cnt[wave][lane] = 0u;
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
         if (valid && rank == 0) wave_cnt[wave][c] = (uint32_t)__popcll(peers);
-        if (lane == 0) {
-            wave_cnt[wave][K] = (uint32_t)__popcll(hm);
-            wave_cnt[wave][K + 1] = (uint32_t)__popcll(lm);
-        }
         __syncthreads();
         if (valid) {
+            const int s = K + grp;
             uint32_t pos = first[c] + running[c] + rank;
-            const int s = heavy ? K : K + 1;
-            uint32_t pf = first[s] + running[s] + (uint32_t)__popcll((heavy ? hm : lm) & lt_mask) +
-                          (heavy ? 0u : first[K + 2]);
+            uint32_t pf = first[NS + grp] + first[s] + running[s] + (uint32_t)__popcll(gm & lt_mask);
             for (int w = 0; w < wave; ++w) {
                 pos += wave_cnt[w][c];
                 pf += wave_cnt[w][s];

@@ -155,12 +155,13 @@ __host__ __device__ inline uint2 pack_tile_rect(int i0, int j0, int i1, int j1, 
 // backward's: by list length, longest first, in classes of lengths (> 192,
 // > 128, ..., > 4, > 0, empty), each class in tile order, so that the longest
 // walks start first and the waves that start last are short.  The forward's:
-// the tiles of the first kOrderHeavyClass + 1 classes (lists of more than 48
-// pairs) first, then the others, each part in tile order.
+// groups of consecutive classes (the last class of each group in
+// kFwdGroupLast), each group in tile order.
 constexpr int kOrderClasses = 16;
-constexpr int kOrderHeavyClass = 5;
 __device__ constexpr uint32_t kOrderBounds[kOrderClasses - 1] = {192, 128, 96, 72, 56, 48, 40, 32,
                                                                  26, 20, 16, 12, 8, 4, 0};
+constexpr int kFwdGroups = 2;   // lists of more than 48 pairs, then the others
+__device__ constexpr int kFwdGroupLast[kFwdGroups] = {5, 15};
 constexpr int kBigChunks = 16;
 __host__ __device__ inline int big_chunk_start(int c, int nrec) {
     return (int)(((int64_t)c * nrec) / kBigChunks);

@@ -151,7 +151,7 @@ def load(path: str = LIB_PATH):
     lib.linprim_loss_value.argtypes = [P, SZ, cm, I32, ctypes.c_float, ctypes.POINTER(ctypes.c_double), P]
     lib.linprim_strerror.restype = ctypes.c_char_p
     lib.linprim_strerror.argtypes = [ctypes.c_int]
-    lib.linprim_debug_pointers.argtypes = [pr, cm, I32, tu, P, P, I64] + [ctypes.POINTER(P)] * 7
+    lib.linprim_debug_pointers.argtypes = [pr, cm, I32, tu, P, P, I64] + [ctypes.POINTER(P)] * 9
     for f in (lib.linprim_preprocess, lib.linprim_pair_count, lib.linprim_bin_sort, lib.linprim_render_fwd,
               lib.linprim_render_fwd_counted, lib.linprim_render_fwd_depth, lib.linprim_render_bwd,
               lib.linprim_raster_bwd,
@@ -403,11 +403,11 @@ def linprim_read_status(view_ws, stream=None):
 
 def linprim_debug_pointers(prims: Prims, cams, tune, view_ws, pair_ws, max_pairs) -> dict:
     p = prims.c()
-    outs = [ctypes.c_void_p() for _ in range(7)]
+    outs = [ctypes.c_void_p() for _ in range(9)]
     _check(load().linprim_debug_pointers(ctypes.byref(p), cams, len(cams), ctypes.byref(tune), _ptr(view_ws),
                                          _ptr(pair_ws), max_pairs, *[ctypes.byref(o) for o in outs]),
            "linprim_debug_pointers")
-    names = ("payload", "depth_keys", "tiles", "offsets", "keys", "values", "ranges")
+    names = ("payload", "depth_keys", "tiles", "offsets", "keys", "values", "ranges", "order_fwd", "order_bwd")
     return {k: int(o.value or 0) for k, o in zip(names, outs)}
 
 

@@ -5,10 +5,11 @@
   pair offsets must equal the exclusive prefix sum of the tile counts and
   the pair count their sum (the definition of the scan, Sec. 3.2 "Global
   Sorting and Tiling").
-* More than 256 blocks of tiles (1M tiles) in the render order: images of
-  40 full-HD views rendered in one call equal those rendered one view at a
-  time (the order only schedules waves), and the sorted pairs equal the
-  oracle's."""
+* More than 256 blocks of tiles in the render orders: images of 40 full-HD
+  views rendered in one call equal those rendered one view at a time (the
+  orders only schedule waves), the sorted pairs equal the oracle's, and both
+  render orders are the documented permutations of the tiles (as with one
+  view, where every block computes its own prefix)."""
 import numpy as np
 import pytest
 import torch
@@ -27,6 +28,31 @@ def _say(msg):
 def _ws_view(ws, base, addr, count, dtype, itemsize):
     off = addr - base
     return ws[off: off + count * itemsize].view(dtype)
+
+
+# list-length classes of the backward order (longest first) and the forward
+# order's split (lists of more than 48 pairs first)
+ORDER_BOUNDS = np.array([192, 128, 96, 72, 56, 48, 40, 32, 26, 20, 16, 12, 8, 4, 0])
+
+
+def _check_orders(rast, prims):
+    """Both render orders against their definitions, from the tile ranges:
+    stable sorts of the tiles by class (backward) and by heaviness (forward)."""
+    ptr = L.linprim_debug_pointers(prims, rast.cams_c, rast.tune, rast.view_ws, rast.pair_ws, rast.max_pairs)
+    base = rast.view_ws.data_ptr()
+    tile = rast.tune.tile
+    nt = int(sum(((c.width + tile - 1) // tile) * ((c.height + tile - 1) // tile)
+                 for c in rast.cams))
+    rg = _ws_view(rast.view_ws, base, ptr["ranges"], 2 * nt, torch.int32, 4).cpu().numpy().view(np.uint32)
+    length = (rg[1::2].astype(np.int64) - rg[0::2]).astype(np.int64)
+    fwd = _ws_view(rast.view_ws, base, ptr["order_fwd"], nt, torch.int32, 4).cpu().numpy().view(np.uint32)
+    bwd = _ws_view(rast.view_ws, base, ptr["order_bwd"], nt, torch.int32, 4).cpu().numpy().view(np.uint32)
+    cls = (length[:, None] <= ORDER_BOUNDS[None, :]).sum(1)
+    tiles = np.arange(nt)
+    assert np.array_equal(bwd, tiles[np.lexsort((tiles, cls))])
+    assert np.array_equal(fwd, tiles[np.lexsort((tiles, (length <= 48).astype(np.int64)))])
+    _say(f"  orders of {nt} tiles: {int((length > 48).sum())} lists of more than 48 pairs, "
+         f"{len(np.unique(cls))} length classes")
 
 
 def test_scan_beyond_direct_blocks():
@@ -70,9 +96,23 @@ def test_render_order_beyond_direct_blocks(oracle_mod):
     _say(f"  pairs {rast.n_pairs}")
     assert np.array_equal(keys, s["keys"])
     assert np.array_equal(vals, s["values"])
+    _check_orders(rast, prims)
     # images do not depend on the order in which waves take the tiles
     for k in range(0, len(cams), 13):
         one = Rasterizer(sc.kind, sc.n, [cams[k]], tile=8)
         rgb1, _, _ = one.forward(prims, (0.1, 0.2, 0.3))
         start = 3 * sum(c.width * c.height for c in cams[:k])
         assert torch.equal(rgb[start: start + rgb1.numel()], rgb1)
+
+
+def test_render_orders_one_view():
+    """One full-HD view (127 blocks of tiles: every block sums the class
+    counts itself), with list lengths from 0 to several hundred."""
+    _say("render orders, one 1920x1080 view")
+    sc = scenes.uniform_octahedra(300_000, seed=11, box=1.0, dmin=0.004, dmax=0.05)
+    cam = scenes.look_at((0.0, 0.2, 2.2), (0, 0, 0), 1920, 1080)
+    prims = L.Prims.from_scene(sc)
+    rast = Rasterizer(sc.kind, sc.n, [cam], tile=8)
+    rast.forward(prims, (0.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    _check_orders(rast, prims)
