@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
 // by a 256-thread block (bitonic network), and lists longer than kLdsList
 // are sorted in kLdsList chunks that are then merged.
 // ---------------------------------------------------------------------------
-constexpr int kShortList = 256;
+constexpr int kShortList = 512;
 constexpr int kLdsList = 4096;
 
 // Writes the sorted pair e of tile g: the full key and the value.
@@ -184,17 +184,20 @@ __device__ inline uint64_t depth_index(const uint64_t* __restrict__ keys, const 
 
 // One wave per tile with at most kShortList pairs: every pair's rank is the
 // number of smaller (depth, index) values in the list.  Longer lists are
-// put on the long-list list.
+// put on the long-list list.  Wave w takes the tile at position w of the
+// backward render order (longest lists first, written just before).
 __global__ __launch_bounds__(64) void k_sort_short_lists(const uint2* __restrict__ ranges, int64_t n_tiles,
                                                          Status* __restrict__ status, uint64_t capacity,
                                                          const uint64_t* __restrict__ in_keys,
                                                          const uint32_t* __restrict__ in_vals,
                                                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-                                                         uint32_t* __restrict__ long_list) {
+                                                         uint32_t* __restrict__ long_list,
+                                                         const uint32_t* __restrict__ order) {
     constexpr int PER = kShortList / 64;
     if (status->n_pairs > capacity) return;
-    const int64_t g = blockIdx.x;
-    if (g >= n_tiles) return;
+    if ((int64_t)blockIdx.x >= n_tiles) return;
+    // longest lists first, so that their quadratic rankings start first
+    const int64_t g = order[blockIdx.x];
     const uint2 rg = ranges[g];
     const int len = (int)(rg.y - rg.x);
     if (len == 0) return;
@@ -849,7 +852,7 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
     if (!radix) {
         // per-list sort from (kin, vin) into (kout, vout)
         hipLaunchKernelGGL(k_sort_short_lists, dim3((unsigned)nt), dim3(64), 0, stream, ranges, nt, status, cap, kin,
-                           vin, kout, vout, long_list);
+                           vin, kout, vout, long_list, reinterpret_cast<const uint32_t*>(vws + L.order_bwd));
         const int64_t lblocks = nt < 512 ? nt : 512;
         hipLaunchKernelGGL(k_sort_long_lists, dim3((unsigned)lblocks), dim3(256), 0, stream, ranges, long_list, status,
                            cap, kin, vin, kout, vout);
