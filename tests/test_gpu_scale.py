@@ -31,7 +31,7 @@ def _ws_view(ws, base, addr, count, dtype, itemsize):
 
 
 # list-length classes of the backward order (longest first) and the forward
-# order's split (lists of more than 48 pairs first)
+# order's split (lists of more than 72 pairs first)
 ORDER_BOUNDS = np.array([192, 128, 96, 72, 56, 48, 40, 32, 26, 20, 16, 12, 8, 4, 0])
 
 
@@ -50,8 +50,8 @@ def _check_orders(rast, prims):
     cls = (length[:, None] <= ORDER_BOUNDS[None, :]).sum(1)
     tiles = np.arange(nt)
     assert np.array_equal(bwd, tiles[np.lexsort((tiles, cls))])
-    assert np.array_equal(fwd, tiles[np.lexsort((tiles, (length <= 48).astype(np.int64)))])
-    _say(f"  orders of {nt} tiles: {int((length > 48).sum())} lists of more than 48 pairs, "
+    assert np.array_equal(fwd, tiles[np.lexsort((tiles, (length <= 72).astype(np.int64)))])
+    _say(f"  orders of {nt} tiles: {int((length > 72).sum())} lists of more than 72 pairs, "
          f"{len(np.unique(cls))} length classes")
 
 
