@@ -160,8 +160,8 @@ __host__ __device__ inline uint2 pack_tile_rect(int i0, int j0, int i1, int j1, 
 constexpr int kOrderClasses = 16;
 __device__ constexpr uint32_t kOrderBounds[kOrderClasses - 1] = {192, 128, 96, 72, 56, 48, 40, 32,
                                                                  26, 20, 16, 12, 8, 4, 0};
-constexpr int kFwdGroups = 2;   // lists of more than 72 pairs, then the others
-__device__ constexpr int kFwdGroupLast[kFwdGroups] = {3, 15};
+constexpr int kFwdGroups = 3;   // lists of more than 128 pairs, of 73-128, the others
+__device__ constexpr int kFwdGroupLast[kFwdGroups] = {1, 3, 15};
 constexpr int kBigChunks = 16;
 __host__ __device__ inline int big_chunk_start(int c, int nrec) {
     return (int)(((int64_t)c * nrec) / kBigChunks);

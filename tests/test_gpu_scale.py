@@ -31,7 +31,7 @@ def _ws_view(ws, base, addr, count, dtype, itemsize):
 
 
 # list-length classes of the backward order (longest first) and the forward
-# order's split (lists of more than 72 pairs first)
+# order's parts (lists of more than 128 pairs, of more than 72, the others)
 ORDER_BOUNDS = np.array([192, 128, 96, 72, 56, 48, 40, 32, 26, 20, 16, 12, 8, 4, 0])
 
 
@@ -50,8 +50,10 @@ def _check_orders(rast, prims):
     cls = (length[:, None] <= ORDER_BOUNDS[None, :]).sum(1)
     tiles = np.arange(nt)
     assert np.array_equal(bwd, tiles[np.lexsort((tiles, cls))])
-    assert np.array_equal(fwd, tiles[np.lexsort((tiles, (length <= 72).astype(np.int64)))])
-    _say(f"  orders of {nt} tiles: {int((length > 72).sum())} lists of more than 72 pairs, "
+    part = (length <= 128).astype(np.int64) + (length <= 72).astype(np.int64)
+    assert np.array_equal(fwd, tiles[np.lexsort((tiles, part))])
+    _say(f"  orders of {nt} tiles: {int((length > 128).sum())} and {int((length > 72).sum())} lists of more than "
+         f"128 and 72 pairs, "
          f"{len(np.unique(cls))} length classes")
 
 
