@@ -175,10 +175,9 @@ int linprim_preprocess(const linprim_prims* prims, const linprim_camera* cams, i
     if (int rc = check_device()) return rc;
     hipStream_t s = (hipStream_t)stream;
     char* ws = (char*)view_ws;
-    hipError_t e = hipSuccess;
-    if (!(tuning && (tuning->flags & LINPRIM_FLAG_VIEWS_RESIDENT)))
-        e = launch_store_views(cams, n_views, tile, reinterpret_cast<ViewInfo*>(ws + L.views), s);
-    if (e == hipSuccess) e = launch_preprocess(*prims, n_views, tile, exact_rays(tuning), antialias(tuning), L, ws, s);
+    const bool resident = tuning && (tuning->flags & LINPRIM_FLAG_VIEWS_RESIDENT);
+    hipError_t e = launch_preprocess(*prims, n_views, tile, exact_rays(tuning), antialias(tuning), L, ws, s,
+                                     resident ? nullptr : cams);
     if (e == hipSuccess) e = launch_scan(L, ws, tile, s);
     return hip_status(e);
 }

@@ -8,9 +8,31 @@
 
 namespace linprim {
 
-struct ViewChunk {
-    ViewInfo v[8];
-};
+// Per-view constants of up to kViewChunk views, computed on the host in
+// double precision and passed by value.
+void fill_view_chunk(const linprim_camera* cams, int v0, int cnt, int tile, int64_t& tile_base, int64_t& pix_base,
+                     ViewChunk& ch) {
+    for (int k = 0; k < cnt; ++k) {
+        const linprim_camera& c = cams[v0 + k];
+        ViewInfo& V = ch.v[k];
+        for (int r = 0; r < 3; ++r) {
+            for (int q = 0; q < 3; ++q) V.Rw[3 * r + q] = (double)c.world_to_cam[4 * r + q];
+            V.tw[r] = (double)c.world_to_cam[4 * r + 3];
+        }
+        // camera position -R^T t
+        for (int q = 0; q < 3; ++q)
+            V.cam_pos[q] = -(V.Rw[q] * V.tw[0] + V.Rw[3 + q] * V.tw[1] + V.Rw[6 + q] * V.tw[2]);
+        V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
+        V.near_z = c.near_z;
+        V.width = c.width; V.height = c.height;
+        V.tiles_x = (c.width + tile - 1) / tile;
+        V.tiles_y = (c.height + tile - 1) / tile;
+        V.tile_base = tile_base;
+        V.pix_base = pix_base;
+        tile_base += (int64_t)V.tiles_x * V.tiles_y;
+        pix_base += (int64_t)c.width * c.height;
+    }
+}
 
 __global__ void k_store_views(ViewChunk chunk, int count, ViewInfo* __restrict__ dst) {
     const int i = threadIdx.x;
@@ -20,29 +42,10 @@ __global__ void k_store_views(ViewChunk chunk, int count, ViewInfo* __restrict__
 hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int tile, ViewInfo* views,
                               hipStream_t stream) {
     int64_t tile_base = 0, pix_base = 0;
-    for (int v0 = 0; v0 < n_views; v0 += 8) {
+    for (int v0 = 0; v0 < n_views; v0 += kViewChunk) {
         ViewChunk ch;
-        const int cnt = (n_views - v0) < 8 ? (n_views - v0) : 8;
-        for (int k = 0; k < cnt; ++k) {
-            const linprim_camera& c = cams[v0 + k];
-            ViewInfo& V = ch.v[k];
-            for (int r = 0; r < 3; ++r) {
-                for (int q = 0; q < 3; ++q) V.Rw[3 * r + q] = (double)c.world_to_cam[4 * r + q];
-                V.tw[r] = (double)c.world_to_cam[4 * r + 3];
-            }
-            // camera position -R^T t
-            for (int q = 0; q < 3; ++q)
-                V.cam_pos[q] = -(V.Rw[q] * V.tw[0] + V.Rw[3 + q] * V.tw[1] + V.Rw[6 + q] * V.tw[2]);
-            V.fx = c.fx; V.fy = c.fy; V.cx = c.cx; V.cy = c.cy;
-            V.near_z = c.near_z;
-            V.width = c.width; V.height = c.height;
-            V.tiles_x = (c.width + tile - 1) / tile;
-            V.tiles_y = (c.height + tile - 1) / tile;
-            V.tile_base = tile_base;
-            V.pix_base = pix_base;
-            tile_base += (int64_t)V.tiles_x * V.tiles_y;
-            pix_base += (int64_t)c.width * c.height;
-        }
+        const int cnt = (n_views - v0) < kViewChunk ? (n_views - v0) : kViewChunk;
+        fill_view_chunk(cams, v0, cnt, tile, tile_base, pix_base, ch);
         hipLaunchKernelGGL(k_store_views, dim3(1), dim3(64), 0, stream, ch, cnt, views + v0);
     }
     return hipGetLastError();
@@ -206,15 +209,19 @@ __device__ inline void preprocess_colour(const float* shv, const float* mu, cons
 // rotation, the world-space offsets, sigma and the SH coefficients are
 // taken once; per view the thread writes the 32-dword payload record, the
 // depth key and the tile count of slot v * n + i.
-template <int KIND, int DEG, bool EXACT>
+template <int KIND, int DEG, bool EXACT, bool BYVAL>
 __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ means, const float* __restrict__ quats,
                                                     const float* __restrict__ dists, const float* __restrict__ opacity,
                                                     const float* __restrict__ sh, int64_t n,
                                                     const ViewInfo* __restrict__ views, int n_views, int tile_shift,
                                                     int aa, float* __restrict__ payload,
                                                     uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tiles,
-                                                    uint2* __restrict__ trect) {
+                                                    uint2* __restrict__ trect, ViewChunk chunk) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // BYVAL: the views (at most kViewChunk) come by value; the kernels after
+    // this one read them from the workspace, where the first block stores them
+    if (BYVAL && blockIdx.x == 0 && threadIdx.x < n_views)
+        const_cast<ViewInfo*>(views)[threadIdx.x] = chunk.v[threadIdx.x];
     if (i >= n) return;
     constexpr int nd = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
     float mu[3], qv[4], dv[nd];
@@ -237,8 +244,8 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
         const int v1 = min(n_views, v0 + 64);
         uint64_t seen = 0;
         for (int v = v0; v < v1; ++v)
-            if (preprocess_view<KIND, EXACT>(ok, G, mu, sigma, views[v], (int64_t)v * n + i, tile_shift, aa, payload,
-                                             depth_keys, tiles, trect))
+            if (preprocess_view<KIND, EXACT>(ok, G, mu, sigma, BYVAL ? chunk.v[v] : views[v], (int64_t)v * n + i,
+                                             tile_shift, aa, payload, depth_keys, tiles, trect))
                 seen |= 1ull << (v - v0);
         if (seen) {
             float shv[48];
@@ -246,13 +253,28 @@ __global__ __launch_bounds__(256) void k_preprocess(const float* __restrict__ me
             while (seen) {
                 const int v = v0 + __builtin_ctzll(seen);
                 seen &= seen - 1;
-                preprocess_colour<DEG>(shv, mu, views[v], payload + ((int64_t)v * n + i) * kRecordWords);
+                preprocess_colour<DEG>(shv, mu, BYVAL ? chunk.v[v] : views[v],
+                                       payload + ((int64_t)v * n + i) * kRecordWords);
             }
         }
     }
 }
 hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, bool aa,
-                             const ViewLayout& L, char* ws, hipStream_t stream) {
+                             const ViewLayout& L, char* ws, hipStream_t stream, const linprim_camera* cams) {
+    // cams != nullptr: the views are not in the workspace yet; up to
+    // kViewChunk of them travel with the launch, more are stored first
+    ViewChunk chunk;
+    int by_value = 0;
+    if (cams) {
+        if (n_views <= kViewChunk && p.n > 0) {
+            int64_t tile_base = 0, pix_base = 0;
+            fill_view_chunk(cams, 0, n_views, tile, tile_base, pix_base, chunk);
+            by_value = 1;
+        } else if (hipError_t e = launch_store_views(cams, n_views, tile, reinterpret_cast<ViewInfo*>(ws + L.views),
+                                                     stream)) {
+            return e;
+        }
+    }
     if (p.n == 0) return hipSuccess;
     const int shift = (tile == 8) ? 3 : (tile == 16) ? 4 : 5;
     dim3 grid((unsigned)((p.n + 255) / 256));
@@ -261,16 +283,16 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
     uint32_t* keys = reinterpret_cast<uint32_t*>(ws + L.depth_keys);
     uint32_t* tiles = reinterpret_cast<uint32_t*>(ws + L.tiles);
     uint2* trect = reinterpret_cast<uint2*>(ws + L.trect);
+#define LP_PRE_K(K_, D_, E_, B_)                                                                            \
+    hipLaunchKernelGGL((k_preprocess<K_, D_, E_, B_>), grid, dim3(256), 0, stream, p.means, p.quats, p.dists,   \
+                       p.opacity, p.sh, p.n, views, n_views, shift, aa ? 1 : 0, payload, keys, tiles, trect, chunk)
 #define LP_PRE(K_, D_)                                                                                     \
     do {                                                                                                     \
-        if (exact)                                                                                           \
-            hipLaunchKernelGGL((k_preprocess<K_, D_, true>), grid, dim3(256), 0, stream, p.means, p.quats,    \
-                               p.dists, p.opacity, p.sh, p.n, views, n_views, shift, aa ? 1 : 0, payload, keys, \
-                               tiles, trect);                                                                    \
-        else                                                                                                 \
-            hipLaunchKernelGGL((k_preprocess<K_, D_, false>), grid, dim3(256), 0, stream, p.means, p.quats,   \
-                               p.dists, p.opacity, p.sh, p.n, views, n_views, shift, aa ? 1 : 0, payload, keys, \
-                               tiles, trect);                                                                    \
+        if (exact) {                                                                                         \
+            if (by_value) LP_PRE_K(K_, D_, true, true); else LP_PRE_K(K_, D_, true, false);                \
+        } else {                                                                                             \
+            if (by_value) LP_PRE_K(K_, D_, false, true); else LP_PRE_K(K_, D_, false, false);              \
+        }                                                                                                    \
     } while (0)
 #define LP_PRE_DEG(K_)                      \
     switch (p.sh_degree) {                  \
@@ -286,6 +308,7 @@ hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, 
     }
 #undef LP_PRE_DEG
 #undef LP_PRE
+#undef LP_PRE_K
     return hipGetLastError();
 }
 

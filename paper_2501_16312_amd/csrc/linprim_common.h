@@ -122,10 +122,16 @@ int key_tile_bits(int64_t n_tiles_total);
 // ----------------------------------------------------------------------------
 // Host-side launchers (one per kernel file).
 // ----------------------------------------------------------------------------
+// Views passed by value in one launch argument.
+constexpr int kViewChunk = 8;
+struct ViewChunk {
+    ViewInfo v[kViewChunk];
+};
 hipError_t launch_store_views(const linprim_camera* cams, int32_t n_views, int tile, ViewInfo* views,
                               hipStream_t stream);
+// cams: the cameras, when the views are not yet stored in the workspace
 hipError_t launch_preprocess(const linprim_prims& p, int32_t n_views, int tile, bool exact, bool aa,
-                             const ViewLayout& L, char* ws, hipStream_t stream);
+                             const ViewLayout& L, char* ws, hipStream_t stream, const linprim_camera* cams);
 hipError_t launch_scan(const ViewLayout& L, char* ws, int tile, hipStream_t stream);
 
 // A (view, primitive) slot whose gradient records number more than kBigRun
