@@ -118,3 +118,26 @@ def test_render_orders_one_view():
     rast.forward(prims, (0.0, 0.0, 0.0))
     torch.cuda.synchronize()
     _check_orders(rast, prims)
+
+
+@pytest.mark.parametrize("n_views", [8, 9])
+def test_views_by_value_and_stored(n_views):
+    """Up to 8 views travel by value with the preprocessing launch (its first
+    block stores them for the later kernels), more are stored by their own
+    launch first: on both sides of the limit, a multi-view render equals the
+    views rendered one at a time (one view always goes by value)."""
+    _say(f"views by value / stored: {n_views} views")
+    sc = scenes.uniform_octahedra(20_000, seed=21, box=1.0, dmin=0.005, dmax=0.05)
+    cams = [scenes.look_at((2.5 * np.cos(a), 0.4, 2.5 * np.sin(a)), (0, 0, 0), 160 + 8 * k, 96 + 4 * k)
+            for k, a in enumerate(np.linspace(0, 2 * np.pi, n_views, endpoint=False))]
+    prims = L.Prims.from_scene(sc)
+    rast = Rasterizer(sc.kind, sc.n, cams, tile=8)
+    rgb, T, last = rast.forward(prims, (0.1, 0.2, 0.3))
+    start = 0
+    for k, cam in enumerate(cams):
+        one = Rasterizer(sc.kind, sc.n, [cam], tile=8)
+        rgb1, T1, last1 = one.forward(prims, (0.1, 0.2, 0.3))
+        npx = cam.width * cam.height
+        assert torch.equal(rgb[3 * start: 3 * (start + npx)], rgb1)
+        assert torch.equal(T[start: start + npx], T1)
+        start += npx
