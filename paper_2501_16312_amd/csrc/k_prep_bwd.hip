@@ -214,6 +214,29 @@ struct ShBack {
     }
 };
 
+// The same terms with the coefficient gradients added to an LDS row:
+// coefficient word w of this thread at acc[w * stride] (coefficient-major,
+// so that the lanes of a wave add to consecutive banks).
+struct ShLds {
+    int K;
+    const float* sh;     // [48] coefficients (registers)
+    float* acc;          // this thread's column of the block's LDS stage
+    int stride;
+    float gr[3];
+    float gdir[3];
+    __device__ inline void term(int k, float Y, float gx, float gy, float gz) {
+        if (k >= K) return;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            acc[(3 * k + ch) * stride] += gr[ch] * Y;
+            const float w = gr[ch] * sh[3 * k + ch];
+            gdir[0] += w * gx;
+            gdir[1] += w * gy;
+            gdir[2] += w * gz;
+        }
+    }
+};
+
 // The same terms with the coefficient gradients stored as they are made
 // (one view: no accumulation over views), so that they need no registers.
 struct ShStore {
@@ -860,16 +883,19 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
                                                   float* __restrict__ g_means, float* __restrict__ g_quats,
                                                   float* __restrict__ g_dists, float* __restrict__ g_opacity,
                                                   float* __restrict__ g_sh) {
-    __shared__ float stage[128 * 48];
+    // SH gradients summed over the views in LDS, coefficient-major with a
+    // padded stride (word w of thread t at w * 129 + t), then stored coalesced
+    constexpr int SP = 129;
+    __shared__ float stage[48 * SP];
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
     const int64_t i = i0 + threadIdx.x;
     constexpr int ND = (KIND == LINPRIM_OCTAHEDRON) ? 3 : 4;
     constexpr int K = (DEG + 1) * (DEG + 1);
     const bool ok = status->n_pairs <= capacity && i < n;
     double gm[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gd[4] = {0, 0, 0, 0}, ga = 0.0;
-    float gsh[48];
+    float* acc = stage + threadIdx.x;
 #pragma unroll
-    for (int k = 0; k < 48; ++k) gsh[k] = 0.0f;
+    for (int k = 0; k < 3 * K; ++k) acc[k * SP] = 0.0f;
     float shp[48], mu[3];
     bool seen = false;
     for (int v = 0; ok && v < n_views; ++v) {
@@ -887,7 +913,10 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
         gq[0] += a.w; gq[1] += b.x; gq[2] += b.y; gq[3] += b.z;
         gd[0] += b.w; gd[1] += c.x; gd[2] += c.y; gd[3] += c.z;
         ga += d.z;
-        view_colour_bwd<K>(shp, mu, views[v], c.w, d.x, d.y, gsh, gm);
+        ShLds S;
+        S.acc = acc;
+        S.stride = SP;
+        view_colour_bwd_t<K>(S, shp, mu, views[v], c.w, d.x, d.y, gm);
     }
     if (i < n) {
         for (int c = 0; c < 3; ++c) g_means[3 * i + c] = (float)gm[c];
@@ -895,15 +924,15 @@ __global__ __launch_bounds__(128) void k_prim_bwd(const float* __restrict__ mean
         for (int c = 0; c < ND; ++c) g_dists[ND * i + c] = (float)gd[c];
         g_opacity[i] = (float)ga;
     }
-    // SH gradients: stage the block's [128][3K] slab in LDS, store coalesced
+    // the block's [128][3K] slab of SH gradients, stored coalesced
     const int w3 = 3 * K;
-#pragma unroll
-    for (int k = 0; k < 48; ++k)
-        if (k < w3) stage[threadIdx.x * w3 + k] = gsh[k];
     __syncthreads();
     const int64_t rows = (n - i0) < 128 ? (n - i0) : 128;
     float* gs = g_sh + i0 * (int64_t)w3;
-    for (int64_t j = threadIdx.x; j < rows * w3; j += 128) gs[j] = stage[j];
+    for (int64_t j = threadIdx.x; j < rows * w3; j += 128) {
+        const int64_t r = j / w3;
+        gs[j] = stage[(j - r * w3) * SP + r];
+    }
 }
 
 hipError_t launch_preprocess_bwd(const linprim_prims& p, int32_t n_views, int tile, bool exact, bool aa,
