@@ -496,10 +496,10 @@ const char *linprim_strerror(int code);
  * [max_pairs] u64 and values [max_pairs] u32 (first n_pairs valid),
  * ranges [total tiles] (u32 start, u32 end), and the two render orders
  * [total tiles] u32 written by linprim_bin_sort (the tile taken by each wave
- * position: forward, lists of more than 128 pairs first, then those of more than
- * 72, then the others, each
- * part in tile order; backward, by classes of list length, longest first,
- * each class in tile order).  Any out-pointer may be NULL. */
+ * position: forward, lists of more than 128 pairs first, then those of more
+ * than 72, then the others, each part in tile order; backward, by classes of
+ * list length, longest first, each class in tile order; the exact variant's
+ * forward takes the backward order).  Any out-pointer may be NULL. */
 int linprim_debug_pointers(const linprim_prims *prims, const linprim_camera *cams, int32_t n_views,
                            const linprim_tuning *tuning, const void *view_ws, const void *pair_ws,
                            int64_t max_pairs, void **payload, void **depth_keys, void **tiles_touched,

@@ -275,9 +275,10 @@ __device__ inline float ray_norm(const ViewInfo& V, int x, int y) {
 // Wave placement: wave w (XCD-chunked) handles group q = w % NQ of the tile at
 // position w / NQ of a render order.  The forward's: heavy tiles first, then
 // the others, each part in tile order, so that consecutive positions are
-// mostly neighbouring tiles.  The backward's: longest lists first in classes
-// of list length (tile order inside a class), so that the waves that start
-// last are short and the kernel has no long tail.
+// mostly neighbouring tiles.  The backward's (also taken by the exact
+// variant's forward): longest lists first in classes of list length (tile
+// order inside a class), so that the waves that start last are short and
+// the kernel has no long tail.
 // ---------------------------------------------------------------------------
 struct Place {
     int v, tx, ty, gx0, gy0, W, H, q;
@@ -1024,7 +1025,8 @@ hipError_t launch_render_fwd_ex(const ViewLayout& L, const char* vws, const Pair
     const uint32_t* vals = reinterpret_cast<const uint32_t*>(pws + (result_in_b ? P.vals_b : P.vals_a));
     const uint2* ranges = reinterpret_cast<const uint2*>(vws + L.ranges);
     const Status* st = reinterpret_cast<const Status*>(vws + L.status);
-    const uint32_t* order = reinterpret_cast<const uint32_t*>(vws + L.order);
+    // the exact variant's heavier step runs best in the backward's order
+    const uint32_t* order = reinterpret_cast<const uint32_t*>(vws + (exact ? L.order_bwd : L.order));
     const uint64_t cap = (uint64_t)P.capacity;
     const bool count = counters != nullptr;
 #define LP_FWD(T_, K_, E_) fwd_dispatch<T_, K_, E_>(count, L, stream, views, n_views, L.n, payload, vals, ranges, st, \

@@ -160,7 +160,8 @@ __host__ __device__ inline uint2 pack_tile_rect(int i0, int j0, int i1, int j1, 
 // The render kernels take the tiles in the orders written by bin_sort.  The
 // backward's: by list length, longest first, in classes of lengths (> 192,
 // > 128, ..., > 4, > 0, empty), each class in tile order, so that the longest
-// walks start first and the waves that start last are short.  The forward's:
+// walks start first and the waves that start last are short (the exact
+// variant's forward takes it too).  The ray-space forward's:
 // groups of consecutive classes (the last class of each group in
 // kFwdGroupLast), each group in tile order.
 constexpr int kOrderClasses = 16;
