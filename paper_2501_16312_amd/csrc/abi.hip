@@ -44,7 +44,8 @@ ViewLayout view_layout(int64_t n, const linprim_camera* cams, int32_t n_views, i
     L.order = off; off = align256(off + (size_t)L.n_tiles_total * 4);
     L.order_bwd = off; off = align256(off + (size_t)L.n_tiles_total * 4);
     L.order_sums = off;
-    off = align256(off + (size_t)(((L.n_tiles_total + kOrderItems - 1) / kOrderItems) * kOrderClasses + 1) * 4);
+    const int64_t oi = order_items(L.n_tiles_total);
+    off = align256(off + (size_t)(((L.n_tiles_total + oi - 1) / oi) * kOrderClasses + 1) * 4);
     L.huge = off; off = align256(off + (size_t)vn * 4);
     L.trect = off; off = align256(off + (size_t)vn * 8);
     L.total = off;

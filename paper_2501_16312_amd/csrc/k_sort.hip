@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
 // by a 256-thread block (bitonic network), and lists longer than kLdsList
 // are sorted in kLdsList chunks that are then merged.
 // ---------------------------------------------------------------------------
-constexpr int kShortList = 512;
+constexpr int kShortList = 256;
 constexpr int kLdsList = 4096;
 
 // Writes the sorted pair e of tile g: the full key and the value.
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
 // more sensitive to cache locality, takes them in kFwdGroups coarser groups
 // of consecutive classes (tile order inside a group).
 // Counts are kept class-major, sums[c * nblocks + b] for class c in block b
-// of kOrderItems tiles, so that one exclusive scan over them gives every
+// of `items` tiles (order_items), so that one exclusive scan over them gives every
 // (class, block) its first position.
 __device__ inline int order_class(uint32_t len) {
     int c = 0;
@@ -590,14 +590,13 @@ __device__ inline int order_class(uint32_t len) {
 
 __global__ __launch_bounds__(256) void k_order_count(const uint2* __restrict__ ranges, int64_t n_tiles,
                                                      const Status* __restrict__ status, uint64_t capacity,
-                                                     uint32_t* __restrict__ sums) {
+                                                     uint32_t* __restrict__ sums, int items) {
     __shared__ uint32_t cnt[kOrderClasses];
     if (status->n_pairs > capacity) return;
     if (threadIdx.x < kOrderClasses) cnt[threadIdx.x] = 0u;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kOrderItems;
-#pragma unroll
-    for (int k = 0; k < kOrderItems / 256; ++k) {
+    const int64_t base = (int64_t)blockIdx.x * items;
+    for (int k = 0; k < items / 256; ++k) {
         const int64_t g = base + k * 256 + threadIdx.x;
         if (g < n_tiles) {
             const uint2 rg = ranges[g];
@@ -659,7 +658,7 @@ __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ r
                                                      const Status* __restrict__ status, uint64_t capacity,
                                                      const uint32_t* __restrict__ sums, int64_t nblocks,
                                                      bool prefixed, uint32_t* __restrict__ order_fwd,
-                                                     uint32_t* __restrict__ order_bwd) {
+                                                     uint32_t* __restrict__ order_bwd, int items) {
     constexpr int K = kOrderClasses, G = kFwdGroups, NS = K + G;
     __shared__ uint32_t first[NS + G];
     __shared__ uint32_t running[NS];
@@ -716,8 +715,8 @@ __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ r
     }
     if (t < NS) running[t] = 0u;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int r = 0; r < kOrderItems / 256; ++r) {
-        const int64_t g = b * kOrderItems + r * 256 + t;
+    for (int r = 0; r < items / 256; ++r) {
+        const int64_t g = b * items + r * 256 + t;
         const bool valid = g < n_tiles;
         int c = 0;
         if (valid) {
@@ -841,13 +840,15 @@ hipError_t launch_bin_sort(const ViewLayout& L, char* vws, const PairLayout& P, 
         uint32_t* order = reinterpret_cast<uint32_t*>(vws + L.order);
         uint32_t* order_bwd = reinterpret_cast<uint32_t*>(vws + L.order_bwd);
         uint32_t* osums = reinterpret_cast<uint32_t*>(vws + L.order_sums);
-        const int64_t ob = (nt + kOrderItems - 1) / kOrderItems;
-        hipLaunchKernelGGL(k_order_count, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums);
+        const int items = order_items(nt);
+        const int64_t ob = (nt + items - 1) / items;
+        hipLaunchKernelGGL(k_order_count, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums,
+                           items);
         const bool prefixed = ob > kOrderDirectBlocks;
         if (prefixed)
             hipLaunchKernelGGL(k_order_prefix, dim3(1), dim3(1024), 0, stream, osums, ob * kOrderClasses, status, cap);
         hipLaunchKernelGGL(k_order_write, dim3((unsigned)ob), dim3(256), 0, stream, ranges, nt, status, cap, osums, ob,
-                           prefixed, order, order_bwd);
+                           prefixed, order, order_bwd, items);
     }
     if (!radix) {
         // per-list sort from (kin, vin) into (kout, vout)

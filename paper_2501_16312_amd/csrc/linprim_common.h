@@ -107,8 +107,16 @@ constexpr int kScanItems = 4096;     // elements per scan block (256 threads x 1
 constexpr int64_t kScanDirectBlocks = 8192;
 // Tiles per block of the render order kernels (256 threads x 4), and the
 // same choice for their per-block counts (256 blocks: 256K tiles).
-constexpr int kOrderItems = 256;
 constexpr int64_t kOrderDirectBlocks = 256;
+// Tiles per block of the render-order kernels: 256, or a multiple of 256 (at
+// most 4096) so that up to 16M tiles need no more than kOrderDirectBlocks
+// blocks, whose counts every block then adds itself (no separate prefix).
+__host__ __device__ inline int order_items(int64_t n_tiles) {
+    const int64_t per = 256 * kOrderDirectBlocks;
+    int64_t rounds = (n_tiles + per - 1) / per;
+    rounds = rounds < 1 ? 1 : (rounds > 16 ? 16 : rounds);
+    return (int)(256 * rounds);
+}
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 4;        // keys per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;

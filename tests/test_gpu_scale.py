@@ -85,7 +85,7 @@ def test_render_order_beyond_direct_blocks(oracle_mod):
     cams = [scenes.look_at((3 * np.cos(a), 0.3, 3 * np.sin(a)), (0, 0, 0), 1920, 1080)
             for a in np.linspace(0, 2 * np.pi, 40, endpoint=False)]
     n_tiles = sum(((c.width + 7) // 8) * ((c.height + 7) // 8) for c in cams)
-    assert n_tiles > 256 * 1024          # more than 256 blocks of 1024 tiles
+    assert n_tiles > 256 * 4096          # more than 256 blocks of the largest size (4096 tiles)
     prims = L.Prims.from_scene(sc)
     rast = Rasterizer(sc.kind, sc.n, cams, tile=8)
     rgb, _, _ = rast.forward(prims, (0.1, 0.2, 0.3))
@@ -107,14 +107,18 @@ def test_render_order_beyond_direct_blocks(oracle_mod):
         assert torch.equal(rgb[start: start + rgb1.numel()], rgb1)
 
 
-def test_render_orders_one_view():
-    """One full-HD view (127 blocks of tiles: every block sums the class
-    counts itself), with list lengths from 0 to several hundred."""
-    _say("render orders, one 1920x1080 view")
+@pytest.mark.parametrize("n_views", [1, 3])
+def test_render_orders_one_view(n_views):
+    """Full-HD views whose tiles fit in at most 256 blocks, so that every
+    block sums the class counts itself: one view (127 blocks of 256 tiles)
+    and three (190 blocks of 512, taken in two rounds), with list lengths from
+    0 to several hundred."""
+    _say(f"render orders, {n_views} 1920x1080 view(s)")
     sc = scenes.uniform_octahedra(300_000, seed=11, box=1.0, dmin=0.004, dmax=0.05)
-    cam = scenes.look_at((0.0, 0.2, 2.2), (0, 0, 0), 1920, 1080)
+    cams = [scenes.look_at((2.2 * np.sin(a), 0.2, 2.2 * np.cos(a)), (0, 0, 0), 1920, 1080)
+            for a in np.linspace(0, 2 * np.pi, n_views, endpoint=False)]
     prims = L.Prims.from_scene(sc)
-    rast = Rasterizer(sc.kind, sc.n, [cam], tile=8)
+    rast = Rasterizer(sc.kind, sc.n, cams, tile=8)
     rast.forward(prims, (0.0, 0.0, 0.0))
     torch.cuda.synchronize()
     _check_orders(rast, prims)
