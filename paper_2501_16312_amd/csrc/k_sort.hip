@@ -162,11 +162,12 @@ __global__ __launch_bounds__(256) void k_emit_pairs(const uint32_t* __restrict__
 // tile's pairs in emission order; each tile's list is then sorted by
 // (depth bits, primitive index), which is unique within a tile, so the
 // result is the order of the stable sort of the full keys.  Lists of up to
-// kShortList entries are ranked by one wave; longer ones are sorted in LDS
-// by a 256-thread block (bitonic network), and lists longer than kLdsList
-// are sorted in kLdsList chunks that are then merged.
+// kShortList entries are sorted by one wave (up to 64 by counting ranks,
+// more by a bitonic network in registers); longer ones are sorted in LDS by
+// a 256-thread block (bitonic network), and lists longer than kLdsList are
+// sorted in kLdsList chunks that are then merged.
 // ---------------------------------------------------------------------------
-constexpr int kShortList = 256;
+constexpr int kShortList = 512;
 constexpr int kLdsList = 4096;
 
 // Writes the sorted pair e of tile g: the full key and the value.
@@ -182,10 +183,68 @@ __device__ inline uint64_t depth_index(const uint64_t* __restrict__ keys, const 
     return ((uint64_t)(uint32_t)keys[e] << 32) | vals[e];
 }
 
-// One wave per tile with at most kShortList pairs: every pair's rank is the
-// number of smaller (depth, index) values in the list.  Longer lists are
-// put on the long-list list.  Wave w takes the tile at position w of the
-// backward render order (longest lists first, written just before).
+// Sorts the (depth, index) keys of a list of up to 64 P pairs with one wave:
+// element e = 64 q + lane in register q (padded with ~0, which sorts last),
+// a bitonic network whose partners in other lanes come by shuffles and whose
+// partners in other registers of the lane are compared in place.
+template <int P>
+__device__ inline void bitonic_list(uint64_t (&k)[P], int lane) {
+    constexpr int N = 64 * P;
+#pragma unroll
+    for (int size = 2; size <= N; size <<= 1) {
+#pragma unroll
+        for (int j = size >> 1; j >= 1; j >>= 1) {
+            if (j >= 64) {
+                const int qj = j >> 6;
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    if (q & qj) continue;   // q holds the lower element of the pair
+                    const bool up = ((q * 64 + lane) & size) == 0;
+                    const uint64_t a = k[q], b = k[q | qj];
+                    const bool sw = up ? (a > b) : (a < b);
+                    k[q] = sw ? b : a;
+                    k[q | qj] = sw ? a : b;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int e = q * 64 + lane;
+                    const uint64_t a = k[q];
+                    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)a, j, 64);
+                    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(a >> 32), j, 64);
+                    const uint64_t b = ((uint64_t)hi << 32) | lo;
+                    const bool keep_min = ((e & size) == 0) == ((e & j) == 0);
+                    const bool a_min = a < b;
+                    k[q] = (keep_min == a_min) ? a : b;
+                }
+            }
+        }
+    }
+}
+
+// A list of 64 < len <= 64 P pairs sorted by one wave (bitonic_list) and
+// written back with its full keys.
+template <int P>
+__device__ inline void sort_list(const uint64_t* __restrict__ in_keys, const uint32_t* __restrict__ in_vals, uint2 rg,
+                                 int len, int lane, uint64_t g, uint64_t* __restrict__ keys,
+                                 uint32_t* __restrict__ vals) {
+    uint64_t k[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const int e = q * 64 + lane;
+        k[q] = (e < len) ? depth_index(in_keys, in_vals, rg.x + e) : ~0ull;
+    }
+    bitonic_list<P>(k, lane);
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        if (q * 64 + lane < len) put_sorted(g, k[q], rg.x + q * 64 + lane, keys, vals);
+}
+
+// One wave per tile with at most kShortList pairs: up to 64 pairs, every
+// pair's rank is the number of smaller (depth, index) values in the list;
+// more, a bitonic sort in registers.  Longer lists are put on the long-list
+// list.  Wave w takes the tile at position w of the backward render order
+// (longest lists first, written just before).
 __global__ __launch_bounds__(64) void k_sort_short_lists(const uint2* __restrict__ ranges, int64_t n_tiles,
                                                          Status* __restrict__ status, uint64_t capacity,
                                                          const uint64_t* __restrict__ in_keys,
@@ -196,7 +255,7 @@ __global__ __launch_bounds__(64) void k_sort_short_lists(const uint2* __restrict
     constexpr int PER = kShortList / 64;
     if (status->n_pairs > capacity) return;
     if ((int64_t)blockIdx.x >= n_tiles) return;
-    // longest lists first, so that their quadratic rankings start first
+    // longest lists first, so that their sorts start first
     const int64_t g = order[blockIdx.x];
     const uint2 rg = ranges[g];
     const int len = (int)(rg.y - rg.x);
@@ -218,31 +277,9 @@ __global__ __launch_bounds__(64) void k_sort_short_lists(const uint2* __restrict
         if (lane < len) put_sorted((uint64_t)g, k, rg.x + rank, keys, vals);
         return;
     }
-    uint64_t k[PER];
-    uint32_t rank[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int e = q * 64 + lane;
-        k[q] = (e < len) ? depth_index(in_keys, in_vals, rg.x + e) : ~0ull;
-        rank[q] = 0;
-    }
-    const int nq = (len + 63) / 64;
-    for (int q2 = 0; q2 < nq; ++q2) {
-        const int jn = min(64, len - q2 * 64);
-        uint64_t reg = k[0];
-#pragma unroll
-        for (int q = 1; q < PER; ++q)
-            if (q == q2) reg = k[q];
-        for (int j = 0; j < jn; ++j) {
-            const uint64_t kj = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(reg >> 32), j) << 32) |
-                                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)reg, j);
-#pragma unroll
-            for (int q = 0; q < PER; ++q) rank[q] += (kj < k[q]) ? 1u : 0u;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < PER; ++q)
-        if (q * 64 + lane < len) put_sorted((uint64_t)g, k[q], rg.x + rank[q], keys, vals);
+    if (len <= 128) sort_list<2>(in_keys, in_vals, rg, len, lane, (uint64_t)g, keys, vals);
+    else if (len <= 256) sort_list<4>(in_keys, in_vals, rg, len, lane, (uint64_t)g, keys, vals);
+    else sort_list<PER>(in_keys, in_vals, rg, len, lane, (uint64_t)g, keys, vals);
 }
 
 __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
