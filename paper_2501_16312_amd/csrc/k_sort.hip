@@ -54,11 +54,7 @@ __device__ inline void emit_wave(int64_t t, int64_t n_vis, const uint32_t* __res
     }
     // short runs: inclusive prefix of their lengths over the wave
     const uint32_t cs = cnt <= kShortRun ? cnt : 0u;
-    uint32_t incl = cs;
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d, 64);
-        if (lane >= d) incl += y;
-    }
+    uint32_t incl = wave_incl_scan_u32(cs);
     const uint32_t excl = incl - cs;
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     for (uint32_t q = (uint32_t)lane; q - lane < total; q += 64) {
@@ -452,11 +448,7 @@ __global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist
     for (int64_t b0 = 0; b0 < nblocks; b0 += 1024) {
         const int64_t idx = b0 + t;
         const uint32_t x = (idx < nblocks) ? row[idx] : 0u;
-        uint32_t incl = x;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
+        uint32_t incl = wave_incl_scan_u32(x);
         if (lane == 63) wsum[wave] = incl;
         __syncthreads();
         uint32_t before = 0, total = 0;
@@ -498,13 +490,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
         for (int d0 = 0; d0 < radix; d0 += 64) {
             const int d = d0 + lane;
             uint32_t x = (d < radix) ? digit_totals[d] : 0u;
-            uint32_t incl = x;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += y;
-            }
+            uint32_t incl = wave_incl_scan_u32(x);
             if (d < radix) base[d] = carry + incl - x + hist[(int64_t)d * nblocks + blockIdx.x];
-            carry += __shfl(incl, 63, 64);
+            carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
     }
     for (int d = t; d < 256; d += kSortThreads) {
@@ -560,13 +548,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
         for (int d0 = 0; d0 < radix; d0 += 64) {
             const int d = d0 + lane;
             const uint32_t x = (d < radix) ? running[d] : 0u;
-            uint32_t incl = x;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += y;
-            }
+            uint32_t incl = wave_incl_scan_u32(x);
             if (d < radix) wave_cnt[0][d] = carry + incl - x;
-            carry += __shfl(incl, 63, 64);
+            carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
     }
     __syncthreads();
@@ -655,11 +639,7 @@ __global__ __launch_bounds__(1024) void k_order_prefix(uint32_t* __restrict__ su
     for (int64_t b0 = 0; b0 < count; b0 += 1024) {
         const int64_t idx = b0 + t;
         const uint32_t x = (idx < count) ? sums[idx] : 0u;
-        uint32_t incl = x;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
+        uint32_t incl = wave_incl_scan_u32(x);
         if (lane == 63) wsum[wave] = incl;
         __syncthreads();
         uint32_t wb = 0, tot = 0;
@@ -683,6 +663,18 @@ __global__ __launch_bounds__(1024) void k_order_prefix(uint32_t* __restrict__ su
 // Counter slots: classes 0..K-1, then groups K..K+G-1; first[K + G + g] is
 // the first position of group g in the whole forward order.
 static_assert(kOrderDirectBlocks <= 256, "direct mode: one block's counts per thread");
+
+// Sum over the 64 lanes of a wave by DPP steps (every lane must be active);
+// lane 63 ends with the total, which is returned to every lane.
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);    // quad_perm(1,0,3,2)
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);    // quad_perm(2,3,0,1)
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xF, 0xF, false);   // row_mirror
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0x8, 0xF, false);   // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
 
 __device__ inline int order_group(int c) {
     int g = 0;
@@ -742,8 +734,7 @@ __global__ __launch_bounds__(256) void k_order_write(const uint2* __restrict__ r
         }
 #pragma unroll
         for (int c = 0; c < NS + G; ++c) {
-            uint32_t v = part[c];
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            const uint32_t v = wave_sum_u32(part[c]);
             if (lane == 0) wave_cnt[wave][c] = v;
         }
         __syncthreads();

@@ -130,6 +130,20 @@ int key_tile_bits(int64_t n_tiles_total);
 // ----------------------------------------------------------------------------
 // Host-side launchers (one per kernel file).
 // ----------------------------------------------------------------------------
+// Inclusive prefix sum over the 64 lanes of a wave by DPP steps (every lane
+// must be active): row shifts by 1, 2, 4 and 8 within each row of 16 lanes,
+// then the last lane of row 0 added to row 1 and of row 2 to row 3, then lane
+// 31 to rows 2 and 3.
+__device__ inline uint32_t wave_incl_scan_u32(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);    // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);    // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);    // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);    // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return v;
+}
+
 // Views passed by value in one launch argument.
 constexpr int kViewChunk = 8;
 struct ViewChunk {
