@@ -594,14 +594,14 @@ __global__ __launch_bounds__(256) void k_tile_ranges(const uint64_t* __restrict_
     if (i == (int64_t)np - 1 || (uint32_t)(keys[i + 1] >> 32) != tile) ranges[tile].y = (uint32_t)(i + 1);
 }
 
-// Render orders.  The backward takes the tiles by list length, longest
-// first, in kOrderClasses classes (tile order inside a class), so that the
-// waves that start last are short.  The forward, whose walks are cheaper and
-// more sensitive to cache locality, takes them in kFwdGroups coarser groups
-// of consecutive classes (tile order inside a group).
-// Counts are kept class-major, sums[c * nblocks + b] for class c in block b
-// of `items` tiles (order_items), so that one exclusive scan over them gives every
-// (class, block) its first position.
+// Render orders.  The backward (and the exact variant's forward) takes the
+// tiles by list length, longest first, in kOrderClasses classes (tile order
+// inside a class), so that the waves that start last are short.  The
+// ray-space forward, whose walks are cheaper and more sensitive to cache
+// locality, takes them in kFwdGroups coarser groups of consecutive classes
+// (tile order inside a group).  Counts are kept class-major, sums[c *
+// nblocks + b] for class c in block b of `items` tiles (order_items), so that
+// one exclusive scan over them gives every (class, block) its first position.
 __device__ inline int order_class(uint32_t len) {
     int c = 0;
 #pragma unroll
