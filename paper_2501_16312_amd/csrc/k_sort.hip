@@ -473,9 +473,13 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
                                                                 const uint32_t* __restrict__ digit_totals,
                                                                 uint64_t* __restrict__ keys_out,
                                                                 uint32_t* __restrict__ vals_out) {
+    constexpr int NW = kSortThreads / 64;
     __shared__ uint32_t base[256];       // global start of each digit for this block
-    __shared__ uint32_t running[256];    // keys of each digit ranked so far in this block
-    __shared__ uint32_t wave_cnt[kSortThreads / 64][256];
+    __shared__ uint32_t running[256];    // keys of each digit in this block
+    __shared__ uint32_t dstart[256];     // first position of each digit in lkey
+    // keys of each digit per (item round, wave), then their exclusive prefix
+    // over the rounds and waves in index order
+    __shared__ uint32_t cnt[kSortItems][NW][256];
     __shared__ uint64_t lkey[kSortTile];  // the block's keys in digit order
     __shared__ uint32_t lval[kSortTile];
     const uint64_t np = status->n_pairs;
@@ -495,10 +499,9 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
             carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
     }
-    for (int d = t; d < 256; d += kSortThreads) {
-        running[d] = 0;
-        for (int w = 0; w < kSortThreads / 64; ++w) wave_cnt[w][d] = 0;
-    }
+    for (int d = t; d < 256; d += kSortThreads)
+        for (int k = 0; k < kSortItems; ++k)
+            for (int w = 0; w < NW; ++w) cnt[k][w][d] = 0;
     __syncthreads();
     // 1. rank of every key among the block's keys of its digit, in index order
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -525,31 +528,33 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
-        if (valid && rank == 0) wave_cnt[wave][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        uint32_t pre = running[d] + rank;
-        for (int w = 0; w < wave; ++w) pre += wave_cnt[w][d];
-        rnk[k] = pre;
-        __syncthreads();
-        for (int dd = t; dd < radix; dd += kSortThreads) {
-            uint32_t sum = 0;
-            for (int w = 0; w < kSortThreads / 64; ++w) {
-                sum += wave_cnt[w][dd];
-                wave_cnt[w][dd] = 0;
-            }
-            running[dd] += sum;
-        }
-        __syncthreads();
+        if (valid && rank == 0) cnt[k][wave][d] = (uint32_t)__popcll(peers);
+        rnk[k] = rank;
     }
+    __syncthreads();
+    // per digit: exclusive prefix over (round, wave) in index order
+    for (int d = t; d < radix; d += kSortThreads) {
+        uint32_t run = 0;
+        for (int k = 0; k < kSortItems; ++k)
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = cnt[k][w][d];
+                cnt[k][w][d] = run;
+                run += c;
+            }
+        running[d] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kSortItems; ++k) rnk[k] += cnt[k][wave][dig[k]];
     // 2. the block's digit starts (exclusive scan of its digit counts, one
-    //    wave; wave_cnt[0] holds them), keys placed in LDS in digit order
+    //    wave), keys placed in LDS in digit order
     if (t < 64) {
         uint32_t carry = 0;
         for (int d0 = 0; d0 < radix; d0 += 64) {
             const int d = d0 + lane;
             const uint32_t x = (d < radix) ? running[d] : 0u;
             uint32_t incl = wave_incl_scan_u32(x);
-            if (d < radix) wave_cnt[0][d] = carry + incl - x;
+            if (d < radix) dstart[d] = carry + incl - x;
             carry += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         }
     }
@@ -559,7 +564,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
     for (int k = 0; k < kSortItems; ++k) {
         const int64_t idx = blk + (int64_t)k * kSortThreads + t;
         if (idx < (int64_t)np) {
-            const uint32_t lp = wave_cnt[0][dig[k]] + rnk[k];
+            const uint32_t lp = dstart[dig[k]] + rnk[k];
             lkey[lp] = key[k];
             lval[lp] = val[k];
         }
@@ -569,7 +574,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(const uint64_t* 
     for (int i = t; i < nk; i += kSortThreads) {
         const uint64_t kk = lkey[i];
         const uint32_t d = (uint32_t)(kk >> shift) & (uint32_t)(radix - 1);
-        const uint32_t pos = base[d] + (uint32_t)i - wave_cnt[0][d];
+        const uint32_t pos = base[d] + (uint32_t)i - dstart[d];
         keys_out[pos] = kk;
         vals_out[pos] = lval[i];
     }
