@@ -155,6 +155,24 @@ def test_sort_long_lists(oracle_mod, n):
         _check_sorted(dbg, s, g["n_pairs"])
 
 
+def test_sort_list_size_classes(oracle_mod):
+    """Per-tile lists in every size class of the list sort: up to 64 pairs
+    (counted ranks), 65-128, 129-256 and 257-512 (a bitonic network in
+    registers with 2, 4 and 8 keys per lane); bit-exact against the oracle's
+    stable sort."""
+    _say("sort list size classes")
+    sc = scenes.uniform_octahedra(6000, seed=6000, box=0.6, dmin=0.01, dmax=0.1)
+    cams = [scenes.look_at((0.1, 0.2, -2.5), (0, 0, 0), 160, 96)]
+    g = GC.gpu_forward(sc, cams, tile=8)
+    dbg = g["rast"].debug_arrays(g["prims"])
+    s = oracle_mod.OracleScene(sc, cams, tile=8).sort()
+    lens = s["ranges"][:, 1] - s["ranges"][:, 0]
+    counts = [int(((lens > a) & (lens <= b)).sum()) for a, b in ((0, 64), (64, 128), (128, 256), (256, 512))]
+    _say(f"  lists per class (1-64, 65-128, 129-256, 257-512): {counts}")
+    assert min(counts) > 0
+    _check_sorted(dbg, s, g["n_pairs"])
+
+
 # ------------------------------------------------------------ forward
 @pytest.mark.parametrize("sh_degree", [0, 1, 2, 3])
 @pytest.mark.parametrize("kind", [OCTA, TETRA])
